@@ -1,0 +1,274 @@
+/*
+ * vcgs -- differentiable tile-based Gaussian rasterizer for voxel-anchored
+ * compact 3D Gaussian SLAM (arXiv 2403.11247), native on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * C ABI.  Every pointer argument that names image, Gaussian, anchor, weight or
+ * gradient data is a DEVICE pointer owned by the caller; the library never
+ * frees caller memory.  Structs passed by pointer (cameras, poses, the
+ * descriptors below) live in HOST memory and are read during the call only.
+ * Every call enqueues work on the caller's `stream` (hipStream_t passed as
+ * void*) and returns before the GPU finishes unless stated otherwise.
+ * Return value: VCGS_OK (0) or a negative VCGS_E_* code; the message of the
+ * last failing call on the calling thread is returned by vcgs_last_error().
+ * A context serves one device; calls on one context must not overlap in time
+ * from different host threads.
+ *
+ * Array layouts (float32 unless noted; n = number of Gaussians):
+ *   mean [3][n], scale [3][n] (linear, not log), quat [4][n] (w, x, y, z; need
+ *   not be unit: the renderer normalises it, a zero quaternion means identity),
+ *   opacity [n], color [3][n];
+ *   images: color [3][H][W], depth [H][W], alpha [H][W] (row-major, x fastest).
+ */
+#ifndef VCGS_H
+#define VCGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VCGS_OK = 0,
+    VCGS_E_INVALID = -1,      /* bad argument: null pointer, negative size, unsupported tile size */
+    VCGS_E_NOMEM = -2,        /* device allocation failed */
+    VCGS_E_CAPACITY = -3,     /* a fixed-capacity buffer was too small (batched/captured mode) */
+    VCGS_E_HIP = -4,          /* a HIP runtime call failed (message holds the HIP error string) */
+    VCGS_E_UNSUPPORTED = -5   /* device is not gfx950 or the request exceeds a documented limit */
+};
+
+typedef struct vcgs_ctx vcgs_ctx;
+typedef struct vcgs_state vcgs_state;
+
+/* Pinhole camera with known intrinsics K (paper Sec. 3: RGB-D frames with known
+ * K).  Pixel (x, y) is sampled at (x + 0.5, y + 0.5).  z_near culls Gaussians
+ * whose mean is not in front of the camera.  tile must be 16. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float z_near;
+    int32_t tile;
+} vcgs_camera;
+
+/* Camera pose {R|t} (paper Sec. 3), world to camera: p_cam = R p_world + t.
+ * R row-major.  The camera looks along +z, x right, y down. */
+typedef struct {
+    float R[9];
+    float t[3];
+} vcgs_pose;
+
+/* Gaussian attributes (paper Sec. 3.2: position, opacity, quaternion, scaling, colour). */
+typedef struct {
+    int64_t n;
+    const float* mean;
+    const float* scale;
+    const float* quat;
+    const float* opacity;
+    const float* color;
+} vcgs_gaussians;
+
+/* Writable Gaussian-shaped buffers: decode output, or gradients. */
+typedef struct {
+    float* mean;
+    float* scale;
+    float* quat;
+    float* opacity;
+    float* color;
+} vcgs_gaussian_buffers;
+
+typedef struct {
+    float* color;  /* [3][H][W]  eq. (16) plus T_final * background */
+    float* depth;  /* [H][W]     eq. (17), not normalised */
+    float* alpha;  /* [H][W]     eq. (18), the silhouette S(p) */
+} vcgs_images;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  Fails with VCGS_E_UNSUPPORTED if
+ * the device is not gfx950. */
+int vcgs_create(int device, vcgs_ctx** out);
+void vcgs_destroy(vcgs_ctx* ctx);
+/* Message of the last failing call on this host thread ("" if none). */
+const char* vcgs_last_error(void);
+/* Library version string. */
+const char* vcgs_version(void);
+
+/* ---- plain render ----------------------------------------------------- */
+
+/* Forward render of one view (paper eqs. (1)-(3) and (16)-(18)).
+ *   Projects every Gaussian (EWA, eq. (3) with W = R), bins it to the 16x16
+ *   tiles its footprint can reach, sorts the (tile, depth) pairs (stable: equal
+ *   keys keep Gaussian index order), and composites each pixel front to back:
+ *     alpha_i = min(0.99, o_i exp(-1/2 d^T Q_i d)), skipped when < 1/255;
+ *     stops before the Gaussian that would take the transmittance below 1e-4;
+ *     C = sum c_i alpha_i T_i + T_final bg, D = sum z_i alpha_i T_i, A = sum alpha_i T_i.
+ *   bg: 3 floats in HOST memory.  out: device images of the camera's size.
+ *   state: if non-NULL, receives a new saved-for-backward object (free with
+ *   vcgs_state_free).  The call synchronises `stream` once, after binning, to
+ *   size the pair buffers.
+ */
+int vcgs_render_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camera* cam,
+                        const vcgs_pose* pose, const float bg[3], vcgs_images* out,
+                        vcgs_state** state, void* stream);
+
+/* Backward of vcgs_render_forward (paper Sec. 4: the renderer's backward
+ * propagation extended to depth, pose and cumulative opacity).
+ *   g, cam, pose, bg must be those of the forward call, unchanged.
+ *   dl_dcolor [3][H][W], dl_ddepth [H][W], dl_dalpha [H][W]: device upstream
+ *   gradients (any may be NULL = zero).
+ *   grads: device buffers of the Gaussian shapes, OVERWRITTEN with dL/d(mean,
+ *   scale, quat, opacity, color) (culled Gaussians get 0); any field may be NULL.
+ *   dl_dpose: device float[6], OVERWRITTEN with dL/dxi for the left
+ *   perturbation {R|t} <- exp(xi^) {R|t}, xi = (rho, phi) at 0; may be NULL.
+ *   The compositing is replayed back to front from the saved final
+ *   transmittance; no per-pixel lists are stored.
+ */
+int vcgs_render_backward(vcgs_ctx* ctx, const vcgs_state* state, const vcgs_gaussians* g,
+                         const vcgs_camera* cam, const vcgs_pose* pose,
+                         const float* dl_dcolor, const float* dl_ddepth, const float* dl_dalpha,
+                         vcgs_gaussian_buffers* grads, float* dl_dpose, void* stream);
+
+void vcgs_state_free(vcgs_ctx* ctx, vcgs_state* state);
+
+/* Read-only view of a saved state, for inspection and tests.  Device pointers
+ * stay valid until vcgs_state_free.
+ *   depth_bits[n]  uint32 bits of the float camera depth (0xFFFFFFFF = culled)
+ *   rect[n]        uint16 x4 (tx0, ty0, tx1, ty1) inclusive tile rectangle
+ *   count[n]       uint32 number of tiles (0 = culled)
+ *   gids[P]        Gaussian index of every (tile, depth)-sorted pair
+ *   ranges[T][2]   [start, end) of each tile's pairs in gids
+ *   t_final[H][W], n_contrib[H][W] (uint32: list entries up to the last contributor)
+ *   splats[n][12]  float: u, v, conic A, B, C, opacity, r, g, b, depth, 0, 0 (visible Gaussians only)
+ */
+typedef struct {
+    int64_t n, n_pairs;
+    int32_t tiles_x, tiles_y;
+    const uint32_t* depth_bits;
+    const uint16_t* rect;
+    const uint32_t* count;
+    const uint32_t* gids;
+    const uint32_t* ranges;
+    const float* t_final;
+    const uint32_t* n_contrib;
+    const float* splats;
+} vcgs_state_view;
+int vcgs_state_query(const vcgs_state* state, vcgs_state_view* out);
+
+/* L1 loss used by tracking and bundle adjustment (paper eq. (19) uses squared
+ * errors; the L1 form with depth weight w_depth is the workload's):
+ *   L = mean_p sum_c |C - C*| + w_depth mean_p |D - D*|.
+ * Writes dl_dcolor, dl_ddepth (device, image shapes; subgradient 0 at equality)
+ * and, if loss is non-NULL, the scalar loss (device float, overwritten). */
+int vcgs_l1_loss(vcgs_ctx* ctx, const vcgs_images* img, const float* target_color,
+                 const float* target_depth, int32_t width, int32_t height, float w_depth,
+                 float* dl_dcolor, float* dl_ddepth, float* loss, void* stream);
+
+/* ---- anchor decode ---------------------------------------------------- */
+
+/* Voxel anchors (paper Sec. 3.2): position x_a [3][na], feature f_a
+ * [na][feat_dim] (row-major), scaling l [3][na], offsets O [na][k][3]. */
+typedef struct {
+    int64_t n_anchor;
+    int32_t k;
+    int32_t feat_dim;   /* must be 32 */
+    const float* xa;
+    const float* feat;
+    const float* scaling;
+    const float* offset;
+} vcgs_anchors;
+
+/* Decoder MLP: h = ReLU(W1 f + b1), y = W2 h + b2.  W1 [32][32], b1 [32],
+ * W2 [k*11][32], b2 [k*11] (row-major, out x in).  Per offset i the 11 outputs
+ * y[11 i ..] are [opacity, r, g, b, 3 log-scales, quaternion w, x, y, z]. */
+typedef struct {
+    const float* W1;
+    const float* b1;
+    const float* W2;
+    const float* b2;
+} vcgs_mlp;
+
+/* Residual codebook (paper Sec. 3.4, eq. (14) first line): value of Gaussian
+ * j = sum over stages s of books[s][idx[s][j]][0..6] = (3 log-scales,
+ * quaternion).  books [stages][size][7], idx int32 [stages][na*k]; an index
+ * outside [0, size) is clamped into it. */
+typedef struct {
+    int32_t stages;
+    int32_t size;
+    const float* books;
+    const int32_t* idx;
+} vcgs_codebook;
+
+/* Decode anchors into na*k Gaussians (Gaussian index a*k + i), paper eqs. (7)-(8):
+ *   mean = x_a + O_i * l (element-wise), opacity = sigmoid, colour = sigmoid,
+ *   scale = exp(log-scale), quaternion passed on raw.
+ *   If cb is non-NULL, log-scale and quaternion come from the codebook instead
+ *   of the MLP.  If mask_logit [na*k] is non-NULL, Gaussians with
+ *   sigmoid(m) <= mask_eps get opacity 0 and scale 0 (paper eqs. (11)-(12)),
+ *   which the renderer culls.
+ *   out: device buffers of na*k Gaussians, overwritten.
+ *   Limits: feat_dim = 32, hidden = 32, 1 <= k <= 16. */
+int vcgs_decode_anchors(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
+                        const vcgs_codebook* cb, const float* mask_logit, float mask_eps,
+                        vcgs_gaussian_buffers* out, void* stream);
+
+/* Gradients of the decode.  Every output pointer may be NULL (not computed);
+ * all are OVERWRITTEN, with the shapes of the matching input. */
+typedef struct {
+    float* feat;
+    float* offset;
+    float* scaling;
+    float* xa;
+    float* W1;
+    float* b1;
+    float* W2;
+    float* b2;
+    float* books;       /* [stages][size][7]: straight-through sums over the Gaussians using each row */
+    float* mask_logit;  /* [na*k]: sigmoid'(m) (s . dL/ds_hat + alpha dL/dalpha_hat); 0 when pruned */
+} vcgs_anchor_grads;
+
+/* dG: dL/d(decoded Gaussians) (device, na*k Gaussians, e.g. from
+ * vcgs_render_backward).  Same a, mlp, cb, mask_logit, mask_eps as the forward. */
+int vcgs_decode_anchors_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
+                                 const vcgs_codebook* cb, const float* mask_logit, float mask_eps,
+                                 const vcgs_gaussian_buffers* dG, vcgs_anchor_grads* out, void* stream);
+
+/* ---- stage timing ------------------------------------------------------ */
+
+/* Stages timed with HIP events on the caller's stream when profiling is on. */
+enum {
+    VCGS_STAGE_DECODE = 0,        /* anchor decode (MFMA MLP, codebook, mask) */
+    VCGS_STAGE_PREPROCESS = 1,    /* EWA projection, keys, tile rectangles */
+    VCGS_STAGE_DEPTH_SORT = 2,    /* radix sort of the depth keys */
+    VCGS_STAGE_PAIR_SCAN = 3,     /* pair counts in depth order, their scan */
+    VCGS_STAGE_EMIT = 4,          /* (tile, Gaussian) pair emission */
+    VCGS_STAGE_TILE_SORT = 5,     /* stable radix sort of the pairs by tile */
+    VCGS_STAGE_TILE_RANGES = 6,   /* per-tile [start, end) */
+    VCGS_STAGE_COMPOSITE = 7,     /* forward compositing */
+    VCGS_STAGE_LOSS = 8,          /* L1 loss and its image gradients */
+    VCGS_STAGE_COMPOSITE_BWD = 9, /* replayed compositing adjoint */
+    VCGS_STAGE_PREPROCESS_BWD = 10, /* projection adjoint and pose reduction */
+    VCGS_STAGE_DECODE_BWD = 11,   /* decode adjoint (MFMA) */
+    VCGS_STAGE_COUNT = 16
+};
+
+/* Turn per-stage event timing on (1) or off (0); turning it on clears the totals. */
+int vcgs_profile_enable(vcgs_ctx* ctx, int on);
+/* Synchronises the recorded events and returns the summed duration (ms) and
+ * the number of timed launches of `stage` since profiling was enabled. */
+int vcgs_profile_read(vcgs_ctx* ctx, int stage, double* total_ms, int64_t* launches);
+
+/* Work counters of the last forward and backward compositing call, filled
+ * when counting is on (slower; for measurement only):
+ *   fwd_evals   (pixel, list entry) footprint evaluations in the forward
+ *   fwd_blends  of which blended into the pixel
+ *   bwd_evals   footprint evaluations replayed in the backward
+ *   bwd_blends  of which produced gradients
+ *   bwd_atomics per-Gaussian gradient flushes (10 atomics each) */
+int vcgs_count_enable(vcgs_ctx* ctx, int on);
+int vcgs_count_read(vcgs_ctx* ctx, int64_t out[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VCGS_H */

@@ -49,8 +49,16 @@ typedef struct {
 #define ORC_ALPHA_MAX (0.99f)
 #define ORC_T_MIN (1e-4f)
 #define ORC_LOWPASS (0.3f)
+#define ORC_LOWPASS2 (0.09f)
 #define ORC_CLAMP_FOV (1.3f)
 #define ORC_TWO_LN2 (1.3862944f)
+
+/* Relative half-widths of the bands in which an FP32 evaluation of the same
+ * footprint may take the other side of a threshold: the FP32 footprint carries
+ * a relative error of a few 1e-6, the transmittance after a few hundred
+ * factors (1 - alpha) up to ~1e-4. */
+#define ORC_BAND_ALPHA (2e-5)
+#define ORC_BAND_T (5e-4)
 
 /* flag bits of an ambiguous pixel (a threshold decision lies within FP32 noise) */
 #define ORC_FLAG_ALPHA 1u
@@ -103,12 +111,6 @@ void orc_keys(int64_t n, const float* mean, const float* scale, const float* qua
         const float s0 = scale[g], s1 = scale[n + g], s2 = scale[2 * n + g];
         float m[9];
         for (int i = 0; i < 3; ++i) { m[3 * i] = r[3 * i] * s0; m[3 * i + 1] = r[3 * i + 1] * s1; m[3 * i + 2] = r[3 * i + 2] * s2; }
-        float S[9];
-        for (int i = 0; i < 3; ++i)
-            for (int j = i; j < 3; ++j) {
-                S[3 * i + j] = (m[3 * i] * m[3 * j] + m[3 * i + 1] * m[3 * j + 1]) + m[3 * i + 2] * m[3 * j + 2];
-                S[3 * j + i] = S[3 * i + j];
-            }
         /* projection Jacobian with clamped x/z, y/z */
         const float txz = X / Z, tyz = Y / Z;
         const float cxz = fminf(fmaxf(txz, -limx), limx);
@@ -120,17 +122,26 @@ void orc_keys(int64_t n, const float* mean, const float* scale, const float* qua
             T[j] = j00 * Rc[j] + j02 * Rc[6 + j];
             T[3 + j] = j11 * Rc[3 + j] + j12 * Rc[6 + j];
         }
-        float U[6];
+        /* Sigma' = K K^T with K = J W R S (2x3), eqs. (2)-(3) */
+        float K[6];
         for (int a = 0; a < 2; ++a)
             for (int j = 0; j < 3; ++j)
-                U[3 * a + j] = (T[3 * a] * S[j] + T[3 * a + 1] * S[3 + j]) + T[3 * a + 2] * S[6 + j];
-        const float ca = ((U[0] * T[0] + U[1] * T[1]) + U[2] * T[2]) + ORC_LOWPASS;
-        const float cb = (U[0] * T[3] + U[1] * T[4]) + U[2] * T[5];
-        const float cc = ((U[3] * T[3] + U[4] * T[4]) + U[5] * T[5]) + ORC_LOWPASS;
-        const float det = ca * cc - cb * cb;
+                K[3 * a + j] = (T[3 * a] * m[j] + T[3 * a + 1] * m[3 + j]) + T[3 * a + 2] * m[6 + j];
+        const float s00 = (K[0] * K[0] + K[1] * K[1]) + K[2] * K[2];
+        const float s01 = (K[0] * K[3] + K[1] * K[4]) + K[2] * K[5];
+        const float s11 = (K[3] * K[3] + K[4] * K[4]) + K[5] * K[5];
+        const float ca = s00 + ORC_LOWPASS;
+        const float cb = s01;
+        const float cc = s11 + ORC_LOWPASS;
+        /* det(Sigma' + 0.3 I) = det(K K^T) + 0.3 tr(K K^T) + 0.09, det(K K^T) as the sum of squared 2x2 minors */
+        const float m01 = K[0] * K[4] - K[1] * K[3];
+        const float m02 = K[0] * K[5] - K[2] * K[3];
+        const float m12 = K[1] * K[5] - K[2] * K[4];
+        const float detk = (m01 * m01 + m02 * m02) + m12 * m12;
+        const float det = (detk + ORC_LOWPASS * (s00 + s11)) + ORC_LOWPASS2;
         if (!(det > 0.0f)) continue;
-        const float mid = 0.5f * (ca + cc);
-        const float lam = mid + sqrtf(fmaxf(mid * mid - det, 0.0f));
+        const float hd = 0.5f * (ca - cc);
+        const float lam = 0.5f * (ca + cc) + sqrtf(hd * hd + cb * cb);
         const float y255 = 255.0f * o;
         const int e = (int)((f2u(y255) >> 23) & 0xFFu) - 127;
         const float kf = ORC_TWO_LN2 * (float)(e + 1);
@@ -338,11 +349,11 @@ static void composite_px(const double* splat, const double* opac, const double* 
     for (uint32_t k = lo; k < hi; ++k) {
         const uint32_t g = gids[k];
         const orc_fp f = footprint(splat + 6 * (size_t)g, opac[g], px, py);
-        if (near_rel(f.raw, (double)ORC_ALPHA_MIN, 1e-4)) fl |= ORC_FLAG_ALPHA;
-        if (near_rel(f.raw, (double)ORC_ALPHA_MAX, 1e-4)) fl |= ORC_FLAG_CLAMP;
+        if (near_rel(f.raw, (double)ORC_ALPHA_MIN, ORC_BAND_ALPHA)) fl |= ORC_FLAG_ALPHA;
+        if (near_rel(f.raw, (double)ORC_ALPHA_MAX, ORC_BAND_ALPHA)) fl |= ORC_FLAG_CLAMP;
         if (f.alpha < (double)ORC_ALPHA_MIN) continue;
         const double Tn = T * (1.0 - f.alpha);
-        if (near_rel(Tn, (double)ORC_T_MIN, 2e-3)) fl |= ORC_FLAG_STOP;
+        if (near_rel(Tn, (double)ORC_T_MIN, ORC_BAND_T)) fl |= ORC_FLAG_STOP;
         if (Tn < (double)ORC_T_MIN) break;
         const double w = f.alpha * T;
         c0 += w * color[g]; c1 += w * color[n + g]; c2 += w * color[2 * n + g];

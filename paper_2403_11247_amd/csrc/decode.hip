@@ -1,0 +1,533 @@
+// Anchor decode (paper Sec. 3.2, eqs. (7)-(8); mask eqs. (11)-(12); residual
+// codebook eq. (14), first line) and its adjoint.
+//
+// The MLP h = ReLU(W1 f + b1), y = W2 h + b2 is the one dense contraction of
+// the path and runs on FP32 MFMA (v_mfma_f32_16x16x4_f32): a wave decodes 16
+// anchors at a time, anchors along the MFMA N dimension.  The second layer
+// consumes the first layer's accumulators in place: its K index is ordered to
+// match the accumulator layout (lane l holds rows 4*(l/16)+i of column l%16),
+// so no data moves between the layers.  Outputs go through a wave-private LDS
+// slab so the per-Gaussian activations are written coalesced, structure of
+// arrays, Gaussian index = anchor * k + offset.
+//
+// Backward recomputes the forward MLP, forms dL/dy in LDS, and runs the three
+// transposed products (dh = W2^T dy, df = W1^T dpre, and the weight gradients
+// dW2 = dy h^T, dW1 = dpre f^T summed over anchors) on MFMA as well.  Weight
+// gradients are summed per wave in registers, per block in a fixed wave order,
+// and across blocks in block order (deterministic).
+#include "internal.h"
+
+namespace vcgs {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kF = 32;
+constexpr int kMaxK = 16;
+constexpr int kMaxO = kMaxK * 11;
+constexpr int kLdsO = kMaxO + 1;
+
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+__device__ __forceinline__ void wsync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Codebook row of Gaussian g at stage s; indices outside [0, size) are clamped.
+__device__ __forceinline__ int code_index(const DecodeArgs& a, int s, int64_t n, int64_t g)
+{
+    const int i = a.idx[(int64_t)s * n + g];
+    return i < 0 ? 0 : (i >= a.cb_size ? a.cb_size - 1 : i);
+}
+
+// Gaussian attributes of one (anchor, offset) from the MLP outputs y[0..10].
+struct Decoded {
+    float o_raw, c[3], s_raw[3], q[4], v[7];
+    bool keep;
+};
+
+__device__ __forceinline__ Decoded decode_one(const DecodeArgs& a, const float* y, int64_t g)
+{
+    Decoded d;
+    d.o_raw = sigm(y[0]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) d.c[i] = sigm(y[1 + i]);
+    if (a.books) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) d.v[i] = 0.0f;
+        const int64_t n = a.na * a.k;
+        for (int s = 0; s < a.stages; ++s) {
+            const float* row = a.books + ((int64_t)s * a.cb_size + code_index(a, s, n, g)) * 7;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) d.v[i] += row[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) d.v[i] = y[4 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) d.s_raw[i] = __expf(d.v[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d.q[i] = d.v[3 + i];
+    d.keep = a.mask_logit ? (a.mask_logit[g] > a.mask_thr) : true;
+    return d;
+}
+
+// First layer for 16 anchors; returns the pre-activations in accumulator layout.
+__device__ __forceinline__ void layer1(const float (&w1)[2][8], const float* __restrict__ feat, int64_t an, bool valid,
+                                       int lane, v4f (&d1)[2])
+{
+    d1[0] = v4f{0.f, 0.f, 0.f, 0.f};
+    d1[1] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        const float b = valid ? feat[an * kF + ks * 4 + (lane >> 4)] : 0.0f;
+        d1[0] = mfma4(w1[0][ks], b, d1[0]);
+        d1[1] = mfma4(w1[1][ks], b, d1[1]);
+    }
+}
+
+template <int OT>
+__device__ __forceinline__ void load_weights(const DecodeArgs& a, int lane, float (&w1)[2][8], float (&b1v)[2][4],
+                                             float (&w2)[OT][8], float (&b2v)[OT][4])
+{
+    const int O = a.k * 11;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) w1[mt][ks] = a.W1[(mt * 16 + (lane & 15)) * kF + ks * 4 + (lane >> 4)];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b1v[mt][i] = a.b1[mt * 16 + 4 * (lane >> 4) + i];
+#pragma unroll
+    for (int t = 0; t < OT; ++t) {
+        const int m = t * 16 + (lane & 15);
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int n = (st >> 2) * 16 + 4 * (lane >> 4) + (st & 3);
+            w2[t][st] = m < O ? a.W2[m * kF + n] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int mm = t * 16 + 4 * (lane >> 4) + i;
+            b2v[t][i] = mm < O ? a.b2[mm] : 0.0f;
+        }
+    }
+}
+
+template <int OT>
+__global__ void __launch_bounds__(256) k_decode_fwd(DecodeArgs a, float* __restrict__ mean, float* __restrict__ scale,
+                                                    float* __restrict__ quat, float* __restrict__ opac,
+                                                    float* __restrict__ color)
+{
+    __shared__ float ys[4][16][kLdsO];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int O = a.k * 11;
+    float w1[2][8], b1v[2][4], w2[OT][8], b2v[OT][4];
+    load_weights<OT>(a, lane, w1, b1v, w2, b2v);
+    const int64_t n = a.na * a.k;
+    const int64_t groups = (a.na + 15) / 16;
+    for (int64_t grp = (int64_t)blockIdx.x * 4 + wave; grp < groups; grp += (int64_t)gridDim.x * 4) {
+        const int64_t a0 = grp * 16;
+        const int64_t an = a0 + (lane & 15);
+        v4f d1[2];
+        layer1(w1, a.feat, an, an < a.na, lane, d1);
+        float h[2][4];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[mt][i] = fmaxf(d1[mt][i] + b1v[mt][i], 0.0f);
+        wsync();
+#pragma unroll
+        for (int t = 0; t < OT; ++t) {
+            v4f d2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < 8; ++st) d2 = mfma4(w2[t][st], h[st >> 2][st & 3], d2);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = t * 16 + 4 * (lane >> 4) + i;
+                if (m < O) ys[wave][lane & 15][m] = d2[i] + b2v[t][i];
+            }
+        }
+        wsync();
+        for (int e = lane; e < 16 * a.k; e += 64) {
+            const int al = e / a.k, off = e - al * a.k;
+            const int64_t anc = a0 + al;
+            if (anc >= a.na) continue;
+            const int64_t g = anc * a.k + off;
+            const Decoded d = decode_one(a, &ys[wave][al][off * 11], g);
+            opac[g] = d.keep ? d.o_raw : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                color[i * n + g] = d.c[i];
+                scale[i * n + g] = d.keep ? d.s_raw[i] : 0.0f;
+                const float* O3 = a.offset + g * 3;
+                mean[i * n + g] = a.xa[i * a.na + anc] + O3[i] * a.scaling[i * a.na + anc];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) quat[i * n + g] = d.q[i];
+        }
+    }
+}
+
+static int out_tiles(int k) { return (k * 11 + 15) / 16; }
+
+void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hipStream_t s)
+{
+    if (a.na <= 0) return;
+    const int64_t groups = (a.na + 15) / 16;
+    const int blocks = (int)std::min<int64_t>((groups + 3) / 4, 4096);
+#define VCGS_DEC_FWD(OT)                                                                                        \
+    case OT:                                                                                                    \
+        k_decode_fwd<OT><<<blocks, 256, 0, s>>>(a, out.mean, out.scale, out.quat, out.opacity, out.color);      \
+        break;
+    switch (out_tiles(a.k)) {
+        VCGS_DEC_FWD(1) VCGS_DEC_FWD(2) VCGS_DEC_FWD(3) VCGS_DEC_FWD(4) VCGS_DEC_FWD(5) VCGS_DEC_FWD(6)
+        VCGS_DEC_FWD(7) VCGS_DEC_FWD(8) VCGS_DEC_FWD(9) VCGS_DEC_FWD(10) VCGS_DEC_FWD(11)
+        default: break;
+    }
+#undef VCGS_DEC_FWD
+}
+
+// ---------------------------------------------------------------------------
+// Backward
+// ---------------------------------------------------------------------------
+constexpr int kBwdWaves = 2;
+constexpr int kBwdMaxBlocks = 256;
+
+// partial layout per block: dW2 [O][32] | db2 [O] | dW1 [32][32] | db1 [32]
+__host__ __device__ int64_t decode_bwd_partial_floats(int k) { return (int64_t)k * 11 * kF + k * 11 + kF * kF + kF; }
+
+int decode_bwd_blocks(int64_t na)
+{
+    const int64_t groups = (na + 15) / 16;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((groups + kBwdWaves - 1) / kBwdWaves, kBwdMaxBlocks));
+}
+
+template <int OT>
+__global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcgs_gaussian_buffers dG,
+                                                               vcgs_anchor_grads out, float* __restrict__ partial)
+{
+    // ys and dys share one buffer that also holds the block reduction at the end
+    __shared__ float smem[2][kBwdWaves][16][kLdsO];
+    float (*ys)[16][kLdsO] = smem[0];
+    float (*dys)[16][kLdsO] = smem[1];
+    __shared__ float hs[kBwdWaves][16][kF + 1];
+    __shared__ float ps[kBwdWaves][16][kF + 1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int O = a.k * 11;
+    const int64_t n = a.na * a.k;
+    float w1[2][8], b1v[2][4], w2[OT][8], b2v[OT][4];
+    load_weights<OT>(a, lane, w1, b1v, w2, b2v);
+    // transposed operands: W2^T (rows n, k = m) and W1^T in the accumulator-ordered K
+    float w2t[2][OT * 4];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int ks = 0; ks < OT * 4; ++ks) {
+            const int m = ks * 4 + (lane >> 4);
+            w2t[nt][ks] = m < O ? a.W2[m * kF + nt * 16 + (lane & 15)] : 0.0f;
+        }
+    float w1t[2][8];
+#pragma unroll
+    for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int nn = (st >> 2) * 16 + 4 * (lane >> 4) + (st & 3);
+            w1t[ft][st] = a.W1[nn * kF + ft * 16 + (lane & 15)];
+        }
+    v4f accW2[OT][2], accW1[2][2];
+#pragma unroll
+    for (int t = 0; t < OT; ++t) accW2[t][0] = accW2[t][1] = v4f{0.f, 0.f, 0.f, 0.f};
+    accW1[0][0] = accW1[0][1] = accW1[1][0] = accW1[1][1] = v4f{0.f, 0.f, 0.f, 0.f};
+    float accB2[(kMaxO + 63) / 64] = {0.f, 0.f, 0.f};
+    float accB1 = 0.0f;
+
+    const int64_t groups = (a.na + 15) / 16;
+    for (int64_t grp = (int64_t)blockIdx.x * kBwdWaves + wave; grp < groups; grp += (int64_t)gridDim.x * kBwdWaves) {
+        const int64_t a0 = grp * 16;
+        const int64_t an = a0 + (lane & 15);
+        const bool avalid = an < a.na;
+        v4f d1[2];
+        layer1(w1, a.feat, an, avalid, lane, d1);
+        float pre[2][4], h[2][4];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                pre[mt][i] = d1[mt][i] + b1v[mt][i];
+                h[mt][i] = avalid ? fmaxf(pre[mt][i], 0.0f) : 0.0f;
+            }
+        wsync();
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) hs[wave][lane & 15][mt * 16 + 4 * (lane >> 4) + i] = h[mt][i];
+#pragma unroll
+        for (int t = 0; t < OT; ++t) {
+            v4f d2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < 8; ++st) d2 = mfma4(w2[t][st], h[st >> 2][st & 3], d2);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = t * 16 + 4 * (lane >> 4) + i;
+                if (m < O) ys[wave][lane & 15][m] = d2[i] + b2v[t][i];
+            }
+        }
+        wsync();
+        // dL/dy per (anchor, offset); codebook and mask gradients
+        for (int e = lane; e < 16 * a.k; e += 64) {
+            const int al = e / a.k, off = e - al * a.k;
+            const int64_t anc = a0 + al;
+            float* dy = &dys[wave][al][off * 11];
+            if (anc >= a.na) {
+#pragma unroll
+                for (int i = 0; i < 11; ++i) dy[i] = 0.0f;
+                continue;
+            }
+            const int64_t g = anc * a.k + off;
+            const Decoded d = decode_one(a, &ys[wave][al][off * 11], g);
+            float ds[3], dq[4], dc[3], dop;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                ds[i] = dG.scale ? dG.scale[i * n + g] : 0.0f;
+                dc[i] = dG.color ? dG.color[i * n + g] : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dq[i] = dG.quat ? dG.quat[i * n + g] : 0.0f;
+            dop = dG.opacity ? dG.opacity[g] : 0.0f;
+            if (a.mask_logit) {
+                const float m = a.mask_logit[g];
+                float gm = 0.0f;
+                if (d.keep) {
+                    const float sg = sigm(m);
+                    gm = sg * (1.0f - sg) * (ds[0] * d.s_raw[0] + ds[1] * d.s_raw[1] + ds[2] * d.s_raw[2] + dop * d.o_raw);
+                } else {
+                    ds[0] = ds[1] = ds[2] = 0.0f;
+                    dop = 0.0f;
+                }
+                if (out.mask_logit) out.mask_logit[g] = gm;
+            }
+            dy[0] = dop * d.o_raw * (1.0f - d.o_raw);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dy[1 + i] = dc[i] * d.c[i] * (1.0f - d.c[i]);
+            float dv[7];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dv[i] = ds[i] * d.s_raw[i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dv[3 + i] = dq[i];
+            if (a.books) {
+#pragma unroll
+                for (int i = 0; i < 7; ++i) dy[4 + i] = 0.0f;
+                if (out.books) {
+                    for (int s = 0; s < a.stages; ++s) {
+                        float* row = out.books + ((int64_t)s * a.cb_size + code_index(a, s, n, g)) * 7;
+#pragma unroll
+                        for (int i = 0; i < 7; ++i) atomicAdd(row + i, dv[i]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 7; ++i) dy[4 + i] = dv[i];
+            }
+        }
+        // per-anchor sums over offsets: scaling, anchor position; and offsets
+        if (lane < 16) {
+            const int64_t anc = a0 + lane;
+            if (anc < a.na) {
+                float dl[3] = {0, 0, 0}, dx[3] = {0, 0, 0};
+                for (int off = 0; off < a.k; ++off) {
+                    const int64_t g = anc * a.k + off;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const float dm = dG.mean ? dG.mean[i * n + g] : 0.0f;
+                        dx[i] += dm;
+                        dl[i] += dm * a.offset[g * 3 + i];
+                        if (out.offset) out.offset[g * 3 + i] = dm * a.scaling[i * a.na + anc];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if (out.scaling) out.scaling[i * a.na + anc] = dl[i];
+                    if (out.xa) out.xa[i * a.na + anc] = dx[i];
+                }
+            }
+        }
+        wsync();
+        // db2 and dW2 += dy h^T  (K = the 16 anchors)
+#pragma unroll
+        for (int j = 0; j < (kMaxO + 63) / 64; ++j) {
+            const int m = lane + 64 * j;
+            if (m < O) {
+                float sacc = 0.0f;
+#pragma unroll
+                for (int al = 0; al < 16; ++al) sacc += dys[wave][al][m];
+                accB2[j] += sacc;
+            }
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int al = ks * 4 + (lane >> 4);
+            const float hb0 = hs[wave][al][lane & 15];
+            const float hb1 = hs[wave][al][16 + (lane & 15)];
+#pragma unroll
+            for (int t = 0; t < OT; ++t) {
+                const int m = t * 16 + (lane & 15);
+                const float av = m < O ? dys[wave][al][m] : 0.0f;
+                accW2[t][0] = mfma4(av, hb0, accW2[t][0]);
+                accW2[t][1] = mfma4(av, hb1, accW2[t][1]);
+            }
+        }
+        // dh = W2^T dy  (K = m)
+        v4f dh[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int ks = 0; ks < OT * 4; ++ks) {
+            const int m = ks * 4 + (lane >> 4);
+            const float bv = m < O ? dys[wave][lane & 15][m] : 0.0f;
+            dh[0] = mfma4(w2t[0][ks], bv, dh[0]);
+            dh[1] = mfma4(w2t[1][ks], bv, dh[1]);
+        }
+        float dpre[2][4];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dpre[mt][i] = (avalid && pre[mt][i] > 0.0f) ? dh[mt][i] : 0.0f;
+        // df = W1^T dpre
+        v4f df[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            df[0] = mfma4(w1t[0][st], dpre[st >> 2][st & 3], df[0]);
+            df[1] = mfma4(w1t[1][st], dpre[st >> 2][st & 3], df[1]);
+        }
+        if (out.feat && avalid) {
+#pragma unroll
+            for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) out.feat[an * kF + ft * 16 + 4 * (lane >> 4) + i] = df[ft][i];
+        }
+        // dW1 += dpre f^T, db1 += sum dpre (K = the 16 anchors)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ps[wave][lane & 15][mt * 16 + 4 * (lane >> 4) + i] = dpre[mt][i];
+        wsync();
+        if (lane < kF) {
+            float sacc = 0.0f;
+#pragma unroll
+            for (int al = 0; al < 16; ++al) sacc += ps[wave][al][lane];
+            accB1 += sacc;
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int al = ks * 4 + (lane >> 4);
+            const int64_t anc = a0 + al;
+            const float f0 = anc < a.na ? a.feat[anc * kF + (lane & 15)] : 0.0f;
+            const float f1 = anc < a.na ? a.feat[anc * kF + 16 + (lane & 15)] : 0.0f;
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const float av = ps[wave][al][nt * 16 + (lane & 15)];
+                accW1[nt][0] = mfma4(av, f0, accW1[nt][0]);
+                accW1[nt][1] = mfma4(av, f1, accW1[nt][1]);
+            }
+        }
+        wsync();
+    }
+    // block reduction in wave order, then one partial row per block
+    __syncthreads();
+    float* red = &smem[0][0][0][0];  // 2 * kBwdWaves * 16 * kLdsO >= decode_bwd_partial_floats(16) floats
+    const int64_t PF = decode_bwd_partial_floats(a.k);
+    for (int w = 0; w < kBwdWaves; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int t = 0; t < OT; ++t)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int m = t * 16 + 4 * (lane >> 4) + i;
+                        const int nn = nt * 16 + (lane & 15);
+                        if (m < O) {
+                            float* p = red + m * kF + nn;
+                            *p = (w == 0 ? 0.0f : *p) + accW2[t][nt][i];
+                        }
+                    }
+#pragma unroll
+            for (int j = 0; j < (kMaxO + 63) / 64; ++j) {
+                const int m = lane + 64 * j;
+                if (m < O) {
+                    float* p = red + O * kF + m;
+                    *p = (w == 0 ? 0.0f : *p) + accB2[j];
+                }
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int nn = nt * 16 + 4 * (lane >> 4) + i;
+                        const int f = ft * 16 + (lane & 15);
+                        float* p = red + O * kF + O + nn * kF + f;
+                        *p = (w == 0 ? 0.0f : *p) + accW1[nt][ft][i];
+                    }
+            if (lane < kF) {
+                float* p = red + O * kF + O + kF * kF + lane;
+                *p = (w == 0 ? 0.0f : *p) + accB1;
+            }
+        }
+        __syncthreads();
+    }
+    for (int64_t i = threadIdx.x; i < PF; i += blockDim.x) partial[blockIdx.x * PF + i] = red[i];
+}
+
+// Sum of the per-block partial rows: each block owns 64 consecutive outputs;
+// its 4 waves add interleaved quarters of the rows and combine in wave order.
+__global__ void __launch_bounds__(256) k_decode_bwd_reduce(const float* __restrict__ partial, int nblocks, int64_t PF,
+                                                           int O, float* __restrict__ dW2, float* __restrict__ db2,
+                                                           float* __restrict__ dW1, float* __restrict__ db1)
+{
+    __shared__ float acc[4][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    float s = 0.0f;
+    if (i < PF)
+        for (int b = wave; b < nblocks; b += 4) s += partial[(int64_t)b * PF + i];
+    acc[wave][lane] = s;
+    __syncthreads();
+    if (wave != 0 || i >= PF) return;
+    s = ((acc[0][lane] + acc[1][lane]) + acc[2][lane]) + acc[3][lane];
+    const int64_t oW2 = (int64_t)O * kF, oB2 = oW2 + O, oW1 = oB2 + kF * kF;
+    if (i < oW2) { if (dW2) dW2[i] = s; }
+    else if (i < oB2) { if (db2) db2[i - oW2] = s; }
+    else if (i < oW1) { if (dW1) dW1[i - oB2] = s; }
+    else { if (db1) db1[i - oW1] = s; }
+}
+
+void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, const vcgs_anchor_grads& out,
+                       float* partial, int nblocks, hipStream_t s)
+{
+    if (a.na <= 0) return;
+    if (out.books && a.books) launch_fill_f32(out.books, 0.0f, (int64_t)a.stages * a.cb_size * 7, s);
+#define VCGS_DEC_BWD(OT)                                                                           \
+    case OT:                                                                                       \
+        k_decode_bwd<OT><<<nblocks, 64 * kBwdWaves, 0, s>>>(a, dG, out, partial);                  \
+        break;
+    switch (out_tiles(a.k)) {
+        VCGS_DEC_BWD(1) VCGS_DEC_BWD(2) VCGS_DEC_BWD(3) VCGS_DEC_BWD(4) VCGS_DEC_BWD(5) VCGS_DEC_BWD(6)
+        VCGS_DEC_BWD(7) VCGS_DEC_BWD(8) VCGS_DEC_BWD(9) VCGS_DEC_BWD(10) VCGS_DEC_BWD(11)
+        default: break;
+    }
+#undef VCGS_DEC_BWD
+    const int64_t PF = decode_bwd_partial_floats(a.k);
+    k_decode_bwd_reduce<<<(unsigned)((PF + 63) / 64), 256, 0, s>>>(partial, nblocks, PF, a.k * 11, out.W2, out.b2,
+                                                                   out.W1, out.b1);
+}
+
+}  // namespace vcgs

@@ -1,0 +1,487 @@
+// Front-to-back compositing of colour, depth and silhouette (paper eqs. (16)-(18))
+// and its replaying adjoint.
+//
+// Footprint of Gaussian i at pixel centre p (eq. (1) on the image plane):
+//   d = p - (u, v),  alpha = min(0.99, o exp(-1/2 d^T Q d)), skipped when alpha < 1/255,
+// with Q = (Sigma' + 0.3 I)^-1 held in eigen form (see Splat): the exponent is a sum
+// of two non-negative terms, accurate in FP32 even for very thin footprints.
+// The Gaussian whose inclusion would take the transmittance below 1e-4 is
+// excluded and the pixel stops.
+//
+// Work layout: one wave64 per (16x16 tile, slice); a wave covers 64 * PPL
+// pixels (PPL pixels per lane, stacked 4 rows apart) and walks its tile's
+// depth-sorted list independently of the other waves.  Records are staged 64
+// at a time in a wave-private LDS slab; while staging, each lane tests its own
+// Gaussian's 1/255 ellipse against the wave's pixel rectangle (exact minimum of
+// the quadratic form over the rectangle, with a safety margin), and the wave
+// then visits only the entries that can reach one of its pixels -- entries it
+// skips could only have produced alpha < 1/255, so results are unchanged.  The
+// wave leaves as soon as all its pixels have stopped.  No block-wide barriers.
+// Blocks are remapped so that consecutive tiles share an XCD (and its L2).
+//
+// Backward: the same walk in reverse, from each pixel's final transmittance and
+// last contributor (saved by the forward), recovering T_i = T_{i+1} / (1 - alpha_i)
+// and the normalised colour behind i by acc <- alpha c + (1 - alpha) acc.  The ten
+// per-Gaussian partial derivatives are summed across the wave with DPP row
+// reductions and cross-row lane reads, then added with one atomic per value.
+#include "internal.h"
+
+namespace vcgs {
+
+struct Fp {
+    float alpha, G;
+    bool clamped;
+    float p1, p2;
+};
+
+// Shared by forward and backward so both take identical skip decisions.
+__device__ __forceinline__ Fp footprint(float dx, float dy, float ex, float ey, float j1, float j2, float o)
+{
+#pragma clang fp contract(off)
+    Fp f;
+    f.p1 = __builtin_fmaf(dy, ey, dx * ex);
+    f.p2 = __builtin_fmaf(dy, ex, -(dx * ey));
+    const float pw = __builtin_fmaf(f.p1, f.p1 * j1, f.p2 * (f.p2 * j2));
+    f.G = __builtin_amdgcn_exp2f(pw);
+    const float raw = o * f.G;
+    f.clamped = raw > kAlphaMax;
+    f.alpha = f.clamped ? kAlphaMax : raw;
+    return f;
+}
+
+// Can the Gaussian reach alpha >= 1/255 at some point of [x0, x1] x [y0, y1]?
+// Exact minimum of q(d) = -(j1 p1^2 + j2 p2^2) (base-2 units) over the
+// rectangle, compared with log2(255 o) plus a margin far above FP32 error.
+__device__ __forceinline__ bool reaches_rect(const Splat& s, float x0, float x1, float y0, float y1)
+{
+    const float u = s.a.x, v = s.a.y, ex = s.a.z, ey = s.a.w;
+    const float k1 = -s.b.x, k2 = -s.b.y, o = s.b.z;  // k > 0
+    const float A = ex * ex * k1 + ey * ey * k2;
+    const float B = ex * ey * (k1 - k2);
+    const float C = ey * ey * k1 + ex * ex * k2;
+    const float thr = __log2f(255.0f * o) * 1.001f + 1e-3f;
+    if (u >= x0 && u <= x1 && v >= y0 && v <= y1) return true;
+    const float dx0 = x0 - u, dx1 = x1 - u, dy0 = y0 - v, dy1 = y1 - v;
+    float best = 3.0e38f;
+    // vertical edges: dx fixed, minimise over dy
+    {
+        const float dx = dx0;
+        const float dy = fminf(fmaxf(-B * dx / C, dy0), dy1);
+        best = fminf(best, A * dx * dx + 2.0f * B * dx * dy + C * dy * dy);
+    }
+    {
+        const float dx = dx1;
+        const float dy = fminf(fmaxf(-B * dx / C, dy0), dy1);
+        best = fminf(best, A * dx * dx + 2.0f * B * dx * dy + C * dy * dy);
+    }
+    // horizontal edges: dy fixed, minimise over dx
+    {
+        const float dy = dy0;
+        const float dx = fminf(fmaxf(-B * dy / A, dx0), dx1);
+        best = fminf(best, A * dx * dx + 2.0f * B * dx * dy + C * dy * dy);
+    }
+    {
+        const float dy = dy1;
+        const float dx = fminf(fmaxf(-B * dy / A, dx0), dx1);
+        best = fminf(best, A * dx * dx + 2.0f * B * dx * dy + C * dy * dy);
+    }
+    return best <= thr;
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, s = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int PPL, bool COUNT>
+__global__ void __launch_bounds__(256) k_composite_fwd(CamK cam, const Splat* __restrict__ rec,
+                                                       const uint32_t* __restrict__ gids,
+                                                       const uint32_t* __restrict__ ranges, float bg0, float bg1,
+                                                       float bg2, float* __restrict__ color, float* __restrict__ depth,
+                                                       float* __restrict__ alpha_out, float* __restrict__ t_final,
+                                                       uint32_t* __restrict__ n_contrib,
+                                                       unsigned long long* __restrict__ counters)
+{
+    constexpr int WPT = 4 / PPL;     // waves per tile
+    constexpr int ROWS = 16 / WPT;   // rows per wave
+    __shared__ float4 slab[4][64][3];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    const int tile = gw / WPT, sub = gw % WPT;
+    const int n_tiles = cam.tiles_x * cam.tiles_y;
+    if (tile >= n_tiles) return;
+    uint32_t n_eval = 0, n_blend = 0;
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const int px = tx * kTile + (lane & 15);
+    const int row0 = ty * kTile + sub * ROWS;
+    // pixel-centre rectangle of this wave
+    const float rx0 = (float)(tx * kTile) + 0.5f, rx1 = rx0 + 15.0f;
+    const float ry0 = (float)row0 + 0.5f, ry1 = ry0 + (float)(ROWS - 1);
+    float dy[PPL];
+    bool done[PPL];
+    float T[PPL], c0[PPL], c1[PPL], c2[PPL], dd[PPL], aa[PPL];
+    uint32_t last[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        const int py = row0 + (lane >> 4) + 4 * j;
+        dy[j] = (float)py + 0.5f;
+        done[j] = !(px < cam.W && py < cam.H);
+        T[j] = 1.0f; c0[j] = c1[j] = c2[j] = dd[j] = aa[j] = 0.0f;
+        last[j] = 0u;
+    }
+    const float pxf = (float)px + 0.5f;
+    const uint32_t gt = cam.tile_base + (uint32_t)tile;
+    const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
+    bool all_done = false;
+    for (uint32_t b = start; b < end && !all_done; b += 64) {
+        bool mine = true;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) mine = mine && done[j];
+        if (__all(mine)) break;
+        wave_lds_sync();
+        const uint32_t idx = b + lane;
+        bool keep = false;
+        if (idx < end) {
+            const Splat sp = rec[gids[idx]];
+            keep = reaches_rect(sp, rx0, rx1, ry0, ry1);
+            slab[wave][lane][0] = sp.a;
+            slab[wave][lane][1] = sp.b;
+            slab[wave][lane][2] = sp.c;
+        }
+        uint64_t hits = __ballot(keep);
+        wave_lds_sync();
+        while (hits) {
+            const int k = __builtin_ctzll(hits);
+            hits &= hits - 1ull;
+            const float4 ra = slab[wave][k][0], rb = slab[wave][k][1], rc = slab[wave][k][2];
+            const float dx = pxf - ra.x;
+            bool lane_done = true;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                if (!done[j]) {
+                    const Fp f = footprint(dx, dy[j] - ra.y, ra.z, ra.w, rb.x, rb.y, rb.z);
+                    if (COUNT) ++n_eval;
+                    if (f.alpha >= kAlphaMin) {
+                        const float Tn = T[j] * (1.0f - f.alpha);
+                        if (Tn < kTMin) {
+                            done[j] = true;
+                        } else {
+                            if (COUNT) ++n_blend;
+                            const float w = f.alpha * T[j];
+                            c0[j] += w * rb.w; c1[j] += w * rc.x; c2[j] += w * rc.y;
+                            dd[j] += w * rc.z; aa[j] += w;
+                            T[j] = Tn;
+                            last[j] = b - start + (uint32_t)k + 1u;
+                        }
+                    }
+                }
+                lane_done = lane_done && done[j];
+            }
+            if (__all(lane_done)) { all_done = true; break; }
+        }
+    }
+    const int HW = cam.W * cam.H;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        const int py = row0 + (lane >> 4) + 4 * j;
+        if (px < cam.W && py < cam.H) {
+            const int p = py * cam.W + px;
+            color[p] = c0[j] + T[j] * bg0;
+            color[HW + p] = c1[j] + T[j] * bg1;
+            color[2 * HW + p] = c2[j] + T[j] * bg2;
+            depth[p] = dd[j];
+            alpha_out[p] = aa[j];
+            t_final[p] = T[j];
+            n_contrib[p] = last[j];
+        }
+    }
+    if (COUNT) {
+        if (n_eval) atomicAdd(counters + 0, (unsigned long long)n_eval);
+        if (n_blend) atomicAdd(counters + 1, (unsigned long long)n_blend);
+    }
+}
+
+// Sum over the 64 lanes, result in every lane.
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x124, 0xF, 0xF, false);  // row_ror:4
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+template <int PPL, bool COUNT>
+__global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __restrict__ rec,
+                                                       const uint32_t* __restrict__ gids,
+                                                       const uint32_t* __restrict__ ranges, float bg0, float bg1,
+                                                       float bg2, const float* __restrict__ t_final,
+                                                       const uint32_t* __restrict__ n_contrib,
+                                                       const float* __restrict__ dl_dc, const float* __restrict__ dl_dd,
+                                                       const float* __restrict__ dl_da, float* __restrict__ g2,
+                                                       unsigned long long* __restrict__ counters)
+{
+    constexpr int WPT = 4 / PPL;
+    constexpr int ROWS = 16 / WPT;
+    __shared__ float4 slab[4][64][3];
+    __shared__ uint32_t slab_gid[4][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    const int tile = gw / WPT, sub = gw % WPT;
+    const int n_tiles = cam.tiles_x * cam.tiles_y;
+    if (tile >= n_tiles) return;
+    uint32_t n_eval = 0, n_blend = 0, n_flush = 0;
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const int px = tx * kTile + (lane & 15);
+    const int row0 = ty * kTile + sub * ROWS;
+    const float rx0 = (float)(tx * kTile) + 0.5f, rx1 = rx0 + 15.0f;
+    const float ry0 = (float)row0 + 0.5f, ry1 = ry0 + (float)(ROWS - 1);
+    const int HW = cam.W * cam.H;
+    float T[PPL], up[PPL][5], acc[PPL][5];
+    uint32_t last[PPL];
+    float pyf[PPL];
+    uint32_t wl = 0;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        const int py = row0 + (lane >> 4) + 4 * j;
+        pyf[j] = (float)py + 0.5f;
+        const bool in = px < cam.W && py < cam.H;
+        const int p = py * cam.W + px;
+        T[j] = in ? t_final[p] : 1.0f;
+        last[j] = in ? n_contrib[p] : 0u;
+        up[j][0] = (in && dl_dc) ? dl_dc[p] : 0.0f;
+        up[j][1] = (in && dl_dc) ? dl_dc[HW + p] : 0.0f;
+        up[j][2] = (in && dl_dc) ? dl_dc[2 * HW + p] : 0.0f;
+        up[j][3] = (in && dl_dd) ? dl_dd[p] : 0.0f;
+        up[j][4] = (in && dl_da) ? dl_da[p] : 0.0f;
+        acc[j][0] = bg0; acc[j][1] = bg1; acc[j][2] = bg2; acc[j][3] = 0.0f; acc[j][4] = 0.0f;
+        wl = max(wl, last[j]);
+    }
+    const float pxf = (float)px + 0.5f;
+    wl = wave_max_u32(wl);
+    if (wl == 0u) return;  // uniform across the wave
+    const uint32_t gt = cam.tile_base + (uint32_t)tile;
+    const uint32_t start = ranges[2 * gt];
+    for (int bs = (int)((wl - 1u) & ~63u); bs >= 0; bs -= 64) {
+        wave_lds_sync();
+        const uint32_t li = (uint32_t)bs + lane;
+        bool keep = false;
+        if (li < wl) {
+            const uint32_t g = gids[start + li];
+            const Splat sp = rec[g];
+            keep = reaches_rect(sp, rx0, rx1, ry0, ry1);
+            slab[wave][lane][0] = sp.a;
+            slab[wave][lane][1] = sp.b;
+            slab[wave][lane][2] = sp.c;
+            slab_gid[wave][lane] = g;
+        }
+        uint64_t hits = __ballot(keep);
+        wave_lds_sync();
+        while (hits) {
+            const int k = 63 - __builtin_clzll(hits);
+            hits &= ~(1ull << k);
+            const uint32_t local = (uint32_t)(bs + k);
+            const float4 ra = slab[wave][k][0], rb = slab[wave][k][1], rc = slab[wave][k][2];
+            const float i1 = -2.0f * kLn2 * rb.x, i2 = -2.0f * kLn2 * rb.y;  // eigenvalues of Q
+            const float dx = pxf - ra.x;
+            float p[10];
+#pragma unroll
+            for (int i = 0; i < 10; ++i) p[i] = 0.0f;
+            bool contrib = false;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                if (local < last[j]) {
+                    const float dyj = pyf[j] - ra.y;
+                    const Fp f = footprint(dx, dyj, ra.z, ra.w, rb.x, rb.y, rb.z);
+                    if (COUNT) ++n_eval;
+                    if (f.alpha >= kAlphaMin) {
+                        contrib = true;
+                        if (COUNT) ++n_blend;
+                        const float a = f.alpha;
+                        const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
+                        const float x[5] = {rb.w, rc.x, rc.y, rc.z, 1.0f};
+                        float dla = 0.0f;
+#pragma unroll
+                        for (int c = 0; c < 5; ++c) {
+                            dla += up[j][c] * (x[c] - acc[j][c]);
+                            acc[j][c] += a * (x[c] - acc[j][c]);
+                        }
+                        dla *= Ti;
+                        const float w = a * Ti;
+                        p[6] += w * up[j][0];
+                        p[7] += w * up[j][1];
+                        p[8] += w * up[j][2];
+                        p[9] += w * up[j][3];
+                        if (!f.clamped) {
+                            const float dp = dla * a;  // dL/dpower, power = -1/2 d^T Q d
+                            const float q1 = i1 * f.p1, q2 = i2 * f.p2;
+                            p[0] += dp * (q1 * ra.z - q2 * ra.w);   // d power / d u = (Q d)_x
+                            p[1] += dp * (q1 * ra.w + q2 * ra.z);   // d power / d v = (Q d)_y
+                            p[2] += dp * (-0.5f * dx * dx);
+                            p[3] += dp * (-dx * dyj);
+                            p[4] += dp * (-0.5f * dyj * dyj);
+                            p[5] += dla * f.G;
+                        }
+                        T[j] = Ti;
+                    }
+                }
+            }
+            if (__ballot(contrib) == 0ull) continue;
+            float mine = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 10; ++i) {
+                const float s = wave_sum(p[i]);
+                if (lane == i) mine = s;
+            }
+            if (lane < 10) atomicAdd(g2 + (size_t)kG2 * slab_gid[wave][k] + lane, mine);
+            if (COUNT && lane == 0) ++n_flush;
+        }
+    }
+    if (COUNT) {
+        if (n_eval) atomicAdd(counters + 2, (unsigned long long)n_eval);
+        if (n_blend) atomicAdd(counters + 3, (unsigned long long)n_blend);
+        if (n_flush) atomicAdd(counters + 4, (unsigned long long)n_flush);
+    }
+}
+
+static int g_ppl = 2;
+
+void set_composite_ppl(int ppl) { g_ppl = (ppl == 1 || ppl == 2 || ppl == 4) ? ppl : 2; }
+int composite_ppl() { return g_ppl; }
+
+template <int PPL>
+static void fwd_launch(int blocks, hipStream_t s, const CamK& cam, const Splat* rec, const uint32_t* gids,
+                       const uint32_t* ranges, const float* bg, float* color, float* depth, float* alpha,
+                       float* t_final, uint32_t* n_contrib, unsigned long long* counters)
+{
+    if (counters)
+        k_composite_fwd<PPL, true><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], color, depth,
+                                                          alpha, t_final, n_contrib, counters);
+    else
+        k_composite_fwd<PPL, false><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], color, depth,
+                                                           alpha, t_final, n_contrib, nullptr);
+}
+
+template <int PPL>
+static void bwd_launch(int blocks, hipStream_t s, const CamK& cam, const Splat* rec, const uint32_t* gids,
+                       const uint32_t* ranges, const float* bg, const float* t_final, const uint32_t* n_contrib,
+                       const float* dl_dc, const float* dl_dd, const float* dl_da, float* g2,
+                       unsigned long long* counters)
+{
+    if (counters)
+        k_composite_bwd<PPL, true><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], t_final,
+                                                          n_contrib, dl_dc, dl_dd, dl_da, g2, counters);
+    else
+        k_composite_bwd<PPL, false><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], t_final,
+                                                           n_contrib, dl_dc, dl_dd, dl_da, g2, nullptr);
+}
+
+void launch_composite_fwd(const CamK& cam, const Splat* rec, const uint32_t* gids, const uint32_t* ranges,
+                          const float* bg, float* color, float* depth, float* alpha, float* t_final,
+                          uint32_t* n_contrib, unsigned long long* counters, hipStream_t s)
+{
+    const int n_tiles = cam.tiles_x * cam.tiles_y;
+    if (n_tiles <= 0) return;
+    const int ppl = g_ppl;
+    const int blocks = (n_tiles * (4 / ppl) + 3) / 4;
+    if (ppl == 4) fwd_launch<4>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters);
+    else if (ppl == 2) fwd_launch<2>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters);
+    else fwd_launch<1>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters);
+}
+
+void launch_composite_bwd(const CamK& cam, const Splat* rec, const uint32_t* gids, const uint32_t* ranges,
+                          const float* bg, const float* t_final, const uint32_t* n_contrib, const float* dl_dc,
+                          const float* dl_dd, const float* dl_da, float* g2, unsigned long long* counters,
+                          hipStream_t s)
+{
+    const int n_tiles = cam.tiles_x * cam.tiles_y;
+    if (n_tiles <= 0) return;
+    const int ppl = g_ppl;
+    const int blocks = (n_tiles * (4 / ppl) + 3) / 4;
+    if (ppl == 4) bwd_launch<4>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters);
+    else if (ppl == 2) bwd_launch<2>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters);
+    else bwd_launch<1>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters);
+}
+
+// L1 loss: L = mean_p (sum_c |C - C*| + w_depth |D - D*|).  Image gradients per
+// pixel; the scalar is reduced per block and then over blocks in block order.
+constexpr int kLossThreads = 256;
+
+__global__ void __launch_bounds__(kLossThreads) k_l1_loss(int64_t npix, const float* __restrict__ c,
+                                                          const float* __restrict__ d, const float* __restrict__ tc,
+                                                          const float* __restrict__ td, float w_depth, float inv_n,
+                                                          float* __restrict__ dl_dc, float* __restrict__ dl_dd,
+                                                          float* __restrict__ partial)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float l = 0.0f;
+    if (p < npix) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float e = c[ch * npix + p] - tc[ch * npix + p];
+            dl_dc[ch * npix + p] = e > 0.0f ? inv_n : (e < 0.0f ? -inv_n : 0.0f);
+            l += fabsf(e);
+        }
+        const float e = d[p] - td[p];
+        dl_dd[p] = e > 0.0f ? w_depth * inv_n : (e < 0.0f ? -w_depth * inv_n : 0.0f);
+        l += w_depth * fabsf(e);
+    }
+    if (partial) {
+        __shared__ float ws[kLossThreads / 64];
+        l = wave_sum(l);
+        if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = l;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ partial, int n, float scale,
+                                                      float* __restrict__ out)
+{
+    __shared__ double acc[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += (double)partial[i];
+    acc[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) acc[threadIdx.x] += acc[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = (float)(acc[0] * (double)scale);
+}
+
+int l1_loss_blocks(int64_t npix) { return (int)((npix + kLossThreads - 1) / kLossThreads); }
+
+void launch_l1_loss(int64_t npix, const float* c, const float* d, const float* tc, const float* td, float w_depth,
+                    float* dl_dc, float* dl_dd, float* loss, float* partial, hipStream_t s)
+{
+    if (npix <= 0) {
+        if (loss) launch_fill_f32(loss, 0.0f, 1, s);
+        return;
+    }
+    const int nb = l1_loss_blocks(npix);
+    const float inv_n = 1.0f / (float)npix;
+    k_l1_loss<<<nb, kLossThreads, 0, s>>>(npix, c, d, tc, td, w_depth, inv_n, dl_dc, dl_dd, loss ? partial : nullptr);
+    if (loss) k_sum_partials<<<1, 256, 0, s>>>(partial, nb, inv_n, loss);
+}
+
+}  // namespace vcgs

@@ -1,0 +1,389 @@
+"""Python binding of libvcgs (ctypes).  Argument marshalling only: every step of
+the render and decode runs in the library's HIP kernels; PyTorch provides the
+device memory and the current stream.
+
+The functions mirror the C ABI in include/vcgs.h:
+    render_forward, render_backward, l1_loss, decode_anchors,
+    decode_anchors_backward, render_batch_* (batched views)
+and ``RenderFn`` / ``DecodeFn`` wrap them as ``torch.autograd.Function``s.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvcgs.so")
+
+_lib = None
+
+c_f = ctypes.c_float
+c_i32 = ctypes.c_int32
+c_i64 = ctypes.c_int64
+c_p = ctypes.c_void_p
+
+
+class CCamera(ctypes.Structure):
+    _fields_ = [("width", c_i32), ("height", c_i32), ("fx", c_f), ("fy", c_f), ("cx", c_f), ("cy", c_f),
+                ("z_near", c_f), ("tile", c_i32)]
+
+
+class CPose(ctypes.Structure):
+    _fields_ = [("R", c_f * 9), ("t", c_f * 3)]
+
+
+class CGaussians(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("mean", c_p), ("scale", c_p), ("quat", c_p), ("opacity", c_p), ("color", c_p)]
+
+
+class CGaussianBuffers(ctypes.Structure):
+    _fields_ = [("mean", c_p), ("scale", c_p), ("quat", c_p), ("opacity", c_p), ("color", c_p)]
+
+
+class CImages(ctypes.Structure):
+    _fields_ = [("color", c_p), ("depth", c_p), ("alpha", c_p)]
+
+
+class CStateView(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("n_pairs", c_i64), ("tiles_x", c_i32), ("tiles_y", c_i32),
+                ("depth_bits", c_p), ("rect", c_p), ("count", c_p), ("gids", c_p), ("ranges", c_p),
+                ("t_final", c_p), ("n_contrib", c_p), ("splats", c_p)]
+
+
+class CAnchors(ctypes.Structure):
+    _fields_ = [("n_anchor", c_i64), ("k", c_i32), ("feat_dim", c_i32), ("xa", c_p), ("feat", c_p),
+                ("scaling", c_p), ("offset", c_p)]
+
+
+class CMLP(ctypes.Structure):
+    _fields_ = [("W1", c_p), ("b1", c_p), ("W2", c_p), ("b2", c_p)]
+
+
+class CCodebook(ctypes.Structure):
+    _fields_ = [("stages", c_i32), ("size", c_i32), ("books", c_p), ("idx", c_p)]
+
+
+class CAnchorGrads(ctypes.Structure):
+    _fields_ = [("feat", c_p), ("offset", c_p), ("scaling", c_p), ("xa", c_p), ("W1", c_p), ("b1", c_p),
+                ("W2", c_p), ("b2", c_p), ("books", c_p), ("mask_logit", c_p)]
+
+
+class VcgsError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libvcgs.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise VcgsError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_11247_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.vcgs_last_error.restype = ctypes.c_char_p
+        L.vcgs_version.restype = ctypes.c_char_p
+        for name in ("vcgs_create", "vcgs_render_forward", "vcgs_render_backward", "vcgs_state_query",
+                     "vcgs_l1_loss", "vcgs_decode_anchors", "vcgs_decode_anchors_backward"):
+            getattr(L, name).restype = ctypes.c_int
+        L.vcgs_destroy.restype = None
+        L.vcgs_state_free.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise VcgsError(f"vcgs error {rc}: {lib().vcgs_last_error().decode()}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return c_p(t.data_ptr())
+
+
+def _dev(t, dtype=torch.float32):
+    if not t.is_cuda:
+        raise VcgsError("tensor must be on the GPU")
+    if t.dtype != dtype:
+        raise VcgsError(f"expected {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def _stream():
+    return c_p(torch.cuda.current_stream().cuda_stream)
+
+
+def camera_struct(cam) -> CCamera:
+    return CCamera(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy),
+                   float(getattr(cam, "z_near", 0.2)), int(getattr(cam, "tile", 16)))
+
+
+def pose_struct(pose) -> CPose:
+    R = np.asarray(pose.R, np.float32).reshape(9)
+    t = np.asarray(pose.t, np.float32).reshape(3)
+    return CPose((c_f * 9)(*R.tolist()), (c_f * 3)(*t.tolist()))
+
+
+class Context:
+    """A library context on one device (default: the current torch device)."""
+
+    def __init__(self, device=None):
+        dev = torch.cuda.current_device() if device is None else int(device)
+        h = c_p()
+        _check(lib().vcgs_create(dev, ctypes.byref(h)))
+        self.h = h
+        self.device = dev
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().vcgs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device=None) -> Context:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _default_ctx:
+        _default_ctx[dev] = Context(dev)
+    return _default_ctx[dev]
+
+
+class State:
+    """Saved-for-backward object of one forward render."""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self.h = h
+
+    def free(self):
+        if self.h is not None and self.h.value:
+            lib().vcgs_state_free(self.ctx.h, self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def view(self) -> dict:
+        """Copies of the saved binning/sort results as torch tensors."""
+        v = CStateView()
+        _check(lib().vcgs_state_query(self.h, ctypes.byref(v)))
+        n, P, T = v.n, v.n_pairs, v.tiles_x * v.tiles_y
+        dev = torch.device("cuda", self.ctx.device)
+
+        def grab(ptr, count, dtype):
+            if count <= 0 or not ptr:
+                return torch.empty(0, dtype=dtype, device=dev)
+            return _wrap(ptr, count, dtype, dev).clone()
+
+        return dict(n=n, n_pairs=P, tiles_x=v.tiles_x, tiles_y=v.tiles_y,
+                    splats=grab(v.splats, 12 * n, torch.float32).view(-1, 12),
+                    depth_bits=grab(v.depth_bits, n, torch.int32),
+                    rect=grab(v.rect, 4 * n, torch.int16).view(-1, 4) if n > 0 else torch.empty(0, 4),
+                    count=grab(v.count, n, torch.int32),
+                    gids=grab(v.gids, P, torch.int32),
+                    ranges=grab(v.ranges, 2 * T, torch.int32).view(-1, 2),
+                    t_final_ptr=v.t_final, n_contrib_ptr=v.n_contrib)
+
+
+_TYPESTR = {torch.int32: "<i4", torch.int16: "<i2", torch.float32: "<f4", torch.uint8: "|u1"}
+
+
+class _DevArray:
+    def __init__(self, ptr, count, dtype):
+        self.__cuda_array_interface__ = {"shape": (count,), "typestr": _TYPESTR[dtype], "data": (int(ptr), False),
+                                         "version": 2}
+
+
+def _wrap(ptr, count, dtype, device):
+    """Zero-copy torch view of library-owned device memory (valid while the owner lives)."""
+    return torch.as_tensor(_DevArray(ptr, count, dtype), device=device)
+
+
+def _gauss(means, scales, quats, opacities, colors):
+    n = int(opacities.shape[0])
+    ts = [_dev(x) for x in (means, scales, quats, opacities, colors)]
+    assert ts[0].shape == (3, n) and ts[1].shape == (3, n) and ts[2].shape == (4, n) and ts[4].shape == (3, n), \
+        "Gaussian attributes must be SoA: mean/scale/color (3, n), quat (4, n), opacity (n,)"
+    return CGaussians(n, *[_ptr(t) for t in ts]), ts
+
+
+def render_forward(means, scales, quats, opacities, colors, camera, pose, bg=(0.0, 0.0, 0.0), keep_state=True,
+                   ctx: Context | None = None):
+    """Forward render.  Returns (color (3,H,W), depth (H,W), alpha (H,W), state or None)."""
+    ctx = ctx or default_context()
+    g, keep = _gauss(means, scales, quats, opacities, colors)
+    H, W = int(camera.height), int(camera.width)
+    dev = means.device
+    color = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+    alpha = torch.empty((H, W), dtype=torch.float32, device=dev)
+    imgs = CImages(_ptr(color), _ptr(depth), _ptr(alpha))
+    cam, ps = camera_struct(camera), pose_struct(pose)
+    bgv = (c_f * 3)(*[float(b) for b in bg])
+    h = c_p()
+    _check(lib().vcgs_render_forward(ctx.h, ctypes.byref(g), ctypes.byref(cam), ctypes.byref(ps), bgv,
+                                     ctypes.byref(imgs), ctypes.byref(h) if keep_state else None, _stream()))
+    st = State(ctx, h) if keep_state else None
+    del keep
+    return color, depth, alpha, st
+
+
+def render_backward(state: State, means, scales, quats, opacities, colors, camera, pose, dl_dcolor=None,
+                    dl_ddepth=None, dl_dalpha=None):
+    """Backward render.  Returns (dict of attribute gradients, dL/dxi (6,))."""
+    ctx = state.ctx
+    g, keep = _gauss(means, scales, quats, opacities, colors)
+    dev = means.device
+    grads = {k: torch.empty_like(t) for k, t in zip(("mean", "scale", "quat", "opacity", "color"), keep)}
+    gb = CGaussianBuffers(*[_ptr(grads[k]) for k in ("mean", "scale", "quat", "opacity", "color")])
+    dpose = torch.empty(6, dtype=torch.float32, device=dev)
+    ups = [None if u is None else _dev(u) for u in (dl_dcolor, dl_ddepth, dl_dalpha)]
+    cam, ps = camera_struct(camera), pose_struct(pose)
+    _check(lib().vcgs_render_backward(ctx.h, state.h, ctypes.byref(g), ctypes.byref(cam), ctypes.byref(ps),
+                                      *[_ptr(u) for u in ups], ctypes.byref(gb), _ptr(dpose), _stream()))
+    return grads, dpose
+
+
+def l1_loss(color, depth, target_color, target_depth, w_depth=0.5, ctx: Context | None = None):
+    """L = mean_p(sum_c |C - C*| + w_depth |D - D*|); returns (loss (1,), dL/dC, dL/dD)."""
+    ctx = ctx or default_context()
+    H, W = depth.shape
+    dlc = torch.empty_like(color)
+    dld = torch.empty_like(depth)
+    loss = torch.empty(1, dtype=torch.float32, device=color.device)
+    imgs = CImages(_ptr(_dev(color)), _ptr(_dev(depth)), None)
+    _check(lib().vcgs_l1_loss(ctx.h, ctypes.byref(imgs), _ptr(_dev(target_color)), _ptr(_dev(target_depth)),
+                              c_i32(W), c_i32(H), c_f(w_depth), _ptr(dlc), _ptr(dld), _ptr(loss), _stream()))
+    return loss, dlc, dld
+
+
+class RenderFn(torch.autograd.Function):
+    """Differentiable render.  ``pose_tangent`` is a (6,) tensor that must be
+    zero; its gradient is dL/dxi for the left perturbation exp(xi^) {R|t}."""
+
+    @staticmethod
+    def forward(fctx, means, scales, quats, opacities, colors, pose_tangent, camera, pose, bg=(0.0, 0.0, 0.0)):
+        color, depth, alpha, st = render_forward(means, scales, quats, opacities, colors, camera, pose, bg)
+        fctx.state = st
+        fctx.camera, fctx.pose = camera, pose
+        fctx.save_for_backward(means, scales, quats, opacities, colors)
+        return color, depth, alpha
+
+    @staticmethod
+    def backward(fctx, dl_dcolor, dl_ddepth, dl_dalpha):
+        means, scales, quats, opacities, colors = fctx.saved_tensors
+        grads, dpose = render_backward(fctx.state, means, scales, quats, opacities, colors, fctx.camera, fctx.pose,
+                                       dl_dcolor, dl_ddepth, dl_dalpha)
+        fctx.state.free()
+        return (grads["mean"], grads["scale"], grads["quat"], grads["opacity"], grads["color"], dpose,
+                None, None, None)
+
+
+def render(means, scales, quats, opacities, colors, camera, pose, pose_tangent=None, bg=(0.0, 0.0, 0.0)):
+    if pose_tangent is None:
+        pose_tangent = torch.zeros(6, dtype=torch.float32, device=means.device)
+    return RenderFn.apply(means, scales, quats, opacities, colors, pose_tangent, camera, pose, bg)
+
+
+def _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx):
+    na, k = int(feat.shape[0]), int(offset.shape[1])
+    ts = [_dev(t) for t in (xa, feat, scaling, offset, W1, b1, W2, b2)]
+    assert ts[0].shape == (3, na) and ts[1].shape == (na, 32) and ts[2].shape == (3, na) and ts[3].shape == (na, k, 3)
+    assert ts[4].shape == (32, 32) and ts[6].shape == (k * 11, 32)
+    a = CAnchors(na, k, 32, *[_ptr(t) for t in ts[:4]])
+    m = CMLP(*[_ptr(t) for t in ts[4:]])
+    cb = None
+    if books is not None:
+        bk = _dev(books)
+        ix = _dev(idx, torch.int32)
+        cb = CCodebook(int(bk.shape[0]), int(bk.shape[1]), _ptr(bk), _ptr(ix))
+        ts += [bk, ix]
+    return a, m, cb, ts, na, k
+
+
+def decode_anchors(xa, feat, scaling, offset, W1, b1, W2, b2, books=None, idx=None, mask_logit=None, mask_eps=0.01,
+                   ctx: Context | None = None):
+    """Decode anchors into na*k Gaussians (dict mean/scale/quat/opacity/color, SoA)."""
+    ctx = ctx or default_context()
+    a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx)
+    n = na * k
+    dv = feat.device
+    out = {"mean": torch.empty((3, n), device=dv), "scale": torch.empty((3, n), device=dv),
+           "quat": torch.empty((4, n), device=dv), "opacity": torch.empty(n, device=dv),
+           "color": torch.empty((3, n), device=dv)}
+    ob = CGaussianBuffers(*[_ptr(out[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
+    ml = None if mask_logit is None else _dev(mask_logit)
+    _check(lib().vcgs_decode_anchors(ctx.h, ctypes.byref(a), ctypes.byref(m), ctypes.byref(cb) if cb else None,
+                                     _ptr(ml), c_f(mask_eps), ctypes.byref(ob), _stream()))
+    del keep
+    return out
+
+
+def decode_anchors_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG, books=None, idx=None, mask_logit=None,
+                            mask_eps=0.01, ctx: Context | None = None):
+    """Gradients of the decode; dG maps mean/scale/quat/opacity/color to dL/d(decoded Gaussians)."""
+    ctx = ctx or default_context()
+    a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx)
+    dg = {f: None if dG.get(f) is None else _dev(dG[f]) for f in ("mean", "scale", "quat", "opacity", "color")}
+    gb = CGaussianBuffers(*[_ptr(dg[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
+    out = {"feat": torch.empty_like(keep[1]), "offset": torch.empty_like(keep[3]),
+           "scaling": torch.empty_like(keep[2]), "xa": torch.empty_like(keep[0]), "W1": torch.empty_like(keep[4]),
+           "b1": torch.empty_like(keep[5]), "W2": torch.empty_like(keep[6]), "b2": torch.empty_like(keep[7])}
+    out["books"] = torch.empty_like(keep[8]) if books is not None else None
+    ml = None if mask_logit is None else _dev(mask_logit)
+    out["mask_logit"] = torch.empty_like(ml) if ml is not None else None
+    ag = CAnchorGrads(*[_ptr(out[f]) for f in ("feat", "offset", "scaling", "xa", "W1", "b1", "W2", "b2", "books",
+                                                "mask_logit")])
+    _check(lib().vcgs_decode_anchors_backward(ctx.h, ctypes.byref(a), ctypes.byref(m),
+                                              ctypes.byref(cb) if cb else None, _ptr(ml), c_f(mask_eps),
+                                              ctypes.byref(gb), ctypes.byref(ag), _stream()))
+    del keep
+    return out
+
+
+STAGES = ["decode", "preprocess", "depth_sort", "pair_scan", "emit", "tile_sort", "tile_ranges", "composite",
+          "loss", "composite_bwd", "preprocess_bwd", "decode_bwd"]
+
+
+def profile_enable(on=True, ctx: Context | None = None):
+    """Per-stage HIP-event timing on the current stream (clears the totals)."""
+    ctx = ctx or default_context()
+    _check(lib().vcgs_profile_enable(ctx.h, c_i32(1 if on else 0)))
+
+
+def profile_read(ctx: Context | None = None) -> dict:
+    """{stage: (total_ms, launches)} since profiling was enabled."""
+    ctx = ctx or default_context()
+    out = {}
+    for i, name in enumerate(STAGES):
+        ms = ctypes.c_double()
+        nl = c_i64()
+        _check(lib().vcgs_profile_read(ctx.h, c_i32(i), ctypes.byref(ms), ctypes.byref(nl)))
+        out[name] = (ms.value, nl.value)
+    return out
+
+
+def count_enable(on=True, ctx: Context | None = None):
+    ctx = ctx or default_context()
+    _check(lib().vcgs_count_enable(ctx.h, c_i32(1 if on else 0)))
+
+
+def count_read(ctx: Context | None = None) -> dict:
+    ctx = ctx or default_context()
+    arr = (c_i64 * 5)()
+    _check(lib().vcgs_count_read(ctx.h, arr))
+    return dict(zip(("fwd_evals", "fwd_blends", "bwd_evals", "bwd_blends", "bwd_flushes"), list(arr)))

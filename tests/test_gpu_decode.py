@@ -1,0 +1,116 @@
+"""GPU parity of the anchor decode (FP32 MFMA) and its adjoint against the
+numpy FP64 oracle, with and without the residual codebook and the mask."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import decode as odec
+from paper_2403_11247_amd import scenes
+from tests.gpu_common import FIELDS, dev, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+DEC_TOL = 1e-5      # decoded attributes, relative to the attribute's scale
+DEC_GRAD_TOL = 1e-4  # per-tensor relative L2 of decode gradients
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_2403_11247_amd import vcgs
+    vcgs.lib()
+    return vcgs
+
+
+def run_decode(V, a, m, books=None, idx=None, mask=None, eps=0.01):
+    from paper_2403_11247_amd.vcgs import decode_anchors
+    return decode_anchors(dev(a.xa), dev(a.feat), dev(a.scaling), dev(a.offset), dev(m.W1), dev(m.b1), dev(m.W2),
+                          dev(m.b2), None if books is None else dev(books),
+                          None if idx is None else dev(idx, torch.int32), None if mask is None else dev(mask), eps)
+
+
+def check_decode(out, ref):
+    for f in FIELDS:
+        a = out[f].cpu().numpy().astype(np.float64)
+        b = ref[f]
+        scale_ = max(np.abs(b).max(), 1e-30)
+        err = np.abs(a - b).max() / scale_
+        say("decode", f, "max err / max |ref| = %.2e" % err)
+        assert err <= DEC_TOL, (f, err)
+
+
+@pytest.mark.parametrize("na,k", [(2000, 10), (37, 10), (513, 3), (100, 16), (16, 1)])
+def test_decode_forward(V, na, k):
+    a = scenes.room_anchors(na, k=k, seed=na)
+    m = scenes.room_mlp(k=k, seed=1)
+    say("decode forward na", na, "k", k)
+    out = run_decode(V, a, m)
+    torch.cuda.synchronize()
+    check_decode(out, odec.decode(a, m))
+
+
+def test_decode_codebook_and_mask(V):
+    a = scenes.room_anchors(1500, k=10, seed=3)
+    m = scenes.room_mlp(k=10, seed=2)
+    n = a.n * a.k
+    logits, books, idx = scenes.mask_and_codebook(n, size=4096, mask_mu=0.0, mask_sigma=3.0)
+    # keep logits away from the threshold so FP32 and FP64 agree on every keep decision
+    thr = np.log(0.01 / 0.99)
+    logits[np.abs(logits - thr) < 1e-4] += 1e-3
+    out = run_decode(V, a, m, books, idx, logits)
+    torch.cuda.synchronize()
+    ref = odec.decode(a, m, books, idx, logits)
+    check_decode(out, ref)
+    assert np.array_equal(out["opacity"].cpu().numpy() == 0, ref["opacity"] == 0)
+
+
+def check_decode_backward(V, a, m, books=None, idx=None, mask=None, seed=0):
+    from paper_2403_11247_amd.vcgs import decode_anchors_backward
+    n = a.n * a.k
+    rng = np.random.default_rng(seed)
+    dG = {"mean": rng.normal(size=(3, n)), "scale": rng.normal(size=(3, n)) * 10, "quat": rng.normal(size=(4, n)),
+          "opacity": rng.normal(size=n), "color": rng.normal(size=(3, n))}
+    dG = {k: v.astype(np.float32) for k, v in dG.items()}
+    fwd = odec.decode(a, m, books, idx, mask)
+    ref = odec.decode_backward(a, m, fwd, dG, books, idx, mask)
+    got = decode_anchors_backward(dev(a.xa), dev(a.feat), dev(a.scaling), dev(a.offset), dev(m.W1), dev(m.b1),
+                                  dev(m.W2), dev(m.b2), {k: dev(v) for k, v in dG.items()},
+                                  None if books is None else dev(books),
+                                  None if idx is None else dev(idx, torch.int32),
+                                  None if mask is None else dev(mask), 0.01)
+    torch.cuda.synchronize()
+    keys = ["feat", "W1", "b1", "W2", "b2", "offset", "scaling", "xa"]
+    if books is not None:
+        keys.append("books")
+        ref["books"] = np.stack(ref["books"])
+    if mask is not None:
+        keys.append("mask_logit")
+    for k in keys:
+        e = rel_err(got[k].cpu().numpy().reshape(np.shape(ref[k])), ref[k])
+        say("decode backward", k, "rel err %.2e" % e)
+        assert e <= DEC_GRAD_TOL, (k, e)
+
+
+@pytest.mark.parametrize("na,k", [(2000, 10), (45, 7), (300, 16)])
+def test_decode_backward(V, na, k):
+    a = scenes.room_anchors(na, k=k, seed=na + 1)
+    m = scenes.room_mlp(k=k, seed=3)
+    check_decode_backward(V, a, m)
+
+
+def test_decode_backward_codebook_and_mask(V):
+    a = scenes.room_anchors(800, k=10, seed=9)
+    m = scenes.room_mlp(k=10, seed=4)
+    n = a.n * a.k
+    logits, books, idx = scenes.mask_and_codebook(n, size=256, mask_mu=0.0, mask_sigma=3.0)
+    thr = np.log(0.01 / 0.99)
+    logits[np.abs(logits - thr) < 1e-4] += 1e-3
+    check_decode_backward(V, a, m, books, idx, logits)
+
+
+def test_decode_full_room(V):
+    a = scenes.room_anchors(40000, k=10)
+    m = scenes.room_mlp()
+    say("decode room 40k anchors")
+    out = run_decode(V, a, m)
+    torch.cuda.synchronize()
+    check_decode(out, odec.decode(a, m))
