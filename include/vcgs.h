@@ -139,7 +139,9 @@ void vcgs_state_free(vcgs_ctx* ctx, vcgs_state* state);
  *   gids[P]        Gaussian index of every (tile, depth)-sorted pair
  *   ranges[T][2]   [start, end) of each tile's pairs in gids
  *   t_final[H][W], n_contrib[H][W] (uint32: list entries up to the last contributor)
- *   splats[n][12]  float: u, v, conic A, B, C, opacity, r, g, b, depth, 0, 0 (visible Gaussians only)
+ *   splats[n][16]  float: u, v, u_lo, v_lo, ex, ey, j1, j2, opacity, r, g, b, depth, 0, 0, 0
+ *                  (visible Gaussians only): screen position u + u_lo, v + v_lo; unit major axis
+ *                  (ex, ey); j1, j2 = -1 / (2 ln2 lambda) for the eigenvalues of Sigma' + 0.3 I
  */
 typedef struct {
     int64_t n, n_pairs;
@@ -232,6 +234,18 @@ typedef struct {
 int vcgs_decode_anchors_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
                                  const vcgs_codebook* cb, const float* mask_logit, float mask_eps,
                                  const vcgs_gaussian_buffers* dG, vcgs_anchor_grads* out, void* stream);
+
+/* ---- kernel configuration ---------------------------------------------- */
+
+/* Process-wide settings read by every later launch (all contexts):
+ *   VCGS_OPT_PPL_FWD / VCGS_OPT_PPL_BWD: pixels per lane of the forward /
+ *     backward compositing, 1, 2 or 4 (a 16x16 tile is walked by 4, 2 or 1 waves);
+ *   VCGS_OPT_CULL: 1 = skip, per wave, tile-list entries whose 1/255 ellipse
+ *     misses the wave's pixels (results are identical either way), 0 = visit all.
+ * Invalid keys or values return VCGS_E_INVALID and change nothing. */
+enum { VCGS_OPT_PPL_FWD = 1, VCGS_OPT_PPL_BWD = 2, VCGS_OPT_CULL = 3 };
+int vcgs_set_option(int key, int value);
+int vcgs_get_option(int key, int* value);
 
 /* ---- stage timing ------------------------------------------------------ */
 

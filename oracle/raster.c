@@ -53,12 +53,20 @@ typedef struct {
 #define ORC_CLAMP_FOV (1.3f)
 #define ORC_TWO_LN2 (1.3862944f)
 
-/* Relative half-widths of the bands in which an FP32 evaluation of the same
- * footprint may take the other side of a threshold: the FP32 footprint carries
- * a relative error of a few 1e-6, the transmittance after a few hundred
- * factors (1 - alpha) up to ~1e-4. */
-#define ORC_BAND_ALPHA (2e-5)
-#define ORC_BAND_T (5e-4)
+/* Bands in which an FP32 evaluation of the same footprint may fall on the
+ * other side of a threshold.  The FP32 projection carries relative errors of
+ * a few unit roundoffs (u = 2^-24) in the 2x3 factor of Sigma'; along the
+ * minor axis of Sigma' + 0.3 I this becomes a relative error of about
+ * 8 u cond in its smaller eigenvalue (cond = lambda_max / lambda_min), so the
+ * exponent of the footprint is off by about 8 u cond |power|.  The band on
+ * alpha is that bound plus a floor of 2e-5; the band on the stop
+ * transmittance is 2e-4 plus the running sum, over the contributors, of each
+ * alpha band times alpha / (1 - alpha). */
+#define ORC_U32 (5.9604644775390625e-08)
+#define ORC_BAND_ALPHA_FLOOR (2e-5)
+#define ORC_BAND_T_FLOOR (2e-4)
+
+#define ORC_SPLAT 8
 
 /* flag bits of an ambiguous pixel (a threshold decision lies within FP32 noise) */
 #define ORC_FLAG_ALPHA 1u
@@ -68,8 +76,9 @@ typedef struct {
 static inline uint32_t f2u(float x) { uint32_t u; memcpy(&u, &x, 4); return u; }
 
 /* ------------------------------------------------------------------------ */
-/* FP32 key path: depth bits and tile rectangle of every Gaussian.           */
-/* Every operation is one IEEE binary32 operation, evaluated left to right.  */
+/* Key path: depth bits and tile rectangle of every Gaussian.  The camera     */
+/* point and screen position are binary64, everything after them binary32;  */
+/* every operation is one IEEE operation, evaluated left to right.          */
 /* ------------------------------------------------------------------------ */
 void orc_keys(int64_t n, const float* mean, const float* scale, const float* quat,
               const float* opac, const orc_camera* cam, const float* Rc, const float* tc,
@@ -84,14 +93,20 @@ void orc_keys(int64_t n, const float* mean, const float* scale, const float* qua
         depth_bits[g] = 0xFFFFFFFFu;
         rect[4 * g + 0] = rect[4 * g + 1] = rect[4 * g + 2] = rect[4 * g + 3] = 0;
         count[g] = 0;
-        const float x = mean[g], y = mean[n + g], z = mean[2 * n + g];
-        /* camera point, eq. (3) W = R */
-        const float X = ((Rc[0] * x + Rc[1] * y) + Rc[2] * z) + tc[0];
-        const float Y = ((Rc[3] * x + Rc[4] * y) + Rc[5] * z) + tc[1];
-        const float Z = ((Rc[6] * x + Rc[7] * y) + Rc[8] * z) + tc[2];
-        if (!(Z > cam->z_near)) continue;
+        /* camera point and screen position in binary64, then rounded to binary32 */
+        const double xd = mean[g], yd = mean[n + g], zd = mean[2 * n + g];
+        const double Xd = (((double)Rc[0] * xd + (double)Rc[1] * yd) + (double)Rc[2] * zd) + (double)tc[0];
+        const double Yd = (((double)Rc[3] * xd + (double)Rc[4] * yd) + (double)Rc[5] * zd) + (double)tc[1];
+        const double Zd = (((double)Rc[6] * xd + (double)Rc[7] * yd) + (double)Rc[8] * zd) + (double)tc[2];
+        if (!(Zd > (double)cam->z_near)) continue;
         const float o = opac[g];
         if (!(o >= ORC_ALPHA_MIN)) continue;  /* never reaches 1/255 anywhere */
+        const double txd = Xd / Zd, tyd = Yd / Zd;
+        const double ud = (double)cam->fx * txd + (double)cam->cx;
+        const double vd = (double)cam->fy * tyd + (double)cam->cy;
+        const float Z = (float)Zd;
+        const float txz = (float)txd, tyz = (float)tyd;
+        const float u = (float)ud, v = (float)vd;
         /* rotation of the normalised quaternion, eq. (2) */
         float qw = quat[g], qx = quat[n + g], qy = quat[2 * n + g], qz = quat[3 * n + g];
         const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
@@ -112,7 +127,6 @@ void orc_keys(int64_t n, const float* mean, const float* scale, const float* qua
         float m[9];
         for (int i = 0; i < 3; ++i) { m[3 * i] = r[3 * i] * s0; m[3 * i + 1] = r[3 * i + 1] * s1; m[3 * i + 2] = r[3 * i + 2] * s2; }
         /* projection Jacobian with clamped x/z, y/z */
-        const float txz = X / Z, tyz = Y / Z;
         const float cxz = fminf(fmaxf(txz, -limx), limx);
         const float cyz = fminf(fmaxf(tyz, -limy), limy);
         const float j00 = cam->fx / Z, j02 = -(cam->fx * cxz) / Z;
@@ -146,8 +160,6 @@ void orc_keys(int64_t n, const float* mean, const float* scale, const float* qua
         const int e = (int)((f2u(y255) >> 23) & 0xFFu) - 127;
         const float kf = ORC_TWO_LN2 * (float)(e + 1);
         const float rad = ceilf(sqrtf(kf * lam));
-        const float u = cam->fx * txz + cam->cx;
-        const float v = cam->fy * tyz + cam->cy;
         if (!(fabsf(u) < 1e30f) || !(fabsf(v) < 1e30f) || !(rad < 1e30f)) continue;
         float xlo = ceilf((u - rad) - 0.5f), xhi = floorf((u + rad) - 0.5f);
         float ylo = ceilf((v - rad) - 0.5f), yhi = floorf((v + rad) - 0.5f);
@@ -301,7 +313,8 @@ static void load_g(int64_t n, int64_t g, const double* mean, const double* scale
     for (int i = 0; i < 4; ++i) q[i] = quat[i * n + g];
 }
 
-/* splat parameters of every Gaussian: (u, v, A, B, C, depth) */
+/* splat parameters of every Gaussian: (u, v, A, B, C, depth, cond, 0), where
+ * cond = lambda_max / lambda_min of Sigma' + 0.3 I */
 void orc_project(int64_t n, const double* mean, const double* scale, const double* quat,
                  const orc_camera* cam, const double* Rc, const double* tc, double* splat)
 {
@@ -311,21 +324,26 @@ void orc_project(int64_t n, const double* mean, const double* scale, const doubl
         load_g(n, g, mean, scale, quat, mu, s, q);
         orc_proj P;
         proj64(mu, s, q, cam, Rc, tc, &P);
-        double* o = splat + 6 * g;
+        double* o = splat + ORC_SPLAT * g;
+        const double hd = 0.5 * (P.a - P.c), mid = 0.5 * (P.a + P.c);
+        const double rt = sqrt(hd * hd + P.b * P.b);
+        const double lmax = mid + rt, lmin = P.det / lmax;
         o[0] = P.u; o[1] = P.v; o[2] = P.conic[0]; o[3] = P.conic[1]; o[4] = P.conic[2]; o[5] = P.pc[2];
+        o[6] = lmax / lmin; o[7] = 0.0;
     }
 }
 
 /* ------------------------------------------------------------------------ */
 /* Footprint and compositing, eqs. (1), (16)-(18).                           */
 /* ------------------------------------------------------------------------ */
-typedef struct { double G, raw, alpha; int clamped; } orc_fp;
+typedef struct { double G, raw, alpha, power; int clamped; } orc_fp;
 
 static inline orc_fp footprint(const double* sp, double o, double px, double py)
 {
     orc_fp f;
     const double dx = px - sp[0], dy = py - sp[1];
     const double power = -0.5 * (sp[2] * dx * dx + sp[4] * dy * dy) - sp[3] * dx * dy;
+    f.power = power;
     f.G = exp(power);
     f.raw = o * f.G;
     f.clamped = f.raw > (double)ORC_ALPHA_MAX;
@@ -344,20 +362,24 @@ static void composite_px(const double* splat, const double* opac, const double* 
                          int32_t* ncontrib, uint8_t* flags)
 {
     double T = 1.0, c0 = 0, c1 = 0, c2 = 0, d = 0, a = 0;
+    double eT = 0.0;  /* running relative error bound of T */
     int32_t last = 0;
     uint8_t fl = 0;
     for (uint32_t k = lo; k < hi; ++k) {
         const uint32_t g = gids[k];
-        const orc_fp f = footprint(splat + 6 * (size_t)g, opac[g], px, py);
-        if (near_rel(f.raw, (double)ORC_ALPHA_MIN, ORC_BAND_ALPHA)) fl |= ORC_FLAG_ALPHA;
-        if (near_rel(f.raw, (double)ORC_ALPHA_MAX, ORC_BAND_ALPHA)) fl |= ORC_FLAG_CLAMP;
+        const double* sp = splat + ORC_SPLAT * (size_t)g;
+        const orc_fp f = footprint(sp, opac[g], px, py);
+        const double band = ORC_BAND_ALPHA_FLOOR + 8.0 * ORC_U32 * sp[6] * (fabs(f.power) + 1.0);
+        if (near_rel(f.raw, (double)ORC_ALPHA_MIN, band)) fl |= ORC_FLAG_ALPHA;
+        if (near_rel(f.raw, (double)ORC_ALPHA_MAX, band)) fl |= ORC_FLAG_CLAMP;
         if (f.alpha < (double)ORC_ALPHA_MIN) continue;
         const double Tn = T * (1.0 - f.alpha);
-        if (near_rel(Tn, (double)ORC_T_MIN, ORC_BAND_T)) fl |= ORC_FLAG_STOP;
+        eT += band * f.alpha / (1.0 - f.alpha) + 2.0 * ORC_U32;
+        if (near_rel(Tn, (double)ORC_T_MIN, ORC_BAND_T_FLOOR + eT)) fl |= ORC_FLAG_STOP;
         if (Tn < (double)ORC_T_MIN) break;
         const double w = f.alpha * T;
         c0 += w * color[g]; c1 += w * color[n + g]; c2 += w * color[2 * n + g];
-        d += w * splat[6 * (size_t)g + 5];
+        d += w * splat[ORC_SPLAT * (size_t)g + 5];
         a += w;
         T = Tn;
         last = (int32_t)(k - lo + 1);
@@ -413,7 +435,7 @@ void orc_render_bwd_2d(int64_t n, const double* splat, const double* opac, const
         double T = 1.0;
         for (uint32_t k = ranges[2 * t]; k < ranges[2 * t + 1]; ++k) {
             const uint32_t g = gids[k];
-            const orc_fp f = footprint(splat + 6 * (size_t)g, opac[g], px, py);
+            const orc_fp f = footprint(splat + ORC_SPLAT * (size_t)g, opac[g], px, py);
             if (f.alpha < (double)ORC_ALPHA_MIN) continue;
             const double Tn = T * (1.0 - f.alpha);
             if (Tn < (double)ORC_T_MIN) break;
@@ -435,7 +457,7 @@ void orc_render_bwd_2d(int64_t n, const double* splat, const double* opac, const
         for (size_t ii = m; ii-- > 0;) {
             const uint32_t g = ids[ii];
             const double a = al[ii], Tb = Ti[ii];
-            const double xval[5] = {color[g], color[n + g], color[2 * n + g], splat[6 * (size_t)g + 5], 1.0};
+            const double xval[5] = {color[g], color[n + g], color[2 * n + g], splat[ORC_SPLAT * (size_t)g + 5], 1.0};
             /* d out_x / d alpha_i = x_i T_i - S_i / (1 - alpha_i) */
             double dl_dalpha = 0.0;
             for (int c = 0; c < 5; ++c) dl_dalpha += up[c] * (xval[c] * Tb - S[c] / (1.0 - a));
@@ -444,7 +466,7 @@ void orc_render_bwd_2d(int64_t n, const double* splat, const double* opac, const
             gg[6] += w * up[0]; gg[7] += w * up[1]; gg[8] += w * up[2];
             gg[9] += w * up[3];
             if (!cl[ii]) {
-                const double* sp = splat + 6 * (size_t)g;
+                const double* sp = splat + ORC_SPLAT * (size_t)g;
                 const double dx = px - sp[0], dy = py - sp[1];
                 const double dl_dpow = dl_dalpha * a;  /* alpha = o exp(power) */
                 gg[0] += dl_dpow * (sp[2] * dx + sp[3] * dy);

@@ -86,9 +86,10 @@ def tile_ranges(keys_sorted, cam):
 
 
 def project(g, cam, pose):
-    """FP64 splat parameters (n, 6): u, v, conic A, B, C, camera depth."""
+    """FP64 splat parameters (n, 8): u, v, conic A, B, C, camera depth,
+    condition number of Sigma' + 0.3 I, 0."""
     n = g.n
-    out = np.empty((n, 6), np.float64)
+    out = np.empty((n, 8), np.float64)
     m, s, q = (_c(x, np.float64) for x in (g.mean, g.scale, g.quat))
     R, t = _c(pose.R, np.float64), _c(pose.t, np.float64)
     c = _cam(cam)

@@ -598,6 +598,36 @@ int vcgs_decode_anchors_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcg
     return VCGS_OK;
 }
 
+int vcgs_set_option(int key, int value)
+{
+    Options& o = options();
+    switch (key) {
+    case VCGS_OPT_PPL_FWD:
+    case VCGS_OPT_PPL_BWD:
+        if (value != 1 && value != 2 && value != 4) return fail(VCGS_E_INVALID, "pixels per lane must be 1, 2 or 4");
+        (key == VCGS_OPT_PPL_FWD ? o.ppl_fwd : o.ppl_bwd) = value;
+        return VCGS_OK;
+    case VCGS_OPT_CULL:
+        if (value != 0 && value != 1) return fail(VCGS_E_INVALID, "cull must be 0 or 1");
+        o.cull = value;
+        return VCGS_OK;
+    default:
+        return fail(VCGS_E_INVALID, "unknown option");
+    }
+}
+
+int vcgs_get_option(int key, int* value)
+{
+    if (!value) return fail(VCGS_E_INVALID, "value is NULL");
+    const Options& o = options();
+    switch (key) {
+    case VCGS_OPT_PPL_FWD: *value = o.ppl_fwd; return VCGS_OK;
+    case VCGS_OPT_PPL_BWD: *value = o.ppl_bwd; return VCGS_OK;
+    case VCGS_OPT_CULL: *value = o.cull; return VCGS_OK;
+    default: return fail(VCGS_E_INVALID, "unknown option");
+    }
+}
+
 int vcgs_profile_enable(vcgs_ctx* ctx, int on)
 {
     if (!ctx) return fail(VCGS_E_INVALID, "ctx is NULL");

@@ -35,12 +35,12 @@ struct PoseK {
     float t[3];
 };
 
-// Projected splat record, 48 bytes: (u, v, ex, ey) (j1, j2, o, r) (g, b, depth, -).
-// The footprint exponent in base 2 is j1 p1^2 + j2 p2^2 with p1 = d . (ex, ey),
-// p2 = d . (-ey, ex), d = pixel centre - (u, v), j = -1 / (2 ln2 lambda) for the two
-// eigenvalues of Sigma' + 0.3 I.
+// Projected splat record, 64 bytes: (u, v, u_lo, v_lo) (ex, ey, j1, j2) (o, r, g, b) (depth, -, -, -).
+// The screen position is u + u_lo (a binary32 pair).  The footprint exponent in base 2
+// is j1 p1^2 + j2 p2^2 with p1 = d . (ex, ey), p2 = d . (-ey, ex), d = pixel centre -
+// (u, v), j = -1 / (2 ln2 lambda) for the two eigenvalues of Sigma' + 0.3 I.
 struct Splat {
-    float4 a, b, c;
+    float4 a, b, c, d;
 };
 
 // Per-Gaussian gradient of the 2D quantities, 12 floats:
@@ -100,8 +100,13 @@ void launch_composite_bwd(const CamK& cam, const Splat* rec, const uint32_t* gid
                           const float* bg, const float* t_final, const uint32_t* n_contrib,
                           const float* dl_dc, const float* dl_dd, const float* dl_da, float* g2,
                           unsigned long long* counters, hipStream_t s);
-void set_composite_ppl(int ppl);
-int composite_ppl();
+// Process-wide kernel configuration (vcgs_set_option).
+struct Options {
+    int ppl_fwd = 1;  // pixels per lane of the forward compositing (1, 2, 4)
+    int ppl_bwd = 1;  // pixels per lane of the backward compositing (1, 2, 4)
+    int cull = 1;     // per-wave ellipse culling of tile-list entries
+};
+Options& options();
 int l1_loss_blocks(int64_t npix);
 // partial: l1_loss_blocks(npix) floats of scratch (only used when loss != nullptr)
 void launch_l1_loss(int64_t npix, const float* c, const float* d, const float* tc, const float* td,

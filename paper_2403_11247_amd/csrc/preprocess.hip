@@ -44,7 +44,8 @@ struct KeyOut {
     float K[6];             // J W Rq S, so that Sigma' = K K^T
     float ca, cb, cc, det;  // Sigma' + 0.3 I entries and determinant
     float lam;              // its larger eigenvalue
-    float u, v;
+    double ud, vd;          // screen position (binary64)
+    float u, v;             // and rounded to binary32
     int tx0, ty0, tx1, ty1;
 };
 
@@ -56,11 +57,20 @@ __device__ __forceinline__ KeyOut key_path(float x, float y, float z, float s0, 
 #pragma clang fp contract(off)
     KeyOut r;
     r.vis = false;
-    r.X = ((P.R[0] * x + P.R[1] * y) + P.R[2] * z) + P.t[0];
-    r.Y = ((P.R[3] * x + P.R[4] * y) + P.R[5] * z) + P.t[1];
-    r.Z = ((P.R[6] * x + P.R[7] * y) + P.R[8] * z) + P.t[2];
-    if (!(r.Z > cam.znear)) return r;
+    // camera point and screen position in binary64 (world coordinates of several
+    // metres would otherwise cost ~1e-3 px), then rounded to binary32
+    const double xd = x, yd = y, zd = z;
+    const double Xd = (((double)P.R[0] * xd + (double)P.R[1] * yd) + (double)P.R[2] * zd) + (double)P.t[0];
+    const double Yd = (((double)P.R[3] * xd + (double)P.R[4] * yd) + (double)P.R[5] * zd) + (double)P.t[1];
+    const double Zd = (((double)P.R[6] * xd + (double)P.R[7] * yd) + (double)P.R[8] * zd) + (double)P.t[2];
+    if (!(Zd > (double)cam.znear)) return r;
     if (!(o >= kAlphaMin)) return r;
+    const double txd = Xd / Zd, tyd = Yd / Zd;
+    r.ud = (double)cam.fx * txd + (double)cam.cx;
+    r.vd = (double)cam.fy * tyd + (double)cam.cy;
+    r.X = (float)Xd; r.Y = (float)Yd; r.Z = (float)Zd;
+    r.u = (float)r.ud; r.v = (float)r.vd;
+    const float txz = (float)txd, tyz = (float)tyd;
     const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
     if (n2 > 0.0f) {
         const float nr = __builtin_sqrtf(n2);
@@ -78,7 +88,6 @@ __device__ __forceinline__ KeyOut key_path(float x, float y, float z, float s0, 
     float m[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i) { m[3 * i] = q[3 * i] * s0; m[3 * i + 1] = q[3 * i + 1] * s1; m[3 * i + 2] = q[3 * i + 2] * s2; }
-    const float txz = r.X / r.Z, tyz = r.Y / r.Z;
     const float cxz = fminf(fmaxf(txz, -cam.limx), cam.limx);
     const float cyz = fminf(fmaxf(tyz, -cam.limy), cam.limy);
     const float j00 = cam.fx / r.Z, j02 = -(cam.fx * cxz) / r.Z;
@@ -116,8 +125,6 @@ __device__ __forceinline__ KeyOut key_path(float x, float y, float z, float s0, 
     const int e = (int)((__float_as_uint(y255) >> 23) & 0xFFu) - 127;
     const float kf = kTwoLn2 * (float)(e + 1);
     const float rad = ceilf(__builtin_sqrtf(kf * lam));
-    r.u = cam.fx * txz + cam.cx;
-    r.v = cam.fy * tyz + cam.cy;
     if (!(fabsf(r.u) < 1e30f) || !(fabsf(r.v) < 1e30f) || !(rad < 1e30f)) return r;
     float xlo = ceilf((r.u - rad) - 0.5f), xhi = floorf((r.u + rad) - 0.5f);
     float ylo = ceilf((r.v - rad) - 0.5f), yhi = floorf((r.v + rad) - 0.5f);
@@ -158,9 +165,10 @@ __global__ void __launch_bounds__(256) k_preprocess(int64_t n, const float* __re
     const float nrm = sqrtf(ex * ex + ey * ey);
     if (nrm > 0.0f) { ex /= nrm; ey /= nrm; } else { ex = 1.0f; ey = 0.0f; }
     Splat sp;
-    sp.a = make_float4(k.u, k.v, ex, ey);
-    sp.b = make_float4(kNegHalfLog2e / k.lam, kNegHalfLog2e / lmin, o, color[g]);
-    sp.c = make_float4(color[n + g], color[2 * n + g], k.Z, 0.0f);
+    sp.a = make_float4(k.u, k.v, (float)(k.ud - (double)k.u), (float)(k.vd - (double)k.v));
+    sp.b = make_float4(ex, ey, kNegHalfLog2e / k.lam, kNegHalfLog2e / lmin);
+    sp.c = make_float4(o, color[g], color[n + g], color[2 * n + g]);
+    sp.d = make_float4(k.Z, 0.0f, 0.0f, 0.0f);
     rec[g] = sp;
     depth_key[g] = __float_as_uint(k.Z);
     count[g] = (uint32_t)((k.tx1 - k.tx0 + 1) * (k.ty1 - k.ty0 + 1));

@@ -54,8 +54,8 @@ __device__ __forceinline__ Fp footprint(float dx, float dy, float ex, float ey, 
 // rectangle, compared with log2(255 o) plus a margin far above FP32 error.
 __device__ __forceinline__ bool reaches_rect(const Splat& s, float x0, float x1, float y0, float y1)
 {
-    const float u = s.a.x, v = s.a.y, ex = s.a.z, ey = s.a.w;
-    const float k1 = -s.b.x, k2 = -s.b.y, o = s.b.z;  // k > 0
+    const float u = s.a.x + s.a.z, v = s.a.y + s.a.w, ex = s.b.x, ey = s.b.y;
+    const float k1 = -s.b.z, k2 = -s.b.w, o = s.c.x;  // k > 0
     const float A = ex * ex * k1 + ey * ey * k2;
     const float B = ex * ey * (k1 - k2);
     const float C = ey * ey * k1 + ex * ex * k2;
@@ -108,11 +108,11 @@ __global__ void __launch_bounds__(256) k_composite_fwd(CamK cam, const Splat* __
                                                        float bg2, float* __restrict__ color, float* __restrict__ depth,
                                                        float* __restrict__ alpha_out, float* __restrict__ t_final,
                                                        uint32_t* __restrict__ n_contrib,
-                                                       unsigned long long* __restrict__ counters)
+                                                       unsigned long long* __restrict__ counters, int cull)
 {
     constexpr int WPT = 4 / PPL;     // waves per tile
     constexpr int ROWS = 16 / WPT;   // rows per wave
-    __shared__ float4 slab[4][64][3];
+    __shared__ float4 slab[4][64][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
     const int tile = gw / WPT, sub = gw % WPT;
@@ -151,10 +151,11 @@ __global__ void __launch_bounds__(256) k_composite_fwd(CamK cam, const Splat* __
         bool keep = false;
         if (idx < end) {
             const Splat sp = rec[gids[idx]];
-            keep = reaches_rect(sp, rx0, rx1, ry0, ry1);
+            keep = !cull || reaches_rect(sp, rx0, rx1, ry0, ry1);
             slab[wave][lane][0] = sp.a;
             slab[wave][lane][1] = sp.b;
             slab[wave][lane][2] = sp.c;
+            slab[wave][lane][3] = sp.d;
         }
         uint64_t hits = __ballot(keep);
         wave_lds_sync();
@@ -162,12 +163,13 @@ __global__ void __launch_bounds__(256) k_composite_fwd(CamK cam, const Splat* __
             const int k = __builtin_ctzll(hits);
             hits &= hits - 1ull;
             const float4 ra = slab[wave][k][0], rb = slab[wave][k][1], rc = slab[wave][k][2];
-            const float dx = pxf - ra.x;
+            const float rz = slab[wave][k][3].x;
+            const float dx = (pxf - ra.x) - ra.z;
             bool lane_done = true;
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 if (!done[j]) {
-                    const Fp f = footprint(dx, dy[j] - ra.y, ra.z, ra.w, rb.x, rb.y, rb.z);
+                    const Fp f = footprint(dx, (dy[j] - ra.y) - ra.w, rb.x, rb.y, rb.z, rb.w, rc.x);
                     if (COUNT) ++n_eval;
                     if (f.alpha >= kAlphaMin) {
                         const float Tn = T[j] * (1.0f - f.alpha);
@@ -176,8 +178,8 @@ __global__ void __launch_bounds__(256) k_composite_fwd(CamK cam, const Splat* __
                         } else {
                             if (COUNT) ++n_blend;
                             const float w = f.alpha * T[j];
-                            c0[j] += w * rb.w; c1[j] += w * rc.x; c2[j] += w * rc.y;
-                            dd[j] += w * rc.z; aa[j] += w;
+                            c0[j] += w * rc.y; c1[j] += w * rc.z; c2[j] += w * rc.w;
+                            dd[j] += w * rz; aa[j] += w;
                             T[j] = Tn;
                             last[j] = b - start + (uint32_t)k + 1u;
                         }
@@ -209,6 +211,16 @@ __global__ void __launch_bounds__(256) k_composite_fwd(CamK cam, const Splat* __
     }
 }
 
+// Sum over each 16-lane row, result in every lane of the row.
+__device__ __forceinline__ float row_sum(float v)
+{
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x124, 0xF, 0xF, false);  // row_ror:4
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    return v;
+}
+
 // Sum over the 64 lanes, result in every lane.
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -230,6 +242,8 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
     return v;
 }
 
+constexpr int kPend = 6;  // Gaussians whose row sums are gathered before one atomic flush
+
 template <int PPL, bool COUNT>
 __global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __restrict__ rec,
                                                        const uint32_t* __restrict__ gids,
@@ -238,18 +252,22 @@ __global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __
                                                        const uint32_t* __restrict__ n_contrib,
                                                        const float* __restrict__ dl_dc, const float* __restrict__ dl_dd,
                                                        const float* __restrict__ dl_da, float* __restrict__ g2,
-                                                       unsigned long long* __restrict__ counters)
+                                                       unsigned long long* __restrict__ counters, int cull)
 {
     constexpr int WPT = 4 / PPL;
     constexpr int ROWS = 16 / WPT;
-    __shared__ float4 slab[4][64][3];
+    __shared__ float4 slab[4][64][4];
     __shared__ uint32_t slab_gid[4][64];
+    // per-Gaussian row sums (4 rows x 10 values) waiting to be added to g2
+    __shared__ float pend[4][kPend][4][10];
+    __shared__ uint32_t pend_gid[4][kPend];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
     const int tile = gw / WPT, sub = gw % WPT;
     const int n_tiles = cam.tiles_x * cam.tiles_y;
     if (tile >= n_tiles) return;
     uint32_t n_eval = 0, n_blend = 0, n_flush = 0;
+    int npend = 0;  // uniform
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * kTile + (lane & 15);
     const int row0 = ty * kTile + sub * ROWS;
@@ -288,10 +306,11 @@ __global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __
         if (li < wl) {
             const uint32_t g = gids[start + li];
             const Splat sp = rec[g];
-            keep = reaches_rect(sp, rx0, rx1, ry0, ry1);
+            keep = !cull || reaches_rect(sp, rx0, rx1, ry0, ry1);
             slab[wave][lane][0] = sp.a;
             slab[wave][lane][1] = sp.b;
             slab[wave][lane][2] = sp.c;
+            slab[wave][lane][3] = sp.d;
             slab_gid[wave][lane] = g;
         }
         uint64_t hits = __ballot(keep);
@@ -301,8 +320,9 @@ __global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __
             hits &= ~(1ull << k);
             const uint32_t local = (uint32_t)(bs + k);
             const float4 ra = slab[wave][k][0], rb = slab[wave][k][1], rc = slab[wave][k][2];
-            const float i1 = -2.0f * kLn2 * rb.x, i2 = -2.0f * kLn2 * rb.y;  // eigenvalues of Q
-            const float dx = pxf - ra.x;
+            const float rz = slab[wave][k][3].x;
+            const float i1 = -2.0f * kLn2 * rb.z, i2 = -2.0f * kLn2 * rb.w;  // eigenvalues of Q
+            const float dx = (pxf - ra.x) - ra.z;
             float p[10];
 #pragma unroll
             for (int i = 0; i < 10; ++i) p[i] = 0.0f;
@@ -310,15 +330,15 @@ __global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 if (local < last[j]) {
-                    const float dyj = pyf[j] - ra.y;
-                    const Fp f = footprint(dx, dyj, ra.z, ra.w, rb.x, rb.y, rb.z);
+                    const float dyj = (pyf[j] - ra.y) - ra.w;
+                    const Fp f = footprint(dx, dyj, rb.x, rb.y, rb.z, rb.w, rc.x);
                     if (COUNT) ++n_eval;
                     if (f.alpha >= kAlphaMin) {
                         contrib = true;
                         if (COUNT) ++n_blend;
                         const float a = f.alpha;
                         const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
-                        const float x[5] = {rb.w, rc.x, rc.y, rc.z, 1.0f};
+                        const float x[5] = {rc.y, rc.z, rc.w, rz, 1.0f};
                         float dla = 0.0f;
 #pragma unroll
                         for (int c = 0; c < 5; ++c) {
@@ -334,8 +354,8 @@ __global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __
                         if (!f.clamped) {
                             const float dp = dla * a;  // dL/dpower, power = -1/2 d^T Q d
                             const float q1 = i1 * f.p1, q2 = i2 * f.p2;
-                            p[0] += dp * (q1 * ra.z - q2 * ra.w);   // d power / d u = (Q d)_x
-                            p[1] += dp * (q1 * ra.w + q2 * ra.z);   // d power / d v = (Q d)_y
+                            p[0] += dp * (q1 * rb.x - q2 * rb.y);   // d power / d u = (Q d)_x
+                            p[1] += dp * (q1 * rb.y + q2 * rb.x);   // d power / d v = (Q d)_y
                             p[2] += dp * (-0.5f * dx * dx);
                             p[3] += dp * (-dx * dyj);
                             p[4] += dp * (-0.5f * dyj * dyj);
@@ -346,14 +366,36 @@ __global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __
                 }
             }
             if (__ballot(contrib) == 0ull) continue;
-            float mine = 0.0f;
+            // row sums; lane 16 r + v keeps row r's sum of value v
+            const int col = lane & 15;
+            float sel = row_sum(p[0]);
 #pragma unroll
-            for (int i = 0; i < 10; ++i) {
-                const float s = wave_sum(p[i]);
-                if (lane == i) mine = s;
+            for (int i = 1; i < 10; ++i) {
+                const float rs = row_sum(p[i]);
+                sel = (col == i) ? rs : sel;
             }
-            if (lane < 10) atomicAdd(g2 + (size_t)kG2 * slab_gid[wave][k] + lane, mine);
+            if (col < 10) pend[wave][npend][lane >> 4][col] = sel;
+            if (lane == 0) pend_gid[wave][npend] = slab_gid[wave][k];
+            ++npend;
             if (COUNT && lane == 0) ++n_flush;
+            if (npend == kPend) {
+                wave_lds_sync();
+                if (lane < 10 * kPend) {
+                    const int sl = lane / 10, v = lane - 10 * sl;
+                    const float t = (pend[wave][sl][0][v] + pend[wave][sl][1][v]) + (pend[wave][sl][2][v] + pend[wave][sl][3][v]);
+                    atomicAdd(g2 + (size_t)kG2 * pend_gid[wave][sl] + v, t);
+                }
+                wave_lds_sync();
+                npend = 0;
+            }
+        }
+    }
+    if (npend > 0) {
+        wave_lds_sync();
+        if (lane < 10 * npend) {
+            const int sl = lane / 10, v = lane - 10 * sl;
+            const float t = (pend[wave][sl][0][v] + pend[wave][sl][1][v]) + (pend[wave][sl][2][v] + pend[wave][sl][3][v]);
+            atomicAdd(g2 + (size_t)kG2 * pend_gid[wave][sl] + v, t);
         }
     }
     if (COUNT) {
@@ -363,36 +405,37 @@ __global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __
     }
 }
 
-static int g_ppl = 2;
-
-void set_composite_ppl(int ppl) { g_ppl = (ppl == 1 || ppl == 2 || ppl == 4) ? ppl : 2; }
-int composite_ppl() { return g_ppl; }
+Options& options()
+{
+    static Options o;
+    return o;
+}
 
 template <int PPL>
 static void fwd_launch(int blocks, hipStream_t s, const CamK& cam, const Splat* rec, const uint32_t* gids,
                        const uint32_t* ranges, const float* bg, float* color, float* depth, float* alpha,
-                       float* t_final, uint32_t* n_contrib, unsigned long long* counters)
+                       float* t_final, uint32_t* n_contrib, unsigned long long* counters, int cull)
 {
     if (counters)
         k_composite_fwd<PPL, true><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], color, depth,
-                                                          alpha, t_final, n_contrib, counters);
+                                                          alpha, t_final, n_contrib, counters, cull);
     else
         k_composite_fwd<PPL, false><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], color, depth,
-                                                           alpha, t_final, n_contrib, nullptr);
+                                                           alpha, t_final, n_contrib, nullptr, cull);
 }
 
 template <int PPL>
 static void bwd_launch(int blocks, hipStream_t s, const CamK& cam, const Splat* rec, const uint32_t* gids,
                        const uint32_t* ranges, const float* bg, const float* t_final, const uint32_t* n_contrib,
                        const float* dl_dc, const float* dl_dd, const float* dl_da, float* g2,
-                       unsigned long long* counters)
+                       unsigned long long* counters, int cull)
 {
     if (counters)
         k_composite_bwd<PPL, true><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], t_final,
-                                                          n_contrib, dl_dc, dl_dd, dl_da, g2, counters);
+                                                          n_contrib, dl_dc, dl_dd, dl_da, g2, counters, cull);
     else
         k_composite_bwd<PPL, false><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], t_final,
-                                                           n_contrib, dl_dc, dl_dd, dl_da, g2, nullptr);
+                                                           n_contrib, dl_dc, dl_dd, dl_da, g2, nullptr, cull);
 }
 
 void launch_composite_fwd(const CamK& cam, const Splat* rec, const uint32_t* gids, const uint32_t* ranges,
@@ -401,11 +444,11 @@ void launch_composite_fwd(const CamK& cam, const Splat* rec, const uint32_t* gid
 {
     const int n_tiles = cam.tiles_x * cam.tiles_y;
     if (n_tiles <= 0) return;
-    const int ppl = g_ppl;
+    const int ppl = options().ppl_fwd, cull = options().cull;
     const int blocks = (n_tiles * (4 / ppl) + 3) / 4;
-    if (ppl == 4) fwd_launch<4>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters);
-    else if (ppl == 2) fwd_launch<2>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters);
-    else fwd_launch<1>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters);
+    if (ppl == 4) fwd_launch<4>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters, cull);
+    else if (ppl == 2) fwd_launch<2>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters, cull);
+    else fwd_launch<1>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters, cull);
 }
 
 void launch_composite_bwd(const CamK& cam, const Splat* rec, const uint32_t* gids, const uint32_t* ranges,
@@ -415,11 +458,11 @@ void launch_composite_bwd(const CamK& cam, const Splat* rec, const uint32_t* gid
 {
     const int n_tiles = cam.tiles_x * cam.tiles_y;
     if (n_tiles <= 0) return;
-    const int ppl = g_ppl;
+    const int ppl = options().ppl_bwd, cull = options().cull;
     const int blocks = (n_tiles * (4 / ppl) + 3) / 4;
-    if (ppl == 4) bwd_launch<4>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters);
-    else if (ppl == 2) bwd_launch<2>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters);
-    else bwd_launch<1>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters);
+    if (ppl == 4) bwd_launch<4>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters, cull);
+    else if (ppl == 2) bwd_launch<2>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters, cull);
+    else bwd_launch<1>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters, cull);
 }
 
 // L1 loss: L = mean_p (sum_c |C - C*| + w_depth |D - D*|).  Image gradients per

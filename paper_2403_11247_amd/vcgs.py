@@ -190,7 +190,7 @@ class State:
             return _wrap(ptr, count, dtype, dev).clone()
 
         return dict(n=n, n_pairs=P, tiles_x=v.tiles_x, tiles_y=v.tiles_y,
-                    splats=grab(v.splats, 12 * n, torch.float32).view(-1, 12),
+                    splats=grab(v.splats, 16 * n, torch.float32).view(-1, 16),
                     depth_bits=grab(v.depth_bits, n, torch.int32),
                     rect=grab(v.rect, 4 * n, torch.int16).view(-1, 4) if n > 0 else torch.empty(0, 4),
                     count=grab(v.count, n, torch.int32),
@@ -387,3 +387,17 @@ def count_read(ctx: Context | None = None) -> dict:
     arr = (c_i64 * 5)()
     _check(lib().vcgs_count_read(ctx.h, arr))
     return dict(zip(("fwd_evals", "fwd_blends", "bwd_evals", "bwd_blends", "bwd_flushes"), list(arr)))
+
+
+OPTIONS = {"ppl_fwd": 1, "ppl_bwd": 2, "cull": 3}
+
+
+def set_option(name: str, value: int):
+    """Process-wide kernel configuration (see vcgs_set_option)."""
+    _check(lib().vcgs_set_option(c_i32(OPTIONS[name]), c_i32(int(value))))
+
+
+def get_option(name: str) -> int:
+    v = c_i32()
+    _check(lib().vcgs_get_option(c_i32(OPTIONS[name]), ctypes.byref(v)))
+    return v.value
