@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--stages", action="store_true", help="also print a per-stage table to stderr")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -74,6 +76,29 @@ def stage_bytes(stage, n, nvis, P, na, W, H):
     if stage == "decode_bwd":
         return na * (272 + 272) + n * 56
     return None
+
+
+KERNEL_SOURCES = {"composite": "render.hip", "composite_bwd": "render.hip", "decode": "decode.hip",
+                  "decode_bwd": "decode.hip", "preprocess": "preprocess.hip", "preprocess_bwd": "preprocess.hip",
+                  "depth_sort": "sort.hip", "tile_sort": "sort.hip", "emit": "binning.hip"}
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of `stage` from the committed counter summary, or
+    None when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path) or stage not in KERNEL_SOURCES:
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(stage)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2403_11247_amd", "csrc", KERNEL_SOURCES[stage])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec.get("source_sha256"):
+            return None
+    return int(rec["bytes_per_launch"])
 
 
 def cpu_baseline(budget_s):
@@ -190,6 +215,7 @@ def main():
         ach = b / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    roof["traffic"] = measured_traffic(dom)
     roof["kernel"] = dom
     roof["avg_ms"] = round(avg_ms, 4)
 
@@ -202,6 +228,14 @@ def main():
            "roofline": roof,
            "stages_ms": {k: round(v, 4) for k, v in per_step.items()},
            "counts": counts}
+    if args.copy_probe_mb > 0:
+        src = torch.empty(args.copy_probe_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget_s)
     if args.stages:

@@ -166,6 +166,48 @@ int vcgs_l1_loss(vcgs_ctx* ctx, const vcgs_images* img, const float* target_colo
                  const float* target_depth, int32_t width, int32_t height, float w_depth,
                  float* dl_dcolor, float* dl_ddepth, float* loss, void* stream);
 
+/* ---- batched views ---------------------------------------------------- */
+
+/* A set of views of one Gaussian map: cams, poses are HOST arrays of n_views. */
+typedef struct {
+    int32_t n_views;  /* 1..16 */
+    const vcgs_camera* cams;
+    const vcgs_pose* poses;
+} vcgs_views;
+
+enum { VCGS_BATCH_GRAPH = 1 };
+
+/* Render n_views views of the same Gaussians in one pass (the keyframes of a
+ * local bundle-adjustment window, paper Sec. 3.5, or the requests of one
+ * serving step), and optionally run the loss and the backward for all of them.
+ *   outs: HOST array of n_views device image sets (sizes of each camera).
+ *   Forward only: target_color = target_depth = grads = dl_dpose = loss = NULL.
+ *   Forward + backward: target_color / target_depth are HOST arrays of
+ *   n_views device images; the L1 loss of vcgs_l1_loss (weight w_depth) is
+ *   applied per view, loss (device float [n_views]) receives each view's loss
+ *   if non-NULL, grads (device, Gaussian shapes) are OVERWRITTEN with the
+ *   gradients summed over the views, dl_dpose (device float [n_views][6]) with
+ *   each view's pose gradient (as in vcgs_render_backward).
+ * Results equal those of per-view vcgs_render_forward / vcgs_l1_loss /
+ * vcgs_render_backward calls up to the order of floating-point sums.
+ * The first call with a given signature (sizes, intrinsics, flags and every
+ * pointer argument) prepares a plan: it allocates the pass's buffers and
+ * synchronises `stream` once to size the pair buffers with headroom.  Later
+ * calls with the same signature (poses and Gaussian values may change) reuse
+ * it without synchronising.  With VCGS_BATCH_GRAPH the whole pass is captured
+ * once into a hipGraph (on a library-owned stream ordered after `stream`) and
+ * replayed as one launch.  If the pairs outgrow the buffers, vcgs_batch_check
+ * reports VCGS_E_CAPACITY; the next call resizes and the pass must be rerun. */
+int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
+                      const float* const* target_color, const float* const* target_depth, float w_depth,
+                      const vcgs_images* outs, vcgs_gaussian_buffers* grads, float* dl_dpose, float* loss,
+                      int flags, void* stream);
+
+/* Waits for the last vcgs_render_batch of ctx to finish.  Returns VCGS_OK, or
+ * VCGS_E_CAPACITY if its pair buffers overflowed (its results are then
+ * incomplete).  pairs (optional) receives the pass's pair count. */
+int vcgs_batch_check(vcgs_ctx* ctx, int64_t* pairs);
+
 /* ---- anchor decode ---------------------------------------------------- */
 
 /* Voxel anchors (paper Sec. 3.2): position x_a [3][na], feature f_a

@@ -21,18 +21,43 @@ constexpr float kLn2 = 0.69314718f;
 constexpr float kClampFov = 1.3f;
 constexpr float kTwoLn2 = 1.3862944f;
 constexpr int kTile = 16;
+constexpr int kMaxViews = 16;  // views rendered by one batched call
 
-// Camera and pose as passed to kernels (by value).
+// Camera as passed to kernels.
 struct CamK {
     int W, H;
     float fx, fy, cx, cy, znear;
     int tiles_x, tiles_y;
     float limx, limy;
-    uint32_t tile_base;  // added to every tile id (several views share one id space)
+    uint32_t tile_base;  // first global tile id of this view
 };
 struct PoseK {
     float R[9];
     float t[3];
+};
+
+// Per-view tables passed by value.  Entry e of the projection outputs is
+// (view e / n, Gaussian e % n); global tile ids are view-major.
+struct ProjTab {
+    int n_views;
+    int64_t n;  // Gaussians per view
+    CamK cam[kMaxViews];
+    PoseK pose[kMaxViews];
+};
+struct ViewTab {
+    int n_views;
+    int64_t n;
+    uint32_t tile_end[kMaxViews];  // exclusive end of each view's global tile ids
+    CamK cam[kMaxViews];
+    float* color[kMaxViews];
+    float* depth[kMaxViews];
+    float* alpha[kMaxViews];
+    float* t_final[kMaxViews];
+    uint32_t* n_contrib[kMaxViews];
+    const float* dl_dc[kMaxViews];
+    const float* dl_dd[kMaxViews];
+    const float* dl_da[kMaxViews];
+    float bg[3];
 };
 
 // Projected splat record, 64 bytes: (u, v, u_lo, v_lo) (ex, ey, j1, j2) (o, r, g, b) (depth, -, -, -).
@@ -43,37 +68,48 @@ struct Splat {
     float4 a, b, c, d;
 };
 
-// Per-Gaussian gradient of the 2D quantities, 12 floats:
+// Per-entry gradient of the 2D quantities, 12 floats:
 // du, dv, dA, dB, dC, dopacity, dr, dg, db, ddepth, -, -.
 constexpr int kG2 = 12;
 
 CamK make_camk(const vcgs_camera& c, uint32_t tile_base = 0);
 PoseK make_posek(const vcgs_pose& p);
 
+// Element counts that may live on the device: when dev != nullptr the count is
+// min(*dev, cap), otherwise cap.  Grids are sized from cap.
+struct Count {
+    int64_t cap;
+    const uint32_t* dev;
+};
+
 // ---- launchers (all asynchronous on `s`) --------------------------------
 // preprocess.hip
-void launch_preprocess(int64_t n, const vcgs_gaussians& g, const CamK& cam, const PoseK& pose,
-                       Splat* rec, uint32_t* depth_key, uint2* rect, uint32_t* count, hipStream_t s);
-void launch_preprocess_bwd(int64_t n, const vcgs_gaussians& g, const CamK& cam, const PoseK& pose,
-                           const uint32_t* count, const float* g2, const vcgs_gaussian_buffers& out,
-                           float* pose_partial, int pose_blocks, hipStream_t s);
+// The kernels read the table from device memory (t_dev, a copy of t) so that a
+// captured graph can be replayed with new poses.
+void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
+                       uint32_t* depth_key, uint2* rect, uint32_t* count, hipStream_t s);
 int preprocess_bwd_blocks(int64_t n);
-void launch_pose_reduce(const float* partial, int nblocks, float* dl_dpose, hipStream_t s);
+// g2 and count have n_views * n entries; pose_partial holds n_views * blocks * 6 floats.
+void launch_preprocess_bwd(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, const uint32_t* count,
+                           const float* g2, const vcgs_gaussian_buffers& out, float* pose_partial, int blocks,
+                           hipStream_t s);
+// dl_dpose: n_views * 6 floats
+void launch_pose_reduce(const float* partial, int n_views, int nblocks, float* dl_dpose, hipStream_t s);
 
 // sort.hip
 struct SortTemp {
     uint32_t* keys_alt;
     uint32_t* vals_alt;
-    uint32_t* hist;     // >= 256 * radix_blocks(n)
-    uint32_t* scan_tmp; // >= scan_temp_words(256 * radix_blocks(n))
+    uint32_t* hist;     // >= 256 * radix_blocks(cap)
+    uint32_t* scan_tmp; // >= scan_temp_words(256 * radix_blocks(cap))
 };
 int radix_blocks(int64_t n);
 int64_t scan_temp_words(int64_t n);
 // Stable LSD radix sort of (keys, vals) on bits [0, end_bit).  With
 // identity_vals the input values are 0..n-1 and `vals` is not read (it must
-// still hold n entries).  Returns 0 if the result is in (keys, vals), 1 if it
-// is in (t.keys_alt, t.vals_alt).
-int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, int64_t n, int end_bit, const SortTemp& t,
+// still hold cap entries).  Returns 0 if the result is in (keys, vals), 1 if
+// it is in (t.keys_alt, t.vals_alt).
+int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
                    hipStream_t s);
 // Exclusive scan of n uint32 values (out may equal in); if total != nullptr
 // the sum is written there.
@@ -81,25 +117,33 @@ void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
                         hipStream_t s);
 
 // binning.hip
-void launch_gather_counts(int64_t n, const uint32_t* order, const uint32_t* count, uint32_t* out,
-                          hipStream_t s);
-void launch_emit_pairs(int64_t n, const uint32_t* order, const uint32_t* offs, const uint32_t* count,
-                       const uint2* rect, int tiles_x, uint32_t tile_base, uint32_t* tile_ids,
-                       uint32_t* gids, hipStream_t s);
-void launch_tile_ranges(int64_t P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges,
-                        hipStream_t s);
+struct EmitTab {
+    int n_views;
+    int64_t n;  // entries per view
+    int tiles_x[kMaxViews];
+    uint32_t tile_base[kMaxViews];
+};
+void launch_gather_counts(int64_t n, const uint32_t* order, const uint32_t* count, uint32_t* out, hipStream_t s);
+// Writes pairs p < cap only; if the total exceeds cap sets *overflow = 1 (when non-null).
+void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* order, const uint32_t* offs,
+                       const uint32_t* count, const uint2* rect, uint32_t* tile_ids, uint32_t* gids, int64_t cap,
+                       const uint32_t* total, uint32_t* overflow, hipStream_t s);
+void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+void launch_copy_u32(uint32_t* dst, const uint32_t* src, Count n, hipStream_t s);
 
 // render.hip
 // counters (optional, 5 x u64): see vcgs_count_read.
-void launch_composite_fwd(const CamK& cam, const Splat* rec, const uint32_t* gids, const uint32_t* ranges,
-                          const float* bg, float* color, float* depth, float* alpha, float* t_final,
-                          uint32_t* n_contrib, unsigned long long* counters, hipStream_t s);
-void launch_composite_bwd(const CamK& cam, const Splat* rec, const uint32_t* gids, const uint32_t* ranges,
-                          const float* bg, const float* t_final, const uint32_t* n_contrib,
-                          const float* dl_dc, const float* dl_dd, const float* dl_da, float* g2,
-                          unsigned long long* counters, hipStream_t s);
+void launch_composite_fwd(const ViewTab& v, uint32_t total_tiles, const Splat* rec, const uint32_t* gids,
+                          const uint32_t* ranges, unsigned long long* counters, hipStream_t s);
+void launch_composite_bwd(const ViewTab& v, uint32_t total_tiles, const Splat* rec, const uint32_t* gids,
+                          const uint32_t* ranges, float* g2, unsigned long long* counters, hipStream_t s);
+int l1_loss_blocks(int64_t npix);
+// partial: l1_loss_blocks(npix) floats of scratch (only used when loss != nullptr)
+void launch_l1_loss(int64_t npix, const float* c, const float* d, const float* tc, const float* td,
+                    float w_depth, float* dl_dc, float* dl_dd, float* loss, float* partial, hipStream_t s);
+
 // Process-wide kernel configuration (vcgs_set_option).
 struct Options {
     int ppl_fwd = 1;  // pixels per lane of the forward compositing (1, 2, 4)
@@ -107,10 +151,6 @@ struct Options {
     int cull = 1;     // per-wave ellipse culling of tile-list entries
 };
 Options& options();
-int l1_loss_blocks(int64_t npix);
-// partial: l1_loss_blocks(npix) floats of scratch (only used when loss != nullptr)
-void launch_l1_loss(int64_t npix, const float* c, const float* d, const float* tc, const float* td,
-                    float w_depth, float* dl_dc, float* dl_dd, float* loss, float* partial, hipStream_t s);
 
 // decode.hip
 struct DecodeArgs {

@@ -137,22 +137,26 @@ __device__ __forceinline__ KeyOut key_path(float x, float y, float z, float s0, 
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_preprocess(int64_t n, const float* __restrict__ mean,
+__global__ void __launch_bounds__(256) k_preprocess(const ProjTab* __restrict__ tabp, const float* __restrict__ mean,
                                                     const float* __restrict__ scale, const float* __restrict__ quat,
                                                     const float* __restrict__ opac, const float* __restrict__ color,
-                                                    CamK cam, PoseK P, Splat* __restrict__ rec,
-                                                    uint32_t* __restrict__ depth_key, uint2* __restrict__ rect,
-                                                    uint32_t* __restrict__ count)
+                                                    Splat* __restrict__ rec, uint32_t* __restrict__ depth_key,
+                                                    uint2* __restrict__ rect, uint32_t* __restrict__ count)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
+    const ProjTab& tab = *tabp;
+    const int64_t n = tab.n;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * tab.n_views) return;
+    const int v = (int)(e / n);
+    const int64_t g = e - (int64_t)v * n;
+    const CamK& cam = tab.cam[v];
     const float o = opac[g];
     const KeyOut k = key_path(mean[g], mean[n + g], mean[2 * n + g], scale[g], scale[n + g], scale[2 * n + g],
-                              quat[g], quat[n + g], quat[2 * n + g], quat[3 * n + g], o, cam, P);
+                              quat[g], quat[n + g], quat[2 * n + g], quat[3 * n + g], o, cam, tab.pose[v]);
     if (!k.vis) {
-        depth_key[g] = 0xFFFFFFFFu;
-        count[g] = 0u;
-        rect[g] = make_uint2(0u, 0u);
+        depth_key[e] = 0xFFFFFFFFu;
+        count[e] = 0u;
+        rect[e] = make_uint2(0u, 0u);
         return;
     }
     // Eigen form of the inverse 2D covariance: d^T Sigma''^-1 d = p1^2 / lam + p2^2 / lmin with
@@ -169,19 +173,19 @@ __global__ void __launch_bounds__(256) k_preprocess(int64_t n, const float* __re
     sp.b = make_float4(ex, ey, kNegHalfLog2e / k.lam, kNegHalfLog2e / lmin);
     sp.c = make_float4(o, color[g], color[n + g], color[2 * n + g]);
     sp.d = make_float4(k.Z, 0.0f, 0.0f, 0.0f);
-    rec[g] = sp;
-    depth_key[g] = __float_as_uint(k.Z);
-    count[g] = (uint32_t)((k.tx1 - k.tx0 + 1) * (k.ty1 - k.ty0 + 1));
-    rect[g] = make_uint2((uint32_t)k.tx0 | ((uint32_t)k.ty0 << 16), (uint32_t)k.tx1 | ((uint32_t)k.ty1 << 16));
+    rec[e] = sp;
+    depth_key[e] = __float_as_uint(k.Z);
+    count[e] = (uint32_t)((k.tx1 - k.tx0 + 1) * (k.ty1 - k.ty0 + 1));
+    rect[e] = make_uint2((uint32_t)k.tx0 | ((uint32_t)k.ty0 << 16), (uint32_t)k.tx1 | ((uint32_t)k.ty1 << 16));
 }
 
-void launch_preprocess(int64_t n, const vcgs_gaussians& g, const CamK& cam, const PoseK& pose, Splat* rec,
+void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
                        uint32_t* depth_key, uint2* rect, uint32_t* count, hipStream_t s)
 {
-    if (n <= 0) return;
-    const int blocks = (int)((n + 255) / 256);
-    k_preprocess<<<blocks, 256, 0, s>>>(n, g.mean, g.scale, g.quat, g.opacity, g.color, cam, pose, rec,
-                                        depth_key, rect, count);
+    const int64_t total = t.n * t.n_views;
+    if (total <= 0) return;
+    k_preprocess<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(t_dev, g.mean, g.scale, g.quat, g.opacity, g.color, rec,
+                                                                 depth_key, rect, count);
 }
 
 // ---------------------------------------------------------------------------
@@ -194,29 +198,37 @@ void launch_preprocess(int64_t n, const vcgs_gaussians& g, const CamK& cam, cons
 constexpr int kBwdThreads = 256;
 
 __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
-    int64_t n, const float* __restrict__ mean, const float* __restrict__ scale, const float* __restrict__ quat,
-    CamK cam, PoseK P, const uint32_t* __restrict__ count, const float* __restrict__ g2,
+    const ProjTab* __restrict__ tabp, const float* __restrict__ mean, const float* __restrict__ scale,
+    const float* __restrict__ quat, const uint32_t* __restrict__ count, const float* __restrict__ g2,
     float* __restrict__ d_mean, float* __restrict__ d_scale, float* __restrict__ d_quat,
     float* __restrict__ d_opac, float* __restrict__ d_color, float* __restrict__ pose_partial)
 {
+    __shared__ float red[6][kBwdThreads];
+    const ProjTab& tab = *tabp;
+    const int64_t n = tab.n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // gradients summed over the views in view order
+    float dmu[3] = {0, 0, 0}, dsc[3] = {0, 0, 0}, dqt[4] = {0, 0, 0, 0}, dop = 0.0f, dcol[3] = {0, 0, 0};
+    for (int vw = 0; vw < tab.n_views; ++vw) {
+    const CamK& cam = tab.cam[vw];
+    const PoseK& P = tab.pose[vw];
+    const int64_t e = (int64_t)vw * n + g;
     float pose6[6] = {0, 0, 0, 0, 0, 0};
     if (g < n) {
-        const bool vis = count[g] != 0u;
+        const bool vis = count[e] != 0u;
         float gg[10];
         if (vis) {
-            const float4 a = *reinterpret_cast<const float4*>(g2 + kG2 * g);
-            const float4 b = *reinterpret_cast<const float4*>(g2 + kG2 * g + 4);
-            const float4 c = *reinterpret_cast<const float4*>(g2 + kG2 * g + 8);
+            const float4 a = *reinterpret_cast<const float4*>(g2 + kG2 * e);
+            const float4 b = *reinterpret_cast<const float4*>(g2 + kG2 * e + 4);
+            const float4 c = *reinterpret_cast<const float4*>(g2 + kG2 * e + 8);
             gg[0] = a.x; gg[1] = a.y; gg[2] = a.z; gg[3] = a.w; gg[4] = b.x;
             gg[5] = b.y; gg[6] = b.z; gg[7] = b.w; gg[8] = c.x; gg[9] = c.y;
         } else {
 #pragma unroll
             for (int i = 0; i < 10; ++i) gg[i] = 0.0f;
         }
-        if (d_opac) d_opac[g] = gg[5];
-        if (d_color) { d_color[g] = gg[6]; d_color[n + g] = gg[7]; d_color[2 * n + g] = gg[8]; }
-        float dmu[3] = {0, 0, 0}, dsc[3] = {0, 0, 0}, dqt[4] = {0, 0, 0, 0};
+        dop += gg[5];
+        dcol[0] += gg[6]; dcol[1] += gg[7]; dcol[2] += gg[8];
         if (vis) {
             const float x = mean[g], y = mean[n + g], z = mean[2 * n + g];
             const float X = P.R[0] * x + P.R[1] * y + P.R[2] * z + P.t[0];
@@ -318,7 +330,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
                 dpc[2] += dJ[5] * cam.fy * Y * iz2 * iz;
             }
 #pragma unroll
-            for (int i = 0; i < 3; ++i) dmu[i] = P.R[i] * dpc[0] + P.R[3 + i] * dpc[1] + P.R[6 + i] * dpc[2];
+            for (int i = 0; i < 3; ++i) dmu[i] += P.R[i] * dpc[0] + P.R[3 + i] * dpc[1] + P.R[6 + i] * dpc[2];
             // pose: camera-frame covariance Sc = W S W^T and its gradient Gc = J^T H J
             float WS[9], Sc[9], Gc[9];
 #pragma unroll
@@ -349,7 +361,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
                     dM[3 * i + j] = 2.0f * (dS[3 * i] * M[j] + dS[3 * i + 1] * M[3 + j] + dS[3 * i + 2] * M[6 + j]);
             float dr[9];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) dsc[j] = dM[j] * r[j] + dM[3 + j] * r[3 + j] + dM[6 + j] * r[6 + j];
+            for (int j = 0; j < 3; ++j) dsc[j] += dM[j] * r[j] + dM[3 + j] * r[3 + j] + dM[6 + j] * r[6 + j];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -362,18 +374,14 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
             if (qok) {
                 const float dot = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
                 const float iq = 1.0f / qn;
-                dqt[0] = (dq[0] - qw * dot) * iq;
-                dqt[1] = (dq[1] - qx * dot) * iq;
-                dqt[2] = (dq[2] - qy * dot) * iq;
-                dqt[3] = (dq[3] - qz * dot) * iq;
+                dqt[0] += (dq[0] - qw * dot) * iq;
+                dqt[1] += (dq[1] - qx * dot) * iq;
+                dqt[2] += (dq[2] - qy * dot) * iq;
+                dqt[3] += (dq[3] - qz * dot) * iq;
             }
         }
-        if (d_mean) { d_mean[g] = dmu[0]; d_mean[n + g] = dmu[1]; d_mean[2 * n + g] = dmu[2]; }
-        if (d_scale) { d_scale[g] = dsc[0]; d_scale[n + g] = dsc[1]; d_scale[2 * n + g] = dsc[2]; }
-        if (d_quat) { d_quat[g] = dqt[0]; d_quat[n + g] = dqt[1]; d_quat[2 * n + g] = dqt[2]; d_quat[3 * n + g] = dqt[3]; }
     }
-    // block reduction of the pose 6-vector, fixed order
-    __shared__ float red[6][kBwdThreads];
+    // block reduction of this view's pose 6-vector, fixed order
 #pragma unroll
     for (int i = 0; i < 6; ++i) red[i][threadIdx.x] = pose6[i];
     __syncthreads();
@@ -384,30 +392,39 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
         }
         __syncthreads();
     }
-    if (threadIdx.x < 6) pose_partial[6 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 6) pose_partial[((int64_t)vw * gridDim.x + blockIdx.x) * 6 + threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    }
+    if (g < n) {
+        if (d_opac) d_opac[g] = dop;
+        if (d_color) { d_color[g] = dcol[0]; d_color[n + g] = dcol[1]; d_color[2 * n + g] = dcol[2]; }
+        if (d_mean) { d_mean[g] = dmu[0]; d_mean[n + g] = dmu[1]; d_mean[2 * n + g] = dmu[2]; }
+        if (d_scale) { d_scale[g] = dsc[0]; d_scale[n + g] = dsc[1]; d_scale[2 * n + g] = dsc[2]; }
+        if (d_quat) { d_quat[g] = dqt[0]; d_quat[n + g] = dqt[1]; d_quat[2 * n + g] = dqt[2]; d_quat[3 * n + g] = dqt[3]; }
+    }
 }
 
 int preprocess_bwd_blocks(int64_t n) { return (int)((n + kBwdThreads - 1) / kBwdThreads); }
 
-void launch_preprocess_bwd(int64_t n, const vcgs_gaussians& g, const CamK& cam, const PoseK& pose,
-                           const uint32_t* count, const float* g2, const vcgs_gaussian_buffers& out,
-                           float* pose_partial, int pose_blocks, hipStream_t s)
+void launch_preprocess_bwd(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, const uint32_t* count,
+                           const float* g2, const vcgs_gaussian_buffers& out, float* pose_partial, int blocks,
+                           hipStream_t s)
 {
-    if (n <= 0) return;
-    k_preprocess_bwd<<<pose_blocks, kBwdThreads, 0, s>>>(n, g.mean, g.scale, g.quat, cam, pose, count, g2,
-                                                         out.mean, out.scale, out.quat, out.opacity, out.color,
-                                                         pose_partial);
+    if (t.n <= 0) return;
+    k_preprocess_bwd<<<blocks, kBwdThreads, 0, s>>>(t_dev, g.mean, g.scale, g.quat, count, g2, out.mean, out.scale,
+                                                    out.quat, out.opacity, out.color, pose_partial);
 }
 
-// Sum of the per-block pose partials in block order (one block, deterministic).
+// Sum of the per-block pose partials in block order, one block per view (deterministic).
 __global__ void __launch_bounds__(256) k_pose_reduce(const float* __restrict__ partial, int nblocks,
                                                      float* __restrict__ out)
 {
     __shared__ double acc[6][256];
+    const float* part = partial + (int64_t)blockIdx.x * nblocks * 6;
     double a[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblocks; b += 256)
 #pragma unroll
-        for (int i = 0; i < 6; ++i) a[i] += (double)partial[6 * b + i];
+        for (int i = 0; i < 6; ++i) a[i] += (double)part[6 * b + i];
 #pragma unroll
     for (int i = 0; i < 6; ++i) acc[i][threadIdx.x] = a[i];
     __syncthreads();
@@ -417,12 +434,13 @@ __global__ void __launch_bounds__(256) k_pose_reduce(const float* __restrict__ p
             for (int i = 0; i < 6; ++i) acc[i][threadIdx.x] += acc[i][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x < 6) out[threadIdx.x] = (float)acc[threadIdx.x][0];
+    if (threadIdx.x < 6) out[6 * blockIdx.x + threadIdx.x] = (float)acc[threadIdx.x][0];
 }
 
-void launch_pose_reduce(const float* partial, int nblocks, float* dl_dpose, hipStream_t s)
+void launch_pose_reduce(const float* partial, int n_views, int nblocks, float* dl_dpose, hipStream_t s)
 {
-    k_pose_reduce<<<1, 256, 0, s>>>(partial, nblocks, dl_dpose);
+    if (n_views <= 0) return;
+    k_pose_reduce<<<n_views, 256, 0, s>>>(partial, nblocks, dl_dpose);
 }
 
 }  // namespace vcgs

@@ -101,13 +101,19 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// View of a global tile id (views are laid out tile-major in id order).
+__device__ __forceinline__ int view_of(const ViewTab& tab, uint32_t t)
+{
+    int v = 0;
+    while (v + 1 < tab.n_views && t >= tab.tile_end[v]) ++v;
+    return v;
+}
+
 template <int PPL, bool COUNT>
-__global__ void __launch_bounds__(256) k_composite_fwd(CamK cam, const Splat* __restrict__ rec,
+__global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t total_tiles,
+                                                       const Splat* __restrict__ rec,
                                                        const uint32_t* __restrict__ gids,
-                                                       const uint32_t* __restrict__ ranges, float bg0, float bg1,
-                                                       float bg2, float* __restrict__ color, float* __restrict__ depth,
-                                                       float* __restrict__ alpha_out, float* __restrict__ t_final,
-                                                       uint32_t* __restrict__ n_contrib,
+                                                       const uint32_t* __restrict__ ranges,
                                                        unsigned long long* __restrict__ counters, int cull)
 {
     constexpr int WPT = 4 / PPL;     // waves per tile
@@ -115,9 +121,18 @@ __global__ void __launch_bounds__(256) k_composite_fwd(CamK cam, const Splat* __
     __shared__ float4 slab[4][64][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-    const int tile = gw / WPT, sub = gw % WPT;
-    const int n_tiles = cam.tiles_x * cam.tiles_y;
-    if (tile >= n_tiles) return;
+    const uint32_t gt = (uint32_t)(gw / WPT);
+    const int sub = gw % WPT;
+    if (gt >= total_tiles) return;
+    const int vw = view_of(tab, gt);
+    const CamK& cam = tab.cam[vw];
+    const int tile = (int)(gt - cam.tile_base);
+    float* __restrict__ color = tab.color[vw];
+    float* __restrict__ depth = tab.depth[vw];
+    float* __restrict__ alpha_out = tab.alpha[vw];
+    float* __restrict__ t_final = tab.t_final[vw];
+    uint32_t* __restrict__ n_contrib = tab.n_contrib[vw];
+    const float bg0 = tab.bg[0], bg1 = tab.bg[1], bg2 = tab.bg[2];
     uint32_t n_eval = 0, n_blend = 0;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * kTile + (lane & 15);
@@ -138,7 +153,6 @@ __global__ void __launch_bounds__(256) k_composite_fwd(CamK cam, const Splat* __
         last[j] = 0u;
     }
     const float pxf = (float)px + 0.5f;
-    const uint32_t gt = cam.tile_base + (uint32_t)tile;
     const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
     bool all_done = false;
     for (uint32_t b = start; b < end && !all_done; b += 64) {
@@ -245,13 +259,10 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 constexpr int kPend = 6;  // Gaussians whose row sums are gathered before one atomic flush
 
 template <int PPL, bool COUNT>
-__global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __restrict__ rec,
+__global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t total_tiles,
+                                                       const Splat* __restrict__ rec,
                                                        const uint32_t* __restrict__ gids,
-                                                       const uint32_t* __restrict__ ranges, float bg0, float bg1,
-                                                       float bg2, const float* __restrict__ t_final,
-                                                       const uint32_t* __restrict__ n_contrib,
-                                                       const float* __restrict__ dl_dc, const float* __restrict__ dl_dd,
-                                                       const float* __restrict__ dl_da, float* __restrict__ g2,
+                                                       const uint32_t* __restrict__ ranges, float* __restrict__ g2,
                                                        unsigned long long* __restrict__ counters, int cull)
 {
     constexpr int WPT = 4 / PPL;
@@ -263,9 +274,18 @@ __global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __
     __shared__ uint32_t pend_gid[4][kPend];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-    const int tile = gw / WPT, sub = gw % WPT;
-    const int n_tiles = cam.tiles_x * cam.tiles_y;
-    if (tile >= n_tiles) return;
+    const uint32_t gt = (uint32_t)(gw / WPT);
+    const int sub = gw % WPT;
+    if (gt >= total_tiles) return;
+    const int vw = view_of(tab, gt);
+    const CamK& cam = tab.cam[vw];
+    const int tile = (int)(gt - cam.tile_base);
+    const float* __restrict__ t_final = tab.t_final[vw];
+    const uint32_t* __restrict__ n_contrib = tab.n_contrib[vw];
+    const float* __restrict__ dl_dc = tab.dl_dc[vw];
+    const float* __restrict__ dl_dd = tab.dl_dd[vw];
+    const float* __restrict__ dl_da = tab.dl_da[vw];
+    const float bg0 = tab.bg[0], bg1 = tab.bg[1], bg2 = tab.bg[2];
     uint32_t n_eval = 0, n_blend = 0, n_flush = 0;
     int npend = 0;  // uniform
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -297,7 +317,6 @@ __global__ void __launch_bounds__(256) k_composite_bwd(CamK cam, const Splat* __
     const float pxf = (float)px + 0.5f;
     wl = wave_max_u32(wl);
     if (wl == 0u) return;  // uniform across the wave
-    const uint32_t gt = cam.tile_base + (uint32_t)tile;
     const uint32_t start = ranges[2 * gt];
     for (int bs = (int)((wl - 1u) & ~63u); bs >= 0; bs -= 64) {
         wave_lds_sync();
@@ -412,57 +431,45 @@ Options& options()
 }
 
 template <int PPL>
-static void fwd_launch(int blocks, hipStream_t s, const CamK& cam, const Splat* rec, const uint32_t* gids,
-                       const uint32_t* ranges, const float* bg, float* color, float* depth, float* alpha,
-                       float* t_final, uint32_t* n_contrib, unsigned long long* counters, int cull)
+static void fwd_launch(int blocks, hipStream_t s, const ViewTab& v, uint32_t total_tiles, const Splat* rec,
+                       const uint32_t* gids, const uint32_t* ranges, unsigned long long* counters, int cull)
 {
     if (counters)
-        k_composite_fwd<PPL, true><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], color, depth,
-                                                          alpha, t_final, n_contrib, counters, cull);
+        k_composite_fwd<PPL, true><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, counters, cull);
     else
-        k_composite_fwd<PPL, false><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], color, depth,
-                                                           alpha, t_final, n_contrib, nullptr, cull);
+        k_composite_fwd<PPL, false><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, nullptr, cull);
 }
 
 template <int PPL>
-static void bwd_launch(int blocks, hipStream_t s, const CamK& cam, const Splat* rec, const uint32_t* gids,
-                       const uint32_t* ranges, const float* bg, const float* t_final, const uint32_t* n_contrib,
-                       const float* dl_dc, const float* dl_dd, const float* dl_da, float* g2,
-                       unsigned long long* counters, int cull)
+static void bwd_launch(int blocks, hipStream_t s, const ViewTab& v, uint32_t total_tiles, const Splat* rec,
+                       const uint32_t* gids, const uint32_t* ranges, float* g2, unsigned long long* counters, int cull)
 {
     if (counters)
-        k_composite_bwd<PPL, true><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], t_final,
-                                                          n_contrib, dl_dc, dl_dd, dl_da, g2, counters, cull);
+        k_composite_bwd<PPL, true><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, g2, counters, cull);
     else
-        k_composite_bwd<PPL, false><<<blocks, 256, 0, s>>>(cam, rec, gids, ranges, bg[0], bg[1], bg[2], t_final,
-                                                           n_contrib, dl_dc, dl_dd, dl_da, g2, nullptr, cull);
+        k_composite_bwd<PPL, false><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, g2, nullptr, cull);
 }
 
-void launch_composite_fwd(const CamK& cam, const Splat* rec, const uint32_t* gids, const uint32_t* ranges,
-                          const float* bg, float* color, float* depth, float* alpha, float* t_final,
-                          uint32_t* n_contrib, unsigned long long* counters, hipStream_t s)
+void launch_composite_fwd(const ViewTab& v, uint32_t total_tiles, const Splat* rec, const uint32_t* gids,
+                          const uint32_t* ranges, unsigned long long* counters, hipStream_t s)
 {
-    const int n_tiles = cam.tiles_x * cam.tiles_y;
-    if (n_tiles <= 0) return;
+    if (total_tiles == 0) return;
     const int ppl = options().ppl_fwd, cull = options().cull;
-    const int blocks = (n_tiles * (4 / ppl) + 3) / 4;
-    if (ppl == 4) fwd_launch<4>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters, cull);
-    else if (ppl == 2) fwd_launch<2>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters, cull);
-    else fwd_launch<1>(blocks, s, cam, rec, gids, ranges, bg, color, depth, alpha, t_final, n_contrib, counters, cull);
+    const int blocks = (int)(((int64_t)total_tiles * (4 / ppl) + 3) / 4);
+    if (ppl == 4) fwd_launch<4>(blocks, s, v, total_tiles, rec, gids, ranges, counters, cull);
+    else if (ppl == 2) fwd_launch<2>(blocks, s, v, total_tiles, rec, gids, ranges, counters, cull);
+    else fwd_launch<1>(blocks, s, v, total_tiles, rec, gids, ranges, counters, cull);
 }
 
-void launch_composite_bwd(const CamK& cam, const Splat* rec, const uint32_t* gids, const uint32_t* ranges,
-                          const float* bg, const float* t_final, const uint32_t* n_contrib, const float* dl_dc,
-                          const float* dl_dd, const float* dl_da, float* g2, unsigned long long* counters,
-                          hipStream_t s)
+void launch_composite_bwd(const ViewTab& v, uint32_t total_tiles, const Splat* rec, const uint32_t* gids,
+                          const uint32_t* ranges, float* g2, unsigned long long* counters, hipStream_t s)
 {
-    const int n_tiles = cam.tiles_x * cam.tiles_y;
-    if (n_tiles <= 0) return;
+    if (total_tiles == 0) return;
     const int ppl = options().ppl_bwd, cull = options().cull;
-    const int blocks = (n_tiles * (4 / ppl) + 3) / 4;
-    if (ppl == 4) bwd_launch<4>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters, cull);
-    else if (ppl == 2) bwd_launch<2>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters, cull);
-    else bwd_launch<1>(blocks, s, cam, rec, gids, ranges, bg, t_final, n_contrib, dl_dc, dl_dd, dl_da, g2, counters, cull);
+    const int blocks = (int)(((int64_t)total_tiles * (4 / ppl) + 3) / 4);
+    if (ppl == 4) bwd_launch<4>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull);
+    else if (ppl == 2) bwd_launch<2>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull);
+    else bwd_launch<1>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull);
 }
 
 // L1 loss: L = mean_p (sum_c |C - C*| + w_depth |D - D*|).  Image gradients per

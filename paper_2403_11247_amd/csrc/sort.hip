@@ -40,9 +40,16 @@ __device__ __forceinline__ uint64_t match8(uint32_t d, uint64_t active)
 
 int radix_blocks(int64_t n) { return (int)((n + kBlockItems - 1) / kBlockItems) > 0 ? (int)((n + kBlockItems - 1) / kBlockItems) : 1; }
 
-__global__ void __launch_bounds__(kThreads) k_radix_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+__device__ __forceinline__ int64_t dev_count(int64_t cap, const uint32_t* dev)
+{
+    return dev ? min((int64_t)*dev, cap) : cap;
+}
+
+__global__ void __launch_bounds__(kThreads) k_radix_hist(const uint32_t* __restrict__ keys, int64_t cap,
+                                                         const uint32_t* __restrict__ ndev, int shift,
                                                          uint32_t* __restrict__ hist, int nb)
 {
+    const int64_t n = dev_count(cap, ndev);
     __shared__ uint32_t h[4][kBins];
     const int w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < 4 * kBins; i += kThreads) (&h[0][0])[i] = 0u;
@@ -66,9 +73,11 @@ __global__ void __launch_bounds__(kThreads) k_radix_hist(const uint32_t* __restr
 __global__ void __launch_bounds__(kThreads) k_radix_scatter(const uint32_t* __restrict__ keys_in,
                                                             const uint32_t* __restrict__ vals_in,
                                                             uint32_t* __restrict__ keys_out,
-                                                            uint32_t* __restrict__ vals_out, int64_t n, int shift,
+                                                            uint32_t* __restrict__ vals_out, int64_t cap,
+                                                            const uint32_t* __restrict__ ndev, int shift,
                                                             const uint32_t* __restrict__ offs, int nb)
 {
+    const int64_t n = dev_count(cap, ndev);
     __shared__ uint32_t cnt[4][kBins];
     const int w = threadIdx.x >> 6;
     const unsigned lane = __lane_id();
@@ -225,19 +234,19 @@ void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
     k_scan_down<<<(unsigned)nb, kThreads, 0, s>>>(in, out, n, sums, total);
 }
 
-int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, int64_t n, int end_bit, const SortTemp& t,
+int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
                    hipStream_t s)
 {
-    if (n <= 0) return 0;
-    const int nb = radix_blocks(n);
+    if (n.cap <= 0) return 0;
+    const int nb = radix_blocks(n.cap);
     uint32_t* kb[2] = {keys, t.keys_alt};
     uint32_t* vb[2] = {vals, t.vals_alt};
     int cur = 0;
     for (int shift = 0; shift < end_bit; shift += 8) {
-        k_radix_hist<<<nb, kThreads, 0, s>>>(kb[cur], n, shift, t.hist, nb);
+        k_radix_hist<<<nb, kThreads, 0, s>>>(kb[cur], n.cap, n.dev, shift, t.hist, nb);
         exclusive_scan_u32(t.hist, t.hist, (int64_t)kBins * nb, nullptr, t.scan_tmp, s);
         k_radix_scatter<<<nb, kThreads, 0, s>>>(kb[cur], identity_vals ? nullptr : vb[cur], kb[cur ^ 1], vb[cur ^ 1],
-                                                n, shift, t.hist, nb);
+                                                n.cap, n.dev, shift, t.hist, nb);
         identity_vals = false;
         cur ^= 1;
     }

@@ -85,7 +85,9 @@ def lib():
         L.vcgs_last_error.restype = ctypes.c_char_p
         L.vcgs_version.restype = ctypes.c_char_p
         for name in ("vcgs_create", "vcgs_render_forward", "vcgs_render_backward", "vcgs_state_query",
-                     "vcgs_l1_loss", "vcgs_decode_anchors", "vcgs_decode_anchors_backward"):
+                     "vcgs_l1_loss", "vcgs_decode_anchors", "vcgs_decode_anchors_backward", "vcgs_render_batch",
+                     "vcgs_batch_check", "vcgs_set_option", "vcgs_get_option", "vcgs_profile_enable",
+                     "vcgs_profile_read", "vcgs_count_enable", "vcgs_count_read"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -401,3 +403,80 @@ def get_option(name: str) -> int:
     v = c_i32()
     _check(lib().vcgs_get_option(c_i32(OPTIONS[name]), ctypes.byref(v)))
     return v.value
+
+
+class CViews(ctypes.Structure):
+    _fields_ = [("n_views", c_i32), ("cams", c_p), ("poses", c_p)]
+
+
+VCGS_E_CAPACITY = -3
+VCGS_BATCH_GRAPH = 1
+
+
+class BatchWindow:
+    """A set of up to 16 views of one Gaussian map rendered in one pass
+    (vcgs_render_batch), with persistent output buffers so that the library's
+    prepared plan -- and with ``graph=True`` its captured hipGraph -- is reused
+    across calls.  ``run`` takes new poses (and in-place-updated Gaussian values)
+    each call.  With targets given it also applies the L1 loss per view and
+    returns the summed Gaussian gradients and per-view pose gradients."""
+
+    def __init__(self, n, cameras, backward=True, graph=False, w_depth=0.5, bg=(0.0, 0.0, 0.0), ctx=None,
+                 device=None):
+        self.ctx = ctx or default_context()
+        self.dev = torch.device("cuda", self.ctx.device if device is None else device)
+        self.cameras = list(cameras)
+        self.V = len(self.cameras)
+        assert 1 <= self.V <= 16
+        self.n = int(n)
+        self.backward = backward
+        self.flags = VCGS_BATCH_GRAPH if graph else 0
+        self.w_depth = float(w_depth)
+        self.bg = (c_f * 3)(*[float(b) for b in bg])
+        self.outs = []
+        for c in self.cameras:
+            H, W = int(c.height), int(c.width)
+            self.outs.append((torch.empty((3, H, W), device=self.dev), torch.empty((H, W), device=self.dev),
+                              torch.empty((H, W), device=self.dev)))
+        self.c_outs = (CImages * self.V)(*[CImages(_ptr(o[0]), _ptr(o[1]), _ptr(o[2])) for o in self.outs])
+        self.c_cams = (CCamera * self.V)(*[camera_struct(c) for c in self.cameras])
+        if backward:
+            self.grads = {"mean": torch.empty((3, self.n), device=self.dev),
+                          "scale": torch.empty((3, self.n), device=self.dev),
+                          "quat": torch.empty((4, self.n), device=self.dev),
+                          "opacity": torch.empty(self.n, device=self.dev),
+                          "color": torch.empty((3, self.n), device=self.dev)}
+            self.dpose = torch.empty((self.V, 6), device=self.dev)
+            self.loss = torch.empty(self.V, device=self.dev)
+            self.c_grads = CGaussianBuffers(*[_ptr(self.grads[k]) for k in ("mean", "scale", "quat", "opacity",
+                                                                             "color")])
+        self.pairs = None
+
+    def run(self, means, scales, quats, opacities, colors, poses, targets=None):
+        """targets: list of (colour (3,H,W), depth (H,W)) per view when backward."""
+        g, keep = _gauss(means, scales, quats, opacities, colors)
+        assert g.n == self.n and len(poses) == self.V
+        views = CViews(self.V, ctypes.cast(self.c_cams, c_p),
+                       ctypes.cast((CPose * self.V)(*[pose_struct(p) for p in poses]), c_p))
+        self._views_keep = views
+        tc = td = None
+        if self.backward:
+            assert targets is not None and len(targets) == self.V
+            self._tkeep = [(_dev(t[0]), _dev(t[1])) for t in targets]
+            tc = (c_p * self.V)(*[_ptr(t[0]) for t in self._tkeep])
+            td = (c_p * self.V)(*[_ptr(t[1]) for t in self._tkeep])
+        for attempt in range(2):
+            _check(lib().vcgs_render_batch(
+                self.ctx.h, ctypes.byref(g), ctypes.byref(views), self.bg, tc, td, c_f(self.w_depth), self.c_outs,
+                ctypes.byref(self.c_grads) if self.backward else None,
+                _ptr(self.dpose) if self.backward else None, _ptr(self.loss) if self.backward else None,
+                c_i32(self.flags), _stream()))
+            pairs = c_i64()
+            rc = lib().vcgs_batch_check(self.ctx.h, ctypes.byref(pairs))
+            self.pairs = pairs.value
+            if rc == VCGS_E_CAPACITY and attempt == 0:
+                continue  # the library resized its pair buffers; run the pass again
+            _check(rc)
+            break
+        del keep
+        return self
