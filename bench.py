@@ -47,6 +47,13 @@ def parse():
     ap.add_argument("--stages", action="store_true", help="also print a per-stage table to stderr")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-ba", action="store_true", help="skip the 12-keyframe bundle-adjustment window")
+    ap.add_argument("--ba-steps", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving replay")
+    ap.add_argument("--serve-requests", type=int, default=400, help="requests per arrival rate")
+    ap.add_argument("--serve-qps", type=str, default="50,100,200,400")
+    ap.add_argument("--only", choices=("main", "ba", "serve"), default=None,
+                    help="run one section only (for profiling)")
     return ap.parse_args()
 
 
@@ -133,6 +140,145 @@ def cpu_baseline(budget_s):
                       f"adjoint single-threaded"}
 
 
+F = ("mean", "scale", "quat", "opacity", "color")
+
+
+def _up(x, dev, dt=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dev, dt or torch.float32)
+
+
+def _decoded_map(n_anchors, spacing, seed, dev):
+    """Room map decoded on the GPU (anchor decode kernel)."""
+    from paper_2403_11247_amd import scenes
+    from paper_2403_11247_amd.vcgs import decode_anchors
+    a = scenes.room_anchors(n_anchors, k=10, spacing=spacing, seed=seed)
+    m = scenes.room_mlp(seed=seed)
+    A = [_up(x, dev) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    G = decode_anchors(*A)
+    return [G[f] for f in F]
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def ba_section(args, dev):
+    """12 keyframes (4 x 320x240, 4 x 640x480, 4 x 1200x680) of a 500k-Gaussian
+    room, forward + L1 loss + backward to the Gaussians and the 12 poses: the
+    plain per-view loop against one batched pass, eager and as a replayed
+    hipGraph, with the compositing configuration chosen by the autotuner."""
+    import torch
+    from paper_2403_11247_amd import autotune, scenes, vcgs
+    gd = _decoded_map(50000, 0.05, 1, dev)
+    n = int(gd[3].shape[0])
+    cams, poses = scenes.ba_window(12)
+    tposes = [scenes.perturb_pose(p, 100 + i) for i, p in enumerate(poses)]
+    targets = []
+    for c, p in zip(cams, tposes):
+        C, D, _, _ = vcgs.render_forward(*gd, c, p, keep_state=False)
+        targets.append((C, D))
+    acc = {k: torch.zeros_like(t) for k, t in zip(F, gd)}
+    dposes = torch.empty((len(cams), 6), device=dev)
+
+    def plain():
+        for t in acc.values():
+            t.zero_()
+        for i, (c, p, tg) in enumerate(zip(cams, poses, targets)):
+            C, D, _, st = vcgs.render_forward(*gd, c, p)
+            _, dlc, dld = vcgs.l1_loss(C, D, tg[0], tg[1], 0.5)
+            gr, dp = vcgs.render_backward(st, *gd, c, p, dlc, dld, None)
+            for k in F:
+                acc[k].add_(gr[k])
+            dposes[i].copy_(dp)
+            st.free()
+
+    saved = autotune.current()
+    eager = vcgs.BatchWindow(n, cams, backward=True)
+    best, table = autotune.tune(eager, (*gd, poses, targets), reps=3)
+    graph = vcgs.BatchWindow(n, cams, backward=True, graph=True)
+    ms_plain = _timed(plain, args.ba_steps, 2)
+    ms_eager = _timed(lambda: eager.run(*gd, poses, targets), args.ba_steps, 2)
+    ms_graph = _timed(lambda: graph.run(*gd, poses, targets), args.ba_steps, 2)
+    # accuracy of the batched pass against the plain loop (same inputs)
+    plain()
+    graph.run(*gd, poses, targets)
+    torch.cuda.synchronize()
+
+    def rel(a, b):
+        return float((a - b).abs().max() / b.abs().max().clamp_min(1e-30))
+
+    g_err = max(rel(graph.grads[k], acc[k]) for k in F)
+    p_err = rel(graph.dpose, dposes)
+    worst = max(table, key=lambda kv: kv[1])[1] if table else None
+    autotune.apply(saved)
+    pix = sum(int(c.width) * int(c.height) for c in cams)
+    return {"workload": "room 50k anchors x 10 (500k Gaussians), 12 keyframes 4x320x240 + 4x640x480 + 4x1200x680 "
+                        "on a 1.5 m circle, fwd + L1 loss + bwd to Gaussians and 12 poses",
+            "gaussians": n, "pixels": pix, "pairs": graph.pairs,
+            "plain_ms": round(ms_plain, 3), "batch_eager_ms": round(ms_eager, 3), "batch_graph_ms": round(ms_graph, 3),
+            "speedup_graph_vs_plain": round(ms_plain / ms_graph, 2),
+            "speedup_eager_vs_plain": round(ms_plain / ms_eager, 2),
+            "batch_graph_mpix_s": round(pix / (ms_graph * 1e-3) / 1e6, 1),
+            "grad_rel_err_vs_plain": g_err, "pose_grad_rel_err_vs_plain": p_err,
+            "autotune": {"best": best, "candidates": len(table),
+                         "best_ms": round(min(t for _, t in table) * 1e3, 3) if table else None,
+                         "worst_ms": round(worst * 1e3, 3) if worst else None}}
+
+
+def serve_section(args, dev):
+    """Novel-view requests against a 1M-Gaussian room map (100k anchors at
+    2 cm): Poisson arrivals at each rate, sizes uniform over 320x240, 640x480,
+    1200x680 and 1920x1080, poses uniform in the room; continuous batching
+    against one-at-a-time plain rendering of the same trace."""
+    import torch
+    from paper_2403_11247_amd import scenes, serve, vcgs
+    gd = _decoded_map(100000, 0.02, 4, dev)
+    n = int(gd[3].shape[0])
+    # pairs-per-pixel estimate from a few plain renders
+    cal = scenes.serve_trace(8, qps=100.0, seed=99)
+    ppp = 0.0
+    for _, c, p in cal:
+        _, _, _, st = vcgs.render_forward(*gd, c, p)
+        ppp = max(ppp, st.view()["n_pairs"] / (c.width * c.height))
+        st.free()
+    torch.cuda.synchronize()
+    cfg = dict(max_views=16, slots=2, pair_budget=64 << 20, pairs_per_pixel=max(ppp * 1.25, 0.5))
+    srv = vcgs.Server(*gd, **cfg)
+    warm = scenes.serve_trace(32, qps=1e6, seed=98)
+    serve.replay(srv, warm)
+    serve.replay_plain(gd, warm[:8])
+    rates = []
+    for q in [float(x) for x in args.serve_qps.split(",") if x]:
+        tr = scenes.serve_trace(args.serve_requests, qps=q, seed=11)
+        r_b = serve.replay(srv, tr)
+        r_p = serve.replay_plain(gd, tr)
+        rates.append({"qps": q, "batched": r_b, "plain": r_p})
+        print(f"serve qps {q:g}: batched p50 {r_b['p50_ms']} p99 {r_b['p99_ms']} ms, "
+              f"plain p50 {r_p['p50_ms']} p99 {r_p['p99_ms']} ms", file=sys.stderr, flush=True)
+    tr = serve.saturate(scenes.serve_trace(args.serve_requests, qps=100.0, seed=12))
+    sat_b = serve.replay(srv, tr)
+    sat_p = serve.replay_plain(gd, tr)
+    srv.close()
+    return {"workload": "room 100k anchors x 10 at 2 cm (1M Gaussians), Poisson arrivals, sizes uniform over "
+                        "320x240/640x480/1200x680/1920x1080, poses uniform in the room, forward only",
+            "gaussians": n, "requests_per_rate": args.serve_requests,
+            "server": {k: cfg[k] for k in ("max_views", "slots", "pair_budget")},
+            "pairs_per_pixel_est": round(cfg["pairs_per_pixel"], 3),
+            "rates": rates,
+            "saturated": {"batched_mpix_s": sat_b["mpix_s"], "plain_mpix_s": sat_p["mpix_s"],
+                          "speedup": round(sat_b["mpix_s"] / max(sat_p["mpix_s"], 1e-9), 2),
+                          "views_per_pass": sat_b["views_per_pass"]}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -146,6 +292,12 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only in ("ba", "serve"):
+        res = ba_section(args, dev) if args.only == "ba" else serve_section(args, dev)
+        print(json.dumps({args.only: res}), flush=True)
+        return
+    if args.only == "main":
+        args.no_ba = args.no_serve = args.no_cpu_baseline = True
     a, m, cam, pose, tpose = room_inputs()
 
     def up(x, dt=torch.float32):
@@ -236,6 +388,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 2 * src.numel() * 4
+    if not args.no_ba:
+        out["ba_window"] = ba_section(args, dev)
+    if not args.no_serve:
+        out["serving"] = serve_section(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget_s)
     if args.stages:

@@ -208,6 +208,61 @@ int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* 
  * incomplete).  pairs (optional) receives the pass's pair count. */
 int vcgs_batch_check(vcgs_ctx* ctx, int64_t* pairs);
 
+/* ---- serving: continuous batching of novel-view requests --------------- */
+
+/* A server renders forward-only novel views of one HBM-resident map (the
+ * paper's rendering of a reconstructed scene from new poses, Sec. 3.1 eqs.
+ * (1)-(6)), batching the requests that are waiting into passes of up to
+ * max_views views.  It has `slots` passes in flight at once, each on its own
+ * stream (default priority) with its own buffers, so a pass that is admitted
+ * while others run overlaps with them on the device.
+ *
+ * Admission is by sort-buffer memory: each slot holds pair buffers of
+ * pair_budget (tile, Gaussian) pairs (16 bytes each plus the sort histograms);
+ * a request is estimated at pixels * pairs_per_pixel pairs and a pass takes
+ * waiting requests in arrival order while their estimates fit.  A pass whose
+ * actual pair count exceeds its buffers is run again (its slot grown to the
+ * count, the estimate raised); results never depend on the batching: every
+ * request's images equal those of vcgs_render_forward of it alone, bit for
+ * bit. */
+typedef struct vcgs_server vcgs_server;
+typedef struct {
+    int32_t max_views;      /* 1..16 */
+    int32_t slots;          /* passes in flight, 1..8 */
+    int64_t pair_budget;    /* pairs per slot, > 0 */
+    float pairs_per_pixel;  /* initial estimate, > 0 */
+    float bg[3];
+} vcgs_server_config;
+
+/* The map's attribute pointers are kept (not copied) and must stay valid and
+ * unchanged while the server lives.  Allocates all slot buffers up front
+ * (about 104 bytes per Gaussian per view of max_views, plus the pair buffers,
+ * per slot); VCGS_E_NOMEM if they do not fit. */
+int vcgs_server_create(vcgs_ctx* ctx, const vcgs_gaussians* map, const vcgs_server_config* cfg,
+                       vcgs_server** out);
+/* Waits for every pass in flight, then frees the server's buffers. */
+void vcgs_server_destroy(vcgs_server* srv);
+/* Queues one request.  out: device images of the camera's size, written when
+ * the request completes; they must stay valid until then.  The request's pass
+ * runs after the work enqueued on `stream` so far (e.g. the map upload or the
+ * last use of the output memory).  ticket receives the request's id (0, 1,
+ * 2, ... in submission order).  Does not launch work.  Requests still queued
+ * when the server is destroyed are dropped. */
+int vcgs_server_submit(vcgs_server* srv, const vcgs_camera* cam, const vcgs_pose* pose, const vcgs_images* out,
+                       int64_t* ticket, void* stream);
+/* Collects passes that finished (their tickets into done[0 .. *n_done), at most
+ * max_done; the rest are reported by later calls), then launches waiting
+ * requests into free slots.  If nothing finished and nothing was launched it
+ * polls again for up to timeout_us microseconds. */
+int vcgs_server_progress(vcgs_server* srv, int64_t timeout_us, int64_t* done, int32_t max_done, int32_t* n_done);
+/* Counters: requests queued, passes in flight, passes run, passes rerun after
+ * an overflow, current pairs-per-pixel estimate. */
+typedef struct {
+    int64_t queued, in_flight, passes, reruns;
+    float pairs_per_pixel;
+} vcgs_server_stats;
+int vcgs_server_stats_read(const vcgs_server* srv, vcgs_server_stats* out);
+
 /* ---- anchor decode ---------------------------------------------------- */
 
 /* Voxel anchors (paper Sec. 3.2): position x_a [3][na], feature f_a
@@ -283,9 +338,13 @@ int vcgs_decode_anchors_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcg
  *   VCGS_OPT_PPL_FWD / VCGS_OPT_PPL_BWD: pixels per lane of the forward /
  *     backward compositing, 1, 2 or 4 (a 16x16 tile is walked by 4, 2 or 1 waves);
  *   VCGS_OPT_CULL: 1 = skip, per wave, tile-list entries whose 1/255 ellipse
- *     misses the wave's pixels (results are identical either way), 0 = visit all.
+ *     misses the wave's pixels (results are identical either way), 0 = visit all;
+ *   VCGS_OPT_SCHED: order in which compositing blocks take tiles, 0 = linear,
+ *     1 = XCD-aware (each of the 8 XCDs gets a contiguous run of tiles, so that
+ *     neighbouring tiles share its L2); results are identical either way.
+ * A captured batch graph keeps the settings it was captured with.
  * Invalid keys or values return VCGS_E_INVALID and change nothing. */
-enum { VCGS_OPT_PPL_FWD = 1, VCGS_OPT_PPL_BWD = 2, VCGS_OPT_CULL = 3 };
+enum { VCGS_OPT_PPL_FWD = 1, VCGS_OPT_PPL_BWD = 2, VCGS_OPT_CULL = 3, VCGS_OPT_SCHED = 4 };
 int vcgs_set_option(int key, int value);
 int vcgs_get_option(int key, int* value);
 

@@ -165,6 +165,10 @@ int vcgs_set_option(int key, int value)
         if (value != 0 && value != 1) return fail(VCGS_E_INVALID, "cull must be 0 or 1");
         o.cull = value;
         return VCGS_OK;
+    case VCGS_OPT_SCHED:
+        if (value != 0 && value != 1) return fail(VCGS_E_INVALID, "sched must be 0 or 1");
+        o.sched = value;
+        return VCGS_OK;
     default:
         return fail(VCGS_E_INVALID, "unknown option");
     }
@@ -178,6 +182,7 @@ int vcgs_get_option(int key, int* value)
     case VCGS_OPT_PPL_FWD: *value = o.ppl_fwd; return VCGS_OK;
     case VCGS_OPT_PPL_BWD: *value = o.ppl_bwd; return VCGS_OK;
     case VCGS_OPT_CULL: *value = o.cull; return VCGS_OK;
+    case VCGS_OPT_SCHED: *value = o.sched; return VCGS_OK;
     default: return fail(VCGS_E_INVALID, "unknown option");
     }
 }

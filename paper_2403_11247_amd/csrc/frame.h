@@ -1,0 +1,79 @@
+// Shared pieces of the render orchestration: the per-call frame of view
+// tables and buffers, and the two halves of a forward pass.
+#pragma once
+
+#include "ctx.h"
+
+namespace vcgs {
+
+struct Frame {
+    int V = 0;
+    int64_t n = 0, E = 0;
+    ProjTab pt;
+    EmitTab et;
+    ViewTab vt;
+    uint32_t total_tiles = 0;
+    ProjTab* pt_dev = nullptr;
+    Splat* rec = nullptr;
+    uint32_t* depth_key = nullptr;
+    uint2* rect = nullptr;
+    uint32_t* count = nullptr;
+    uint32_t* ranges = nullptr;
+    uint32_t* gids = nullptr;
+    int64_t cap = 0;  // pair capacity (exact pair count in the synchronising path)
+};
+
+struct Work {
+    uint32_t *dk, *order, *kaltE, *valtE, *histE, *scanE, *cnt, *offs, *total, *overflow;
+    uint32_t *tile_ids, *kaltP, *valtP, *histP, *scanP;
+};
+
+int check_camera(const vcgs_camera* c);
+int check_gaussians(const vcgs_gaussians* g, int V);
+// Fills the projection, emission and compositing tables of V views (outputs,
+// final transmittance and upstream-gradient pointers of vt are left null).
+void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* poses, const float bg[3], Frame& f);
+// Projection, depth order of all entries, pair offsets; the pair count ends
+// up in w.total on the device.  Returns the depth order.
+const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s);
+// Pairs (at most f.cap, overflow flagged in w.overflow), stable tile sort,
+// tile ranges, forward compositing.
+void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s);
+
+// Significant bits of v (at least 1).
+inline int bits_for(uint32_t v)
+{
+    int b = 1;
+    while (b < 32 && (v >> b) != 0u) ++b;
+    return b;
+}
+
+// Allocation of the entry-sized work buffers through `get` (a pool or a plan).
+template <class Get>
+inline void alloc_work_e(Work& w, int64_t E, Get get)
+{
+    const int nb = radix_blocks(E);
+    w.dk = get(E);
+    w.order = get(E);
+    w.kaltE = get(E);
+    w.valtE = get(E);
+    w.histE = get((int64_t)256 * nb);
+    w.scanE = get(std::max(scan_temp_words((int64_t)256 * nb), scan_temp_words(E)) + 8);
+    w.cnt = get(E);
+    w.offs = get(E);
+    w.total = get(4);
+    w.overflow = get(4);
+}
+
+template <class Get>
+inline void alloc_work_p(Work& w, int64_t cap, Get get)
+{
+    const int nb = radix_blocks(cap);
+    w.tile_ids = get(cap);
+    w.kaltP = get(cap);
+    w.valtP = get(cap);
+    w.histP = get((int64_t)256 * nb);
+    w.scanP = get(scan_temp_words((int64_t)256 * nb) + 8);
+}
+
+}  // namespace vcgs

@@ -13,42 +13,13 @@
 // stable tile sort gives every tile of every view its own depth-ordered list.
 #include <cmath>
 
-#include "ctx.h"
+#include "frame.h"
 
 using namespace vcgs;
 
 namespace vcgs {
 
-static int bits_for(uint32_t v)
-{
-    int b = 1;
-    while (b < 32 && (v >> b) != 0u) ++b;
-    return b;
-}
-
-struct Frame {
-    int V = 0;
-    int64_t n = 0, E = 0;
-    ProjTab pt;
-    EmitTab et;
-    ViewTab vt;
-    uint32_t total_tiles = 0;
-    ProjTab* pt_dev = nullptr;
-    Splat* rec = nullptr;
-    uint32_t* depth_key = nullptr;
-    uint2* rect = nullptr;
-    uint32_t* count = nullptr;
-    uint32_t* ranges = nullptr;
-    uint32_t* gids = nullptr;
-    int64_t cap = 0;  // pair capacity (exact pair count in the synchronising path)
-};
-
-struct Work {
-    uint32_t *dk, *order, *kaltE, *valtE, *histE, *scanE, *cnt, *offs, *total, *overflow;
-    uint32_t *tile_ids, *kaltP, *valtP, *histP, *scanP;
-};
-
-static void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* poses, const float bg[3],
+void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* poses, const float bg[3],
                          Frame& f)
 {
     f.V = V;
@@ -74,39 +45,10 @@ static void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_p
     for (int i = 0; i < 3; ++i) f.vt.bg[i] = bg[i];
 }
 
-// Allocation of the entry-sized work buffers through `get` (a pool or a plan).
-template <class Get>
-static void alloc_work_e(Work& w, int64_t E, Get get)
-{
-    const int nb = radix_blocks(E);
-    w.dk = get(E);
-    w.order = get(E);
-    w.kaltE = get(E);
-    w.valtE = get(E);
-    w.histE = get((int64_t)256 * nb);
-    w.scanE = get(std::max(scan_temp_words((int64_t)256 * nb), scan_temp_words(E)) + 8);
-    w.cnt = get(E);
-    w.offs = get(E);
-    w.total = get(4);
-    w.overflow = get(4);
-}
-
-template <class Get>
-static void alloc_work_p(Work& w, int64_t cap, Get get)
-{
-    const int nb = radix_blocks(cap);
-    w.tile_ids = get(cap);
-    w.kaltP = get(cap);
-    w.valtP = get(cap);
-    w.histP = get((int64_t)256 * nb);
-    w.scanP = get(scan_temp_words((int64_t)256 * nb) + 8);
-}
-
 // Projection, depth order of all entries, pair offsets; the pair count ends
 // up in w.total on the device.  Returns the depth order.
-static const uint32_t* phase_a(vcgs_ctx* ctx, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s)
+const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s)
 {
-    Prof& pf = ctx->prof;
     pf.begin(VCGS_STAGE_PREPROCESS, s);
     launch_preprocess(f.pt, f.pt_dev, g, f.rec, f.depth_key, f.rect, f.count, s);
     pf.end(VCGS_STAGE_PREPROCESS, s);
@@ -124,9 +66,8 @@ static const uint32_t* phase_a(vcgs_ctx* ctx, const vcgs_gaussians& g, Frame& f,
 }
 
 // Pairs, stable tile sort, tile ranges, forward compositing.
-static void phase_b(vcgs_ctx* ctx, Frame& f, Work& w, const uint32_t* ord, hipStream_t s)
+void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s)
 {
-    Prof& pf = ctx->prof;
     launch_fill_u32(f.ranges, 0u, 2 * (int64_t)f.total_tiles, s);
     launch_fill_u32(w.overflow, 0u, 1, s);
     if (f.cap > 0) {
@@ -176,7 +117,7 @@ static void backward_core(vcgs_ctx* ctx, Frame& f, const vcgs_gaussians& g, cons
     pf.end(VCGS_STAGE_PREPROCESS_BWD, s);
 }
 
-static int check_camera(const vcgs_camera* c)
+int check_camera(const vcgs_camera* c)
 {
     if (!c) return fail(VCGS_E_INVALID, "camera is NULL");
     if (c->width <= 0 || c->height <= 0) return fail(VCGS_E_INVALID, "camera width/height must be positive");
@@ -186,7 +127,7 @@ static int check_camera(const vcgs_camera* c)
     return VCGS_OK;
 }
 
-static int check_gaussians(const vcgs_gaussians* g, int V)
+int check_gaussians(const vcgs_gaussians* g, int V)
 {
     if (!g) return fail(VCGS_E_INVALID, "gaussians is NULL");
     if (g->n < 0) return fail(VCGS_E_INVALID, "negative Gaussian count");
@@ -296,8 +237,8 @@ static void enqueue_plan(vcgs_ctx* ctx, BatchPlan& p, const vcgs_gaussians& g, c
                          const float* const* tc, const float* const* td, const vcgs_gaussian_buffers& gb,
                          float* dl_dpose, float* loss, hipStream_t s)
 {
-    const uint32_t* ord = phase_a(ctx, g, p.f, p.w, s);
-    phase_b(ctx, p.f, p.w, ord, s);
+    const uint32_t* ord = phase_a(ctx->prof, g, p.f, p.w, s);
+    phase_b(ctx->prof, p.f, p.w, ord, s);
     if (!p.backward) return;
     ctx->prof.begin(VCGS_STAGE_LOSS, s);
     for (int v = 0; v < p.V; ++v) {
@@ -415,7 +356,7 @@ int vcgs_render_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camer
         std::memcpy(ctx->host_tab, &f.pt, sizeof(ProjTab));
         if (hipMemcpyAsync(f.pt_dev, ctx->host_tab, sizeof(ProjTab), hipMemcpyHostToDevice, s) != hipSuccess)
             return drop(VCGS_E_HIP, "table upload failed");
-        const uint32_t* ord = f.E > 0 ? phase_a(ctx, *g, f, w, s) : nullptr;
+        const uint32_t* ord = f.E > 0 ? phase_a(ctx->prof, *g, f, w, s) : nullptr;
         if (f.E > 0) {
             if (hipMemcpyAsync(ctx->host_u32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
@@ -427,7 +368,7 @@ int vcgs_render_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camer
         f.gids = st->get<uint32_t>(f.cap);
         if (f.cap > 0) alloc_work_p(w, f.cap, [&](int64_t c) { return sc.get<uint32_t>(c); });
         if (!st->ok() || sc.oom) return drop(VCGS_E_NOMEM, "device allocation failed (pairs)");
-        phase_b(ctx, f, w, ord, s);
+        phase_b(ctx->prof, f, w, ord, s);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return drop(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     }
@@ -590,7 +531,7 @@ int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* 
     // size the pair buffers once (and again after an overflow was reported)
     if (f.cap == 0 || plan->need > f.cap) {
         plan->drop_graph();
-        const uint32_t* ord = phase_a(ctx, *g, f, plan->w, s);
+        const uint32_t* ord = phase_a(ctx->prof, *g, f, plan->w, s);
         (void)ord;
         HIP_TRY(hipMemcpyAsync(plan->host_flags, plan->w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));

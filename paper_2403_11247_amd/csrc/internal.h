@@ -149,6 +149,7 @@ struct Options {
     int ppl_fwd = 1;  // pixels per lane of the forward compositing (1, 2, 4)
     int ppl_bwd = 1;  // pixels per lane of the backward compositing (1, 2, 4)
     int cull = 1;     // per-wave ellipse culling of tile-list entries
+    int sched = 1;    // compositing block order: 0 linear, 1 XCD-aware (consecutive tiles on one XCD)
 };
 Options& options();
 

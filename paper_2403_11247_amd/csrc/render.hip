@@ -114,13 +114,13 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
                                                        const Splat* __restrict__ rec,
                                                        const uint32_t* __restrict__ gids,
                                                        const uint32_t* __restrict__ ranges,
-                                                       unsigned long long* __restrict__ counters, int cull)
+                                                       unsigned long long* __restrict__ counters, int cull, int sched)
 {
     constexpr int WPT = 4 / PPL;     // waves per tile
     constexpr int ROWS = 16 / WPT;   // rows per wave
     __shared__ float4 slab[4][64][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    const int gw = (sched ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + wave;
     const uint32_t gt = (uint32_t)(gw / WPT);
     const int sub = gw % WPT;
     if (gt >= total_tiles) return;
@@ -215,8 +215,10 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
             color[2 * HW + p] = c2[j] + T[j] * bg2;
             depth[p] = dd[j];
             alpha_out[p] = aa[j];
-            t_final[p] = T[j];
-            n_contrib[p] = last[j];
+            if (t_final) {  // null for forward-only callers
+                t_final[p] = T[j];
+                n_contrib[p] = last[j];
+            }
         }
     }
     if (COUNT) {
@@ -263,7 +265,7 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
                                                        const Splat* __restrict__ rec,
                                                        const uint32_t* __restrict__ gids,
                                                        const uint32_t* __restrict__ ranges, float* __restrict__ g2,
-                                                       unsigned long long* __restrict__ counters, int cull)
+                                                       unsigned long long* __restrict__ counters, int cull, int sched)
 {
     constexpr int WPT = 4 / PPL;
     constexpr int ROWS = 16 / WPT;
@@ -273,7 +275,7 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
     __shared__ float pend[4][kPend][4][10];
     __shared__ uint32_t pend_gid[4][kPend];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    const int gw = (sched ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + wave;
     const uint32_t gt = (uint32_t)(gw / WPT);
     const int sub = gw % WPT;
     if (gt >= total_tiles) return;
@@ -432,44 +434,48 @@ Options& options()
 
 template <int PPL>
 static void fwd_launch(int blocks, hipStream_t s, const ViewTab& v, uint32_t total_tiles, const Splat* rec,
-                       const uint32_t* gids, const uint32_t* ranges, unsigned long long* counters, int cull)
+                       const uint32_t* gids, const uint32_t* ranges, unsigned long long* counters, int cull,
+                       int sched)
 {
     if (counters)
-        k_composite_fwd<PPL, true><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, counters, cull);
+        k_composite_fwd<PPL, true><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, counters, cull, sched);
     else
-        k_composite_fwd<PPL, false><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, nullptr, cull);
+        k_composite_fwd<PPL, false><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, nullptr, cull, sched);
 }
 
 template <int PPL>
 static void bwd_launch(int blocks, hipStream_t s, const ViewTab& v, uint32_t total_tiles, const Splat* rec,
-                       const uint32_t* gids, const uint32_t* ranges, float* g2, unsigned long long* counters, int cull)
+                       const uint32_t* gids, const uint32_t* ranges, float* g2, unsigned long long* counters, int cull,
+                       int sched)
 {
     if (counters)
-        k_composite_bwd<PPL, true><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, g2, counters, cull);
+        k_composite_bwd<PPL, true><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, g2, counters, cull,
+                                                           sched);
     else
-        k_composite_bwd<PPL, false><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, g2, nullptr, cull);
+        k_composite_bwd<PPL, false><<<blocks, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, g2, nullptr, cull,
+                                                            sched);
 }
 
 void launch_composite_fwd(const ViewTab& v, uint32_t total_tiles, const Splat* rec, const uint32_t* gids,
                           const uint32_t* ranges, unsigned long long* counters, hipStream_t s)
 {
     if (total_tiles == 0) return;
-    const int ppl = options().ppl_fwd, cull = options().cull;
+    const int ppl = options().ppl_fwd, cull = options().cull, sched = options().sched;
     const int blocks = (int)(((int64_t)total_tiles * (4 / ppl) + 3) / 4);
-    if (ppl == 4) fwd_launch<4>(blocks, s, v, total_tiles, rec, gids, ranges, counters, cull);
-    else if (ppl == 2) fwd_launch<2>(blocks, s, v, total_tiles, rec, gids, ranges, counters, cull);
-    else fwd_launch<1>(blocks, s, v, total_tiles, rec, gids, ranges, counters, cull);
+    if (ppl == 4) fwd_launch<4>(blocks, s, v, total_tiles, rec, gids, ranges, counters, cull, sched);
+    else if (ppl == 2) fwd_launch<2>(blocks, s, v, total_tiles, rec, gids, ranges, counters, cull, sched);
+    else fwd_launch<1>(blocks, s, v, total_tiles, rec, gids, ranges, counters, cull, sched);
 }
 
 void launch_composite_bwd(const ViewTab& v, uint32_t total_tiles, const Splat* rec, const uint32_t* gids,
                           const uint32_t* ranges, float* g2, unsigned long long* counters, hipStream_t s)
 {
     if (total_tiles == 0) return;
-    const int ppl = options().ppl_bwd, cull = options().cull;
+    const int ppl = options().ppl_bwd, cull = options().cull, sched = options().sched;
     const int blocks = (int)(((int64_t)total_tiles * (4 / ppl) + 3) / 4);
-    if (ppl == 4) bwd_launch<4>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull);
-    else if (ppl == 2) bwd_launch<2>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull);
-    else bwd_launch<1>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull);
+    if (ppl == 4) bwd_launch<4>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull, sched);
+    else if (ppl == 2) bwd_launch<2>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull, sched);
+    else bwd_launch<1>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull, sched);
 }
 
 // L1 loss: L = mean_p (sum_c |C - C*| + w_depth |D - D*|).  Image gradients per

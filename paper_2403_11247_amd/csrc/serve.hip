@@ -1,0 +1,363 @@
+// Continuous-batching server for forward-only novel views of one resident
+// map.  Each slot is one pass in flight: its own stream, pinned staging and
+// buffers sized for max_views views of the map.  progress() retires finished
+// passes and packs waiting requests, in arrival order, into free slots while
+// their pair estimates fit the slot's sort buffers.  A pass is the same
+// projection / depth sort / tile sort / compositing as every other render
+// call, over the views of its requests (entry e = view e / n, Gaussian e % n),
+// so each request's images do not depend on what it was batched with.
+#include <chrono>
+#include <cmath>
+#include <deque>
+#include <sched.h>
+
+#include "frame.h"
+
+using namespace vcgs;
+
+namespace {
+
+struct Req {
+    int64_t ticket;
+    vcgs_camera cam;
+    vcgs_pose pose;
+    vcgs_images out;
+    int64_t pixels;
+    hipEvent_t submitted;  // recorded on the submitting stream; the pass waits for it
+};
+
+struct Slot {
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;
+    Frame f;
+    Work w{};
+    ProjTab* pt_host = nullptr;      // pinned
+    uint32_t* flags_host = nullptr;  // pinned: pair count, overflow
+    int64_t cap = 0;                 // pair capacity
+    int64_t tiles_cap = 0;           // capacity of f.ranges in tiles
+    std::vector<Req> reqs;
+    bool busy = false;
+    std::vector<void*> blocks_e, blocks_p, blocks_r;
+};
+
+Prof& quiet_prof()
+{
+    static Prof p;  // never enabled: passes of different streams are not timed
+    return p;
+}
+
+}  // namespace
+
+struct vcgs_server {
+    vcgs_ctx* ctx = nullptr;
+    vcgs_gaussians map{};
+    vcgs_server_config cfg{};
+    std::deque<Req> queue;
+    std::vector<Slot> slots;
+    std::deque<int64_t> ready;
+    int64_t next_ticket = 0, passes = 0, reruns = 0;
+    double ppp = 1.0;
+    bool oom = false;
+    std::vector<hipEvent_t> spare_events;
+
+    hipEvent_t event()
+    {
+        if (!spare_events.empty()) {
+            hipEvent_t e = spare_events.back();
+            spare_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        return e;
+    }
+
+    void* dalloc(size_t bytes, std::vector<void*>& list)
+    {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+            (void)hipGetLastError();
+            oom = true;
+            return nullptr;
+        }
+        list.push_back(p);
+        return p;
+    }
+    static void dfree(std::vector<void*>& list)
+    {
+        for (void* p : list) (void)hipFree(p);
+        list.clear();
+    }
+    // (Re)allocates a slot's pair buffers; the slot must be idle.  On failure
+    // the slot is left with no pair buffers (cap 0) and is not used again.
+    int alloc_pairs(Slot& sl, int64_t cap)
+    {
+        dfree(sl.blocks_p);
+        oom = false;
+        sl.f.gids = static_cast<uint32_t*>(dalloc((size_t)cap * 4, sl.blocks_p));
+        alloc_work_p(sl.w, cap, [&](int64_t c) { return static_cast<uint32_t*>(dalloc((size_t)c * 4, sl.blocks_p)); });
+        if (oom) {
+            dfree(sl.blocks_p);
+            sl.cap = 0;
+            return fail(VCGS_E_NOMEM, "server: pair buffers do not fit");
+        }
+        sl.cap = cap;
+        return VCGS_OK;
+    }
+    int alloc_ranges(Slot& sl, int64_t tiles)
+    {
+        dfree(sl.blocks_r);
+        oom = false;
+        sl.f.ranges = static_cast<uint32_t*>(dalloc((size_t)tiles * 8, sl.blocks_r));
+        if (oom) {
+            sl.tiles_cap = 0;
+            return fail(VCGS_E_NOMEM, "server: tile ranges do not fit");
+        }
+        sl.tiles_cap = tiles;
+        return VCGS_OK;
+    }
+    int64_t estimate(const Req& r) const { return (int64_t)std::ceil((double)r.pixels * ppp); }
+
+    // Takes waiting requests into the free slot sl and enqueues their pass; on
+    // an error the requests go back to the front of the queue.
+    int launch(Slot& sl)
+    {
+        const int rc = launch_inner(sl);
+        if (rc != VCGS_OK) {
+            for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it) queue.push_front(*it);
+            sl.reqs.clear();
+            sl.busy = false;
+        }
+        return rc;
+    }
+
+    int launch_inner(Slot& sl)
+    {
+        // admission: arrival order, while the pair estimates fit the slot's sort buffers
+        sl.reqs.clear();
+        int64_t est = 0, tiles = 0;
+        while (!queue.empty() && (int)sl.reqs.size() < cfg.max_views) {
+            const Req& r = queue.front();
+            const int64_t e = estimate(r);
+            if (!sl.reqs.empty() && est + e > sl.cap) break;
+            est += e;
+            tiles += (int64_t)((r.cam.width + kTile - 1) / kTile) * ((r.cam.height + kTile - 1) / kTile);
+            sl.reqs.push_back(r);
+            queue.pop_front();
+        }
+        const int V = (int)sl.reqs.size();
+        if (tiles > sl.tiles_cap) {
+            int rc = alloc_ranges(sl, tiles + tiles / 4);
+            if (rc != VCGS_OK) return rc;
+        }
+        vcgs_camera cams[kMaxViews];
+        vcgs_pose poses[kMaxViews];
+        for (int v = 0; v < V; ++v) {
+            cams[v] = sl.reqs[v].cam;
+            poses[v] = sl.reqs[v].pose;
+        }
+        Frame& f = sl.f;
+        build_tables(V, map.n, cams, poses, cfg.bg, f);
+        for (int v = 0; v < V; ++v) {
+            f.vt.color[v] = sl.reqs[v].out.color;
+            f.vt.depth[v] = sl.reqs[v].out.depth;
+            f.vt.alpha[v] = sl.reqs[v].out.alpha;
+        }
+        f.cap = sl.cap;
+        // order the pass after whatever each request's submitting stream had enqueued
+        for (const Req& r : sl.reqs) HIP_TRY(hipStreamWaitEvent(sl.s, r.submitted, 0));
+        // the slot is idle, so its previous table upload has completed
+        std::memcpy(sl.pt_host, &f.pt, sizeof(ProjTab));
+        HIP_TRY(hipMemcpyAsync(f.pt_dev, sl.pt_host, sizeof(ProjTab), hipMemcpyHostToDevice, sl.s));
+        if (f.E > 0) {
+            const uint32_t* ord = phase_a(quiet_prof(), map, f, sl.w, sl.s);
+            phase_b(quiet_prof(), f, sl.w, ord, sl.s);
+            HIP_TRY(hipMemcpyAsync(sl.flags_host, sl.w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, sl.s));
+            HIP_TRY(hipMemcpyAsync(sl.flags_host + 1, sl.w.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, sl.s));
+        } else {
+            f.cap = 0;
+            phase_b(quiet_prof(), f, sl.w, nullptr, sl.s);  // background images
+            sl.flags_host[0] = sl.flags_host[1] = 0u;
+        }
+        HIP_TRY(hipEventRecord(sl.done, sl.s));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("server: kernel launch failed: ") + hipGetErrorString(e));
+        sl.busy = true;
+        ++passes;
+        return VCGS_OK;
+    }
+
+    int finish(Slot& sl)
+    {
+        sl.busy = false;
+        const int64_t total = sl.flags_host[0];
+        if (sl.flags_host[1] != 0u) {
+            // overflow: grow the slot, raise the estimate, rerun these requests first
+            int64_t pix = 0;
+            for (const Req& r : sl.reqs) pix += r.pixels;
+            ppp = std::max(ppp, 1.125 * (double)total / (double)std::max<int64_t>(pix, 1));
+            ++reruns;
+            for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it) queue.push_front(*it);
+            sl.reqs.clear();
+            if (total > sl.cap) return alloc_pairs(sl, total + total / 8 + 4096);
+            return VCGS_OK;
+        }
+        for (const Req& r : sl.reqs) {
+            ready.push_back(r.ticket);
+            spare_events.push_back(r.submitted);
+        }
+        sl.reqs.clear();
+        return VCGS_OK;
+    }
+
+    void release()
+    {
+        for (Slot& sl : slots) {
+            if (sl.s) (void)hipStreamSynchronize(sl.s);
+            dfree(sl.blocks_e);
+            dfree(sl.blocks_p);
+            dfree(sl.blocks_r);
+            if (sl.pt_host) (void)hipHostFree(sl.pt_host);
+            if (sl.flags_host) (void)hipHostFree(sl.flags_host);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.s) (void)hipStreamDestroy(sl.s);
+        }
+        slots.clear();
+        for (const Req& r : queue) spare_events.push_back(r.submitted);
+        queue.clear();
+        for (hipEvent_t e : spare_events) (void)hipEventDestroy(e);
+        spare_events.clear();
+    }
+};
+
+extern "C" {
+
+int vcgs_server_create(vcgs_ctx* ctx, const vcgs_gaussians* map, const vcgs_server_config* cfg, vcgs_server** out)
+{
+    if (!ctx || !cfg || !out) return fail(VCGS_E_INVALID, "ctx, cfg or out is NULL");
+    *out = nullptr;
+    int rc;
+    if (cfg->max_views < 1 || cfg->max_views > kMaxViews) return fail(VCGS_E_INVALID, "max_views must be in [1, 16]");
+    if (cfg->slots < 1 || cfg->slots > 8) return fail(VCGS_E_INVALID, "slots must be in [1, 8]");
+    if (cfg->pair_budget <= 0 || !(cfg->pairs_per_pixel > 0.0f))
+        return fail(VCGS_E_INVALID, "pair_budget and pairs_per_pixel must be positive");
+    if ((rc = check_gaussians(map, cfg->max_views)) != VCGS_OK) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    vcgs_server* srv = new vcgs_server();
+    srv->ctx = ctx;
+    srv->map = *map;
+    srv->cfg = *cfg;
+    srv->ppp = cfg->pairs_per_pixel;
+    srv->slots.resize(cfg->slots);
+    const int64_t Emax = (int64_t)cfg->max_views * map->n;
+    for (Slot& sl : srv->slots) {
+        bool ok = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+                  hipHostMalloc((void**)&sl.pt_host, sizeof(ProjTab), hipHostMallocDefault) == hipSuccess &&
+                  hipHostMalloc((void**)&sl.flags_host, 16, hipHostMallocDefault) == hipSuccess;
+        if (!ok) {
+            srv->release();
+            delete srv;
+            return fail(VCGS_E_HIP, "server: stream, event or pinned allocation failed");
+        }
+        Frame& f = sl.f;
+        f.pt_dev = static_cast<ProjTab*>(srv->dalloc(sizeof(ProjTab), sl.blocks_e));
+        f.rec = static_cast<Splat*>(srv->dalloc((size_t)Emax * sizeof(Splat), sl.blocks_e));
+        f.depth_key = static_cast<uint32_t*>(srv->dalloc((size_t)Emax * 4, sl.blocks_e));
+        f.rect = static_cast<uint2*>(srv->dalloc((size_t)Emax * 8, sl.blocks_e));
+        f.count = static_cast<uint32_t*>(srv->dalloc((size_t)Emax * 4, sl.blocks_e));
+        alloc_work_e(sl.w, Emax, [&](int64_t c) { return static_cast<uint32_t*>(srv->dalloc((size_t)c * 4, sl.blocks_e)); });
+        if (srv->oom || srv->alloc_pairs(sl, cfg->pair_budget) != VCGS_OK || srv->alloc_ranges(sl, 4096) != VCGS_OK) {
+            srv->release();
+            delete srv;
+            return fail(VCGS_E_NOMEM, "server: slot buffers do not fit");
+        }
+    }
+    *out = srv;
+    return VCGS_OK;
+}
+
+void vcgs_server_destroy(vcgs_server* srv)
+{
+    if (!srv) return;
+    (void)hipSetDevice(srv->ctx->device);
+    srv->release();
+    delete srv;
+}
+
+int vcgs_server_submit(vcgs_server* srv, const vcgs_camera* cam, const vcgs_pose* pose, const vcgs_images* out,
+                       int64_t* ticket, void* stream)
+{
+    if (!srv || !pose || !out) return fail(VCGS_E_INVALID, "srv, pose or out is NULL");
+    int rc;
+    if ((rc = check_camera(cam)) != VCGS_OK) return rc;
+    if (!out->color || !out->depth || !out->alpha) return fail(VCGS_E_INVALID, "an output image is NULL");
+    Req r;
+    r.ticket = srv->next_ticket++;
+    r.cam = *cam;
+    r.pose = *pose;
+    r.out = *out;
+    r.pixels = (int64_t)cam->width * cam->height;
+    HIP_TRY(hipSetDevice(srv->ctx->device));
+    r.submitted = srv->event();
+    if (!r.submitted) return fail(VCGS_E_HIP, "server: event creation failed");
+    if (hipEventRecord(r.submitted, (hipStream_t)stream) != hipSuccess) {
+        srv->spare_events.push_back(r.submitted);
+        return fail(VCGS_E_HIP, "server: event record failed");
+    }
+    srv->queue.push_back(r);
+    if (ticket) *ticket = r.ticket;
+    return VCGS_OK;
+}
+
+int vcgs_server_progress(vcgs_server* srv, int64_t timeout_us, int64_t* done, int32_t max_done, int32_t* n_done)
+{
+    if (!srv || !n_done || (max_done > 0 && !done)) return fail(VCGS_E_INVALID, "srv, done or n_done is NULL");
+    *n_done = 0;
+    HIP_TRY(hipSetDevice(srv->ctx->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        bool moved = false;
+        for (Slot& sl : srv->slots) {
+            if (!sl.busy) continue;
+            const hipError_t q = hipEventQuery(sl.done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return fail(VCGS_E_HIP, std::string("server: pass failed: ") + hipGetErrorString(q));
+            int rc = srv->finish(sl);
+            if (rc != VCGS_OK) return rc;
+            moved = true;
+        }
+        for (Slot& sl : srv->slots) {
+            if (srv->queue.empty()) break;
+            if (sl.busy || sl.cap == 0) continue;  // cap 0: a failed resize retired the slot
+            int rc = srv->launch(sl);
+            if (rc != VCGS_OK) return rc;
+            moved = true;
+        }
+        bool usable = false;
+        for (const Slot& sl : srv->slots) usable = usable || sl.cap > 0;
+        if (!usable) return fail(VCGS_E_NOMEM, "server: no slot has pair buffers left");
+        while (!srv->ready.empty() && *n_done < max_done) {
+            done[(*n_done)++] = srv->ready.front();
+            srv->ready.pop_front();
+        }
+        if (moved || *n_done > 0) return VCGS_OK;
+        const auto us = std::chrono::duration_cast<std::chrono::microseconds>(std::chrono::steady_clock::now() - t0);
+        if (us.count() >= timeout_us) return VCGS_OK;
+        sched_yield();
+    }
+}
+
+int vcgs_server_stats_read(const vcgs_server* srv, vcgs_server_stats* out)
+{
+    if (!srv || !out) return fail(VCGS_E_INVALID, "srv or out is NULL");
+    out->queued = (int64_t)srv->queue.size();
+    out->in_flight = 0;
+    for (const Slot& sl : srv->slots) out->in_flight += sl.busy ? 1 : 0;
+    out->passes = srv->passes;
+    out->reruns = srv->reruns;
+    out->pairs_per_pixel = (float)srv->ppp;
+    return VCGS_OK;
+}
+
+}  // extern "C"

@@ -71,6 +71,16 @@ class CAnchorGrads(ctypes.Structure):
                 ("W2", c_p), ("b2", c_p), ("books", c_p), ("mask_logit", c_p)]
 
 
+class CServerConfig(ctypes.Structure):
+    _fields_ = [("max_views", c_i32), ("slots", c_i32), ("pair_budget", c_i64), ("pairs_per_pixel", c_f),
+                ("bg", c_f * 3)]
+
+
+class CServerStats(ctypes.Structure):
+    _fields_ = [("queued", c_i64), ("in_flight", c_i64), ("passes", c_i64), ("reruns", c_i64),
+                ("pairs_per_pixel", c_f)]
+
+
 class VcgsError(RuntimeError):
     pass
 
@@ -87,10 +97,12 @@ def lib():
         for name in ("vcgs_create", "vcgs_render_forward", "vcgs_render_backward", "vcgs_state_query",
                      "vcgs_l1_loss", "vcgs_decode_anchors", "vcgs_decode_anchors_backward", "vcgs_render_batch",
                      "vcgs_batch_check", "vcgs_set_option", "vcgs_get_option", "vcgs_profile_enable",
-                     "vcgs_profile_read", "vcgs_count_enable", "vcgs_count_read"):
+                     "vcgs_profile_read", "vcgs_count_enable", "vcgs_count_read", "vcgs_server_create",
+                     "vcgs_server_submit", "vcgs_server_progress", "vcgs_server_stats_read"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
+        L.vcgs_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -391,7 +403,7 @@ def count_read(ctx: Context | None = None) -> dict:
     return dict(zip(("fwd_evals", "fwd_blends", "bwd_evals", "bwd_blends", "bwd_flushes"), list(arr)))
 
 
-OPTIONS = {"ppl_fwd": 1, "ppl_bwd": 2, "cull": 3}
+OPTIONS = {"ppl_fwd": 1, "ppl_bwd": 2, "cull": 3, "sched": 4}
 
 
 def set_option(name: str, value: int):
@@ -480,3 +492,67 @@ class BatchWindow:
             break
         del keep
         return self
+
+
+class Server:
+    """Continuous-batching novel-view server over one resident map
+    (vcgs_server_*).  ``submit`` queues a request and returns its ticket and
+    its output images (allocated here, or passed in); ``progress`` retires
+    finished passes and launches waiting requests into free slots, returning the
+    tickets that completed."""
+
+    def __init__(self, means, scales, quats, opacities, colors, max_views=16, slots=2, pair_budget=1 << 25,
+                 pairs_per_pixel=4.0, bg=(0.0, 0.0, 0.0), ctx=None):
+        self.ctx = ctx or default_context()
+        self._g, self._keep = _gauss(means, scales, quats, opacities, colors)
+        self.dev = self._keep[0].device
+        cfg = CServerConfig(int(max_views), int(slots), int(pair_budget), float(pairs_per_pixel),
+                            (c_f * 3)(*[float(b) for b in bg]))
+        h = c_p()
+        _check(lib().vcgs_server_create(self.ctx.h, ctypes.byref(self._g), ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+        self._outs = {}
+        self._done = (c_i64 * 64)()
+
+    def submit(self, camera, pose, out=None):
+        H, W = int(camera.height), int(camera.width)
+        if out is None:
+            out = (torch.empty((3, H, W), device=self.dev), torch.empty((H, W), device=self.dev),
+                   torch.empty((H, W), device=self.dev))
+        imgs = CImages(_ptr(out[0]), _ptr(out[1]), _ptr(out[2]))
+        t = c_i64()
+        _check(lib().vcgs_server_submit(self.h, ctypes.byref(camera_struct(camera)), ctypes.byref(pose_struct(pose)),
+                                        ctypes.byref(imgs), ctypes.byref(t), _stream()))
+        self._outs[t.value] = out
+        return t.value, out
+
+    def progress(self, timeout_us=0):
+        """Tickets completed since the last call (their images are ready)."""
+        n = c_i32()
+        _check(lib().vcgs_server_progress(self.h, c_i64(int(timeout_us)), self._done, c_i32(64), ctypes.byref(n)))
+        out = [self._done[i] for i in range(n.value)]
+        for t in out:
+            self._outs.pop(t, None)
+        return out
+
+    def drain(self, timeout_us=100):
+        done = []
+        while self._outs:
+            done += self.progress(timeout_us)
+        return done
+
+    def stats(self):
+        st = CServerStats()
+        _check(lib().vcgs_server_stats_read(self.h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in CServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            lib().vcgs_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

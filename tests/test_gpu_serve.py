@@ -1,0 +1,107 @@
+"""Continuous-batching server (vcgs_server_*): every request's images are the
+same alone and in the mix (bit for bit: the pass gives each view its own
+depth-ordered tile lists and the same arithmetic), under admission limits that
+force several passes, overflow reruns and two passes in flight; one request is
+also checked against the oracle (1e-4 on unflagged pixels)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import raster
+from paper_2403_11247_amd import scenes
+from tests.gpu_common import FIELDS, compare_images, gauss_dev, say
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(160, 120), (320, 240), (96, 64), (200, 100), (33, 47)]
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_2403_11247_amd import vcgs
+    vcgs.lib()
+    return vcgs
+
+
+@pytest.fixture(scope="module")
+def room_map():
+    from oracle import decode as odec
+    a = scenes.room_anchors(5000, k=10, seed=3)
+    m = scenes.room_mlp(seed=3)
+    dec = odec.decode(a, m)
+    return scenes.Gaussians(*[dec[f].astype(np.float32) for f in FIELDS])
+
+
+def alone(V, gd, trace):
+    out = []
+    for _, cam, pose in trace:
+        C, D, A, _ = V.render_forward(*gd, cam, pose, keep_state=False)
+        out.append((C, D, A))
+    torch.cuda.synchronize()
+    return out
+
+
+def serve_all(V, gd, trace, **cfg):
+    srv = V.Server(*gd, **cfg)
+    tickets = []
+    for _, cam, pose in trace:
+        tickets.append(srv.submit(cam, pose))
+    done = srv.drain(timeout_us=200)
+    st = srv.stats()
+    srv.close()
+    assert sorted(done) == [t for t, _ in tickets]
+    return [o for _, o in tickets], st
+
+
+def assert_same(a, b, what):
+    for i, (x, y) in enumerate(zip(a, b)):
+        for k in range(3):
+            assert torch.equal(x[k], y[k]), (what, i, k)
+
+
+def test_mix_equals_alone(V, room_map):
+    gd = gauss_dev(room_map)
+    trace = scenes.serve_trace(14, qps=100.0, seed=21, sizes=SIZES)
+    ref = alone(V, gd, trace)
+    for cfg in (dict(max_views=16, slots=1), dict(max_views=5, slots=2), dict(max_views=1, slots=3)):
+        got, st = serve_all(V, gd, trace, pair_budget=1 << 22, pairs_per_pixel=4.0, **cfg)
+        say("serve", cfg, st)
+        assert_same(got, ref, cfg)
+
+
+def test_admission_limits_and_overflow_reruns(V, room_map):
+    gd = gauss_dev(room_map)
+    trace = scenes.serve_trace(10, qps=100.0, seed=22, sizes=SIZES)
+    ref = alone(V, gd, trace)
+    # an estimate far too low: passes overflow, slots grow, requests are rerun
+    got, st = serve_all(V, gd, trace, max_views=8, slots=2, pair_budget=5000, pairs_per_pixel=0.01)
+    say("overflow", st)
+    assert st["reruns"] >= 1 and st["pairs_per_pixel"] > 0.01
+    assert_same(got, ref, "overflow")
+    # a budget that admits one request per pass
+    got, st = serve_all(V, gd, trace, max_views=8, slots=2, pair_budget=1000, pairs_per_pixel=1e3)
+    assert st["passes"] - st["reruns"] == len(trace), st
+    assert_same(got, ref, "budget")
+
+
+def test_served_view_matches_oracle(V, room_map):
+    gd = gauss_dev(room_map)
+    trace = scenes.serve_trace(4, qps=100.0, seed=23, sizes=[(160, 120)])
+    got, _ = serve_all(V, gd, trace, max_views=4, slots=1, pair_budget=1 << 22)
+    for (_, cam, pose), (C, D, A) in zip(trace[:2], got[:2]):
+        r = compare_images(C, D, A, raster.render(room_map, cam, pose))
+        say("served vs oracle colour %.2e depth %.2e flagged %d" % (r["color"], r["depth"], r["flagged"]))
+        assert r["pass_"], r
+
+
+def test_empty_map_gives_background(V):
+    empty = [torch.empty((3, 0), device="cuda"), torch.empty((3, 0), device="cuda"),
+             torch.empty((4, 0), device="cuda"), torch.empty(0, device="cuda"), torch.empty((3, 0), device="cuda")]
+    srv = V.Server(*empty, max_views=4, slots=1, pair_budget=1024, bg=(0.25, 0.5, 1.0))
+    cam = scenes.Camera(40, 24, 30.0, 30.0, 20.0, 12.0)
+    t, (C, D, A) = srv.submit(cam, scenes.identity_pose())
+    srv.drain()
+    srv.close()
+    for ch, b in enumerate((0.25, 0.5, 1.0)):
+        assert torch.all(C[ch] == b)
+    assert torch.all(D == 0) and torch.all(A == 0)
