@@ -163,7 +163,9 @@ struct vcgs_server {
             f.vt.depth[v] = sl.reqs[v].out.depth;
             f.vt.alpha[v] = sl.reqs[v].out.alpha;
         }
-        f.cap = sl.cap;
+        // grids of the pair stages are sized from the capacity: use the pass's own
+        // estimate (with a margin) rather than the whole slot
+        f.cap = std::min<int64_t>(sl.cap, est + est / 4 + 4096);
         // order the pass after whatever each request's submitting stream had enqueued
         for (const Req& r : sl.reqs) HIP_TRY(hipStreamWaitEvent(sl.s, r.submitted, 0));
         // the slot is idle, so its previous table upload has completed
@@ -199,7 +201,7 @@ struct vcgs_server {
             ++reruns;
             for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it) queue.push_front(*it);
             sl.reqs.clear();
-            if (total > sl.cap) return alloc_pairs(sl, total + total / 8 + 4096);
+            if (total + total / 8 + 4096 > sl.cap) return alloc_pairs(sl, total + total / 8 + 4096);
             return VCGS_OK;
         }
         for (const Req& r : sl.reqs) {
