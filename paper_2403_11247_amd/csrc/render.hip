@@ -22,8 +22,9 @@
 // Backward: the same walk in reverse, from each pixel's final transmittance and
 // last contributor (saved by the forward), recovering T_i = T_{i+1} / (1 - alpha_i)
 // and the normalised colour behind i by acc <- alpha c + (1 - alpha) acc.  The ten
-// per-Gaussian partial derivatives are summed across the wave with DPP row
-// reductions and cross-row lane reads, then added with one atomic per value.
+// per-Gaussian partial derivatives are reduce-scattered over each 16-lane row
+// with DPP, parked in LDS for six Gaussians, and then summed over the four rows
+// and added to the Gaussian's gradient slot with one atomic per value.
 #include "internal.h"
 
 namespace vcgs {
@@ -61,28 +62,31 @@ __device__ __forceinline__ bool reaches_rect(const Splat& s, float x0, float x1,
     const float C = ey * ey * k1 + ex * ex * k2;
     const float thr = __log2f(255.0f * o) * 1.001f + 1e-3f;
     if (u >= x0 && u <= x1 && v >= y0 && v <= y1) return true;
+    // the edge minimisers need not be exact: any point of an edge bounds the
+    // minimum from above, and a 1-ulp error moves q far less than the margin
+    const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
     const float dx0 = x0 - u, dx1 = x1 - u, dy0 = y0 - v, dy1 = y1 - v;
     float best = 3.0e38f;
     // vertical edges: dx fixed, minimise over dy
     {
         const float dx = dx0;
-        const float dy = fminf(fmaxf(-B * dx / C, dy0), dy1);
+        const float dy = fminf(fmaxf(-B * dx * iC, dy0), dy1);
         best = fminf(best, A * dx * dx + 2.0f * B * dx * dy + C * dy * dy);
     }
     {
         const float dx = dx1;
-        const float dy = fminf(fmaxf(-B * dx / C, dy0), dy1);
+        const float dy = fminf(fmaxf(-B * dx * iC, dy0), dy1);
         best = fminf(best, A * dx * dx + 2.0f * B * dx * dy + C * dy * dy);
     }
     // horizontal edges: dy fixed, minimise over dx
     {
         const float dy = dy0;
-        const float dx = fminf(fmaxf(-B * dy / A, dx0), dx1);
+        const float dx = fminf(fmaxf(-B * dy * iA, dx0), dx1);
         best = fminf(best, A * dx * dx + 2.0f * B * dx * dy + C * dy * dy);
     }
     {
         const float dy = dy1;
-        const float dx = fminf(fmaxf(-B * dy / A, dx0), dx1);
+        const float dx = fminf(fmaxf(-B * dy * iA, dx0), dx1);
         best = fminf(best, A * dx * dx + 2.0f * B * dx * dy + C * dy * dy);
     }
     return best <= thr;
@@ -154,12 +158,31 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     }
     const float pxf = (float)px + 0.5f;
     const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
-    bool all_done = false;
-    for (uint32_t b = start; b < end && !all_done; b += 64) {
+    // One footprint blended front to back into pixel j; returns whether the
+    // pixel stopped on it.  Branch-free: a skipped or stopping Gaussian blends
+    // with weight zero, which leaves the sums unchanged.
+    auto blend = [&](int j, const Fp& f, const float4& rc, float rz, uint32_t idx, bool en) -> bool {
+        const bool ok = en && !done[j] && f.alpha >= kAlphaMin;
+        const float Tn = T[j] * (1.0f - f.alpha);
+        const bool stop = ok && Tn < kTMin;
+        const bool take = ok && !stop;
+        if (COUNT) { n_eval += (en && !done[j]) ? 1u : 0u; n_blend += take ? 1u : 0u; }
+        const float w = take ? f.alpha * T[j] : 0.0f;
+        c0[j] += w * rc.y; c1[j] += w * rc.z; c2[j] += w * rc.w;
+        dd[j] += w * rz; aa[j] += w;
+        T[j] = take ? Tn : T[j];
+        last[j] = take ? idx : last[j];
+        done[j] = done[j] || stop;
+        return stop;
+    };
+    bool all_done;
+    {
         bool mine = true;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) mine = mine && done[j];
-        if (__all(mine)) break;
+        all_done = __all(mine);  // e.g. rows below the image
+    }
+    for (uint32_t b = start; b < end && !all_done; b += 64) {
         wave_lds_sync();
         const uint32_t idx = b + lane;
         bool keep = false;
@@ -173,35 +196,33 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
         }
         uint64_t hits = __ballot(keep);
         wave_lds_sync();
+        const uint32_t base = b - start + 1u;
+        // two Gaussians per round: both footprints are independent, the blends are in order
         while (hits) {
-            const int k = __builtin_ctzll(hits);
+            const int k1 = __builtin_ctzll(hits);
             hits &= hits - 1ull;
-            const float4 ra = slab[wave][k][0], rb = slab[wave][k][1], rc = slab[wave][k][2];
-            const float rz = slab[wave][k][3].x;
-            const float dx = (pxf - ra.x) - ra.z;
-            bool lane_done = true;
+            const bool two = hits != 0ull;
+            const int k2 = two ? __builtin_ctzll(hits) : k1;
+            hits &= hits - 1ull;
+            const float4 a1 = slab[wave][k1][0], b1 = slab[wave][k1][1], r1 = slab[wave][k1][2];
+            const float z1 = slab[wave][k1][3].x;
+            const float4 a2 = slab[wave][k2][0], b2 = slab[wave][k2][1], r2 = slab[wave][k2][2];
+            const float z2 = slab[wave][k2][3].x;
+            const float dx1 = (pxf - a1.x) - a1.z, dx2 = (pxf - a2.x) - a2.z;
+            bool stopped = false;
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
-                if (!done[j]) {
-                    const Fp f = footprint(dx, (dy[j] - ra.y) - ra.w, rb.x, rb.y, rb.z, rb.w, rc.x);
-                    if (COUNT) ++n_eval;
-                    if (f.alpha >= kAlphaMin) {
-                        const float Tn = T[j] * (1.0f - f.alpha);
-                        if (Tn < kTMin) {
-                            done[j] = true;
-                        } else {
-                            if (COUNT) ++n_blend;
-                            const float w = f.alpha * T[j];
-                            c0[j] += w * rc.y; c1[j] += w * rc.z; c2[j] += w * rc.w;
-                            dd[j] += w * rz; aa[j] += w;
-                            T[j] = Tn;
-                            last[j] = b - start + (uint32_t)k + 1u;
-                        }
-                    }
-                }
-                lane_done = lane_done && done[j];
+                const Fp f1 = footprint(dx1, (dy[j] - a1.y) - a1.w, b1.x, b1.y, b1.z, b1.w, r1.x);
+                const Fp f2 = footprint(dx2, (dy[j] - a2.y) - a2.w, b2.x, b2.y, b2.z, b2.w, r2.x);
+                stopped = blend(j, f1, r1, z1, base + (uint32_t)k1, true) || stopped;
+                stopped = blend(j, f2, r2, z2, base + (uint32_t)k2, two) || stopped;
             }
-            if (__all(lane_done)) { all_done = true; break; }
+            if (__ballot(stopped) != 0ull) {
+                bool mine = true;
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) mine = mine && done[j];
+                if (__all(mine)) { all_done = true; break; }
+            }
         }
     }
     const int HW = cam.W * cam.H;
@@ -227,16 +248,6 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     }
 }
 
-// Sum over each 16-lane row, result in every lane of the row.
-__device__ __forceinline__ float row_sum(float v)
-{
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x124, 0xF, 0xF, false);  // row_ror:4
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x128, 0xF, 0xF, false);  // row_ror:8
-    return v;
-}
-
 // Sum over the 64 lanes, result in every lane.
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -256,6 +267,43 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
     return v;
+}
+
+// keep + (the partner lane's send) for a DPP partner pattern within 16-lane rows.
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float keep, float send)
+{
+    return keep + __builtin_amdgcn_update_dpp(0.0f, send, CTRL, 0xF, 0xF, true);
+}
+
+// Reduce-scatter of ten per-lane values over each 16-lane row.  Every step
+// pairs lanes that differ in one bit of the column c (c^8 by row_ror:8, then the
+// half-row mirror, then c^2, c^1); each lane keeps half of the values still
+// held, adds its partner's copy of that half and passes on the other half.
+// Afterwards the row sum of value rs_index(c) is in column c, for the ten
+// columns 0,1,2,4,5 (values 0-4) and 8,9,10,12,13 (values 5-9): 33 lane
+// operations instead of 40 for ten separate row sums, and no select chain.
+__device__ __forceinline__ float reduce_scatter10(const float p[10], int lane)
+{
+    const bool h3 = lane & 8, h2 = lane & 4, h1 = lane & 2, h0 = lane & 1;
+    float r[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) r[k] = dpp_add<0x128>(h3 ? p[k + 5] : p[k], h3 ? p[k] : p[k + 5]);
+    const float s0 = dpp_add<0x141>(h2 ? r[3] : r[0], h2 ? r[0] : r[3]);
+    const float s1 = dpp_add<0x141>(h2 ? r[4] : r[1], h2 ? r[1] : r[4]);
+    const float s2 = dpp_add<0x141>(h2 ? 0.0f : r[2], h2 ? r[2] : 0.0f);
+    const float t0 = dpp_add<0x4E>(h1 ? s2 : s0, h1 ? s0 : s2);
+    const float t1 = dpp_add<0x4E>(h1 ? 0.0f : s1, h1 ? s1 : 0.0f);
+    return dpp_add<0xB1>(h0 ? t1 : t0, h0 ? t0 : t1);
+}
+__device__ __forceinline__ bool rs_valid(int lane)
+{
+    const bool h2 = lane & 4, h1 = lane & 2, h0 = lane & 1;
+    return !((h2 && h1) || (!h2 && h1 && h0));
+}
+__device__ __forceinline__ int rs_index(int lane)
+{
+    return 5 * ((lane >> 3) & 1) + 3 * ((lane >> 2) & 1) + 2 * ((lane >> 1) & 1) + (lane & 1);
 }
 
 constexpr int kPend = 6;  // Gaussians whose row sums are gathered before one atomic flush
@@ -290,6 +338,8 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
     const float bg0 = tab.bg[0], bg1 = tab.bg[1], bg2 = tab.bg[2];
     uint32_t n_eval = 0, n_blend = 0, n_flush = 0;
     int npend = 0;  // uniform
+    const bool rsv = rs_valid(threadIdx.x & 63);
+    const int rsi = rs_index(threadIdx.x & 63);
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * kTile + (lane & 15);
     const int row0 = ty * kTile + sub * ROWS;
@@ -350,52 +400,44 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
             bool contrib = false;
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
-                if (local < last[j]) {
-                    const float dyj = (pyf[j] - ra.y) - ra.w;
-                    const Fp f = footprint(dx, dyj, rb.x, rb.y, rb.z, rb.w, rc.x);
-                    if (COUNT) ++n_eval;
-                    if (f.alpha >= kAlphaMin) {
-                        contrib = true;
-                        if (COUNT) ++n_blend;
-                        const float a = f.alpha;
-                        const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
-                        const float x[5] = {rc.y, rc.z, rc.w, rz, 1.0f};
-                        float dla = 0.0f;
+                // branch-free: every lane evaluates, only contributing pixels change state
+                const float dyj = (pyf[j] - ra.y) - ra.w;
+                const Fp f = footprint(dx, dyj, rb.x, rb.y, rb.z, rb.w, rc.x);
+                const bool in = local < last[j];
+                const bool c = in && f.alpha >= kAlphaMin;
+                if (COUNT) { n_eval += in ? 1u : 0u; n_blend += c ? 1u : 0u; }
+                const float a = f.alpha;
+                const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
+                const float x[5] = {rc.y, rc.z, rc.w, rz, 1.0f};
+                float dla = 0.0f;
 #pragma unroll
-                        for (int c = 0; c < 5; ++c) {
-                            dla += up[j][c] * (x[c] - acc[j][c]);
-                            acc[j][c] += a * (x[c] - acc[j][c]);
-                        }
-                        dla *= Ti;
-                        const float w = a * Ti;
-                        p[6] += w * up[j][0];
-                        p[7] += w * up[j][1];
-                        p[8] += w * up[j][2];
-                        p[9] += w * up[j][3];
-                        if (!f.clamped) {
-                            const float dp = dla * a;  // dL/dpower, power = -1/2 d^T Q d
-                            const float q1 = i1 * f.p1, q2 = i2 * f.p2;
-                            p[0] += dp * (q1 * rb.x - q2 * rb.y);   // d power / d u = (Q d)_x
-                            p[1] += dp * (q1 * rb.y + q2 * rb.x);   // d power / d v = (Q d)_y
-                            p[2] += dp * (-0.5f * dx * dx);
-                            p[3] += dp * (-dx * dyj);
-                            p[4] += dp * (-0.5f * dyj * dyj);
-                            p[5] += dla * f.G;
-                        }
-                        T[j] = Ti;
-                    }
+                for (int ch = 0; ch < 5; ++ch) {
+                    const float d = x[ch] - acc[j][ch];
+                    dla += up[j][ch] * d;
+                    const float an = acc[j][ch] + a * d;
+                    acc[j][ch] = c ? an : acc[j][ch];
                 }
+                dla *= Ti;
+                const float w = c ? a * Ti : 0.0f;
+                p[6] += w * up[j][0];
+                p[7] += w * up[j][1];
+                p[8] += w * up[j][2];
+                p[9] += w * up[j][3];
+                const bool g = c && !f.clamped;
+                const float dp = g ? dla * a : 0.0f;  // dL/dpower, power = -1/2 d^T Q d
+                const float q1 = i1 * f.p1, q2 = i2 * f.p2;
+                p[0] += dp * (q1 * rb.x - q2 * rb.y);   // d power / d u = (Q d)_x
+                p[1] += dp * (q1 * rb.y + q2 * rb.x);   // d power / d v = (Q d)_y
+                p[2] += dp * (-0.5f * dx * dx);
+                p[3] += dp * (-dx * dyj);
+                p[4] += dp * (-0.5f * dyj * dyj);
+                p[5] += g ? dla * f.G : 0.0f;
+                T[j] = c ? Ti : T[j];
+                contrib = contrib || c;
             }
             if (__ballot(contrib) == 0ull) continue;
-            // row sums; lane 16 r + v keeps row r's sum of value v
-            const int col = lane & 15;
-            float sel = row_sum(p[0]);
-#pragma unroll
-            for (int i = 1; i < 10; ++i) {
-                const float rs = row_sum(p[i]);
-                sel = (col == i) ? rs : sel;
-            }
-            if (col < 10) pend[wave][npend][lane >> 4][col] = sel;
+            const float rsum = reduce_scatter10(p, lane);
+            if (rsv) pend[wave][npend][lane >> 4][rsi] = rsum;
             if (lane == 0) pend_gid[wave][npend] = slab_gid[wave][k];
             ++npend;
             if (COUNT && lane == 0) ++n_flush;
