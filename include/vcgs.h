@@ -339,9 +339,11 @@ int vcgs_decode_anchors_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcg
  *     backward compositing, 1, 2 or 4 (a 16x16 tile is walked by 4, 2 or 1 waves);
  *   VCGS_OPT_CULL: 1 = skip, per wave, tile-list entries whose 1/255 ellipse
  *     misses the wave's pixels (results are identical either way), 0 = visit all;
- *   VCGS_OPT_SCHED: order in which compositing blocks take tiles, 0 = linear,
- *     1 = XCD-aware (each of the 8 XCDs gets a contiguous run of tiles, so that
- *     neighbouring tiles share its L2); results are identical either way.
+ *   VCGS_OPT_SCHED: order in which compositing blocks take tiles, 0 = linear
+ *     (default), 1 = XCD-aware (each of the 8 XCDs gets a contiguous run of
+ *     tiles, so that neighbouring tiles share its L2); results are identical
+ *     either way.
+ * Defaults: 1 pixel per lane both ways, culling on, linear order.
  * A captured batch graph keeps the settings it was captured with.
  * Invalid keys or values return VCGS_E_INVALID and change nothing. */
 enum { VCGS_OPT_PPL_FWD = 1, VCGS_OPT_PPL_BWD = 2, VCGS_OPT_CULL = 3, VCGS_OPT_SCHED = 4 };

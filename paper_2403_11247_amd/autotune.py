@@ -59,22 +59,20 @@ def _time(fn, reps):
     return ts[len(ts) // 2]
 
 
-def tune(win, run_args, reps=3, warmup=1, verbose=False):
-    """Pick the fastest option set for ``win`` (a vcgs.BatchWindow, normally
-    eager) running ``win.run(*run_args)``.  Returns (best config, table of
-    (config, seconds))."""
-    sig = signature(win)
+def tune_fn(fn, sig, backward=True, reps=3, warmup=1, verbose=False):
+    """Pick the fastest option set for an arbitrary pass ``fn`` (e.g. one plain
+    forward + backward step); ``sig`` names it in the cache."""
     if sig in _cache:
         apply(_cache[sig])
         return _cache[sig], []
     saved = current()
     table = []
     try:
-        for cfg in candidates(win.backward):
+        for cfg in candidates(backward):
             apply(cfg)
             for _ in range(warmup):
-                win.run(*run_args)
-            t = _time(lambda: win.run(*run_args), reps)
+                fn()
+            t = _time(fn, reps)
             table.append((dict(cfg), t))
             if verbose:
                 print(f"  {cfg} {t * 1e3:.3f} ms", flush=True)
@@ -84,6 +82,13 @@ def tune(win, run_args, reps=3, warmup=1, verbose=False):
     apply(best)
     _cache[sig] = best
     return best, table
+
+
+def tune(win, run_args, reps=3, warmup=1, verbose=False):
+    """Pick the fastest option set for ``win`` (a vcgs.BatchWindow, normally
+    eager) running ``win.run(*run_args)``.  Returns (best config, table of
+    (config, seconds)); the table is empty when the signature was cached."""
+    return tune_fn(lambda: win.run(*run_args), signature(win), win.backward, reps, warmup, verbose)
 
 
 def save(path):

@@ -46,77 +46,112 @@ void launch_copy_u32(uint32_t* dst, const uint32_t* src, Count n, hipStream_t s)
 }
 
 __global__ void __launch_bounds__(256) k_gather_counts(int64_t n, const uint32_t* __restrict__ order,
-                                                       const uint32_t* __restrict__ count, uint32_t* __restrict__ out)
+                                                       const uint32_t* __restrict__ count,
+                                                       const uint32_t* __restrict__ nvis, uint32_t* __restrict__ out)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) out[k] = count[order[k]];
+    const int64_t m = nvis ? min((int64_t)*nvis, n) : n;
+    if (k < n) out[k] = k < m ? count[order[k]] : 0u;
 }
 
-void launch_gather_counts(int64_t n, const uint32_t* order, const uint32_t* count, uint32_t* out, hipStream_t s)
+void launch_gather_counts(int64_t n, const uint32_t* order, const uint32_t* count, const uint32_t* nvis,
+                          uint32_t* out, hipStream_t s)
 {
     if (n <= 0) return;
-    k_gather_counts<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, order, count, out);
+    k_gather_counts<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, order, count, nvis, out);
 }
 
-// One block per 256 depth-ordered entries; its threads walk the block's
-// output range with a stride of 256 (coalesced stores) and locate the owning
-// entry of each position by binary search over the block's offsets.  Entry e
-// belongs to view e / n and its pairs carry that view's global tile ids.
+// Pair emission, balanced over the output: block c writes pairs
+// [c * kChunk, (c + 1) * kChunk).  k_chunk_starts records, for every chunk, the
+// depth-ordered entry that owns its first pair; the block then stages the
+// entries from there (offsets, Gaussian ids, rectangles) in LDS, and its
+// threads stride over the chunk's pairs (coalesced stores), locating each
+// pair's owner by binary search over the staged offsets.  Entry e belongs to
+// view e / n, and its pairs carry that view's global tile ids, row-major
+// within its rectangle.
 constexpr int kEmitG = 256;
+constexpr int kChunk = 2048;  // pairs per block
+constexpr int kSpan = 1024;   // entries staged at a time
 
-__global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_entries,
+__global__ void __launch_bounds__(256) k_chunk_starts(int64_t n_all, const uint32_t* __restrict__ nvis,
+                                                      const uint32_t* __restrict__ offs,
+                                                      const uint32_t* __restrict__ cnt, int64_t cap,
+                                                      uint32_t* __restrict__ chunk_start)
+{
+    const int64_t n = nvis ? min((int64_t)*nvis, n_all) : n_all;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t lo = offs[k], hi = min(lo + (int64_t)cnt[k], cap);
+    for (int64_t c = (lo + kChunk - 1) / kChunk; c * kChunk < hi; ++c) chunk_start[c] = (uint32_t)k;
+}
+
+__global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_all, const uint32_t* __restrict__ nvis,
                                                        const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ offs,
-                                                       const uint32_t* __restrict__ count,
-                                                       const uint2* __restrict__ rect, uint32_t* __restrict__ tile_ids,
-                                                       uint32_t* __restrict__ gids, int64_t cap,
-                                                       const uint32_t* __restrict__ total,
+                                                       const uint32_t* __restrict__ cnt,
+                                                       const uint2* __restrict__ rect,
+                                                       const uint32_t* __restrict__ chunk_start,
+                                                       uint32_t* __restrict__ tile_ids, uint32_t* __restrict__ gids,
+                                                       int64_t cap, const uint32_t* __restrict__ total,
                                                        uint32_t* __restrict__ overflow)
 {
-    __shared__ uint32_t s_off[kEmitG + 1];
-    __shared__ uint32_t s_gid[kEmitG];
-    __shared__ uint2 s_rect[kEmitG];
-    const int64_t k0 = (int64_t)blockIdx.x * kEmitG;
-    const int64_t k = k0 + threadIdx.x;
-    const int m = (int)((n_entries - k0) < kEmitG ? (n_entries - k0) : kEmitG);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && overflow && total && (int64_t)*total > cap) *overflow = 1u;
-    if (k < n_entries) {
-        const uint32_t g = order[k];
-        s_gid[threadIdx.x] = g;
-        s_rect[threadIdx.x] = rect[g];
-        s_off[threadIdx.x] = offs[k];
-        if ((int)threadIdx.x == m - 1) s_off[m] = offs[k] + count[g];
-    }
-    __syncthreads();
-    const uint32_t lo = s_off[0];
-    const uint32_t hi = (int64_t)s_off[m] < cap ? s_off[m] : (uint32_t)cap;
-    for (uint32_t p = lo + threadIdx.x; p < hi; p += kEmitG) {
-        // largest j in [0, m) with s_off[j] <= p
-        int a = 0, b = m - 1;
-        while (a < b) {
-            const int mid = (a + b + 1) >> 1;
-            if (s_off[mid] <= p) a = mid; else b = mid - 1;
+    __shared__ uint32_t s_off[kSpan + 1];
+    __shared__ uint32_t s_gid[kSpan];
+    __shared__ uint2 s_rect[kSpan];
+    const int64_t n = nvis ? min((int64_t)*nvis, n_all) : n_all;
+    const int64_t P = min((int64_t)*total, cap);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && overflow && (int64_t)*total > cap) *overflow = 1u;
+    const int64_t p0 = (int64_t)blockIdx.x * kChunk;
+    if (p0 >= P) return;  // uniform
+    const int64_t p1 = min(p0 + kChunk, P);
+    int64_t kbase = chunk_start[blockIdx.x];
+    int64_t pcur = p0;
+    while (pcur < p1 && kbase < n) {  // uniform; every round consumes kSpan entries or ends the chunk
+        const int S = (int)min((int64_t)kSpan, n - kbase);
+        for (int i = threadIdx.x; i < S; i += kEmitG) {
+            const uint32_t g = order[kbase + i];
+            s_gid[i] = g;
+            s_rect[i] = rect[g];
+            s_off[i] = offs[kbase + i];
+            if (i == S - 1) s_off[S] = offs[kbase + i] + cnt[kbase + i];
         }
-        const uint32_t e = s_gid[a];
-        const int v = (int)(e / (uint32_t)tab.n);
-        const uint2 r = s_rect[a];
-        const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu;
-        const uint32_t w = tx1 - tx0 + 1u;
-        const uint32_t local = p - s_off[a];
-        const uint32_t ty = ty0 + local / w, tx = tx0 + local % w;
-        tile_ids[p] = tab.tile_base[v] + ty * (uint32_t)tab.tiles_x[v] + tx;
-        gids[p] = e;
+        __syncthreads();
+        const int64_t pend = min(p1, (int64_t)s_off[S]);
+        for (int64_t p = pcur + threadIdx.x; p < pend; p += kEmitG) {
+            // largest j in [0, S) with s_off[j] <= p
+            int a = 0, b = S - 1;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if ((int64_t)s_off[mid] <= p) a = mid; else b = mid - 1;
+            }
+            const uint32_t e = s_gid[a];
+            const int v = (int)(e / (uint32_t)tab.n);
+            const uint2 r = s_rect[a];
+            const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu;
+            const uint32_t w = tx1 - tx0 + 1u;
+            const uint32_t local = (uint32_t)p - s_off[a];
+            const uint32_t ty = ty0 + local / w, tx = tx0 + local % w;
+            tile_ids[p] = tab.tile_base[v] + ty * (uint32_t)tab.tiles_x[v] + tx;
+            gids[p] = e;
+        }
+        __syncthreads();
+        pcur = pend;
+        kbase += S;
     }
 }
 
-void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* order, const uint32_t* offs,
-                       const uint32_t* count, const uint2* rect, uint32_t* tile_ids, uint32_t* gids, int64_t cap,
-                       const uint32_t* total, uint32_t* overflow, hipStream_t s)
+void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis, const uint32_t* order,
+                       const uint32_t* offs, const uint32_t* cnt, const uint2* rect, uint32_t* chunk_start,
+                       uint32_t* tile_ids, uint32_t* gids, int64_t cap, const uint32_t* total, uint32_t* overflow,
+                       hipStream_t s)
 {
-    if (n_entries <= 0) return;
-    k_emit_pairs<<<(unsigned)((n_entries + kEmitG - 1) / kEmitG), kEmitG, 0, s>>>(
-        t, n_entries, order, offs, count, rect, tile_ids, gids, cap, total, overflow);
+    if (n_entries <= 0 || cap <= 0) return;
+    k_chunk_starts<<<(unsigned)((n_entries + 255) / 256), 256, 0, s>>>(n_entries, nvis, offs, cnt, cap, chunk_start);
+    k_emit_pairs<<<(unsigned)((cap + kChunk - 1) / kChunk), kEmitG, 0, s>>>(
+        t, n_entries, nvis, order, offs, cnt, rect, chunk_start, tile_ids, gids, cap, total, overflow);
 }
+
+int64_t emit_chunk_words(int64_t cap) { return (cap + kChunk - 1) / kChunk + 1; }
 
 // [start, end) of every tile's run in the tile-sorted pair list (ranges must
 // be zero-filled beforehand so that empty tiles read [0, 0)).

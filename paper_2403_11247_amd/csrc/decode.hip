@@ -199,11 +199,14 @@ void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hi
 // ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
-constexpr int kBwdWaves = 2;
+constexpr int kBwdWaves = 4;
 constexpr int kBwdMaxBlocks = 256;
 
 // partial layout per block: dW2 [O][32] | db2 [O] | dW1 [32][32] | db1 [32]
 __host__ __device__ int64_t decode_bwd_partial_floats(int k) { return (int64_t)k * 11 * kF + k * 11 + kF * kF + kF; }
+
+// the per-wave y buffers of a block double as the block's reduction buffer
+static_assert(kBwdWaves * 16 * kLdsO >= kMaxO * kF + kMaxO + kF * kF + kF, "reduction buffer too small");
 
 int decode_bwd_blocks(int64_t na)
 {
@@ -215,10 +218,12 @@ template <int OT>
 __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcgs_gaussian_buffers dG,
                                                                vcgs_anchor_grads out, float* __restrict__ partial)
 {
-    // ys and dys share one buffer that also holds the block reduction at the end
-    __shared__ float smem[2][kBwdWaves][16][kLdsO];
-    float (*ys)[16][kLdsO] = smem[0];
-    float (*dys)[16][kLdsO] = smem[1];
+    // Each wave's [16 anchors][k * 11] outputs y are overwritten in place by
+    // dL/dy (every slot is read before it is written, by the same lane); the
+    // buffer also holds the block reduction at the end.
+    __shared__ float smem[kBwdWaves][16][kLdsO];
+    float (*ys)[16][kLdsO] = smem;
+    float (*dys)[16][kLdsO] = smem;
     __shared__ float hs[kBwdWaves][16][kF + 1];
     __shared__ float ps[kBwdWaves][16][kF + 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -441,7 +446,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
     }
     // block reduction in wave order, then one partial row per block
     __syncthreads();
-    float* red = &smem[0][0][0][0];  // 2 * kBwdWaves * 16 * kLdsO >= decode_bwd_partial_floats(16) floats
+    float* red = &smem[0][0][0];  // kBwdWaves * 16 * kLdsO >= decode_bwd_partial_floats(16) floats
     const int64_t PF = decode_bwd_partial_floats(a.k);
     for (int w = 0; w < kBwdWaves; ++w) {
         if (wave == w) {

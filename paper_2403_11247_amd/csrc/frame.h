@@ -25,7 +25,8 @@ struct Frame {
 
 struct Work {
     uint32_t *dk, *order, *kaltE, *valtE, *histE, *scanE, *cnt, *offs, *total, *overflow;
-    uint32_t *tile_ids, *kaltP, *valtP, *histP, *scanP;
+    uint32_t *tile_ids, *kaltP, *valtP, *histP, *scanP;  // scanP: emission chunk starts
+    const uint32_t* nvis;  // device count of entries in the depth order (culled ones are dropped)
 };
 
 int check_camera(const vcgs_camera* c);
@@ -52,13 +53,12 @@ inline int bits_for(uint32_t v)
 template <class Get>
 inline void alloc_work_e(Work& w, int64_t E, Get get)
 {
-    const int nb = radix_blocks(E);
     w.dk = get(E);
     w.order = get(E);
     w.kaltE = get(E);
     w.valtE = get(E);
-    w.histE = get((int64_t)256 * nb);
-    w.scanE = get(std::max(scan_temp_words((int64_t)256 * nb), scan_temp_words(E)) + 8);
+    w.histE = get(sort_temp_words(E));
+    w.scanE = get(scan_temp_words(E) + 8);
     w.cnt = get(E);
     w.offs = get(E);
     w.total = get(4);
@@ -68,12 +68,11 @@ inline void alloc_work_e(Work& w, int64_t E, Get get)
 template <class Get>
 inline void alloc_work_p(Work& w, int64_t cap, Get get)
 {
-    const int nb = radix_blocks(cap);
     w.tile_ids = get(cap);
     w.kaltP = get(cap);
     w.valtP = get(cap);
-    w.histP = get((int64_t)256 * nb);
-    w.scanP = get(scan_temp_words((int64_t)256 * nb) + 8);
+    w.histP = get(sort_temp_words(cap));
+    w.scanP = get(emit_chunk_words(cap));
 }
 
 }  // namespace vcgs

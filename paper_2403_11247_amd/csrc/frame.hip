@@ -53,13 +53,13 @@ const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hi
     launch_preprocess(f.pt, f.pt_dev, g, f.rec, f.depth_key, f.rect, f.count, s);
     pf.end(VCGS_STAGE_PREPROCESS, s);
     pf.begin(VCGS_STAGE_DEPTH_SORT, s);
-    launch_copy_u32(w.dk, f.depth_key, Count{f.E, nullptr}, s);
+    // culled entries carry the drop key and leave the depth order in its first pass
     const SortTemp t{w.kaltE, w.valtE, w.histE, w.scanE};
-    const int which = radix_sort_u32(w.dk, w.order, true, Count{f.E, nullptr}, 32, t, s);
+    const int which = radix_sort_u32(w.dk, w.order, true, Count{f.E, nullptr}, 32, t, s, &w.nvis, f.depth_key);
     pf.end(VCGS_STAGE_DEPTH_SORT, s);
     const uint32_t* ord = which ? w.valtE : w.order;
     pf.begin(VCGS_STAGE_PAIR_SCAN, s);
-    launch_gather_counts(f.E, ord, f.count, w.cnt, s);
+    launch_gather_counts(f.E, ord, f.count, w.nvis, w.cnt, s);
     exclusive_scan_u32(w.cnt, w.offs, f.E, w.total, w.scanE, s);
     pf.end(VCGS_STAGE_PAIR_SCAN, s);
     return ord;
@@ -73,7 +73,8 @@ void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s)
     if (f.cap > 0) {
         const Count P{f.cap, w.total};
         pf.begin(VCGS_STAGE_EMIT, s);
-        launch_emit_pairs(f.et, f.E, ord, w.offs, f.count, f.rect, w.tile_ids, f.gids, f.cap, w.total, w.overflow, s);
+        launch_emit_pairs(f.et, f.E, w.nvis, ord, w.offs, w.cnt, f.rect, w.scanP, w.tile_ids, f.gids, f.cap,
+                          w.total, w.overflow, s);
         pf.end(VCGS_STAGE_EMIT, s);
         pf.begin(VCGS_STAGE_TILE_SORT, s);
         const SortTemp tp{w.kaltP, w.valtP, w.histP, w.scanP};
@@ -131,7 +132,7 @@ int check_gaussians(const vcgs_gaussians* g, int V)
 {
     if (!g) return fail(VCGS_E_INVALID, "gaussians is NULL");
     if (g->n < 0) return fail(VCGS_E_INVALID, "negative Gaussian count");
-    if (g->n * std::max(V, 1) >= ((int64_t)1 << 31)) return fail(VCGS_E_UNSUPPORTED, "at most 2^31-1 Gaussian-view entries");
+    if (g->n * std::max(V, 1) > kMaxSortItems) return fail(VCGS_E_UNSUPPORTED, "at most 2^30-1 Gaussian-view entries");
     if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity || !g->color))
         return fail(VCGS_E_INVALID, "a Gaussian attribute pointer is NULL");
     return VCGS_OK;
@@ -152,7 +153,7 @@ struct BatchPlan {
     float w_depth = 0.5f;
     // buffers
     Frame f;
-    Work w;
+    Work w{};
     float* dlc[kMaxViews] = {};
     float* dld[kMaxViews] = {};
     float* loss_partial = nullptr;
@@ -348,7 +349,7 @@ int vcgs_render_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camer
     if (!st->ok()) return drop(VCGS_E_NOMEM, "device allocation failed (state)");
     {
         Scratch sc(&ctx->pool);
-        Work w;
+        Work w{};
         alloc_work_e(w, f.E, [&](int64_t c) { return sc.get<uint32_t>(c); });
         if (sc.oom) return drop(VCGS_E_NOMEM, "device allocation failed (depth sort)");
         // the table is read by the kernels from device memory; the stream is
@@ -363,6 +364,7 @@ int vcgs_render_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camer
                 return drop(VCGS_E_HIP, std::string("pair count readback failed: ") +
                                             hipGetErrorString(hipGetLastError()));
             st->P = ctx->host_u32[0];
+            if (st->P > kMaxSortItems) return drop(VCGS_E_UNSUPPORTED, "more than 2^30-1 (tile, Gaussian) pairs");
         }
         f.cap = st->P;
         f.gids = st->get<uint32_t>(f.cap);
@@ -536,8 +538,9 @@ int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* 
         HIP_TRY(hipMemcpyAsync(plan->host_flags, plan->w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const int64_t P = std::max<int64_t>(plan->host_flags[0], plan->need);
+        if (P > kMaxSortItems) return fail(VCGS_E_UNSUPPORTED, "more than 2^30-1 (tile, Gaussian) pairs");
         plan->release_p();
-        f.cap = std::max<int64_t>(P + P / 8 + 4096, 4096);
+        f.cap = std::min<int64_t>(std::max<int64_t>(P + P / 8 + 4096, 4096), kMaxSortItems);
         f.gids = plan->get_p<uint32_t>(f.cap);
         alloc_work_p(plan->w, f.cap, [&](int64_t c) { return plan->get_p<uint32_t>(c); });
         if (!plan->ok()) return fail(VCGS_E_NOMEM, "allocation failed (batch pairs)");

@@ -100,17 +100,25 @@ void launch_pose_reduce(const float* partial, int n_views, int nblocks, float* d
 struct SortTemp {
     uint32_t* keys_alt;
     uint32_t* vals_alt;
-    uint32_t* hist;     // >= 256 * radix_blocks(cap)
-    uint32_t* scan_tmp; // >= scan_temp_words(256 * radix_blocks(cap))
+    uint32_t* hist;     // >= sort_temp_words(cap): digit counts, partition counters, look-back state
+    uint32_t* scan_tmp; // unused by the sort
 };
+constexpr int64_t kMaxSortItems = (1ll << 30) - 1;
 int radix_blocks(int64_t n);
+int64_t sort_temp_words(int64_t cap);
 int64_t scan_temp_words(int64_t n);
-// Stable LSD radix sort of (keys, vals) on bits [0, end_bit).  With
+// Stable LSD radix sort of (keys, vals) on bits [0, end_bit), end_bit <= 32.  With
 // identity_vals the input values are 0..n-1 and `vals` is not read (it must
 // still hold cap entries).  Returns 0 if the result is in (keys, vals), 1 if
-// it is in (t.keys_alt, t.vals_alt).
+// it is in (t.keys_alt, t.vals_alt).  At most kMaxSortItems items (returns -1
+// and does nothing above that).
+// With kept != nullptr, items whose key is kDropKey are dropped (the others
+// keep their order) and *kept receives a device pointer to the number kept.
+// With keys_src, the first pass reads its keys from there (not modified) and
+// `keys` is only used as a buffer.
+constexpr uint32_t kDropKey = 0xFFFFFFFFu;
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
-                   hipStream_t s);
+                   hipStream_t s, const uint32_t** kept = nullptr, const uint32_t* keys_src = nullptr);
 // Exclusive scan of n uint32 values (out may equal in); if total != nullptr
 // the sum is written there.
 void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
@@ -123,11 +131,18 @@ struct EmitTab {
     int tiles_x[kMaxViews];
     uint32_t tile_base[kMaxViews];
 };
-void launch_gather_counts(int64_t n, const uint32_t* order, const uint32_t* count, uint32_t* out, hipStream_t s);
-// Writes pairs p < cap only; if the total exceeds cap sets *overflow = 1 (when non-null).
-void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* order, const uint32_t* offs,
-                       const uint32_t* count, const uint2* rect, uint32_t* tile_ids, uint32_t* gids, int64_t cap,
-                       const uint32_t* total, uint32_t* overflow, hipStream_t s);
+// out[k] = count[order[k]] for k < min(n, *nvis), 0 above (order is only read below *nvis).
+void launch_gather_counts(int64_t n, const uint32_t* order, const uint32_t* count, const uint32_t* nvis,
+                          uint32_t* out, hipStream_t s);
+// Entries k < min(n_entries, *nvis) of the depth order (offsets offs and
+// counts cnt in that order) emit their pairs; writes pairs p < cap only; if the
+// total exceeds cap sets *overflow = 1 (when non-null).  chunk_start: scratch
+// of emit_chunk_words(cap) words.
+void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis, const uint32_t* order,
+                       const uint32_t* offs, const uint32_t* cnt, const uint2* rect, uint32_t* chunk_start,
+                       uint32_t* tile_ids, uint32_t* gids, int64_t cap, const uint32_t* total, uint32_t* overflow,
+                       hipStream_t s);
+int64_t emit_chunk_words(int64_t cap);
 void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
@@ -149,7 +164,7 @@ struct Options {
     int ppl_fwd = 1;  // pixels per lane of the forward compositing (1, 2, 4)
     int ppl_bwd = 1;  // pixels per lane of the backward compositing (1, 2, 4)
     int cull = 1;     // per-wave ellipse culling of tile-list entries
-    int sched = 1;    // compositing block order: 0 linear, 1 XCD-aware (consecutive tiles on one XCD)
+    int sched = 0;    // compositing block order: 0 linear, 1 XCD-aware (consecutive tiles on one XCD)
 };
 Options& options();
 

@@ -201,7 +201,9 @@ struct vcgs_server {
             ++reruns;
             for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it) queue.push_front(*it);
             sl.reqs.clear();
-            if (total + total / 8 + 4096 > sl.cap) return alloc_pairs(sl, total + total / 8 + 4096);
+            if (total > kMaxSortItems) return fail(VCGS_E_UNSUPPORTED, "server: a pass needs more than 2^30-1 pairs");
+            if (total + total / 8 + 4096 > sl.cap)
+                return alloc_pairs(sl, std::min<int64_t>(total + total / 8 + 4096, kMaxSortItems));
             return VCGS_OK;
         }
         for (const Req& r : sl.reqs) {
@@ -243,6 +245,7 @@ int vcgs_server_create(vcgs_ctx* ctx, const vcgs_gaussians* map, const vcgs_serv
     if (cfg->slots < 1 || cfg->slots > 8) return fail(VCGS_E_INVALID, "slots must be in [1, 8]");
     if (cfg->pair_budget <= 0 || !(cfg->pairs_per_pixel > 0.0f))
         return fail(VCGS_E_INVALID, "pair_budget and pairs_per_pixel must be positive");
+    if (cfg->pair_budget > kMaxSortItems) return fail(VCGS_E_UNSUPPORTED, "pair_budget above 2^30-1");
     if ((rc = check_gaussians(map, cfg->max_views)) != VCGS_OK) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     vcgs_server* srv = new vcgs_server();

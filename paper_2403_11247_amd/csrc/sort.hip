@@ -1,14 +1,19 @@
 // Stable LSD radix sort of (uint32 key, uint32 value) pairs and a device-wide
 // exclusive scan, written for wave64.
 //
-// Radix pass (8-bit digit), reduce-then-scan:
-//   1. histogram: per 4096-item block, digit counts (lanes with equal digits are
-//      grouped by 8 ballots so one lane adds each group's count; no LDS atomics);
-//      written digit-major, hist[d * nblocks + b];
-//   2. exclusive scan of hist -> global offset of (digit d, block b);
-//   3. scatter: each wave owns 1024 consecutive items of its block and ranks
-//      them in order, 64 at a time, against its own per-digit counters, so
-//      equal digits keep their input order (stable).
+// Sort: one launch per 8-bit digit pass (single sweep), after one histogram
+// launch for all passes:
+//   1. histogram: every digit of every pass counted over the whole input;
+//   2. per pass, each block takes the next 4096-item partition (the partition
+//      number comes from an atomic counter, so every lower partition is already
+//      running), ranks its items stably (each wave walks its 1024 items in
+//      order, 64 at a time, grouping equal digits with 8 ballots), publishes its
+//      digit counts, and looks back over the published counts of the lower
+//      partitions for its global offsets (decoupled look-back: a partition
+//      publishes its own counts before it waits on anyone, so the wait always
+//      ends); items are then staged in LDS in digit order and written out so
+//      that consecutive threads write consecutive addresses of a digit's run.
+#include "internal.h"
 #include "internal.h"
 
 namespace vcgs {
@@ -43,93 +48,6 @@ int radix_blocks(int64_t n) { return (int)((n + kBlockItems - 1) / kBlockItems) 
 __device__ __forceinline__ int64_t dev_count(int64_t cap, const uint32_t* dev)
 {
     return dev ? min((int64_t)*dev, cap) : cap;
-}
-
-__global__ void __launch_bounds__(kThreads) k_radix_hist(const uint32_t* __restrict__ keys, int64_t cap,
-                                                         const uint32_t* __restrict__ ndev, int shift,
-                                                         uint32_t* __restrict__ hist, int nb)
-{
-    const int64_t n = dev_count(cap, ndev);
-    __shared__ uint32_t h[4][kBins];
-    const int w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < 4 * kBins; i += kThreads) (&h[0][0])[i] = 0u;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kBlockItems + (int64_t)w * kWaveItems;
-#pragma unroll 4
-    for (int r = 0; r < kWaveItems / 64; ++r) {
-        const int64_t idx = base + r * 64 + __lane_id();
-        const bool valid = idx < n;
-        const uint32_t d = valid ? (keys[idx] >> shift) & 0xFFu : 0u;
-        const uint64_t active = __ballot(valid);
-        if (active == 0ull) break;
-        const uint64_t m = match8(d, active);
-        if (valid && (m & lanemask_lt()) == 0ull) h[w][d] += (uint32_t)__popcll(m);
-    }
-    __syncthreads();
-    const uint32_t c = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] + h[3][threadIdx.x];
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = c;
-}
-
-__global__ void __launch_bounds__(kThreads) k_radix_scatter(const uint32_t* __restrict__ keys_in,
-                                                            const uint32_t* __restrict__ vals_in,
-                                                            uint32_t* __restrict__ keys_out,
-                                                            uint32_t* __restrict__ vals_out, int64_t cap,
-                                                            const uint32_t* __restrict__ ndev, int shift,
-                                                            const uint32_t* __restrict__ offs, int nb)
-{
-    const int64_t n = dev_count(cap, ndev);
-    __shared__ uint32_t cnt[4][kBins];
-    const int w = threadIdx.x >> 6;
-    const unsigned lane = __lane_id();
-    for (int i = threadIdx.x; i < 4 * kBins; i += kThreads) (&cnt[0][0])[i] = 0u;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kBlockItems + (int64_t)w * kWaveItems;
-    uint32_t key[kItems], val[kItems];
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t idx = base + r * 64 + lane;
-        key[r] = idx < n ? keys_in[idx] : 0u;
-        val[r] = idx < n ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
-    }
-    const uint64_t lt = lanemask_lt();
-    // per-wave digit histogram
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const bool valid = base + r * 64 + lane < n;
-        const uint64_t active = __ballot(valid);
-        if (active == 0ull) continue;
-        const uint32_t d = (key[r] >> shift) & 0xFFu;
-        const uint64_t m = match8(d, active);
-        if (valid && (m & lt) == 0ull) cnt[w][d] += (uint32_t)__popcll(m);
-    }
-    __syncthreads();
-    {
-        const int d = threadIdx.x;
-        uint32_t run = offs[(int64_t)d * nb + blockIdx.x];
-#pragma unroll
-        for (int ww = 0; ww < 4; ++ww) {
-            const uint32_t c = cnt[ww][d];
-            cnt[ww][d] = run;
-            run += c;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const bool valid = base + r * 64 + lane < n;
-        const uint64_t active = __ballot(valid);
-        if (active == 0ull) continue;
-        const uint32_t d = (key[r] >> shift) & 0xFFu;
-        const uint64_t m = match8(d, active);
-        uint32_t pos = 0;
-        if (valid) pos = cnt[w][d];
-        const uint32_t rank = (uint32_t)__popcll(m & lt);
-        if (valid && rank == 0u) cnt[w][d] = pos + (uint32_t)__popcll(m);
-        if (valid) {
-            keys_out[pos + rank] = key[r];
-            vals_out[pos + rank] = val[r];
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -234,22 +152,208 @@ void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
     k_scan_down<<<(unsigned)nb, kThreads, 0, s>>>(in, out, n, sums, total);
 }
 
-int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
-                   hipStream_t s)
+// ---------------------------------------------------------------------------
+// Single-sweep radix sort
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kFlagAgg = 1u << 30;       // partition's own digit count published
+constexpr uint32_t kFlagInc = 2u << 30;       // count including all lower partitions
+constexpr uint32_t kCountMask = kFlagAgg - 1u;
+constexpr int kMaxPasses = 4;
+constexpr int64_t kStateBase = kMaxPasses * kBins + 64;  // words: histograms, counters, kept count
+
+// Temp layout (uint32 words): [pass][256] global digit counts, [pass] partition
+// counters (at kMaxPasses * 256), the kept count, then [pass][partition][256]
+// look-back state.
+int64_t sort_temp_words(int64_t cap)
 {
+    return kStateBase + (int64_t)kMaxPasses * radix_blocks(cap) * kBins;
+}
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Digit counts of every pass over all n items (per-wave LDS histograms).  With
+// drop, items whose key is kDropKey are left out and the number of the others
+// is added to *kept.
+__global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restrict__ keys, int64_t cap,
+                                                        const uint32_t* __restrict__ ndev, int passes,
+                                                        uint32_t* __restrict__ ghist, int drop,
+                                                        uint32_t* __restrict__ kept)
+{
+    __shared__ uint32_t h[4][kMaxPasses][kBins];
+    __shared__ uint32_t s_kept;
+    const int64_t n = dev_count(cap, ndev);
+    for (int i = threadIdx.x; i < 4 * kMaxPasses * kBins; i += kThreads) (&h[0][0][0])[i] = 0u;
+    if (threadIdx.x == 0) s_kept = 0u;
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    uint32_t mine = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const uint32_t k = keys[i];
+        if (drop && k == kDropKey) continue;
+        ++mine;
+        for (int p = 0; p < passes; ++p) atomicAdd(&h[w][p][(k >> (8 * p)) & 0xFFu], 1u);
+    }
+    if (drop && mine) atomicAdd(&s_kept, mine);
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * kBins; i += kThreads) {
+        const int p = i / kBins, b = i % kBins;
+        const uint32_t c = h[0][p][b] + h[1][p][b] + h[2][p][b] + h[3][p][b];
+        if (c) atomicAdd(&ghist[i], c);
+    }
+    if (drop && threadIdx.x == 0 && s_kept) atomicAdd(kept, s_kept);
+}
+
+// One digit pass.  ghist: this pass's 256 global counts; state: this pass's
+// [partition][256] look-back words (zero on entry); counter: zero on entry.
+__global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restrict__ keys_in,
+                                                        const uint32_t* __restrict__ vals_in,
+                                                        uint32_t* __restrict__ keys_out,
+                                                        uint32_t* __restrict__ vals_out, int64_t cap,
+                                                        const uint32_t* __restrict__ ndev, int shift,
+                                                        const uint32_t* __restrict__ ghist, uint32_t* state,
+                                                        uint32_t* counter, int drop)
+{
+    __shared__ uint32_t s_key[kBlockItems];
+    __shared__ uint32_t s_val[kBlockItems];
+    __shared__ uint32_t cnt[4][kBins];
+    __shared__ uint32_t s_start[kBins];  // block-local first slot of each digit
+    __shared__ uint32_t s_out[kBins];    // global position of that slot
+    __shared__ uint32_t s_part;
+    const int64_t n = dev_count(cap, ndev);
+    if (threadIdx.x == 0) s_part = atomicAdd(counter, 1u);
+    for (int i = threadIdx.x; i < 4 * kBins; i += kThreads) (&cnt[0][0])[i] = 0u;
+    __syncthreads();
+    const uint32_t part = s_part;
+    const int64_t base = (int64_t)part * kBlockItems;
+    if (base >= n) return;  // every partition above this one is empty too
+    const int w = threadIdx.x >> 6;
+    const unsigned lane = __lane_id();
+    const int64_t wbase = base + (int64_t)w * kWaveItems;
+    const uint64_t lt = lanemask_lt();
+    uint32_t key[kItems], val[kItems], rank[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t idx = wbase + r * 64 + lane;
+        const bool valid = idx < n;
+        key[r] = valid ? keys_in[idx] : 0u;
+        val[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
+    }
+    // stable rank of every item among the wave's items of its digit
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const bool valid = wbase + r * 64 + lane < n && !(drop && key[r] == kDropKey);
+        const uint64_t active = __ballot(valid);
+        rank[r] = 0u;
+        if (active == 0ull) continue;
+        const uint32_t d = (key[r] >> shift) & 0xFFu;
+        const uint64_t m = match8(d, active);
+        const uint32_t before = valid ? cnt[w][d] : 0u;
+        rank[r] = before + (uint32_t)__popcll(m & lt);
+        if (valid && (m & lt) == 0ull) cnt[w][d] = before + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;  // one thread per digit from here
+    const uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d], c3 = cnt[3][d];
+    const uint32_t bc = c0 + c1 + c2 + c3;
+    store_agent(state + (int64_t)part * kBins + d, (part == 0 ? kFlagInc : kFlagAgg) | bc);
+    cnt[0][d] = 0u;
+    cnt[1][d] = c0;
+    cnt[2][d] = c0 + c1;
+    cnt[3][d] = c0 + c1 + c2;
+    uint32_t tot;
+    const uint32_t start = block_excl_scan(bc, &tot);
+    // look back: sum this digit's counts over all lower partitions, reading
+    // eight predecessors at a time (their loads are in flight together)
+    uint32_t excl = 0u;
+    if (part > 0) {
+        constexpr int kWin = 8;
+        int64_t q = (int64_t)part - 1;
+        while (q >= 0) {  // partition 0 publishes an inclusive count, so this ends there at the latest
+            uint32_t v[kWin];
+#pragma unroll
+            for (int i = 0; i < kWin; ++i) v[i] = q - i >= 0 ? load_agent(state + (q - i) * kBins + d) : kFlagInc;
+            int used = 0;
+            bool found = false;
+#pragma unroll
+            for (int i = 0; i < kWin; ++i) {
+                if (found || used < i) continue;  // stop at the first inclusive or unpublished word
+                const uint32_t flag = v[i] & ~kCountMask;
+                if (flag == 0u) continue;
+                excl += v[i] & kCountMask;
+                ++used;
+                found = flag == kFlagInc;
+            }
+            if (found) break;
+            q -= used;
+            if (used < kWin) __builtin_amdgcn_s_sleep(1);  // partition q has not published yet; it is running
+        }
+        store_agent(state + (int64_t)part * kBins + d, kFlagInc | (excl + bc));
+    }
+    uint32_t gtot;
+    const uint32_t gstart = block_excl_scan(ghist[d], &gtot);
+    s_start[d] = start;
+    s_out[d] = gstart + excl;
+    __syncthreads();
+    // stage in digit order, then write runs out with consecutive addresses
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        if (wbase + r * 64 + lane < n && !(drop && key[r] == kDropKey)) {
+            const uint32_t dd = (key[r] >> shift) & 0xFFu;
+            const uint32_t li = s_start[dd] + cnt[w][dd] + rank[r];
+            s_key[li] = key[r];
+            s_val[li] = val[r];
+        }
+    }
+    __syncthreads();
+    const int m_items = (int)tot;  // items kept by this partition
+    for (int i = threadIdx.x; i < m_items; i += kThreads) {
+        const uint32_t k = s_key[i];
+        const uint32_t dd = (k >> shift) & 0xFFu;
+        const uint32_t pos = s_out[dd] + ((uint32_t)i - s_start[dd]);
+        keys_out[pos] = k;
+        vals_out[pos] = s_val[i];
+    }
+}
+
+int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
+                   hipStream_t s, const uint32_t** kept, const uint32_t* keys_src)
+{
+    if (kept) *kept = nullptr;
     if (n.cap <= 0) return 0;
+    if (n.cap > (int64_t)kCountMask) return -1;  // counts share a word with the look-back flags
     const int nb = radix_blocks(n.cap);
+    const int passes = std::min(kMaxPasses, (end_bit + 7) / 8);
+    uint32_t* ghist = t.hist;
+    uint32_t* counters = t.hist + kMaxPasses * kBins;
+    uint32_t* kept_dev = counters + kMaxPasses;
+    uint32_t* state = t.hist + kStateBase;
+    const int drop = kept != nullptr;
+    launch_fill_u32(t.hist, 0u, kStateBase + (int64_t)passes * nb * kBins, s);
+    const int hb = std::min(nb, 1024);
+    const uint32_t* first = keys_src ? keys_src : keys;
+    k_sort_hist<<<hb, kThreads, 0, s>>>(first, n.cap, n.dev, passes, ghist, drop, kept_dev);
     uint32_t* kb[2] = {keys, t.keys_alt};
     uint32_t* vb[2] = {vals, t.vals_alt};
     int cur = 0;
-    for (int shift = 0; shift < end_bit; shift += 8) {
-        k_radix_hist<<<nb, kThreads, 0, s>>>(kb[cur], n.cap, n.dev, shift, t.hist, nb);
-        exclusive_scan_u32(t.hist, t.hist, (int64_t)kBins * nb, nullptr, t.scan_tmp, s);
-        k_radix_scatter<<<nb, kThreads, 0, s>>>(kb[cur], identity_vals ? nullptr : vb[cur], kb[cur ^ 1], vb[cur ^ 1],
-                                                n.cap, n.dev, shift, t.hist, nb);
+    for (int p = 0; p < passes; ++p) {
+        // after a dropping first pass the later ones see only the kept items
+        const uint32_t* nd = (p > 0 && drop) ? kept_dev : n.dev;
+        k_sort_pass<<<nb, kThreads, 0, s>>>(p == 0 ? first : kb[cur], identity_vals ? nullptr : vb[cur],
+                                            kb[cur ^ 1], vb[cur ^ 1],
+                                            n.cap, nd, 8 * p, ghist + p * kBins,
+                                            state + (int64_t)p * nb * kBins, counters + p, p == 0 ? drop : 0);
         identity_vals = false;
         cur ^= 1;
     }
+    if (kept) *kept = kept_dev;
     return cur;
 }
 

@@ -1,0 +1,54 @@
+"""Every launch configuration the autotuner may pick (pixels per lane of the
+forward and backward compositing, culling, block order) gives the same
+images bit for bit and the same gradients up to summation order (1e-5
+relative), on a ragged image whose tiles have long lists."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import raster
+from paper_2403_11247_amd import autotune, scenes
+from tests.gpu_common import FIELDS, compare_images, dev, gauss_dev, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_2403_11247_amd import vcgs
+    vcgs.lib()
+    return vcgs
+
+
+def run(V, gd, cam, pose, up):
+    C, D, A, st = V.render_forward(*gd, cam, pose)
+    grads, dpose = V.render_backward(st, *gd, cam, pose, *up)
+    st.free()
+    torch.cuda.synchronize()
+    return C, D, A, grads, dpose
+
+
+def test_all_launch_configurations_agree(V):
+    g = scenes.random_scene(6000, seed=11, xy=1.3, log_scale=(0.02, 0.12))
+    gd = gauss_dev(g)
+    cam = scenes.Camera(200, 136, 160.0, 160.0, 100.0, 68.0)
+    pose = scenes.perturb_pose(scenes.identity_pose(), 5, trans=0.05, rot_deg=2.0)
+    up = [dev(x) for x in scenes.upstream_grads(cam.width, cam.height, seed=4)]
+    saved = autotune.current()
+    try:
+        autotune.apply({"ppl_fwd": 1, "ppl_bwd": 1, "cull": 1, "sched": 0})
+        C0, D0, A0, G0, P0 = run(V, gd, cam, pose, up)
+        r = compare_images(C0, D0, A0, raster.render(g, cam, pose))
+        assert r["pass_"], r
+        n = 0
+        for cfg in autotune.candidates(True):
+            autotune.apply(cfg)
+            C, D, A, G, P = run(V, gd, cam, pose, up)
+            assert torch.equal(C, C0) and torch.equal(D, D0) and torch.equal(A, A0), cfg
+            worst = max(rel_err(G[k].cpu().numpy(), G0[k].cpu().numpy()) for k in FIELDS)
+            worst = max(worst, rel_err(P.cpu().numpy(), P0.cpu().numpy()))
+            assert worst <= 1e-5, (cfg, worst)
+            n += 1
+        say("launch configurations checked:", n)
+    finally:
+        autotune.apply(saved)
