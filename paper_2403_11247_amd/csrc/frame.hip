@@ -242,11 +242,21 @@ static void enqueue_plan(vcgs_ctx* ctx, BatchPlan& p, const vcgs_gaussians& g, c
     phase_b(ctx->prof, p.f, p.w, ord, s);
     if (!p.backward) return;
     ctx->prof.begin(VCGS_STAGE_LOSS, s);
+    LossTab lt;
+    std::memset(&lt, 0, sizeof(lt));
+    lt.n_views = p.V;
+    lt.w_depth = p.w_depth;
     for (int v = 0; v < p.V; ++v) {
-        const int64_t npix = (int64_t)p.cams[v].width * p.cams[v].height;
-        launch_l1_loss(npix, outs[v].color, outs[v].depth, tc[v], td[v], p.w_depth, p.dlc[v], p.dld[v],
-                       loss ? loss + v : nullptr, p.loss_partial + (int64_t)v * p.loss_blocks, s);
+        lt.npix[v] = (int64_t)p.cams[v].width * p.cams[v].height;
+        lt.block0[v + 1] = lt.block0[v] + l1_loss_blocks(lt.npix[v]);
+        lt.c[v] = outs[v].color;
+        lt.d[v] = outs[v].depth;
+        lt.tc[v] = tc[v];
+        lt.td[v] = td[v];
+        lt.dlc[v] = p.dlc[v];
+        lt.dld[v] = p.dld[v];
     }
+    launch_l1_loss_views(lt, loss, p.loss_partial, s);
     ctx->prof.end(VCGS_STAGE_LOSS, s);
     backward_core(ctx, p.f, g, gb, dl_dpose, p.g2, p.partial, p.pb, s);
 }

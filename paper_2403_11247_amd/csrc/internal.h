@@ -155,6 +155,22 @@ void launch_composite_fwd(const ViewTab& v, uint32_t total_tiles, const Splat* r
 void launch_composite_bwd(const ViewTab& v, uint32_t total_tiles, const Splat* rec, const uint32_t* gids,
                           const uint32_t* ranges, float* g2, unsigned long long* counters, hipStream_t s);
 int l1_loss_blocks(int64_t npix);
+// Per-view L1 losses of a batch; view v owns loss blocks [block0[v], block0[v+1]),
+// block0[v+1] - block0[v] = l1_loss_blocks(npix[v]).
+struct LossTab {
+    int n_views;
+    float w_depth;
+    int64_t npix[kMaxViews];
+    int block0[kMaxViews + 1];
+    const float* c[kMaxViews];
+    const float* d[kMaxViews];
+    const float* tc[kMaxViews];
+    const float* td[kMaxViews];
+    float* dlc[kMaxViews];
+    float* dld[kMaxViews];
+};
+// loss: n_views floats (or null); partial: block0[n_views] floats of scratch.
+void launch_l1_loss_views(const LossTab& t, float* loss, float* partial, hipStream_t s);
 // partial: l1_loss_blocks(npix) floats of scratch (only used when loss != nullptr)
 void launch_l1_loss(int64_t npix, const float* c, const float* d, const float* tc, const float* td,
                     float w_depth, float* dl_dc, float* dl_dd, float* loss, float* partial, hipStream_t s);

@@ -552,8 +552,8 @@ __global__ void __launch_bounds__(kLossThreads) k_l1_loss(int64_t npix, const fl
     }
 }
 
-__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ partial, int n, float scale,
-                                                      float* __restrict__ out)
+__device__ __forceinline__ void k_sum_partials_body(const float* __restrict__ partial, int n, float scale,
+                                                    float* __restrict__ out)
 {
     __shared__ double acc[256];
     double a = 0.0;
@@ -567,7 +567,61 @@ __global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ 
     if (threadIdx.x == 0) *out = (float)(acc[0] * (double)scale);
 }
 
+__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ partial, int n, float scale,
+                                                      float* __restrict__ out)
+{
+    k_sum_partials_body(partial, n, scale, out);
+}
+
+// The same loss for up to 16 views in two launches: view v owns blocks
+// [block0[v], block0[v+1]) of the first and block v of the second, with the
+// per-view arithmetic and summation order of the single-view launch.
+__global__ void __launch_bounds__(kLossThreads) k_l1_loss_views(LossTab t, float* __restrict__ partial)
+{
+    int v = 0;
+    while (v + 1 < t.n_views && (int)blockIdx.x >= t.block0[v + 1]) ++v;
+    const int64_t npix = t.npix[v];
+    const float inv_n = 1.0f / (float)npix;
+    const int64_t p = (int64_t)(blockIdx.x - t.block0[v]) * kLossThreads + threadIdx.x;
+    const float* __restrict__ c = t.c[v];
+    const float* __restrict__ d = t.d[v];
+    const float* __restrict__ tc = t.tc[v];
+    const float* __restrict__ td = t.td[v];
+    float l = 0.0f;
+    if (p < npix) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float e = c[ch * npix + p] - tc[ch * npix + p];
+            t.dlc[v][ch * npix + p] = e > 0.0f ? inv_n : (e < 0.0f ? -inv_n : 0.0f);
+            l += fabsf(e);
+        }
+        const float e = d[p] - td[p];
+        t.dld[v][p] = e > 0.0f ? t.w_depth * inv_n : (e < 0.0f ? -t.w_depth * inv_n : 0.0f);
+        l += t.w_depth * fabsf(e);
+    }
+    __shared__ float ws[kLossThreads / 64];
+    l = wave_sum(l);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+__global__ void __launch_bounds__(256) k_sum_partials_views(const float* __restrict__ partial, LossTab t,
+                                                            float* __restrict__ loss)
+{
+    const int v = blockIdx.x;
+    k_sum_partials_body(partial + t.block0[v], t.block0[v + 1] - t.block0[v], 1.0f / (float)t.npix[v], loss + v);
+}
+
 int l1_loss_blocks(int64_t npix) { return (int)((npix + kLossThreads - 1) / kLossThreads); }
+
+void launch_l1_loss_views(const LossTab& t, float* loss, float* partial, hipStream_t s)
+{
+    if (t.n_views <= 0) return;
+    const int nb = t.block0[t.n_views];
+    if (nb > 0) k_l1_loss_views<<<nb, kLossThreads, 0, s>>>(t, partial);
+    if (loss) k_sum_partials_views<<<t.n_views, 256, 0, s>>>(partial, t, loss);
+}
 
 void launch_l1_loss(int64_t npix, const float* c, const float* d, const float* tc, const float* td, float w_depth,
                     float* dl_dc, float* dl_dd, float* loss, float* partial, hipStream_t s)

@@ -11,7 +11,7 @@
 //      digit counts, and looks back over the published counts of the lower
 //      partitions for its global offsets (decoupled look-back: a partition
 //      publishes its own counts before it waits on anyone, so the wait always
-//      ends); items are then staged in LDS in digit order and written out so
+//      ends; sixteen predecessors are read at a time); items are then staged in LDS in digit order and written out so
 //      that consecutive threads write consecutive addresses of a digit's run.
 #include "internal.h"
 #include "internal.h"
@@ -160,11 +160,13 @@ constexpr uint32_t kFlagAgg = 1u << 30;       // partition's own digit count pub
 constexpr uint32_t kFlagInc = 2u << 30;       // count including all lower partitions
 constexpr uint32_t kCountMask = kFlagAgg - 1u;
 constexpr int kMaxPasses = 4;
-constexpr int64_t kStateBase = kMaxPasses * kBins + 64;  // words: histograms, counters, kept count
+constexpr int kHistRep = 8;  // histogram copies (block b adds to copy b % 8): 8x less atomic contention
+constexpr int64_t kHistWords = (int64_t)kHistRep * kMaxPasses * kBins;
+constexpr int64_t kStateBase = kHistWords + 64;  // words: histograms, counters, kept count
 
-// Temp layout (uint32 words): [pass][256] global digit counts, [pass] partition
-// counters (at kMaxPasses * 256), the kept count, then [pass][partition][256]
-// look-back state.
+// Temp layout (uint32 words): [copy][pass][256] global digit counts, [pass]
+// partition counters (at kHistWords), the kept count, then
+// [pass][partition][256] look-back state.
 int64_t sort_temp_words(int64_t cap)
 {
     return kStateBase + (int64_t)kMaxPasses * radix_blocks(cap) * kBins;
@@ -195,24 +197,41 @@ __global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restri
     __syncthreads();
     const int w = threadIdx.x >> 6;
     uint32_t mine = 0u;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const uint32_t k = keys[i];
-        if (drop && k == kDropKey) continue;
-        ++mine;
-        for (int p = 0; p < passes; ++p) atomicAdd(&h[w][p][(k >> (8 * p)) & 0xFFu], 1u);
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    const int64_t i0 = (int64_t)blockIdx.x * kThreads;
+    for (int64_t b = i0; b < n; b += stride) {  // uniform per wave
+        const int64_t i = b + threadIdx.x;
+        const uint32_t k = i < n ? keys[i] : kDropKey;
+        const bool valid = i < n && !(drop && k == kDropKey);
+        const uint64_t active = __ballot(valid);
+        if (active == 0ull) continue;
+        if (valid) ++mine;
+        const int first = __builtin_ctzll(active);
+        for (int p = 0; p < passes; ++p) {
+            const uint32_t d = (k >> (8 * p)) & 0xFFu;
+            const uint32_t d0 = __shfl(d, first, 64);
+            // skewed digits (e.g. the exponent byte of depths) are mostly one
+            // value per wave: one lane adds them all instead of 64 conflicting atomics
+            if (__ballot(valid && d != d0) == 0ull) {
+                if (__lane_id() == (unsigned)first) atomicAdd(&h[w][p][d0], (uint32_t)__popcll(active));
+            } else if (valid) {
+                atomicAdd(&h[w][p][d], 1u);
+            }
+        }
     }
     if (drop && mine) atomicAdd(&s_kept, mine);
     __syncthreads();
     for (int i = threadIdx.x; i < passes * kBins; i += kThreads) {
         const int p = i / kBins, b = i % kBins;
         const uint32_t c = h[0][p][b] + h[1][p][b] + h[2][p][b] + h[3][p][b];
-        if (c) atomicAdd(&ghist[i], c);
+        if (c) atomicAdd(&ghist[(int64_t)(blockIdx.x % kHistRep) * kMaxPasses * kBins + i], c);
     }
     if (drop && threadIdx.x == 0 && s_kept) atomicAdd(kept, s_kept);
 }
 
-// One digit pass.  ghist: this pass's 256 global counts; state: this pass's
-// [partition][256] look-back words (zero on entry); counter: zero on entry.
+// One digit pass.  ghist: this pass's 256 global counts in histogram copy 0
+// (the other copies follow at a stride of kMaxPasses * 256); state: this
+// pass's [partition][256] look-back words (zero on entry); counter: zero on entry.
 __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restrict__ keys_in,
                                                         const uint32_t* __restrict__ vals_in,
                                                         uint32_t* __restrict__ keys_out,
@@ -254,7 +273,8 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
         rank[r] = 0u;
         if (active == 0ull) continue;
         const uint32_t d = (key[r] >> shift) & 0xFFu;
-        const uint64_t m = match8(d, active);
+        const uint32_t d0 = __shfl(d, __builtin_ctzll(active), 64);
+        const uint64_t m = __ballot(valid && d != d0) == 0ull ? active : match8(d, active);
         const uint32_t before = valid ? cnt[w][d] : 0u;
         rank[r] = before + (uint32_t)__popcll(m & lt);
         if (valid && (m & lt) == 0ull) cnt[w][d] = before + (uint32_t)__popcll(m);
@@ -271,10 +291,10 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
     uint32_t tot;
     const uint32_t start = block_excl_scan(bc, &tot);
     // look back: sum this digit's counts over all lower partitions, reading
-    // eight predecessors at a time (their loads are in flight together)
+    // sixteen predecessors at a time (their loads are in flight together)
     uint32_t excl = 0u;
     if (part > 0) {
-        constexpr int kWin = 8;
+        constexpr int kWin = 16;
         int64_t q = (int64_t)part - 1;
         while (q >= 0) {  // partition 0 publishes an inclusive count, so this ends there at the latest
             uint32_t v[kWin];
@@ -298,7 +318,10 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
         store_agent(state + (int64_t)part * kBins + d, kFlagInc | (excl + bc));
     }
     uint32_t gtot;
-    const uint32_t gstart = block_excl_scan(ghist[d], &gtot);
+    uint32_t gcount = 0u;
+#pragma unroll
+    for (int r = 0; r < kHistRep; ++r) gcount += ghist[(int64_t)r * kMaxPasses * kBins + d];
+    const uint32_t gstart = block_excl_scan(gcount, &gtot);
     s_start[d] = start;
     s_out[d] = gstart + excl;
     __syncthreads();
@@ -332,7 +355,7 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, 
     const int nb = radix_blocks(n.cap);
     const int passes = std::min(kMaxPasses, (end_bit + 7) / 8);
     uint32_t* ghist = t.hist;
-    uint32_t* counters = t.hist + kMaxPasses * kBins;
+    uint32_t* counters = t.hist + kHistWords;
     uint32_t* kept_dev = counters + kMaxPasses;
     uint32_t* state = t.hist + kStateBase;
     const int drop = kept != nullptr;
