@@ -24,7 +24,9 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kF = 32;
 constexpr int kMaxK = 16;
 constexpr int kMaxO = kMaxK * 11;
-constexpr int kLdsO = kMaxO + 1;
+// Row stride of the per-wave [16 anchors][k * 11] output buffers for OT
+// 16-row output tiles (padded by one float against bank conflicts).
+constexpr int lds_o(int OT) { return OT * 16 + 1; }
 
 __device__ __forceinline__ v4f mfma4(float a, float b, v4f c)
 {
@@ -127,7 +129,8 @@ __global__ void __launch_bounds__(256) k_decode_fwd(DecodeArgs a, float* __restr
                                                     float* __restrict__ quat, float* __restrict__ opac,
                                                     float* __restrict__ color)
 {
-    __shared__ float ys[4][16][kLdsO];
+    constexpr int LO = lds_o(OT);
+    __shared__ float ys[4][16][LO];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int O = a.k * 11;
     float w1[2][8], b1v[2][4], w2[OT][8], b2v[OT][4];
@@ -205,8 +208,13 @@ constexpr int kBwdMaxBlocks = 256;
 // partial layout per block: dW2 [O][32] | db2 [O] | dW1 [32][32] | db1 [32]
 __host__ __device__ int64_t decode_bwd_partial_floats(int k) { return (int64_t)k * 11 * kF + k * 11 + kF * kF + kF; }
 
-// the per-wave y buffers of a block double as the block's reduction buffer
-static_assert(kBwdWaves * 16 * kLdsO >= kMaxO * kF + kMaxO + kF * kF + kF, "reduction buffer too small");
+// The per-wave y buffers of a block double as the block's reduction buffer:
+// floats for both uses with OT output tiles.
+constexpr int bwd_smem_floats(int OT)
+{
+    return kBwdWaves * 16 * lds_o(OT) > 16 * OT * (kF + 1) + kF * kF + kF ? kBwdWaves * 16 * lds_o(OT)
+                                                                          : 16 * OT * (kF + 1) + kF * kF + kF;
+}
 
 int decode_bwd_blocks(int64_t na)
 {
@@ -221,9 +229,10 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
     // Each wave's [16 anchors][k * 11] outputs y are overwritten in place by
     // dL/dy (every slot is read before it is written, by the same lane); the
     // buffer also holds the block reduction at the end.
-    __shared__ float smem[kBwdWaves][16][kLdsO];
-    float (*ys)[16][kLdsO] = smem;
-    float (*dys)[16][kLdsO] = smem;
+    constexpr int LO = lds_o(OT);
+    __shared__ float smem[bwd_smem_floats(OT)];
+    float (*ys)[16][LO] = reinterpret_cast<float (*)[16][LO]>(smem);
+    float (*dys)[16][LO] = ys;
     __shared__ float hs[kBwdWaves][16][kF + 1];
     __shared__ float ps[kBwdWaves][16][kF + 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -446,7 +455,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
     }
     // block reduction in wave order, then one partial row per block
     __syncthreads();
-    float* red = &smem[0][0][0];  // kBwdWaves * 16 * kLdsO >= decode_bwd_partial_floats(16) floats
+    float* red = smem;  // bwd_smem_floats(OT) >= decode_bwd_partial_floats(k) floats
     const int64_t PF = decode_bwd_partial_floats(a.k);
     for (int w = 0; w < kBwdWaves; ++w) {
         if (wave == w) {
@@ -502,8 +511,10 @@ __global__ void __launch_bounds__(256) k_decode_bwd_reduce(const float* __restri
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     float s = 0.0f;
-    if (i < PF)
+    if (i < PF) {
+#pragma unroll 8
         for (int b = wave; b < nblocks; b += 4) s += partial[(int64_t)b * PF + i];
+    }
     acc[wave][lane] = s;
     __syncthreads();
     if (wave != 0 || i >= PF) return;
