@@ -9,7 +9,8 @@
 // excluded and the pixel stops.
 //
 // Work layout: one wave64 per (16x16 tile, slice); a wave covers 64 * PPL
-// pixels (PPL pixels per lane, stacked 4 rows apart) and walks its tile's
+// pixels (an 8x8 quadrant at one pixel per lane; 16 wide with PPL pixels per
+// lane stacked 4 rows apart otherwise) and walks its tile's
 // depth-sorted list independently of the other waves.  Records are staged 64
 // at a time in a wave-private LDS slab; while staging, each lane tests its own
 // Gaussian's 1/255 ellipse against the wave's pixel rectangle (exact minimum of
@@ -121,7 +122,9 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
                                                        unsigned long long* __restrict__ counters, int cull, int sched)
 {
     constexpr int WPT = 4 / PPL;     // waves per tile
-    constexpr int ROWS = 16 / WPT;   // rows per wave
+    constexpr int SW = PPL == 1 ? 8 : 16;  // width of a wave's pixel block (8x8 quadrants at 1 pixel per lane)
+    constexpr int LR = 64 / SW;            // rows of lanes
+    constexpr int SH = LR * PPL;           // height of a wave's pixel block
     __shared__ float4 slab[4][64][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gw = (sched ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + wave;
@@ -139,18 +142,19 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     const float bg0 = tab.bg[0], bg1 = tab.bg[1], bg2 = tab.bg[2];
     uint32_t n_eval = 0, n_blend = 0;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    const int px = tx * kTile + (lane & 15);
-    const int row0 = ty * kTile + sub * ROWS;
+    const int qx = PPL == 1 ? (sub & 1) : 0, qy = PPL == 1 ? (sub >> 1) : sub;
+    const int px = tx * kTile + qx * SW + lane % SW;
+    const int row0 = ty * kTile + qy * SH;
     // pixel-centre rectangle of this wave
-    const float rx0 = (float)(tx * kTile) + 0.5f, rx1 = rx0 + 15.0f;
-    const float ry0 = (float)row0 + 0.5f, ry1 = ry0 + (float)(ROWS - 1);
+    const float rx0 = (float)(tx * kTile + qx * SW) + 0.5f, rx1 = rx0 + (float)(SW - 1);
+    const float ry0 = (float)row0 + 0.5f, ry1 = ry0 + (float)(SH - 1);
     float dy[PPL];
     bool done[PPL];
     float T[PPL], c0[PPL], c1[PPL], c2[PPL], dd[PPL], aa[PPL];
     uint32_t last[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
-        const int py = row0 + (lane >> 4) + 4 * j;
+        const int py = row0 + lane / SW + LR * j;
         dy[j] = (float)py + 0.5f;
         done[j] = !(px < cam.W && py < cam.H);
         T[j] = 1.0f; c0[j] = c1[j] = c2[j] = dd[j] = aa[j] = 0.0f;
@@ -228,7 +232,7 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     const int HW = cam.W * cam.H;
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
-        const int py = row0 + (lane >> 4) + 4 * j;
+        const int py = row0 + lane / SW + LR * j;
         if (px < cam.W && py < cam.H) {
             const int p = py * cam.W + px;
             color[p] = c0[j] + T[j] * bg0;
@@ -316,7 +320,9 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
                                                        unsigned long long* __restrict__ counters, int cull, int sched)
 {
     constexpr int WPT = 4 / PPL;
-    constexpr int ROWS = 16 / WPT;
+    constexpr int SW = PPL == 1 ? 8 : 16;
+    constexpr int LR = 64 / SW;
+    constexpr int SH = LR * PPL;
     __shared__ float4 slab[4][64][4];
     __shared__ uint32_t slab_gid[4][64];
     // per-Gaussian row sums (4 rows x 10 values) waiting to be added to g2
@@ -341,10 +347,11 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
     const bool rsv = rs_valid(threadIdx.x & 63);
     const int rsi = rs_index(threadIdx.x & 63);
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    const int px = tx * kTile + (lane & 15);
-    const int row0 = ty * kTile + sub * ROWS;
-    const float rx0 = (float)(tx * kTile) + 0.5f, rx1 = rx0 + 15.0f;
-    const float ry0 = (float)row0 + 0.5f, ry1 = ry0 + (float)(ROWS - 1);
+    const int qx = PPL == 1 ? (sub & 1) : 0, qy = PPL == 1 ? (sub >> 1) : sub;
+    const int px = tx * kTile + qx * SW + lane % SW;
+    const int row0 = ty * kTile + qy * SH;
+    const float rx0 = (float)(tx * kTile + qx * SW) + 0.5f, rx1 = rx0 + (float)(SW - 1);
+    const float ry0 = (float)row0 + 0.5f, ry1 = ry0 + (float)(SH - 1);
     const int HW = cam.W * cam.H;
     float T[PPL], up[PPL][5], acc[PPL][5];
     uint32_t last[PPL];
@@ -352,7 +359,7 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
     uint32_t wl = 0;
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
-        const int py = row0 + (lane >> 4) + 4 * j;
+        const int py = row0 + lane / SW + LR * j;
         pyf[j] = (float)py + 0.5f;
         const bool in = px < cam.W && py < cam.H;
         const int p = py * cam.W + px;
