@@ -148,44 +148,44 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     // pixel-centre rectangle of this wave
     const float rx0 = (float)(tx * kTile + qx * SW) + 0.5f, rx1 = rx0 + (float)(SW - 1);
     const float ry0 = (float)row0 + 0.5f, ry1 = ry0 + (float)(SH - 1);
+    // T < 0 marks a pixel that has stopped (or lies outside the image); |T| is
+    // then its final transmittance.  Keeping the state in the sign lets the
+    // blend below run without any per-lane branch or mask bookkeeping.
     float dy[PPL];
-    bool done[PPL];
     float T[PPL], c0[PPL], c1[PPL], c2[PPL], dd[PPL], aa[PPL];
     uint32_t last[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
         const int py = row0 + lane / SW + LR * j;
         dy[j] = (float)py + 0.5f;
-        done[j] = !(px < cam.W && py < cam.H);
-        T[j] = 1.0f; c0[j] = c1[j] = c2[j] = dd[j] = aa[j] = 0.0f;
+        T[j] = (px < cam.W && py < cam.H) ? 1.0f : -1.0f;
+        c0[j] = c1[j] = c2[j] = dd[j] = aa[j] = 0.0f;
         last[j] = 0u;
     }
     const float pxf = (float)px + 0.5f;
     const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
-    // One footprint blended front to back into pixel j; returns whether the
-    // pixel stopped on it.  Branch-free: a skipped or stopping Gaussian blends
-    // with weight zero, which leaves the sums unchanged.
-    auto blend = [&](int j, const Fp& f, const float4& rc, float rz, uint32_t idx, bool en) -> bool {
-        const bool ok = en && !done[j] && f.alpha >= kAlphaMin;
-        const float Tn = T[j] * (1.0f - f.alpha);
-        const bool stop = ok && Tn < kTMin;
-        const bool take = ok && !stop;
-        if (COUNT) { n_eval += (en && !done[j]) ? 1u : 0u; n_blend += take ? 1u : 0u; }
-        const float w = take ? f.alpha * T[j] : 0.0f;
+    // One footprint blended front to back into pixel j.  A Gaussian below
+    // 1/255 takes alpha 0, which leaves T (>= 1e-4 while running) unchanged;
+    // one that would take T below 1e-4 stops the pixel with weight 0; a stopped
+    // pixel (T < 0) gets Tn <= 0 and so stays stopped with weight 0.
+    auto blend = [&](int j, const Fp& f, const float4& rc, float rz, uint32_t idx, bool en) {
+        const float a = (en && f.alpha >= kAlphaMin) ? f.alpha : 0.0f;
+        const float Tn = T[j] * (1.0f - a);
+        const bool stop = Tn < kTMin;
+        const float w = stop ? 0.0f : a * T[j];
+        if (COUNT) { n_eval += (en && T[j] > 0.0f) ? 1u : 0u; n_blend += w > 0.0f ? 1u : 0u; }
         c0[j] += w * rc.y; c1[j] += w * rc.z; c2[j] += w * rc.w;
         dd[j] += w * rz; aa[j] += w;
-        T[j] = take ? Tn : T[j];
-        last[j] = take ? idx : last[j];
-        done[j] = done[j] || stop;
-        return stop;
+        last[j] = w > 0.0f ? idx : last[j];
+        T[j] = stop ? -fabsf(T[j]) : Tn;
     };
-    bool all_done;
-    {
+    auto wave_done = [&]() {
         bool mine = true;
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) mine = mine && done[j];
-        all_done = __all(mine);  // e.g. rows below the image
-    }
+        for (int j = 0; j < PPL; ++j) mine = mine && T[j] < 0.0f;
+        return __all(mine);
+    };
+    bool all_done = wave_done();  // e.g. rows below the image
     for (uint32_t b = start; b < end && !all_done; b += 64) {
         wave_lds_sync();
         const uint32_t idx = b + lane;
@@ -213,22 +213,18 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
             const float4 a2 = slab[wave][k2][0], b2 = slab[wave][k2][1], r2 = slab[wave][k2][2];
             const float z2 = slab[wave][k2][3].x;
             const float dx1 = (pxf - a1.x) - a1.z, dx2 = (pxf - a2.x) - a2.z;
-            bool stopped = false;
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 const Fp f1 = footprint(dx1, (dy[j] - a1.y) - a1.w, b1.x, b1.y, b1.z, b1.w, r1.x);
                 const Fp f2 = footprint(dx2, (dy[j] - a2.y) - a2.w, b2.x, b2.y, b2.z, b2.w, r2.x);
-                stopped = blend(j, f1, r1, z1, base + (uint32_t)k1, true) || stopped;
-                stopped = blend(j, f2, r2, z2, base + (uint32_t)k2, two) || stopped;
+                blend(j, f1, r1, z1, base + (uint32_t)k1, true);
+                blend(j, f2, r2, z2, base + (uint32_t)k2, two);
             }
-            if (__ballot(stopped) != 0ull) {
-                bool mine = true;
-#pragma unroll
-                for (int j = 0; j < PPL; ++j) mine = mine && done[j];
-                if (__all(mine)) { all_done = true; break; }
-            }
+            if (wave_done()) { all_done = true; break; }
         }
     }
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) T[j] = fabsf(T[j]);
     const int HW = cam.W * cam.H;
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
