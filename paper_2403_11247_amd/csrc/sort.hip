@@ -197,11 +197,19 @@ __global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restri
     __syncthreads();
     const int w = threadIdx.x >> 6;
     uint32_t mine = 0u;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    const int64_t i0 = (int64_t)blockIdx.x * kThreads;
-    for (int64_t b = i0; b < n; b += stride) {  // uniform per wave
-        const int64_t i = b + threadIdx.x;
-        const uint32_t k = i < n ? keys[i] : kDropKey;
+    // each thread counts kItems keys, all loaded before any is counted so that
+    // their latencies overlap; the block's items are strided by kThreads
+    const int64_t i0 = (int64_t)blockIdx.x * kBlockItems;
+    uint32_t key[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = i0 + (int64_t)r * kThreads + threadIdx.x;
+        key[r] = i < n ? keys[i] : kDropKey;
+    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = i0 + (int64_t)r * kThreads + threadIdx.x;
+        const uint32_t k = key[r];
         const bool valid = i < n && !(drop && k == kDropKey);
         const uint64_t active = __ballot(valid);
         if (active == 0ull) continue;
@@ -253,6 +261,10 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
     const uint32_t part = s_part;
     const int64_t base = (int64_t)part * kBlockItems;
     if (base >= n) return;  // every partition above this one is empty too
+    // this digit's global count (thread t = digit t), loaded early so its latency overlaps the ranking
+    uint32_t gcount = 0u;
+#pragma unroll
+    for (int r = 0; r < kHistRep; ++r) gcount += ghist[(int64_t)r * kMaxPasses * kBins + threadIdx.x];
     const int w = threadIdx.x >> 6;
     const unsigned lane = __lane_id();
     const int64_t wbase = base + (int64_t)w * kWaveItems;
@@ -318,9 +330,6 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
         store_agent(state + (int64_t)part * kBins + d, kFlagInc | (excl + bc));
     }
     uint32_t gtot;
-    uint32_t gcount = 0u;
-#pragma unroll
-    for (int r = 0; r < kHistRep; ++r) gcount += ghist[(int64_t)r * kMaxPasses * kBins + d];
     const uint32_t gstart = block_excl_scan(gcount, &gtot);
     s_start[d] = start;
     s_out[d] = gstart + excl;
@@ -360,7 +369,7 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, 
     uint32_t* state = t.hist + kStateBase;
     const int drop = kept != nullptr;
     launch_fill_u32(t.hist, 0u, kStateBase + (int64_t)passes * nb * kBins, s);
-    const int hb = std::min(nb, 1024);
+    const int hb = nb;  // one block per 4096 items
     const uint32_t* first = keys_src ? keys_src : keys;
     k_sort_hist<<<hb, kThreads, 0, s>>>(first, n.cap, n.dev, passes, ghist, drop, kept_dev);
     uint32_t* kb[2] = {keys, t.keys_alt};
