@@ -82,7 +82,7 @@ class Anchors:
 
 @dataclasses.dataclass
 class MLP:
-    W1: np.ndarray  # (hidden, in)  = (32, 32)
+    W1: np.ndarray  # (hidden, in)  = (32, 32), or (32, 36) with the view input
     b1: np.ndarray  # (hidden,)
     W2: np.ndarray  # (k*11, hidden) = (110, 32)
     b2: np.ndarray  # (k*11,)
@@ -256,6 +256,17 @@ def room_mlp(k=10, hidden=32, feat_dim=32, seed=0, scale_m=0.02) -> MLP:
     bias = np.array([0.0, 0.0, 0.0, 0.0] + [math.log(scale_m)] * 3 + [1.0, 0.0, 0.0, 0.0])
     b2 = np.tile(bias, k)
     return MLP(_f32(W1), _f32(b1), _f32(W2), _f32(b2))
+
+
+def room_mlp_view(k=10, hidden=32, feat_dim=32, seed=0, scale_m=0.02, view_gain=1.0) -> MLP:
+    """The same decoder with the view-dependent input of eq. (9): W1 gets four
+    more columns for [delta, d_x, d_y, d_z] (drawn from their own stream, so the
+    feature columns equal ``room_mlp``'s), U[-g, g] * sqrt(6 / 36) * view_gain."""
+    m = room_mlp(k, hidden, feat_dim, seed, scale_m)
+    rng = np.random.default_rng(seed + 13)
+    b = math.sqrt(6.0 / (feat_dim + 4)) * view_gain
+    Wv = rng.uniform(-b, b, (hidden, 4))
+    return MLP(_f32(np.concatenate([m.W1.astype(np.float64), Wv], axis=1)), m.b1, m.W2, m.b2)
 
 
 def room_camera(width=1200, height=680, f=600.0, position=(0.3, 0.3, 1.5), target=(6.0, 5.0, 1.2)):

@@ -432,3 +432,117 @@ def test_mask_prunes_like_removal():
     r2 = raster.render(sub, cam, pose)
     np.testing.assert_array_equal(r1["color"], r2["color"])
     np.testing.assert_array_equal(r1["depth"], r2["depth"])
+
+
+# ---------------------------------------------------------------------------
+# view-dependent decode (eqs. (8)-(9): input [f_a, delta, d])
+# ---------------------------------------------------------------------------
+
+CAM_C = np.array([2.9, 2.4, 1.3])
+
+
+def _view_loss(a, m, cam, weights):
+    out = odec.decode(a, m, cam=cam)
+    return sum((out[k] * weights[k]).sum() for k in ("mean", "scale", "quat", "opacity", "color"))
+
+
+def test_view_decode_with_zero_view_weights_is_the_feature_decode():
+    a, m = small_anchors(25, 4, seed=3)
+    mv = scenes.room_mlp_view(k=4, seed=3)
+    np.testing.assert_array_equal(mv.W1[:, :32], m.W1)
+    m0 = scenes.MLP(np.concatenate([m.W1, np.zeros((32, 4), np.float32)], axis=1), m.b1, m.W2, m.b2)
+    o1, o2 = odec.decode(a, m), odec.decode(a, m0, cam=CAM_C)
+    for k in ("mean", "scale", "quat", "opacity", "color"):
+        np.testing.assert_allclose(o2[k], o1[k], rtol=1e-14, atol=1e-15)
+    rng = np.random.default_rng(4)
+    wts = {k: rng.normal(size=o1[k].shape) for k in ("mean", "scale", "quat", "opacity", "color")}
+    g1, g2 = odec.decode_backward(a, m, o1, wts), odec.decode_backward(a, m0, o2, wts, cam=CAM_C)
+    for k in ("feat", "b1", "W2", "b2", "offset", "scaling", "xa"):
+        np.testing.assert_allclose(g2[k], g1[k], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(g2["W1"][:, :32], g1["W1"], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(g2["cam"], 0.0, atol=1e-14)
+
+
+def test_view_inputs_are_distance_and_unit_direction():
+    a, _ = small_anchors(10, 2, seed=5)
+    vin = odec.view_inputs(a, CAM_C)
+    for i in (0, 4, 9):
+        v = a.xa[:, i].astype(np.float64) - CAM_C
+        assert abs(vin[i, 0] - math.sqrt(v @ v)) < 1e-13
+        np.testing.assert_allclose(vin[i, 1:] * vin[i, 0], v, rtol=1e-13)
+
+
+def test_view_decode_is_translation_invariant():
+    """The MLP sees x_a - x_c only: moving anchors and camera together changes
+    nothing but the means, so without a mean gradient the camera gradient is
+    minus the sum of the anchor-position gradients."""
+    a, _ = small_anchors(20, 3, seed=6)
+    m = scenes.room_mlp_view(k=3, seed=6, view_gain=4.0)
+    import copy
+    u = np.array([0.3, -0.7, 0.2])
+    a2 = copy.copy(a)
+    a2.xa = (a.xa.astype(np.float64) + u[:, None])
+    o1, o2 = odec.decode(a, m, cam=CAM_C), odec.decode(a2, m, cam=CAM_C + u)
+    for k in ("scale", "quat", "opacity", "color"):
+        np.testing.assert_allclose(o2[k], o1[k], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(o2["mean"], o1["mean"] + u[:, None], rtol=1e-12, atol=1e-12)
+    rng = np.random.default_rng(7)
+    wts = {k: rng.normal(size=o1[k].shape) for k in ("scale", "quat", "opacity", "color")}
+    wts["mean"] = np.zeros_like(o1["mean"])
+    gr = odec.decode_backward(a, m, o1, wts, cam=CAM_C)
+    assert np.abs(gr["cam"]).max() > 1e-3
+    np.testing.assert_allclose(gr["xa"].sum(1), -gr["cam"], rtol=1e-10, atol=1e-12)
+
+
+def test_view_decode_backward_finite_differences():
+    a, _ = small_anchors(10, 3, seed=8)
+    m = scenes.room_mlp_view(k=3, seed=8, view_gain=4.0)
+    rng = np.random.default_rng(9)
+    out = odec.decode(a, m, cam=CAM_C)
+    wts = {k: rng.normal(size=out[k].shape) for k in ("mean", "scale", "quat", "opacity", "color")}
+    gr = odec.decode_backward(a, m, out, wts, cam=CAM_C)
+    h = 1e-6
+    import copy
+    for obj, field, key in [(a, "feat", "feat"), (m, "W1", "W1"), (a, "xa", "xa"), (m, "b1", "b1")]:
+        base = getattr(obj, field).astype(np.float64)
+        picks = rng.choice(base.size, 6, replace=False)
+        if key == "W1":
+            picks = np.concatenate([picks, [32, 33 + 36, 35 + 72]])  # view columns
+        for j in picks:
+            vals = []
+            for sgn in (+1, -1):
+                o2 = copy.copy(obj)
+                arr = base.copy()
+                arr.reshape(-1)[j] += sgn * h
+                setattr(o2, field, arr)
+                vals.append(_view_loss(o2 if obj is a else a, o2 if obj is m else m, CAM_C, wts))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = gr[key].reshape(-1)[j]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (key, j, fd, an)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        fd = (_view_loss(a, m, CAM_C + e, wts) - _view_loss(a, m, CAM_C - e, wts)) / (2 * h)
+        assert abs(fd - gr["cam"][i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, gr["cam"][i])
+
+
+def test_camera_centre_pose_gradient():
+    """c = -R^T t under the left perturbation exp(xi^) {R|t}: finite differences
+    of a linear function of c over xi = (rho, phi)."""
+    pose = scenes.look_at((1.0, 2.0, 1.5), (4.0, 3.0, 1.0))
+    R, t = pose.R.astype(np.float64), pose.t.astype(np.float64)
+    w = np.array([0.7, -1.3, 0.4])
+    def centre(xi):
+        rho, phi = xi[:3], xi[3:]
+        ang = np.linalg.norm(phi)
+        E = scenes._axis_angle(phi, ang) if ang > 0 else np.eye(3)
+        R2 = E @ R
+        t2 = E @ t + rho  # first order in xi is all the gradient needs
+        return -R2.T @ t2
+    g = odec.pose_grad_from_centre(R, w)
+    h = 1e-6
+    for i in range(6):
+        e = np.zeros(6)
+        e[i] = h
+        fd = (w @ centre(e) - w @ centre(-e)) / (2 * h)
+        assert abs(fd - g[i]) < 1e-7, (i, fd, g[i])
