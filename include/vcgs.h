@@ -324,6 +324,7 @@ typedef struct {
     float* b2;
     float* books;       /* [stages][size][7]: straight-through sums over the Gaussians using each row */
     float* mask_logit;  /* [na*k]: sigmoid'(m) (s . dL/ds_hat + alpha dL/dalpha_hat); 0 when pruned */
+    float* cam;         /* [3]: dL/d camera centre (view-dependent decode only; ignored otherwise) */
 } vcgs_anchor_grads;
 
 /* dG: dL/d(decoded Gaussians) (device, na*k Gaussians, e.g. from
@@ -331,6 +332,26 @@ typedef struct {
 int vcgs_decode_anchors_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
                                  const vcgs_codebook* cb, const float* mask_logit, float mask_eps,
                                  const vcgs_gaussian_buffers* dG, vcgs_anchor_grads* out, void* stream);
+
+/* View-dependent decode, paper eqs. (8)-(9): the MLP input is the 36-d
+ * [f_a, delta, d] with delta = |x_a - x_c| and d = (x_a - x_c) / delta for the
+ * camera centre x_c = cam_centre (host, 3 floats; for a world-to-camera pose
+ * {R|t} it is -R^T t).  mlp->W1 is [32][36] (row-major, the last four columns
+ * weigh delta, d_x, d_y, d_z); everything else as vcgs_decode_anchors.  An
+ * anchor at the camera centre (delta = 0) has no direction: such input is
+ * outside the operation's domain. */
+int vcgs_decode_anchors_view(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
+                             const float* mask_logit, float mask_eps, const float cam_centre[3],
+                             vcgs_gaussian_buffers* out, void* stream);
+
+/* Gradients of vcgs_decode_anchors_view: as vcgs_decode_anchors_backward, with
+ * W1 [32][36], xa including the path through delta and d, and out->cam (if
+ * non-NULL) receiving dL/d(camera centre).  For the left-perturbed pose the
+ * centre moves by -R^T rho, so its share of dL/dxi is (-R dL/dcam, 0). */
+int vcgs_decode_anchors_view_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
+                                      const vcgs_codebook* cb, const float* mask_logit, float mask_eps,
+                                      const float cam_centre[3], const vcgs_gaussian_buffers* dG,
+                                      vcgs_anchor_grads* out, void* stream);
 
 /* ---- kernel configuration ---------------------------------------------- */
 

@@ -78,8 +78,12 @@ int vcgs_l1_loss(vcgs_ctx* ctx, const vcgs_images* img, const float* target_colo
 }
 
 static int make_decode_args(const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
-                            const float* mask_logit, float mask_eps, DecodeArgs* d)
+                            const float* mask_logit, float mask_eps, DecodeArgs* d, const float* cam = nullptr)
 {
+    d->in_dim = cam ? 36 : 32;
+    d->cam[0] = cam ? cam[0] : 0.0f;
+    d->cam[1] = cam ? cam[1] : 0.0f;
+    d->cam[2] = cam ? cam[2] : 0.0f;
     if (!a || !mlp) return fail(VCGS_E_INVALID, "anchors or mlp is NULL");
     if (a->n_anchor < 0) return fail(VCGS_E_INVALID, "negative anchor count");
     if (a->feat_dim != 32) return fail(VCGS_E_UNSUPPORTED, "feat_dim must be 32");
@@ -108,12 +112,13 @@ static int make_decode_args(const vcgs_anchors* a, const vcgs_mlp* mlp, const vc
     return VCGS_OK;
 }
 
-int vcgs_decode_anchors(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
-                        const float* mask_logit, float mask_eps, vcgs_gaussian_buffers* out, void* stream)
+static int decode_fwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
+                      const float* mask_logit, float mask_eps, const float* cam, vcgs_gaussian_buffers* out,
+                      void* stream)
 {
     if (!ctx || !out) return fail(VCGS_E_INVALID, "ctx or out is NULL");
     DecodeArgs d;
-    int rc = make_decode_args(a, mlp, cb, mask_logit, mask_eps, &d);
+    int rc = make_decode_args(a, mlp, cb, mask_logit, mask_eps, &d, cam);
     if (rc != VCGS_OK) return rc;
     if (d.na > 0 && (!out->mean || !out->scale || !out->quat || !out->opacity || !out->color))
         return fail(VCGS_E_INVALID, "an output pointer is NULL");
@@ -126,23 +131,24 @@ int vcgs_decode_anchors(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* ml
     return VCGS_OK;
 }
 
-int vcgs_decode_anchors_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
-                                 const float* mask_logit, float mask_eps, const vcgs_gaussian_buffers* dG,
-                                 vcgs_anchor_grads* out, void* stream)
+static int decode_bwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
+                      const float* mask_logit, float mask_eps, const float* cam, const vcgs_gaussian_buffers* dG,
+                      vcgs_anchor_grads* out, void* stream)
 {
     if (!ctx || !out || !dG) return fail(VCGS_E_INVALID, "ctx, dG or out is NULL");
     DecodeArgs d;
-    int rc = make_decode_args(a, mlp, cb, mask_logit, mask_eps, &d);
+    int rc = make_decode_args(a, mlp, cb, mask_logit, mask_eps, &d, cam);
     if (rc != VCGS_OK) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     vcgs_anchor_grads o = *out;
     if (!cb) o.books = nullptr;
     if (!mask_logit) o.mask_logit = nullptr;
+    if (!cam) o.cam = nullptr;
     if (d.na == 0) return VCGS_OK;
     Scratch sc(&ctx->pool);
     const int nb = decode_bwd_blocks(d.na);
-    float* partial = sc.get<float>((int64_t)nb * decode_bwd_partial_floats(d.k));
+    float* partial = sc.get<float>((int64_t)nb * decode_bwd_partial_floats(d.k, d.in_dim));
     if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (decode backward)");
     ctx->prof.begin(VCGS_STAGE_DECODE_BWD, s);
     launch_decode_bwd(d, *dG, o, partial, nb, s);
@@ -150,6 +156,36 @@ int vcgs_decode_anchors_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcg
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return VCGS_OK;
+}
+
+int vcgs_decode_anchors(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
+                        const float* mask_logit, float mask_eps, vcgs_gaussian_buffers* out, void* stream)
+{
+    return decode_fwd(ctx, a, mlp, cb, mask_logit, mask_eps, nullptr, out, stream);
+}
+
+int vcgs_decode_anchors_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
+                                 const float* mask_logit, float mask_eps, const vcgs_gaussian_buffers* dG,
+                                 vcgs_anchor_grads* out, void* stream)
+{
+    return decode_bwd(ctx, a, mlp, cb, mask_logit, mask_eps, nullptr, dG, out, stream);
+}
+
+int vcgs_decode_anchors_view(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
+                             const float* mask_logit, float mask_eps, const float cam_centre[3],
+                             vcgs_gaussian_buffers* out, void* stream)
+{
+    if (!cam_centre) return fail(VCGS_E_INVALID, "cam_centre is NULL");
+    return decode_fwd(ctx, a, mlp, cb, mask_logit, mask_eps, cam_centre, out, stream);
+}
+
+int vcgs_decode_anchors_view_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
+                                      const vcgs_codebook* cb, const float* mask_logit, float mask_eps,
+                                      const float cam_centre[3], const vcgs_gaussian_buffers* dG,
+                                      vcgs_anchor_grads* out, void* stream)
+{
+    if (!cam_centre) return fail(VCGS_E_INVALID, "cam_centre is NULL");
+    return decode_bwd(ctx, a, mlp, cb, mask_logit, mask_eps, cam_centre, dG, out, stream);
 }
 
 int vcgs_set_option(int key, int value)

@@ -1,5 +1,9 @@
-// Anchor decode (paper Sec. 3.2, eqs. (7)-(8); mask eqs. (11)-(12); residual
+// Anchor decode (paper Sec. 3.2, eqs. (7)-(9); mask eqs. (11)-(12); residual
 // codebook eq. (14), first line) and its adjoint.
+//
+// The MLP input is the 32-d anchor feature, or with a camera centre x_c the
+// 36-d [f_a, delta, d] of eq. (9) (delta = |x_a - x_c|, d = (x_a - x_c) / delta):
+// the four view inputs are one more K step of the first layer's MFMA.
 //
 // The MLP h = ReLU(W1 f + b1), y = W2 h + b2 is the one dense contraction of
 // the path and runs on FP32 MFMA (v_mfma_f32_16x16x4_f32): a wave decodes 16
@@ -81,29 +85,46 @@ __device__ __forceinline__ Decoded decode_one(const DecodeArgs& a, const float* 
     return d;
 }
 
-// First layer for 16 anchors; returns the pre-activations in accumulator layout.
-__device__ __forceinline__ void layer1(const float (&w1)[2][8], const float* __restrict__ feat, int64_t an, bool valid,
-                                       int lane, v4f (&d1)[2])
+// View input c of anchor an (eq. (9)): c = 0 the distance, 1..3 the unit direction.
+__device__ __forceinline__ float view_input(const DecodeArgs& a, int64_t an, int c)
+{
+    const float vx = a.xa[an] - a.cam[0], vy = a.xa[a.na + an] - a.cam[1], vz = a.xa[2 * a.na + an] - a.cam[2];
+    const float dist = sqrtf(vx * vx + vy * vy + vz * vz);
+    return c == 0 ? dist : (c == 1 ? vx : (c == 2 ? vy : vz)) / dist;
+}
+
+// First layer for 16 anchors; returns the pre-activations in accumulator layout
+// and, with the view input, this lane's view value (anchor lane % 16, input lane / 16).
+__device__ __forceinline__ void layer1(const float (&w1)[2][9], const DecodeArgs& a, int64_t an, bool valid,
+                                       int lane, v4f (&d1)[2], float& vin)
 {
     d1[0] = v4f{0.f, 0.f, 0.f, 0.f};
     d1[1] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
-        const float b = valid ? feat[an * kF + ks * 4 + (lane >> 4)] : 0.0f;
+        const float b = valid ? a.feat[an * kF + ks * 4 + (lane >> 4)] : 0.0f;
         d1[0] = mfma4(w1[0][ks], b, d1[0]);
         d1[1] = mfma4(w1[1][ks], b, d1[1]);
+    }
+    vin = 0.0f;
+    if (a.in_dim > kF) {  // uniform
+        vin = valid ? view_input(a, an, lane >> 4) : 0.0f;
+        d1[0] = mfma4(w1[0][8], vin, d1[0]);
+        d1[1] = mfma4(w1[1][8], vin, d1[1]);
     }
 }
 
 template <int OT>
-__device__ __forceinline__ void load_weights(const DecodeArgs& a, int lane, float (&w1)[2][8], float (&b1v)[2][4],
+__device__ __forceinline__ void load_weights(const DecodeArgs& a, int lane, float (&w1)[2][9], float (&b1v)[2][4],
                                              float (&w2)[OT][8], float (&b2v)[OT][4])
 {
     const int O = a.k * 11;
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) w1[mt][ks] = a.W1[(mt * 16 + (lane & 15)) * kF + ks * 4 + (lane >> 4)];
+        for (int ks = 0; ks < 9; ++ks)
+            w1[mt][ks] = (ks < 8 || a.in_dim > kF) ? a.W1[(mt * 16 + (lane & 15)) * a.in_dim + ks * 4 + (lane >> 4)]
+                                                   : 0.0f;
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -133,7 +154,7 @@ __global__ void __launch_bounds__(256) k_decode_fwd(DecodeArgs a, float* __restr
     __shared__ float ys[4][16][LO];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int O = a.k * 11;
-    float w1[2][8], b1v[2][4], w2[OT][8], b2v[OT][4];
+    float w1[2][9], b1v[2][4], w2[OT][8], b2v[OT][4];
     load_weights<OT>(a, lane, w1, b1v, w2, b2v);
     const int64_t n = a.na * a.k;
     const int64_t groups = (a.na + 15) / 16;
@@ -141,7 +162,8 @@ __global__ void __launch_bounds__(256) k_decode_fwd(DecodeArgs a, float* __restr
         const int64_t a0 = grp * 16;
         const int64_t an = a0 + (lane & 15);
         v4f d1[2];
-        layer1(w1, a.feat, an, an < a.na, lane, d1);
+        float vin;
+        layer1(w1, a, an, an < a.na, lane, d1, vin);
         float h[2][4];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
@@ -206,14 +228,18 @@ constexpr int kBwdWaves = 4;
 constexpr int kBwdMaxBlocks = 256;
 
 // partial layout per block: dW2 [O][32] | db2 [O] | dW1 [32][32] | db1 [32]
-__host__ __device__ int64_t decode_bwd_partial_floats(int k) { return (int64_t)k * 11 * kF + k * 11 + kF * kF + kF; }
+// Partial row of one block: dW2 [O][32], db2 [O], dW1 [32][in_dim], db1 [32], dL/dcam [3].
+__host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim)
+{
+    return (int64_t)k * 11 * kF + k * 11 + (int64_t)kF * in_dim + kF + 3;
+}
 
 // The per-wave y buffers of a block double as the block's reduction buffer:
 // floats for both uses with OT output tiles.
+constexpr int bwd_red_floats(int OT) { return 16 * OT * (kF + 1) + kF * (kF + 4) + kF + 3; }
 constexpr int bwd_smem_floats(int OT)
 {
-    return kBwdWaves * 16 * lds_o(OT) > 16 * OT * (kF + 1) + kF * kF + kF ? kBwdWaves * 16 * lds_o(OT)
-                                                                          : 16 * OT * (kF + 1) + kF * kF + kF;
+    return kBwdWaves * 16 * lds_o(OT) > bwd_red_floats(OT) ? kBwdWaves * 16 * lds_o(OT) : bwd_red_floats(OT);
 }
 
 int decode_bwd_blocks(int64_t na)
@@ -235,10 +261,12 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
     float (*dys)[16][LO] = ys;
     __shared__ float hs[kBwdWaves][16][kF + 1];
     __shared__ float ps[kBwdWaves][16][kF + 1];
+    __shared__ float vs[kBwdWaves][16][4];  // view inputs of the wave's 16 anchors
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int O = a.k * 11;
     const int64_t n = a.na * a.k;
-    float w1[2][8], b1v[2][4], w2[OT][8], b2v[OT][4];
+    const bool view = a.in_dim > kF;  // uniform
+    float w1[2][9], b1v[2][4], w2[OT][8], b2v[OT][4];
     load_weights<OT>(a, lane, w1, b1v, w2, b2v);
     // transposed operands: W2^T (rows n, k = m) and W1^T in the accumulator-ordered K
     float w2t[2][OT * 4];
@@ -249,20 +277,26 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
             const int m = ks * 4 + (lane >> 4);
             w2t[nt][ks] = m < O ? a.W2[m * kF + nt * 16 + (lane & 15)] : 0.0f;
         }
-    float w1t[2][8];
+    // input tile 2 holds the four view inputs (rows 32..35), zero without them
+    float w1t[3][8];
 #pragma unroll
-    for (int ft = 0; ft < 2; ++ft)
+    for (int ft = 0; ft < 3; ++ft)
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
             const int nn = (st >> 2) * 16 + 4 * (lane >> 4) + (st & 3);
-            w1t[ft][st] = a.W1[nn * kF + ft * 16 + (lane & 15)];
+            const int f = ft * 16 + (lane & 15);
+            w1t[ft][st] = f < a.in_dim ? a.W1[nn * a.in_dim + f] : 0.0f;
         }
-    v4f accW2[OT][2], accW1[2][2];
+    v4f accW2[OT][2], accW1[2][3];
 #pragma unroll
     for (int t = 0; t < OT; ++t) accW2[t][0] = accW2[t][1] = v4f{0.f, 0.f, 0.f, 0.f};
-    accW1[0][0] = accW1[0][1] = accW1[1][0] = accW1[1][1] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int ft = 0; ft < 3; ++ft) accW1[nt][ft] = v4f{0.f, 0.f, 0.f, 0.f};
     float accB2[(kMaxO + 63) / 64] = {0.f, 0.f, 0.f};
     float accB1 = 0.0f;
+    float accCam[3] = {0.f, 0.f, 0.f};  // dL/d camera centre of this lane's anchors
 
     const int64_t groups = (a.na + 15) / 16;
     for (int64_t grp = (int64_t)blockIdx.x * kBwdWaves + wave; grp < groups; grp += (int64_t)gridDim.x * kBwdWaves) {
@@ -270,7 +304,9 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
         const int64_t an = a0 + (lane & 15);
         const bool avalid = an < a.na;
         v4f d1[2];
-        layer1(w1, a.feat, an, avalid, lane, d1);
+        float vin;
+        layer1(w1, a, an, avalid, lane, d1, vin);
+        if (view) vs[wave][lane & 15][lane >> 4] = vin;
         float pre[2][4], h[2][4];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
@@ -413,12 +449,28 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) dpre[mt][i] = (avalid && pre[mt][i] > 0.0f) ? dh[mt][i] : 0.0f;
-        // df = W1^T dpre
-        v4f df[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+        // df = W1^T dpre (tile 2: the view inputs)
+        v4f df[3] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
             df[0] = mfma4(w1t[0][st], dpre[st >> 2][st & 3], df[0]);
             df[1] = mfma4(w1t[1][st], dpre[st >> 2][st & 3], df[1]);
+            if (view) df[2] = mfma4(w1t[2][st], dpre[st >> 2][st & 3], df[2]);
+        }
+        if (view && lane < 16 && avalid) {
+            // lanes 0-15 hold rows 32..35 (dL/d distance, dL/d direction) of anchor `lane`:
+            // dL/dv = dL/ddelta d + (dL/dd - (dL/dd . d) d) / delta,  v = x_a - x_c
+            const float dist = vs[wave][lane][0];
+            const float d0 = vs[wave][lane][1], d1v = vs[wave][lane][2], d2 = vs[wave][lane][3];
+            const float gd = df[2][1] * d0 + df[2][2] * d1v + df[2][3] * d2;
+            const float dv[3] = {df[2][0] * d0 + (df[2][1] - gd * d0) / dist,
+                                 df[2][0] * d1v + (df[2][2] - gd * d1v) / dist,
+                                 df[2][0] * d2 + (df[2][3] - gd * d2) / dist};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                if (out.xa) out.xa[i * a.na + an] += dv[i];
+                accCam[i] -= dv[i];
+            }
         }
         if (out.feat && avalid) {
 #pragma unroll
@@ -444,19 +496,26 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
             const int64_t anc = a0 + al;
             const float f0 = anc < a.na ? a.feat[anc * kF + (lane & 15)] : 0.0f;
             const float f1 = anc < a.na ? a.feat[anc * kF + 16 + (lane & 15)] : 0.0f;
+            const float f2 = (view && (lane & 15) < 4) ? vs[wave][al][lane & 15] : 0.0f;
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
                 const float av = ps[wave][al][nt * 16 + (lane & 15)];
                 accW1[nt][0] = mfma4(av, f0, accW1[nt][0]);
                 accW1[nt][1] = mfma4(av, f1, accW1[nt][1]);
+                if (view) accW1[nt][2] = mfma4(av, f2, accW1[nt][2]);
             }
         }
         wsync();
     }
     // block reduction in wave order, then one partial row per block
     __syncthreads();
-    float* red = smem;  // bwd_smem_floats(OT) >= decode_bwd_partial_floats(k) floats
-    const int64_t PF = decode_bwd_partial_floats(a.k);
+    float* red = smem;  // bwd_smem_floats(OT) >= decode_bwd_partial_floats(k, in_dim) floats
+    const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim);
+    const int oW1 = O * kF + O, oB1 = oW1 + kF * a.in_dim, oCam = oB1 + kF;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) accCam[i] += __shfl_xor(accCam[i], o, 64);
     for (int w = 0; w < kBwdWaves; ++w) {
         if (wave == w) {
 #pragma unroll
@@ -483,17 +542,23 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-                for (int ft = 0; ft < 2; ++ft)
+                for (int ft = 0; ft < 3; ++ft)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int nn = nt * 16 + 4 * (lane >> 4) + i;
                         const int f = ft * 16 + (lane & 15);
-                        float* p = red + O * kF + O + nn * kF + f;
-                        *p = (w == 0 ? 0.0f : *p) + accW1[nt][ft][i];
+                        if (f < a.in_dim) {
+                            float* p = red + oW1 + nn * a.in_dim + f;
+                            *p = (w == 0 ? 0.0f : *p) + accW1[nt][ft][i];
+                        }
                     }
             if (lane < kF) {
-                float* p = red + O * kF + O + kF * kF + lane;
+                float* p = red + oB1 + lane;
                 *p = (w == 0 ? 0.0f : *p) + accB1;
+            }
+            if (lane < 3) {
+                float* p = red + oCam + lane;
+                *p = (w == 0 ? 0.0f : *p) + accCam[lane];
             }
         }
         __syncthreads();
@@ -504,8 +569,9 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
 // Sum of the per-block partial rows: each block owns 64 consecutive outputs;
 // its 4 waves add interleaved quarters of the rows and combine in wave order.
 __global__ void __launch_bounds__(256) k_decode_bwd_reduce(const float* __restrict__ partial, int nblocks, int64_t PF,
-                                                           int O, float* __restrict__ dW2, float* __restrict__ db2,
-                                                           float* __restrict__ dW1, float* __restrict__ db1)
+                                                           int O, int in_dim, float* __restrict__ dW2,
+                                                           float* __restrict__ db2, float* __restrict__ dW1,
+                                                           float* __restrict__ db1, float* __restrict__ dcam)
 {
     __shared__ float acc[4][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -519,11 +585,12 @@ __global__ void __launch_bounds__(256) k_decode_bwd_reduce(const float* __restri
     __syncthreads();
     if (wave != 0 || i >= PF) return;
     s = ((acc[0][lane] + acc[1][lane]) + acc[2][lane]) + acc[3][lane];
-    const int64_t oW2 = (int64_t)O * kF, oB2 = oW2 + O, oW1 = oB2 + kF * kF;
+    const int64_t oW2 = (int64_t)O * kF, oB2 = oW2 + O, oW1 = oB2 + (int64_t)kF * in_dim, oB1 = oW1 + kF;
     if (i < oW2) { if (dW2) dW2[i] = s; }
     else if (i < oB2) { if (db2) db2[i - oW2] = s; }
     else if (i < oW1) { if (dW1) dW1[i - oB2] = s; }
-    else { if (db1) db1[i - oW1] = s; }
+    else if (i < oB1) { if (db1) db1[i - oW1] = s; }
+    else { if (dcam && in_dim > kF) dcam[i - oB1] = s; }
 }
 
 void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, const vcgs_anchor_grads& out,
@@ -541,9 +608,9 @@ void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, con
         default: break;
     }
 #undef VCGS_DEC_BWD
-    const int64_t PF = decode_bwd_partial_floats(a.k);
-    k_decode_bwd_reduce<<<(unsigned)((PF + 63) / 64), 256, 0, s>>>(partial, nblocks, PF, a.k * 11, out.W2, out.b2,
-                                                                   out.W1, out.b1);
+    const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim);
+    k_decode_bwd_reduce<<<(unsigned)((PF + 63) / 64), 256, 0, s>>>(partial, nblocks, PF, a.k * 11, a.in_dim, out.W2,
+                                                                   out.b2, out.W1, out.b1, out.cam);
 }
 
 }  // namespace vcgs

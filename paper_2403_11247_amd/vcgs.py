@@ -68,7 +68,7 @@ class CCodebook(ctypes.Structure):
 
 class CAnchorGrads(ctypes.Structure):
     _fields_ = [("feat", c_p), ("offset", c_p), ("scaling", c_p), ("xa", c_p), ("W1", c_p), ("b1", c_p),
-                ("W2", c_p), ("b2", c_p), ("books", c_p), ("mask_logit", c_p)]
+                ("W2", c_p), ("b2", c_p), ("books", c_p), ("mask_logit", c_p), ("cam", c_p)]
 
 
 class CServerConfig(ctypes.Structure):
@@ -98,7 +98,8 @@ def lib():
                      "vcgs_l1_loss", "vcgs_decode_anchors", "vcgs_decode_anchors_backward", "vcgs_render_batch",
                      "vcgs_batch_check", "vcgs_set_option", "vcgs_get_option", "vcgs_profile_enable",
                      "vcgs_profile_read", "vcgs_count_enable", "vcgs_count_read", "vcgs_server_create",
-                     "vcgs_server_submit", "vcgs_server_progress", "vcgs_server_stats_read"):
+                     "vcgs_server_submit", "vcgs_server_progress", "vcgs_server_stats_read",
+                     "vcgs_decode_anchors_view", "vcgs_decode_anchors_view_backward"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -313,11 +314,11 @@ def render(means, scales, quats, opacities, colors, camera, pose, pose_tangent=N
     return RenderFn.apply(means, scales, quats, opacities, colors, pose_tangent, camera, pose, bg)
 
 
-def _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx):
+def _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx, in_dim=32):
     na, k = int(feat.shape[0]), int(offset.shape[1])
     ts = [_dev(t) for t in (xa, feat, scaling, offset, W1, b1, W2, b2)]
     assert ts[0].shape == (3, na) and ts[1].shape == (na, 32) and ts[2].shape == (3, na) and ts[3].shape == (na, k, 3)
-    assert ts[4].shape == (32, 32) and ts[6].shape == (k * 11, 32)
+    assert ts[4].shape == (32, in_dim) and ts[6].shape == (k * 11, 32), "W1 must be (32, 32), or (32, 36) with a camera"
     a = CAnchors(na, k, 32, *[_ptr(t) for t in ts[:4]])
     m = CMLP(*[_ptr(t) for t in ts[4:]])
     cb = None
@@ -329,11 +330,29 @@ def _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx):
     return a, m, cb, ts, na, k
 
 
+def _centre(cam_centre):
+    return None if cam_centre is None else (c_f * 3)(*[float(x) for x in np.asarray(cam_centre).reshape(3)])
+
+
+def camera_centre(pose):
+    """Camera centre -R^T t of a world-to-camera pose."""
+    R = np.asarray(pose.R, np.float64)
+    return -R.T @ np.asarray(pose.t, np.float64)
+
+
+def pose_grad_from_centre(pose, dcam):
+    """Share of dL/dxi (rho, phi) of the camera-centre input: (-R dL/dcam, 0)."""
+    R = torch.as_tensor(np.asarray(pose.R, np.float32), device=dcam.device)
+    return torch.cat([-(R @ dcam), torch.zeros(3, device=dcam.device)])
+
+
 def decode_anchors(xa, feat, scaling, offset, W1, b1, W2, b2, books=None, idx=None, mask_logit=None, mask_eps=0.01,
-                   ctx: Context | None = None):
-    """Decode anchors into na*k Gaussians (dict mean/scale/quat/opacity/color, SoA)."""
+                   cam_centre=None, ctx: Context | None = None):
+    """Decode anchors into na*k Gaussians (dict mean/scale/quat/opacity/color, SoA).
+    With cam_centre (3 values) the decode is view-dependent and W1 is (32, 36)."""
     ctx = ctx or default_context()
-    a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx)
+    a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx,
+                                            32 if cam_centre is None else 36)
     n = na * k
     dv = feat.device
     out = {"mean": torch.empty((3, n), device=dv), "scale": torch.empty((3, n), device=dv),
@@ -341,17 +360,24 @@ def decode_anchors(xa, feat, scaling, offset, W1, b1, W2, b2, books=None, idx=No
            "color": torch.empty((3, n), device=dv)}
     ob = CGaussianBuffers(*[_ptr(out[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
     ml = None if mask_logit is None else _dev(mask_logit)
-    _check(lib().vcgs_decode_anchors(ctx.h, ctypes.byref(a), ctypes.byref(m), ctypes.byref(cb) if cb else None,
-                                     _ptr(ml), c_f(mask_eps), ctypes.byref(ob), _stream()))
+    if cam_centre is None:
+        _check(lib().vcgs_decode_anchors(ctx.h, ctypes.byref(a), ctypes.byref(m), ctypes.byref(cb) if cb else None,
+                                         _ptr(ml), c_f(mask_eps), ctypes.byref(ob), _stream()))
+    else:
+        _check(lib().vcgs_decode_anchors_view(ctx.h, ctypes.byref(a), ctypes.byref(m),
+                                              ctypes.byref(cb) if cb else None, _ptr(ml), c_f(mask_eps),
+                                              _centre(cam_centre), ctypes.byref(ob), _stream()))
     del keep
     return out
 
 
 def decode_anchors_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG, books=None, idx=None, mask_logit=None,
-                            mask_eps=0.01, ctx: Context | None = None):
-    """Gradients of the decode; dG maps mean/scale/quat/opacity/color to dL/d(decoded Gaussians)."""
+                            mask_eps=0.01, cam_centre=None, ctx: Context | None = None):
+    """Gradients of the decode; dG maps mean/scale/quat/opacity/color to dL/d(decoded Gaussians).
+    With cam_centre the result also holds "cam", dL/d(camera centre)."""
     ctx = ctx or default_context()
-    a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx)
+    a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx,
+                                            32 if cam_centre is None else 36)
     dg = {f: None if dG.get(f) is None else _dev(dG[f]) for f in ("mean", "scale", "quat", "opacity", "color")}
     gb = CGaussianBuffers(*[_ptr(dg[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
     out = {"feat": torch.empty_like(keep[1]), "offset": torch.empty_like(keep[3]),
@@ -360,11 +386,18 @@ def decode_anchors_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG, books
     out["books"] = torch.empty_like(keep[8]) if books is not None else None
     ml = None if mask_logit is None else _dev(mask_logit)
     out["mask_logit"] = torch.empty_like(ml) if ml is not None else None
+    out["cam"] = torch.empty(3, device=keep[0].device) if cam_centre is not None else None
     ag = CAnchorGrads(*[_ptr(out[f]) for f in ("feat", "offset", "scaling", "xa", "W1", "b1", "W2", "b2", "books",
-                                                "mask_logit")])
-    _check(lib().vcgs_decode_anchors_backward(ctx.h, ctypes.byref(a), ctypes.byref(m),
-                                              ctypes.byref(cb) if cb else None, _ptr(ml), c_f(mask_eps),
-                                              ctypes.byref(gb), ctypes.byref(ag), _stream()))
+                                                "mask_logit", "cam")])
+    if cam_centre is None:
+        _check(lib().vcgs_decode_anchors_backward(ctx.h, ctypes.byref(a), ctypes.byref(m),
+                                                  ctypes.byref(cb) if cb else None, _ptr(ml), c_f(mask_eps),
+                                                  ctypes.byref(gb), ctypes.byref(ag), _stream()))
+    else:
+        _check(lib().vcgs_decode_anchors_view_backward(ctx.h, ctypes.byref(a), ctypes.byref(m),
+                                                       ctypes.byref(cb) if cb else None, _ptr(ml), c_f(mask_eps),
+                                                       _centre(cam_centre), ctypes.byref(gb), ctypes.byref(ag),
+                                                       _stream()))
     del keep
     return out
 
