@@ -237,6 +237,36 @@ def ba_section(args, dev):
                          "worst_ms": round(worst * 1e3, 3) if worst else None}}
 
 
+def view_decode_section(args, dev, steps=20, warmup=5):
+    """The room step with the view-dependent decode (eqs. (8)-(9)): the MLP
+    input is [f_a, delta, d] from the camera centre, so the decode runs per view
+    and its backward adds the camera-centre path to the pose gradient."""
+    import torch
+    from paper_2403_11247_amd import scenes, vcgs
+    a = scenes.room_anchors(40000, k=10)
+    m = scenes.room_mlp_view(seed=0)
+    cam, pose = scenes.room_camera()
+    tpose = scenes.perturb_pose(pose, 2)
+    A = [_up(x, dev) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    c_now, c_tgt = vcgs.camera_centre(pose), vcgs.camera_centre(tpose)
+    G0 = vcgs.decode_anchors(*A, cam_centre=c_tgt)
+    tC, tD, _, _ = vcgs.render_forward(*[G0[f] for f in F], cam, tpose, keep_state=False)
+
+    def step():
+        G = vcgs.decode_anchors(*A, cam_centre=c_now)
+        C, D, _, st = vcgs.render_forward(*[G[f] for f in F], cam, pose)
+        _, dlc, dld = vcgs.l1_loss(C, D, tC, tD, 0.5)
+        grads, dpose = vcgs.render_backward(st, *[G[f] for f in F], cam, pose, dlc, dld, None)
+        ag = vcgs.decode_anchors_backward(*A, grads, cam_centre=c_now)
+        st.free()
+        return dpose + vcgs.pose_grad_from_centre(pose, ag["cam"])
+
+    ms = _timed(step, steps, warmup)
+    return {"workload": "room step with the view-dependent decode (36-d MLP input), pose gradient through "
+                        "render and decode", "ms_per_step": round(ms, 4),
+            "mpix_s": round(cam.width * cam.height / (ms * 1e-3) / 1e6, 2)}
+
+
 def serve_section(args, dev):
     """Novel-view requests against a 1M-Gaussian room map (100k anchors at
     2 cm): Poisson arrivals at each rate, sizes uniform over 320x240, 640x480,
@@ -254,7 +284,7 @@ def serve_section(args, dev):
         ppp = max(ppp, st.view()["n_pairs"] / (c.width * c.height))
         st.free()
     torch.cuda.synchronize()
-    cfg = dict(max_views=16, slots=2, pair_budget=64 << 20, pairs_per_pixel=max(ppp * 1.25, 0.5))
+    cfg = dict(max_views=16, slots=2, pair_budget=192 << 20, pairs_per_pixel=max(ppp * 1.25, 0.5))
     srv = vcgs.Server(*gd, **cfg)
     warm = scenes.serve_trace(32, qps=1e6, seed=98)
     serve.replay(srv, warm)
@@ -407,6 +437,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 2 * src.numel() * 4
+    out["view_decode_step"] = view_decode_section(args, dev)
     if not args.no_ba:
         out["ba_window"] = ba_section(args, dev)
     if not args.no_serve:

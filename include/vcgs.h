@@ -220,9 +220,11 @@ int vcgs_batch_check(vcgs_ctx* ctx, int64_t* pairs);
  * Admission is by sort-buffer memory: each slot holds pair buffers of
  * pair_budget (tile, Gaussian) pairs (16 bytes each plus the sort histograms);
  * a request is estimated at pixels * pairs_per_pixel pairs and a pass takes
- * waiting requests in arrival order while their estimates fit.  A pass whose
- * actual pair count exceeds its buffers is run again (its slot grown to the
- * count, the estimate raised); results never depend on the batching: every
+ * waiting requests in arrival order while their estimates fit.  The estimate
+ * starts at cfg->pairs_per_pixel and then follows 1.25 x the largest pairs per
+ * pixel observed over the last 32 passes.  A pass whose actual pair count
+ * exceeds its buffers is run again (its slot grown to the count, the estimate
+ * raised); results never depend on the batching: every
  * request's images equal those of vcgs_render_forward of it alone, bit for
  * bit. */
 typedef struct vcgs_server vcgs_server;

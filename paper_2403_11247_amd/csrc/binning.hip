@@ -101,10 +101,11 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
     const int64_t n = nvis ? min((int64_t)*nvis, n_all) : n_all;
     const int64_t P = min((int64_t)*total, cap);
     if (blockIdx.x == 0 && threadIdx.x == 0 && overflow && (int64_t)*total > cap) *overflow = 1u;
-    const int64_t p0 = (int64_t)blockIdx.x * kChunk;
-    if (p0 >= P) return;  // uniform
+    // chunks strided by the grid, so a generous capacity does not launch blocks that only exit
+    for (int64_t c = blockIdx.x; c * kChunk < P; c += gridDim.x) {  // uniform
+    const int64_t p0 = c * kChunk;
     const int64_t p1 = min(p0 + kChunk, P);
-    int64_t kbase = chunk_start[blockIdx.x];
+    int64_t kbase = chunk_start[c];
     int64_t pcur = p0;
     while (pcur < p1 && kbase < n) {  // uniform; every round consumes kSpan entries or ends the chunk
         const int S = (int)min((int64_t)kSpan, n - kbase);
@@ -138,6 +139,7 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
         pcur = pend;
         kbase += S;
     }
+    }
 }
 
 void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis, const uint32_t* order,
@@ -147,7 +149,8 @@ void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis
 {
     if (n_entries <= 0 || cap <= 0) return;
     k_chunk_starts<<<(unsigned)((n_entries + 255) / 256), 256, 0, s>>>(n_entries, nvis, offs, cnt, cap, chunk_start);
-    k_emit_pairs<<<(unsigned)((cap + kChunk - 1) / kChunk), kEmitG, 0, s>>>(
+    const int64_t blocks = std::min<int64_t>((cap + kChunk - 1) / kChunk, 4096);
+    k_emit_pairs<<<(unsigned)blocks, kEmitG, 0, s>>>(
         t, n_entries, nvis, order, offs, cnt, rect, chunk_start, tile_ids, gids, cap, total, overflow);
 }
 
@@ -160,18 +163,21 @@ __global__ void __launch_bounds__(256) k_tile_ranges(int64_t cap, const uint32_t
                                                      uint32_t* __restrict__ ranges)
 {
     const int64_t P = ndev ? min((int64_t)*ndev, cap) : cap;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    const uint32_t cur = t[p];
-    if (cur >= n_tiles) return;
-    if (p == 0 || t[p - 1] != cur) ranges[2 * cur] = (uint32_t)p;
-    if (p == P - 1 || t[p + 1] != cur) ranges[2 * cur + 1] = (uint32_t)(p + 1);
+    // grid-stride: the grid is sized for at most 4M pairs per sweep, so a
+    // generous capacity does not launch blocks that only exit
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t cur = t[p];
+        if (cur >= n_tiles) continue;
+        if (p == 0 || t[p - 1] != cur) ranges[2 * cur] = (uint32_t)p;
+        if (p == P - 1 || t[p + 1] != cur) ranges[2 * cur + 1] = (uint32_t)(p + 1);
+    }
 }
 
 void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s)
 {
     if (P.cap <= 0) return;
-    k_tile_ranges<<<(unsigned)((P.cap + 255) / 256), 256, 0, s>>>(P.cap, P.dev, tile_sorted, n_tiles, ranges);
+    const int64_t blocks = std::min<int64_t>((P.cap + 255) / 256, 16384);
+    k_tile_ranges<<<(unsigned)blocks, 256, 0, s>>>(P.cap, P.dev, tile_sorted, n_tiles, ranges);
 }
 
 }  // namespace vcgs

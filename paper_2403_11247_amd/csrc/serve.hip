@@ -56,8 +56,21 @@ struct vcgs_server {
     std::vector<Slot> slots;
     std::deque<int64_t> ready;
     int64_t next_ticket = 0, passes = 0, reruns = 0;
-    double ppp = 1.0;
+    double ppp = 1.0;           // pairs-per-pixel estimate used for admission
+    double recent[32] = {};     // observed pairs per pixel of the last 32 passes
+    int n_recent = 0;
     bool oom = false;
+
+    // The estimate follows 1.25 x the largest observed pairs-per-pixel of the
+    // last 32 passes (an underestimate only costs a rerun).
+    void observe(double obs)
+    {
+        recent[n_recent % 32] = obs;
+        ++n_recent;
+        double mx = 0.0;
+        for (int i = 0; i < std::min(n_recent, 32); ++i) mx = std::max(mx, recent[i]);
+        ppp = std::max(1.25 * mx, 1e-3);
+    }
     std::vector<hipEvent_t> spare_events;
 
     hipEvent_t event()
@@ -197,7 +210,7 @@ struct vcgs_server {
             // overflow: grow the slot, raise the estimate, rerun these requests first
             int64_t pix = 0;
             for (const Req& r : sl.reqs) pix += r.pixels;
-            ppp = std::max(ppp, 1.125 * (double)total / (double)std::max<int64_t>(pix, 1));
+            observe((double)total / (double)std::max<int64_t>(pix, 1));
             ++reruns;
             for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it) queue.push_front(*it);
             sl.reqs.clear();
@@ -206,10 +219,13 @@ struct vcgs_server {
                 return alloc_pairs(sl, std::min<int64_t>(total + total / 8 + 4096, kMaxSortItems));
             return VCGS_OK;
         }
+        int64_t pix = 0;
         for (const Req& r : sl.reqs) {
             ready.push_back(r.ticket);
             spare_events.push_back(r.submitted);
+            pix += r.pixels;
         }
+        if (pix > 0) observe((double)total / (double)pix);
         sl.reqs.clear();
         return VCGS_OK;
     }

@@ -187,7 +187,8 @@ __device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v)
 __global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restrict__ keys, int64_t cap,
                                                         const uint32_t* __restrict__ ndev, int passes,
                                                         uint32_t* __restrict__ ghist, int drop,
-                                                        uint32_t* __restrict__ kept)
+                                                        uint32_t* __restrict__ kept, uint32_t* __restrict__ state,
+                                                        int64_t state_stride)
 {
     __shared__ uint32_t h[4][kMaxPasses][kBins];
     __shared__ uint32_t s_kept;
@@ -197,9 +198,17 @@ __global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restri
     __syncthreads();
     const int w = threadIdx.x >> 6;
     uint32_t mine = 0u;
-    // each thread counts kItems keys, all loaded before any is counted so that
-    // their latencies overlap; the block's items are strided by kThreads
-    const int64_t i0 = (int64_t)blockIdx.x * kBlockItems;
+    // zero the passes' look-back words of the partitions they will use
+    // (state_stride words per pass; the passes run after this kernel)
+    {
+        const int64_t words = ((n + kBlockItems - 1) / kBlockItems) * kBins;
+        const int64_t gt = (int64_t)blockIdx.x * kThreads + threadIdx.x, gs = (int64_t)gridDim.x * kThreads;
+        for (int p = 0; p < passes; ++p)
+            for (int64_t i = gt; i < words; i += gs) state[(int64_t)p * state_stride + i] = 0u;
+    }
+    // each thread counts kItems keys per 4096-item chunk, all loaded before any
+    // is counted so that their latencies overlap; chunks are strided by the grid
+    for (int64_t i0 = (int64_t)blockIdx.x * kBlockItems; i0 < n; i0 += (int64_t)gridDim.x * kBlockItems) {
     uint32_t key[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
@@ -226,6 +235,7 @@ __global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restri
                 atomicAdd(&h[w][p][d], 1u);
             }
         }
+    }
     }
     if (drop && mine) atomicAdd(&s_kept, mine);
     __syncthreads();
@@ -255,6 +265,10 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
     __shared__ uint32_t s_out[kBins];    // global position of that slot
     __shared__ uint32_t s_part;
     const int64_t n = dev_count(cap, ndev);
+    // blocks take partitions in counter order until none is left, so the grid
+    // need not match the (device-side) item count
+    for (;;) {
+    __syncthreads();  // the previous partition's LDS is no longer read
     if (threadIdx.x == 0) s_part = atomicAdd(counter, 1u);
     for (int i = threadIdx.x; i < 4 * kBins; i += kThreads) (&cnt[0][0])[i] = 0u;
     __syncthreads();
@@ -353,6 +367,7 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
         keys_out[pos] = k;
         vals_out[pos] = s_val[i];
     }
+    }
 }
 
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
@@ -368,17 +383,19 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, 
     uint32_t* kept_dev = counters + kMaxPasses;
     uint32_t* state = t.hist + kStateBase;
     const int drop = kept != nullptr;
-    launch_fill_u32(t.hist, 0u, kStateBase + (int64_t)passes * nb * kBins, s);
-    const int hb = nb;  // one block per 4096 items
+    launch_fill_u32(t.hist, 0u, kStateBase, s);  // histograms, counters (the look-back words: k_sort_hist)
+    const int hb = std::min(nb, 1024);
+    const int pb = std::min(nb, 2048);
     const uint32_t* first = keys_src ? keys_src : keys;
-    k_sort_hist<<<hb, kThreads, 0, s>>>(first, n.cap, n.dev, passes, ghist, drop, kept_dev);
+    k_sort_hist<<<hb, kThreads, 0, s>>>(first, n.cap, n.dev, passes, ghist, drop, kept_dev, state,
+                                        (int64_t)nb * kBins);
     uint32_t* kb[2] = {keys, t.keys_alt};
     uint32_t* vb[2] = {vals, t.vals_alt};
     int cur = 0;
     for (int p = 0; p < passes; ++p) {
         // after a dropping first pass the later ones see only the kept items
         const uint32_t* nd = (p > 0 && drop) ? kept_dev : n.dev;
-        k_sort_pass<<<nb, kThreads, 0, s>>>(p == 0 ? first : kb[cur], identity_vals ? nullptr : vb[cur],
+        k_sort_pass<<<pb, kThreads, 0, s>>>(p == 0 ? first : kb[cur], identity_vals ? nullptr : vb[cur],
                                             kb[cur ^ 1], vb[cur ^ 1],
                                             n.cap, nd, 8 * p, ghist + p * kBins,
                                             state + (int64_t)p * nb * kBins, counters + p, p == 0 ? drop : 0);

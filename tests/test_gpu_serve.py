@@ -78,9 +78,11 @@ def test_admission_limits_and_overflow_reruns(V, room_map):
     say("overflow", st)
     assert st["reruns"] >= 1 and st["pairs_per_pixel"] > 0.01
     assert_same(got, ref, "overflow")
-    # a budget that admits one request per pass
+    # a budget that admits one request per pass at first; the estimate then
+    # follows the observed pairs per pixel and the grown slots admit more
     got, st = serve_all(V, gd, trace, max_views=8, slots=2, pair_budget=1000, pairs_per_pixel=1e3)
-    assert st["passes"] - st["reruns"] == len(trace), st
+    say("budget", st)
+    assert st["passes"] - st["reruns"] >= 2 and st["pairs_per_pixel"] < 1e3, st
     assert_same(got, ref, "budget")
 
 
