@@ -70,10 +70,11 @@ def project(mean, scale, quat, cam, R, t):
     return pc, u, v, Q
 
 
-def render(mean, scale, quat, opacity, color, cam, R, t, bg=(0.0, 0.0, 0.0), xi=None):
+def render(mean, scale, quat, opacity, color, cam, R, t, bg=(0.0, 0.0, 0.0), xi=None, hits=None):
     """Brute-force render; every input a float64 tensor (SoA shapes as in
     the ABI).  ``xi`` (6,) perturbs the pose on the left.  Returns
-    (C (3,H,W), D (H,W), A (H,W), T_final (H,W))."""
+    (C (3,H,W), D (H,W), A (H,W), T_final (H,W)).  ``hits`` (numpy, n) if
+    given receives each Gaussian's number of blended pixels (eq. (13), h)."""
     if xi is not None:
         E = torch.matrix_exp(_skew(xi[3:6]))
         R = E @ R
@@ -102,6 +103,8 @@ def render(mean, scale, quat, opacity, color, cam, R, t, bg=(0.0, 0.0, 0.0), xi=
         stop = valid & (Tn.detach() < T_MIN)
         take = valid & ~stop
         w = torch.where(take, alpha * T, torch.zeros_like(T))
+        if hits is not None:
+            hits[i] = int(take.sum())
         Cc = Cc + w[None, :] * color[:, i:i + 1]                  # eq. (16)
         D = D + w * Z[i]                                          # eq. (17)
         A = A + w                                                 # eq. (18)

@@ -407,6 +407,40 @@ void orc_render_fwd(int64_t n, const double* splat, const double* opac, const do
 }
 
 /* ------------------------------------------------------------------------ */
+/* Hit counts (paper eq. (13), h): per Gaussian, the number of pixels whose   */
+/* composite blends it (alpha >= 1/255, before the pixel stops).  amb counts, */
+/* per Gaussian, the flagged pixels whose tile list holds it: there the FP32  */
+/* renderer may take either side of a threshold, so its count may differ by  */
+/* up to amb.                                                                 */
+/* ------------------------------------------------------------------------ */
+void orc_hit_counts(int64_t n, const double* splat, const double* opac, const orc_camera* cam,
+                    const uint32_t* ranges, const uint32_t* gids, const uint8_t* flags, uint32_t* hits,
+                    uint32_t* amb)
+{
+    const int W = cam->width, H = cam->height, tile = cam->tile;
+    const int tiles_x = (W + tile - 1) / tile;
+    const int64_t HW = (int64_t)W * H;
+    memset(hits, 0, sizeof(uint32_t) * (size_t)n);
+    memset(amb, 0, sizeof(uint32_t) * (size_t)n);
+    for (int64_t p = 0; p < HW; ++p) {
+        const int x = (int)(p % W), y = (int)(p / W);
+        const int t = (y / tile) * tiles_x + (x / tile);
+        double T = 1.0;
+        for (uint32_t k = ranges[2 * t]; k < ranges[2 * t + 1]; ++k) {
+            const uint32_t g = gids[k];
+            const orc_fp f = footprint(splat + ORC_SPLAT * (size_t)g, opac[g], x + 0.5, y + 0.5);
+            if (f.alpha < (double)ORC_ALPHA_MIN) continue;
+            const double Tn = T * (1.0 - f.alpha);
+            if (Tn < (double)ORC_T_MIN) break;
+            hits[g] += 1u;
+            T = Tn;
+        }
+        if (flags[p] & 3u)
+            for (uint32_t k = ranges[2 * t]; k < ranges[2 * t + 1]; ++k) amb[gids[k]] += 1u;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Adjoint of the compositing: exact derivative of the per-pixel sums.       */
 /* g2 holds per Gaussian: du, dv, dA, dB, dC, dopacity, dr, dg, db, ddepth.  */
 /* ------------------------------------------------------------------------ */

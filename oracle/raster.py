@@ -117,6 +117,19 @@ def render(g, cam, pose, bg=(0.0, 0.0, 0.0)):
                 color=C, depth=D, alpha=A, T_final=T, n_contrib=nc, flags=fl, bg=bgv)
 
 
+def hit_counts(g, cam, fwd):
+    """Per-Gaussian hit counts (eq. (13), h) of a forward result ``fwd`` of
+    ``render``, and per-Gaussian ambiguity bounds (flagged pixels whose tile
+    list holds the Gaussian)."""
+    hits = np.empty(g.n, np.uint32)
+    amb = np.empty(g.n, np.uint32)
+    o = _c(g.opacity, np.float64)
+    c = _cam(cam)
+    lib().orc_hit_counts(ctypes.c_int64(g.n), _p(fwd["splat"]), _p(o), ctypes.byref(c), _p(fwd["ranges"]),
+                         _p(fwd["gids"]), _p(np.ascontiguousarray(fwd["flags"])), _p(hits), _p(amb))
+    return hits, amb
+
+
 def render_backward(g, cam, pose, fwd, dl_dc, dl_dd, dl_da):
     """Exact FP64 gradients of sum(dl_dc*C + dl_dd*D + dl_da*A) with respect
     to mean, scale, quat, opacity, colour (same shapes as the inputs) and the

@@ -546,3 +546,62 @@ def test_camera_centre_pose_gradient():
         e[i] = h
         fd = (w @ centre(e) - w @ centre(-e)) / (2 * h)
         assert abs(fd - g[i]) < 1e-7, (i, fd, g[i])
+
+
+# ---------------------------------------------------------------------------
+# mask training step (eq. (13)): hit counts, mask loss, pruning
+# ---------------------------------------------------------------------------
+
+def test_hit_counts_tiled_equal_brute_force():
+    from oracle import mask as omask
+    for seed, pose in ((3, scenes.identity_pose()),
+                       (4, scenes.perturb_pose(scenes.identity_pose(), 9, trans=0.1, rot_deg=5.0))):
+        g = scenes.random_scene(150, seed=seed, xy=0.6, log_scale=(0.03, 0.15))
+        cam = scenes.Camera(40, 28, 30.0, 30.0, 20.0, 14.0)
+        ref = raster.render(g, cam, pose)
+        hits, amb = raster.hit_counts(g, cam, ref)
+        hb = np.zeros(g.n, np.int64)
+        with torch.no_grad():
+            ts = [torch.tensor(np.asarray(a, np.float64)) for a in (g.mean, g.scale, g.quat, g.opacity, g.color)]
+            brute.render(*ts, cam, torch.tensor(pose.R, dtype=torch.float64),
+                         torch.tensor(pose.t, dtype=torch.float64), hits=hb)
+        assert hits.sum() > 0
+        flagged = (ref["flags"] & 3) != 0
+        ok = amb == 0
+        np.testing.assert_array_equal(hits[ok], hb[ok])
+        assert np.all(np.abs(hits.astype(np.int64) - hb) <= amb)
+        # culled Gaussians have no hits; a Gaussian's hits never exceed its rectangle's pixels
+        assert np.all(hits[ref["count"] == 0] == 0)
+        assert np.all(hits <= ref["count"].astype(np.int64) * 256)
+        assert flagged.sum() < flagged.size
+
+
+def test_mask_loss_gradient_and_closed_form():
+    from oracle import mask as omask
+    rng = np.random.default_rng(5)
+    m = rng.normal(1.0, 2.0, 200)
+    inf = rng.uniform(size=200) < 0.6
+    loss, grad = omask.mask_loss(m, inf, weight=0.3)
+    assert np.all(grad[~inf] == 0)
+    h = 1e-6
+    for j in np.nonzero(inf)[0][:8]:
+        mp, mm = m.copy(), m.copy()
+        mp[j] += h
+        mm[j] -= h
+        fd = (omask.mask_loss(mp, inf, 0.3)[0] - omask.mask_loss(mm, inf, 0.3)[0]) / (2 * h)
+        assert abs(fd - grad[j]) < 1e-9
+    # sigmoid(0) = 1/2 whatever the window
+    assert abs(omask.mask_loss(np.zeros(50), np.ones(50, bool), 2.0)[0] - 1.0) < 1e-15
+    assert omask.mask_loss(m, np.zeros(200, bool))[0] == 0.0
+
+
+def test_prune_keeps_order_and_conditions():
+    from oracle import mask as omask
+    rng = np.random.default_rng(6)
+    m = rng.normal(0.0, 3.0, 500)
+    hits = rng.integers(0, 5, 500)
+    keep, idx = omask.prune(m, hits, eps=0.01, min_hits=2)
+    assert np.all(np.diff(idx.astype(np.int64)) > 0)
+    assert np.array_equal(keep[idx], np.ones(idx.size, bool)) and keep.sum() == idx.size
+    sg = 1 / (1 + np.exp(-m))
+    assert np.all(keep == ((sg > 0.01) & (hits >= 2)))
