@@ -265,6 +265,32 @@ typedef struct {
 } vcgs_server_stats;
 int vcgs_server_stats_read(const vcgs_server* srv, vcgs_server_stats* out);
 
+/* ---- mask training step (paper Sec. 3.3, eq. (13)) --------------------- */
+
+/* vcgs_render_forward that also adds, for every Gaussian, the number of
+ * pixels whose composite blends it (alpha >= 1/255, before the pixel stops)
+ * to hits [n] (device uint32; accumulated, so a sliding window sums its
+ * views; the caller zeroes it). */
+int vcgs_render_forward_hits(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camera* cam, const vcgs_pose* pose,
+                             const float bg[3], vcgs_images* out, vcgs_state** state_out, uint32_t* hits,
+                             void* stream);
+
+/* Mask loss restricted to the view frustum: L_m = weight * mean over the
+ * Gaussians with in_frustum_count[g] > 0 (e.g. the tile counts of a render
+ * state; NULL = all n) of sigmoid(mask_logit[g]).  loss (device, 1 float, or
+ * NULL) is overwritten; dl_dm (device [n] or NULL) gets weight * sigmoid'(m) /
+ * N ADDED for the Gaussians in the frustum (others unchanged).  Deterministic. */
+int vcgs_mask_loss(vcgs_ctx* ctx, int64_t n, const float* mask_logit, const uint32_t* in_frustum_count,
+                   float weight, float* dl_dm, float* loss, void* stream);
+
+/* Pruning at the end of a window: keep[g] = sigmoid(mask_logit[g]) > mask_eps
+ * and hits[g] >= min_hits (hits NULL: the mask alone); kept_index receives the
+ * kept Gaussians' indices in increasing order (capacity n; NULL to skip).
+ * keep is uint8 [n] (or NULL).  *n_kept (host) receives their number; the call
+ * synchronises the stream to read it. */
+int vcgs_mask_prune(vcgs_ctx* ctx, int64_t n, const float* mask_logit, float mask_eps, const uint32_t* hits,
+                    uint32_t min_hits, uint8_t* keep, uint32_t* kept_index, int64_t* n_kept, void* stream);
+
 /* ---- anchor decode ---------------------------------------------------- */
 
 /* Voxel anchors (paper Sec. 3.2): position x_a [3][na], feature f_a

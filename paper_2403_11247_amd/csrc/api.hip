@@ -188,6 +188,46 @@ int vcgs_decode_anchors_view_backward(vcgs_ctx* ctx, const vcgs_anchors* a, cons
     return decode_bwd(ctx, a, mlp, cb, mask_logit, mask_eps, cam_centre, dG, out, stream);
 }
 
+int vcgs_mask_loss(vcgs_ctx* ctx, int64_t n, const float* mask_logit, const uint32_t* in_frustum_count,
+                   float weight, float* dl_dm, float* loss, void* stream)
+{
+    if (!ctx) return fail(VCGS_E_INVALID, "ctx is NULL");
+    if (n < 0) return fail(VCGS_E_INVALID, "negative Gaussian count");
+    if (n > 0 && !mask_logit) return fail(VCGS_E_INVALID, "mask_logit is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(&ctx->pool);
+    float* partial = sc.get<float>(2 * (int64_t)mask_loss_blocks(n) + 1);
+    if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (mask loss)");
+    launch_mask_loss(n, mask_logit, in_frustum_count, weight, dl_dm, loss, partial, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return VCGS_OK;
+}
+
+int vcgs_mask_prune(vcgs_ctx* ctx, int64_t n, const float* mask_logit, float mask_eps, const uint32_t* hits,
+                    uint32_t min_hits, uint8_t* keep, uint32_t* kept_index, int64_t* n_kept, void* stream)
+{
+    if (!ctx || !n_kept) return fail(VCGS_E_INVALID, "ctx or n_kept is NULL");
+    if (n < 0 || n > kMaxSortItems) return fail(VCGS_E_INVALID, "n must be in [0, 2^30)");
+    if (n > 0 && !mask_logit) return fail(VCGS_E_INVALID, "mask_logit is NULL");
+    if (!(mask_eps > 0.0f && mask_eps < 1.0f)) return fail(VCGS_E_INVALID, "mask_eps must be in (0, 1)");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(&ctx->pool);
+    uint32_t* flags = sc.get<uint32_t>(n);
+    uint32_t* offs = sc.get<uint32_t>(n);
+    uint32_t* cnt = sc.get<uint32_t>(4);
+    uint32_t* tmp = sc.get<uint32_t>(scan_temp_words(n) + 8);
+    if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (prune)");
+    const float thr = (float)std::log((double)mask_eps / (1.0 - (double)mask_eps));
+    launch_mask_prune(n, mask_logit, thr, hits, min_hits, keep, flags, offs, kept_index, cnt, tmp, s);
+    HIP_TRY(hipMemcpyAsync(ctx->host_u32, cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_kept = ctx->host_u32[0];
+    return VCGS_OK;
+}
+
 int vcgs_set_option(int key, int value)
 {
     Options& o = options();

@@ -320,8 +320,9 @@ int vcgs_state_query(const vcgs_state* st, vcgs_state_view* out)
     return VCGS_OK;
 }
 
-int vcgs_render_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camera* cam, const vcgs_pose* pose,
-                        const float bg[3], vcgs_images* out, vcgs_state** state_out, void* stream)
+static int render_forward_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camera* cam,
+                               const vcgs_pose* pose, const float bg[3], vcgs_images* out, vcgs_state** state_out,
+                               uint32_t* hits, void* stream)
 {
     if (!ctx) return fail(VCGS_E_INVALID, "ctx is NULL");
     int rc;
@@ -351,6 +352,7 @@ int vcgs_render_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camer
     f.vt.alpha[0] = out->alpha;
     f.vt.t_final[0] = st->t_final;
     f.vt.n_contrib[0] = st->n_contrib;
+    f.vt.hits = hits;
     auto drop = [&](int code, const std::string& m) {
         st->release();
         delete st;
@@ -391,6 +393,20 @@ int vcgs_render_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camer
         delete st;
     }
     return VCGS_OK;
+}
+
+int vcgs_render_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camera* cam, const vcgs_pose* pose,
+                        const float bg[3], vcgs_images* out, vcgs_state** state_out, void* stream)
+{
+    return render_forward_impl(ctx, g, cam, pose, bg, out, state_out, nullptr, stream);
+}
+
+int vcgs_render_forward_hits(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camera* cam, const vcgs_pose* pose,
+                             const float bg[3], vcgs_images* out, vcgs_state** state_out, uint32_t* hits,
+                             void* stream)
+{
+    if (!hits) return fail(VCGS_E_INVALID, "hits is NULL");
+    return render_forward_impl(ctx, g, cam, pose, bg, out, state_out, hits, stream);
 }
 
 int vcgs_render_backward(vcgs_ctx* ctx, const vcgs_state* st_, const vcgs_gaussians* g, const vcgs_camera* cam,

@@ -58,6 +58,7 @@ struct ViewTab {
     const float* dl_dd[kMaxViews];
     const float* dl_da[kMaxViews];
     float bg[3];
+    uint32_t* hits;  // optional: per-Gaussian count of blended pixels, accumulated (Gaussian = entry % n)
 };
 
 // Projected splat record, 64 bytes: (u, v, u_lo, v_lo) (ex, ey, j1, j2) (o, r, g, b) (depth, -, -, -).
@@ -174,6 +175,18 @@ void launch_l1_loss_views(const LossTab& t, float* loss, float* partial, hipStre
 // partial: l1_loss_blocks(npix) floats of scratch (only used when loss != nullptr)
 void launch_l1_loss(int64_t npix, const float* c, const float* d, const float* tc, const float* td,
                     float w_depth, float* dl_dc, float* dl_dd, float* loss, float* partial, hipStream_t s);
+
+// mask.hip: mask loss over the view frustum and pruning (paper eq. (13)).
+// in_frustum: per-Gaussian tile counts of the view (count > 0 = in the frustum).
+// partial: mask_loss_blocks(n) * 2 floats of scratch.
+int mask_loss_blocks(int64_t n);
+void launch_mask_loss(int64_t n, const float* logit, const uint32_t* count, float weight, float* dl_dm, float* loss,
+                      float* partial, hipStream_t s);
+// keep[g] = sigmoid(m) > eps && hits[g] >= min_hits (m above thr = logit(eps));
+// kept_index: stable compaction; n_kept (device, 1 word).  tmp: scan_temp_words(n) + 8 words.
+void launch_mask_prune(int64_t n, const float* logit, float thr, const uint32_t* hits, uint32_t min_hits,
+                       uint8_t* keep, uint32_t* flags_tmp, uint32_t* offs_tmp, uint32_t* kept_index,
+                       uint32_t* n_kept, uint32_t* scan_tmp, hipStream_t s);
 
 // Process-wide kernel configuration (vcgs_set_option).
 struct Options {

@@ -126,6 +126,7 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     constexpr int LR = 64 / SW;            // rows of lanes
     constexpr int SH = LR * PPL;           // height of a wave's pixel block
     __shared__ float4 slab[4][64][4];
+    __shared__ uint32_t slab_gid[4][64];  // entries of the slab (kept only for hit counts)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gw = (sched ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + wave;
     const uint32_t gt = (uint32_t)(gw / WPT);
@@ -134,6 +135,7 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     const int vw = view_of(tab, gt);
     const CamK& cam = tab.cam[vw];
     const int tile = (int)(gt - cam.tile_base);
+    uint32_t* __restrict__ hits = tab.hits;  // uniform
     float* __restrict__ color = tab.color[vw];
     float* __restrict__ depth = tab.depth[vw];
     float* __restrict__ alpha_out = tab.alpha[vw];
@@ -168,7 +170,7 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     // 1/255 takes alpha 0, which leaves T (>= 1e-4 while running) unchanged;
     // one that would take T below 1e-4 stops the pixel with weight 0; a stopped
     // pixel (T < 0) gets Tn <= 0 and so stays stopped with weight 0.
-    auto blend = [&](int j, const Fp& f, const float4& rc, float rz, uint32_t idx, bool en) {
+    auto blend = [&](int j, const Fp& f, const float4& rc, float rz, uint32_t idx, bool en) -> bool {
         const float a = (en && f.alpha >= kAlphaMin) ? f.alpha : 0.0f;
         const float Tn = T[j] * (1.0f - a);
         const bool stop = Tn < kTMin;
@@ -178,6 +180,11 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
         dd[j] += w * rz; aa[j] += w;
         last[j] = w > 0.0f ? idx : last[j];
         T[j] = stop ? -fabsf(T[j]) : Tn;
+        return w > 0.0f;
+    };
+    // pixels of the wave that blended Gaussian slot k, added to its hit count
+    auto add_hits = [&](int k, uint32_t nh) {
+        if (lane == 0 && nh) atomicAdd(hits + slab_gid[wave][k] % (uint32_t)tab.n, nh);
     };
     auto wave_done = [&]() {
         bool mine = true;
@@ -191,34 +198,45 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
         const uint32_t idx = b + lane;
         bool keep = false;
         if (idx < end) {
-            const Splat sp = rec[gids[idx]];
+            const uint32_t e = gids[idx];
+            const Splat sp = rec[e];
             keep = !cull || reaches_rect(sp, rx0, rx1, ry0, ry1);
             slab[wave][lane][0] = sp.a;
             slab[wave][lane][1] = sp.b;
             slab[wave][lane][2] = sp.c;
             slab[wave][lane][3] = sp.d;
+            if (hits) slab_gid[wave][lane] = e;
         }
-        uint64_t hits = __ballot(keep);
+        uint64_t todo = __ballot(keep);
         wave_lds_sync();
         const uint32_t base = b - start + 1u;
         // two Gaussians per round: both footprints are independent, the blends are in order
-        while (hits) {
-            const int k1 = __builtin_ctzll(hits);
-            hits &= hits - 1ull;
-            const bool two = hits != 0ull;
-            const int k2 = two ? __builtin_ctzll(hits) : k1;
-            hits &= hits - 1ull;
+        while (todo) {
+            const int k1 = __builtin_ctzll(todo);
+            todo &= todo - 1ull;
+            const bool two = todo != 0ull;
+            const int k2 = two ? __builtin_ctzll(todo) : k1;
+            todo &= todo - 1ull;
             const float4 a1 = slab[wave][k1][0], b1 = slab[wave][k1][1], r1 = slab[wave][k1][2];
             const float z1 = slab[wave][k1][3].x;
             const float4 a2 = slab[wave][k2][0], b2 = slab[wave][k2][1], r2 = slab[wave][k2][2];
             const float z2 = slab[wave][k2][3].x;
             const float dx1 = (pxf - a1.x) - a1.z, dx2 = (pxf - a2.x) - a2.z;
+            uint32_t h1 = 0u, h2 = 0u;
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 const Fp f1 = footprint(dx1, (dy[j] - a1.y) - a1.w, b1.x, b1.y, b1.z, b1.w, r1.x);
                 const Fp f2 = footprint(dx2, (dy[j] - a2.y) - a2.w, b2.x, b2.y, b2.z, b2.w, r2.x);
-                blend(j, f1, r1, z1, base + (uint32_t)k1, true);
-                blend(j, f2, r2, z2, base + (uint32_t)k2, two);
+                const bool t1 = blend(j, f1, r1, z1, base + (uint32_t)k1, true);
+                const bool t2 = blend(j, f2, r2, z2, base + (uint32_t)k2, two);
+                if (hits) {
+                    h1 += (uint32_t)__popcll(__ballot(t1));
+                    h2 += (uint32_t)__popcll(__ballot(t2));
+                }
+            }
+            if (hits) {
+                add_hits(k1, h1);
+                if (two) add_hits(k2, h2);
             }
             if (wave_done()) { all_done = true; break; }
         }

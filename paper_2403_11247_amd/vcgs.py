@@ -99,7 +99,8 @@ def lib():
                      "vcgs_batch_check", "vcgs_set_option", "vcgs_get_option", "vcgs_profile_enable",
                      "vcgs_profile_read", "vcgs_count_enable", "vcgs_count_read", "vcgs_server_create",
                      "vcgs_server_submit", "vcgs_server_progress", "vcgs_server_stats_read",
-                     "vcgs_decode_anchors_view", "vcgs_decode_anchors_view_backward"):
+                     "vcgs_decode_anchors_view", "vcgs_decode_anchors_view_backward", "vcgs_render_forward_hits",
+                     "vcgs_mask_loss", "vcgs_mask_prune"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -237,8 +238,10 @@ def _gauss(means, scales, quats, opacities, colors):
 
 
 def render_forward(means, scales, quats, opacities, colors, camera, pose, bg=(0.0, 0.0, 0.0), keep_state=True,
-                   ctx: Context | None = None):
-    """Forward render.  Returns (color (3,H,W), depth (H,W), alpha (H,W), state or None)."""
+                   ctx: Context | None = None, hits=None):
+    """Forward render.  Returns (color (3,H,W), depth (H,W), alpha (H,W), state or None).
+    hits: optional int32/uint32 (n,) device tensor to which each Gaussian's
+    number of blended pixels is added."""
     ctx = ctx or default_context()
     g, keep = _gauss(means, scales, quats, opacities, colors)
     H, W = int(camera.height), int(camera.width)
@@ -250,8 +253,14 @@ def render_forward(means, scales, quats, opacities, colors, camera, pose, bg=(0.
     cam, ps = camera_struct(camera), pose_struct(pose)
     bgv = (c_f * 3)(*[float(b) for b in bg])
     h = c_p()
-    _check(lib().vcgs_render_forward(ctx.h, ctypes.byref(g), ctypes.byref(cam), ctypes.byref(ps), bgv,
-                                     ctypes.byref(imgs), ctypes.byref(h) if keep_state else None, _stream()))
+    if hits is None:
+        _check(lib().vcgs_render_forward(ctx.h, ctypes.byref(g), ctypes.byref(cam), ctypes.byref(ps), bgv,
+                                         ctypes.byref(imgs), ctypes.byref(h) if keep_state else None, _stream()))
+    else:
+        assert hits.is_cuda and hits.dtype == torch.int32 and hits.numel() == g.n and hits.is_contiguous()
+        _check(lib().vcgs_render_forward_hits(ctx.h, ctypes.byref(g), ctypes.byref(cam), ctypes.byref(ps), bgv,
+                                              ctypes.byref(imgs), ctypes.byref(h) if keep_state else None,
+                                              _ptr(hits), _stream()))
     st = State(ctx, h) if keep_state else None
     del keep
     return color, depth, alpha, st
@@ -400,6 +409,35 @@ def decode_anchors_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG, books
                                                        _stream()))
     del keep
     return out
+
+
+def mask_loss(mask_logit, in_frustum_count=None, weight=1.0, dl_dm=None, ctx: Context | None = None):
+    """L_m = weight * mean over the frustum of sigmoid(m) (eq. (13)); returns
+    (loss (1,), dl_dm) with the gradient added into dl_dm (created zero if None)."""
+    ctx = ctx or default_context()
+    m = _dev(mask_logit)
+    n = int(m.numel())
+    if dl_dm is None:
+        dl_dm = torch.zeros_like(m)
+    loss = torch.empty(1, device=m.device)
+    cnt = None if in_frustum_count is None else in_frustum_count.contiguous()
+    _check(lib().vcgs_mask_loss(ctx.h, c_i64(n), _ptr(m), _ptr(cnt), c_f(weight), _ptr(dl_dm), _ptr(loss),
+                                _stream()))
+    return loss, dl_dm
+
+
+def mask_prune(mask_logit, hits=None, mask_eps=0.01, min_hits=1, ctx: Context | None = None):
+    """(keep uint8 (n,), kept indices int32 (n_kept,)) of eq. (13)'s pruning."""
+    ctx = ctx or default_context()
+    m = _dev(mask_logit)
+    n = int(m.numel())
+    keep = torch.empty(n, dtype=torch.uint8, device=m.device)
+    idx = torch.empty(max(n, 1), dtype=torch.int32, device=m.device)
+    nk = c_i64()
+    h = None if hits is None else hits.contiguous()
+    _check(lib().vcgs_mask_prune(ctx.h, c_i64(n), _ptr(m), c_f(mask_eps), _ptr(h), ctypes.c_uint32(int(min_hits)),
+                                 _ptr(keep), _ptr(idx), ctypes.byref(nk), _stream()))
+    return keep, idx[:nk.value]
 
 
 STAGES = ["decode", "preprocess", "depth_sort", "pair_scan", "emit", "tile_sort", "tile_ranges", "composite",
