@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving replay")
     ap.add_argument("--serve-requests", type=int, default=400, help="requests per arrival rate")
     ap.add_argument("--serve-qps", type=str, default="50,100,200,400")
-    ap.add_argument("--only", choices=("main", "ba", "serve"), default=None,
+    ap.add_argument("--only", choices=("main", "ba", "serve", "view", "mask"), default=None,
                     help="run one section only (for profiling)")
     return ap.parse_args()
 
@@ -267,6 +267,44 @@ def view_decode_section(args, dev, steps=20, warmup=5):
             "mpix_s": round(cam.width * cam.height / (ms * 1e-3) / 1e6, 2)}
 
 
+def mask_step_section(args, dev, steps=20, warmup=5, lam=5e-4):
+    """The room step with the mask training of eq. (13): decode with the mask,
+    forward with per-Gaussian hit counts, L1 loss, backward, the mask loss over
+    the view frustum added to the decode's mask gradient; and the pruning that
+    ends a window (mask and hit counts), timed on its own."""
+    import torch
+    from paper_2403_11247_amd import scenes, vcgs
+    a = scenes.room_anchors(40000, k=10)
+    m = scenes.room_mlp(seed=0)
+    n = a.xa.shape[1] * 10
+    mask, _, _ = scenes.mask_and_codebook(n)
+    cam, pose = scenes.room_camera()
+    tpose = scenes.perturb_pose(pose, 2)
+    A = [_up(x, dev) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    ml = _up(mask, dev)
+    G0 = vcgs.decode_anchors(*A, mask_logit=ml)
+    tC, tD, _, _ = vcgs.render_forward(*[G0[f] for f in F], cam, tpose, keep_state=False)
+    hits = torch.zeros(n, dtype=torch.int32, device=dev)
+
+    def step():
+        G = vcgs.decode_anchors(*A, mask_logit=ml)
+        C, D, _, st = vcgs.render_forward(*[G[f] for f in F], cam, pose, hits=hits)
+        _, dlc, dld = vcgs.l1_loss(C, D, tC, tD, 0.5)
+        grads, dpose = vcgs.render_backward(st, *[G[f] for f in F], cam, pose, dlc, dld, None)
+        ag = vcgs.decode_anchors_backward(*A, grads, mask_logit=ml)
+        lm, _ = vcgs.mask_loss(ml, st.tile_count(), lam, dl_dm=ag["mask_logit"])
+        st.free()
+        return dpose, ag, lm
+
+    ms = _timed(step, steps, warmup)
+    ms_prune = _timed(lambda: vcgs.mask_prune(ml, hits, 0.01, 1), steps, warmup)
+    keep, idx = vcgs.mask_prune(ml, hits, 0.01, 1)
+    return {"workload": "room step with the mask training of eq. (13) (hit counts, frustum mask loss) and the "
+                        "window-end pruning, 400k Gaussians, 1200x680",
+            "ms_per_step": round(ms, 4), "mpix_s": round(cam.width * cam.height / (ms * 1e-3) / 1e6, 2),
+            "prune_ms": round(ms_prune, 4), "kept": int(idx.numel()), "n": n}
+
+
 def serve_section(args, dev):
     """Novel-view requests against a 1M-Gaussian room map (100k anchors at
     2 cm): Poisson arrivals at each rate, sizes uniform over 320x240, 640x480,
@@ -325,8 +363,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    if args.only in ("ba", "serve"):
-        res = ba_section(args, dev) if args.only == "ba" else serve_section(args, dev)
+    if args.only in ("ba", "serve", "view", "mask"):
+        res = {"ba": ba_section, "serve": serve_section, "view": view_decode_section,
+               "mask": mask_step_section}[args.only](args, dev)
         print(json.dumps({args.only: res}), flush=True)
         return
     if args.only == "main":
@@ -438,6 +477,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 2 * src.numel() * 4
     out["view_decode_step"] = view_decode_section(args, dev)
+    out["mask_step"] = mask_step_section(args, dev)
     if not args.no_ba:
         out["ba_window"] = ba_section(args, dev)
     if not args.no_serve:

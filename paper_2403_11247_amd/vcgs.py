@@ -193,6 +193,16 @@ class State:
         except Exception:
             pass
 
+    def tile_count(self):
+        """Zero-copy (n,) int32 view of each Gaussian's tile count (0 = outside
+        the view frustum); valid until free()."""
+        v = CStateView()
+        _check(lib().vcgs_state_query(self.h, ctypes.byref(v)))
+        dev = torch.device("cuda", self.ctx.device)
+        if v.n <= 0 or not v.count:
+            return torch.empty(0, dtype=torch.int32, device=dev)
+        return _wrap(v.count, v.n, torch.int32, dev)
+
     def view(self) -> dict:
         """Copies of the saved binning/sort results as torch tensors."""
         v = CStateView()
