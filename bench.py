@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving replay")
     ap.add_argument("--serve-requests", type=int, default=400, help="requests per arrival rate")
     ap.add_argument("--serve-qps", type=str, default="50,100,200,400")
-    ap.add_argument("--only", choices=("main", "ba", "serve", "view", "mask"), default=None,
+    ap.add_argument("--only", choices=("main", "ba", "serve", "view", "mask", "rvq"), default=None,
                     help="run one section only (for profiling)")
     return ap.parse_args()
 
@@ -305,6 +305,31 @@ def mask_step_section(args, dev, steps=20, warmup=5, lam=5e-4):
             "prune_ms": round(ms_prune, 4), "kept": int(idx.numel()), "n": n}
 
 
+def rvq_section(args, dev, steps=50, warmup=5):
+    """Residual vector quantization (eqs. (14)-(15)) of the room map's
+    attributes: assignment, reconstruction, loss and code gradient in one call.
+    Algorithmic work: n * L * P * 2D flops of distance (the compare and select
+    per code are not counted), priced against the FP32 vector peak."""
+    import torch
+    from paper_2403_11247_amd import scenes, vcgs
+    rows = []
+    for kind, n, L, P in (("scaling", 40_000, 6, 64), ("offset", 40_000, 6, 64), ("gauss", 400_000, 6, 64),
+                          ("feature", 40_000, 1, 256)):
+        books, x = scenes.rvq_problem(kind, n, L, P, seed=1)
+        b, xx = _up(books, dev), _up(x, dev)
+        D = x.shape[1]
+        dbooks = torch.zeros_like(b)
+        ms = _timed(lambda: vcgs.rvq_assign(b, xx, dbooks=dbooks, grad=True), steps, warmup)
+        flops = 2.0 * n * L * P * D
+        rows.append({"kind": kind, "n": n, "stages": L, "codes": P, "dim": D, "ms": round(ms, 4),
+                     "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                     "frac_fp32": round(flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)})
+    return {"workload": "R-VQ of the room map: anchor scaling (3-d) and offsets (30-d), 64 codes x 6 stages, "
+                        "40k anchors; per-Gaussian log-scale + rotation (7-d), 64 x 6, 400k Gaussians; "
+                        "anchor features (32-d), 256 codes (1-byte), 40k anchors",
+            "rows": rows}
+
+
 def serve_section(args, dev):
     """Novel-view requests against a 1M-Gaussian room map (100k anchors at
     2 cm): Poisson arrivals at each rate, sizes uniform over 320x240, 640x480,
@@ -363,9 +388,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    if args.only in ("ba", "serve", "view", "mask"):
+    if args.only in ("ba", "serve", "view", "mask", "rvq"):
         res = {"ba": ba_section, "serve": serve_section, "view": view_decode_section,
-               "mask": mask_step_section}[args.only](args, dev)
+               "mask": mask_step_section, "rvq": rvq_section}[args.only](args, dev)
         print(json.dumps({args.only: res}), flush=True)
         return
     if args.only == "main":
@@ -478,6 +503,7 @@ def main():
         out["copy_probe_bytes"] = 2 * src.numel() * 4
     out["view_decode_step"] = view_decode_section(args, dev)
     out["mask_step"] = mask_step_section(args, dev)
+    out["rvq"] = rvq_section(args, dev)
     if not args.no_ba:
         out["ba_window"] = ba_section(args, dev)
     if not args.no_serve:

@@ -291,6 +291,34 @@ int vcgs_mask_loss(vcgs_ctx* ctx, int64_t n, const float* mask_logit, const uint
 int vcgs_mask_prune(vcgs_ctx* ctx, int64_t n, const float* mask_logit, float mask_eps, const uint32_t* hits,
                     uint32_t min_hits, uint8_t* keep, uint32_t* kept_index, int64_t* n_kept, void* stream);
 
+/* ---- residual vector quantization (paper Sec. 3.4, eqs. (14)-(15)) ---- */
+
+/* L cascaded codebooks of P codes of dimension D: books is device float
+ * [L][P][D] (row-major).  Limits: 1 <= D <= 32, 1 <= L <= 8, 1 <= P <= 256;
+ * with a code gradient also L * P * (D + 1) <= 15360. */
+typedef struct {
+    int32_t dim;
+    int32_t stages;
+    int32_t codes;
+    const float* books;
+} vcgs_rvq_books;
+
+/* Assign n vectors x (device float [n][D], finite) stage by stage: stage l
+ * picks the code of books[l] nearest to the residual x - xhat, xhat being the
+ * sum of the codes picked so far (eq. (14)).  The distance is decided in
+ * binary32 as |c|^2 - 2 c.r in a fixed order; ties go to the lowest index.
+ * Outputs (each NULL to skip, all device):
+ *   idx    [L][n], idx_bytes = 1 (uint8, P <= 256) or 4 (int32);
+ *   recon  float [n][D]: xhat after the last stage;
+ *   loss   1 float, overwritten: eq. (15), 1/(n P) sum over stages and vectors
+ *          of |r - C[i]|^2;
+ *   dbooks float [L][P][D]: the loss's gradient to the codes is ADDED (the
+ *          residual is under a stop-gradient, so x gets none).
+ * Code sums inside a block are float atomics: dbooks is reproducible to
+ * rounding, not bit for bit; idx and recon are exact. */
+int vcgs_rvq_assign(vcgs_ctx* ctx, const vcgs_rvq_books* q, int64_t n, const float* x, void* idx, int32_t idx_bytes,
+                    float* recon, float* loss, float* dbooks, void* stream);
+
 /* ---- anchor decode ---------------------------------------------------- */
 
 /* Voxel anchors (paper Sec. 3.2): position x_a [3][na], feature f_a

@@ -309,4 +309,31 @@ int vcgs_count_read(vcgs_ctx* ctx, int64_t out[5])
     return VCGS_OK;
 }
 
+int vcgs_rvq_assign(vcgs_ctx* ctx, const vcgs_rvq_books* q, int64_t n, const float* x, void* idx, int32_t idx_bytes,
+                    float* recon, float* loss, float* dbooks, void* stream)
+{
+    if (!ctx || !q) return fail(VCGS_E_INVALID, "ctx or q is NULL");
+    const int D = q->dim, L = q->stages, P = q->codes;
+    if (D < 1 || D > 32 || L < 1 || L > 8 || P < 1 || P > 256)
+        return fail(VCGS_E_INVALID, "R-VQ needs 1 <= dim <= 32, 1 <= stages <= 8, 1 <= codes <= 256");
+    if (dbooks && (int64_t)L * P * (D + 1) > 15360)
+        return fail(VCGS_E_INVALID, "stages * codes * (dim + 1) exceeds 15360 with a code gradient");
+    if (!q->books) return fail(VCGS_E_INVALID, "books is NULL");
+    if (n < 0 || n > ((int64_t)1 << 40)) return fail(VCGS_E_INVALID, "n out of range");
+    if (n > 0 && !x) return fail(VCGS_E_INVALID, "x is NULL");
+    if (idx && idx_bytes != 1 && idx_bytes != 4) return fail(VCGS_E_INVALID, "idx_bytes must be 1 or 4");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(&ctx->pool);
+    float* tab = sc.get<float>((int64_t)L * P * (rvq_padded_dim(D) + 4));
+    const bool grad = dbooks != nullptr;
+    float* partial = (loss || grad) ? sc.get<float>(rvq_partial_floats(n, L, P, D, grad)) : nullptr;
+    double* red = (loss || grad) ? sc.get<double>((int64_t)L * P * (D + 1) + 1) : nullptr;
+    if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (R-VQ)");
+    launch_rvq(n, D, L, P, q->books, x, idx, idx_bytes, recon, loss, dbooks, tab, partial, red, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return VCGS_OK;
+}
+
 }  // extern "C"

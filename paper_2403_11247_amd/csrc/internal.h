@@ -188,6 +188,13 @@ void launch_mask_prune(int64_t n, const float* logit, float thr, const uint32_t*
                        uint8_t* keep, uint32_t* flags_tmp, uint32_t* offs_tmp, uint32_t* kept_index,
                        uint32_t* n_kept, uint32_t* scan_tmp, hipStream_t s);
 
+// Residual vector quantization (rvq.hip).  tab: L * P * (rvq_padded_dim(D) + 4)
+// floats; partial: rvq_partial_floats(...) floats; red: L * P * (D + 1) + 1 doubles.
+int rvq_padded_dim(int d);
+int64_t rvq_partial_floats(int64_t n, int L, int P, int D, bool grad);
+void launch_rvq(int64_t n, int D, int L, int P, const float* books, const float* x, void* idx, int idx_bytes,
+                float* recon, float* loss, float* dbooks, float* tab, float* partial, double* red, hipStream_t s);
+
 // Process-wide kernel configuration (vcgs_set_option).
 struct Options {
     int ppl_fwd = 1;  // pixels per lane of the forward compositing (1, 2, 4)

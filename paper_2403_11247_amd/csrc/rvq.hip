@@ -1,0 +1,267 @@
+// Residual vector quantization on the GPU (paper Sec. 3.4, eqs. (14)-(15)).
+//
+// Stage l assigns each vector x_n the code of C^l nearest to its residual
+// r^l_n = x_n - xhat^{l-1}_n; xhat is the running sum of the picked codes.
+// The loss of eq. (15) and its gradient to the codes (the residual sits under
+// a stop-gradient) are accumulated in the same pass.
+//
+// The search is plain VALU work, one vector per lane, with the codes read as
+// wave-uniform scalar operands: for each code the distance is D fused
+// multiply-adds on a precomputed row (|c|^2, -2c), then a compare and two
+// selects.  At the paper's sizes (P <= 256 codes, D <= 32) the compare and
+// select are a sizeable part of the work and the whole search over a million
+// vectors takes microseconds; matrix cores would also round the dot products in
+// an order no CPU check can follow, while the pick is an integer that has to
+// match one.  The 256 threads of a block hold the same 64 vectors and split the
+// codebook in four contiguous quarters; after each stage the quarters' winners
+// are merged through LDS in code order, which keeps the first index among
+// equal distances.
+//
+// Decision arithmetic (binary32, no contraction beyond the explicit fmaf):
+//   |c|^2 = c_0 c_0, then fmaf(c_j, c_j, .);  e = |c|^2, then fmaf(-2 c_j, r_j, .);
+//   xhat_j += c_j and r_j = x_j - xhat_j.
+// Code gradients: per-block sums of residuals and counts per code in LDS (float
+// atomics, so the order inside a block is not fixed), blocks summed in binary64
+// in block order, then dL/dC = 2/(N P) (count * C - sum r).
+#include "internal.h"
+
+namespace vcgs {
+
+constexpr int kRvqThreads = 256;
+constexpr int kRvqMaxGridPartial = 512;
+constexpr int kRvqMaxGrid = 8192;
+
+typedef __attribute__((address_space(4))) const float CFloat;
+
+__host__ __device__ constexpr int rvq_row(int dm) { return dm + 4; }  // |c|^2, -2c (dm), padding
+
+int rvq_padded_dim(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32; }
+
+// one thread per (stage, code): row = (|c|^2, -2 c_0 .. -2 c_{D-1}, 0 ...)
+__global__ void __launch_bounds__(256) k_rvq_table(int rows, int D, int dm, const float* __restrict__ books,
+                                                   float* __restrict__ tab)
+{
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= rows) return;
+    const float* c = books + (int64_t)i * D;
+    float* t = tab + (int64_t)i * rvq_row(dm);
+    float s = c[0] * c[0];
+    for (int j = 1; j < D; ++j) s = fmaf(c[j], c[j], s);
+    t[0] = s;
+    for (int j = 0; j < rvq_row(dm) - 1; ++j) t[1 + j] = j < D ? -2.0f * c[j] : 0.0f;
+}
+
+struct RvqArgs {
+    int64_t n;
+    int D, L, P;
+    const float* tab;    // [L][P][row]
+    const float* books;  // [L][P][D]
+    const float* x;      // [n][D]
+    void* idx;           // [L][n], 1 or 4 bytes
+    int idx_bytes;
+    float* recon;        // [n][D] or null
+    float* partial;      // [grid][pstride] or null: code sums and counts [L][P][D+1], then the loss
+    int grad;            // accumulate code sums
+    int pstride;
+};
+
+template <int DM>
+__global__ void __launch_bounds__(kRvqThreads) k_rvq_assign(RvqArgs a)
+{
+#pragma clang fp contract(off)
+    extern __shared__ float s_grad[];
+    __shared__ float s_e[2][4][64];
+    __shared__ int s_k[2][4][64];
+    constexpr int S = rvq_row(DM);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int k0 = (w * a.P) >> 2;
+    const int k1 = ((w + 1) * a.P) >> 2;
+    const int E = a.grad ? a.L * a.P * (a.D + 1) : 0;
+    for (int i = threadIdx.x; i < E; i += kRvqThreads) s_grad[i] = 0.0f;
+    __syncthreads();
+    float lsum = 0.0f;
+    int phase = 0;
+    const int64_t groups = (a.n + 63) >> 6;
+    for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        const int64_t v = grp * 64 + lane;
+        const bool valid = v < a.n;
+        float xr[DM], xh[DM];
+#pragma unroll
+        for (int j = 0; j < DM; ++j) {
+            xr[j] = (valid && j < a.D) ? a.x[v * a.D + j] : 0.0f;
+            xh[j] = 0.0f;
+        }
+        for (int l = 0; l < a.L; ++l) {
+            float r[DM];
+#pragma unroll
+            for (int j = 0; j < DM; ++j) r[j] = xr[j] - xh[j];
+            float be = __builtin_inff();
+            int bk = 0x7fffffff;
+            // wave-uniform rows read through the constant address space: scalar loads
+            const CFloat* t = (const CFloat*)(a.tab + ((int64_t)l * a.P + k0) * S);
+#pragma unroll DM <= 8 ? 4 : 2
+            for (int k = k0; k < k1; ++k, t += S) {
+                float e = t[0];
+#pragma unroll
+                for (int j = 0; j < DM; ++j) e = fmaf(t[1 + j], r[j], e);
+                if (e < be) {
+                    be = e;
+                    bk = k;
+                }
+            }
+            const int buf = phase & 1;
+            ++phase;
+            s_e[buf][w][lane] = be;
+            s_k[buf][w][lane] = bk;
+            __syncthreads();
+            be = s_e[buf][0][lane];
+            bk = s_k[buf][0][lane];
+#pragma unroll
+            for (int u = 1; u < 4; ++u) {
+                const float e2 = s_e[buf][u][lane];
+                if (e2 < be) {
+                    be = e2;
+                    bk = s_k[buf][u][lane];
+                }
+            }
+            if (bk < 0 || bk >= a.P) bk = 0;  // non-finite distances everywhere
+            const float* c = a.books + ((int64_t)l * a.P + bk) * a.D;
+            float cv[DM];
+#pragma unroll
+            for (int j = 0; j < DM; ++j) cv[j] = j < a.D ? c[j] : 0.0f;
+            if (valid) {
+                if (w == 0 && a.idx) {
+                    if (a.idx_bytes == 1)
+                        static_cast<uint8_t*>(a.idx)[(int64_t)l * a.n + v] = (uint8_t)bk;
+                    else
+                        static_cast<int32_t*>(a.idx)[(int64_t)l * a.n + v] = bk;
+                }
+                if (a.partial) {
+                    float* g = s_grad + (l * a.P + bk) * (a.D + 1);
+                    if (w == 0) {
+                        float q = 0.0f;
+#pragma unroll
+                        for (int j = 0; j < DM; ++j) {
+                            if (j < a.D) {
+                                const float d = r[j] - cv[j];
+                                q = fmaf(d, d, q);
+                            }
+                        }
+                        lsum += q;
+                        if (a.grad) atomicAdd(g + a.D, 1.0f);
+                    }
+                    if (a.grad) {
+#pragma unroll
+                        for (int j = 0; j < DM; ++j)
+                            if (j < a.D && (j & 3) == w) atomicAdd(g + j, r[j]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < DM; ++j) xh[j] = xh[j] + cv[j];
+        }
+        if (valid && a.recon) {
+#pragma unroll
+            for (int j = 0; j < DM; ++j)
+                if (j < a.D && (j & 3) == w) a.recon[v * a.D + j] = xh[j];
+        }
+    }
+    if (a.partial) {
+        __syncthreads();
+        float* p = a.partial + (int64_t)blockIdx.x * a.pstride;
+        for (int i = threadIdx.x; i < E; i += kRvqThreads) p[i] = s_grad[i];
+        if (w == 0) {
+            for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+            if (lane == 0) p[E] = lsum;
+        }
+    }
+}
+
+// blocks summed in binary64, block order: 64 entries x 4 slices per block
+__global__ void __launch_bounds__(256) k_rvq_reduce(const float* __restrict__ partial, int grid, int stride,
+                                                    int entries, double* __restrict__ red)
+{
+    __shared__ double sm[4][64];
+    const int lane = threadIdx.x & 63;
+    const int s = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    double acc = 0.0;
+    if (e < entries)
+        for (int b = s; b < grid; b += 4) acc += (double)partial[(int64_t)b * stride + e];
+    sm[s][lane] = acc;
+    __syncthreads();
+    if (s == 0 && e < entries) red[e] = ((sm[0][lane] + sm[1][lane]) + sm[2][lane]) + sm[3][lane];
+}
+
+// dL/dC += 2/(N P) (count C - sum r); the loss = sum / (N P)
+__global__ void __launch_bounds__(256) k_rvq_apply(int L, int P, int D, int grad, const float* __restrict__ books,
+                                                   const double* __restrict__ red, double inv_np,
+                                                   float* __restrict__ dbooks, float* __restrict__ loss)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int E = grad ? L * P * (D + 1) : 0;
+    if (i == 0 && loss) *loss = (float)(red[E] * inv_np);
+    if (!grad || i >= L * P * D) return;
+    const int row = i / D, j = i - row * D;
+    const double cnt = red[row * (D + 1) + D];
+    const double sr = red[row * (D + 1) + j];
+    dbooks[i] += (float)(2.0 * inv_np * (cnt * (double)books[i] - sr));
+}
+
+int rvq_grid(int64_t n, bool partial)
+{
+    const int64_t groups = (n + 63) / 64;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(groups, partial ? kRvqMaxGridPartial : kRvqMaxGrid));
+}
+
+int64_t rvq_partial_floats(int64_t n, int L, int P, int D, bool grad)
+{
+    const int64_t stride = (grad ? (int64_t)L * P * (D + 1) : 0) + 1;
+    return stride * rvq_grid(n, true);
+}
+
+void launch_rvq(int64_t n, int D, int L, int P, const float* books, const float* x, void* idx, int idx_bytes,
+                float* recon, float* loss, float* dbooks, float* tab, float* partial, double* red, hipStream_t s)
+{
+    const bool want_partial = loss || dbooks;
+    const int grad = dbooks ? 1 : 0;
+    if (n <= 0) {
+        if (loss) launch_fill_f32(loss, 0.0f, 1, s);
+        return;
+    }
+    const int dm = rvq_padded_dim(D);
+    const int rows = L * P;
+    k_rvq_table<<<(rows + 255) / 256, 256, 0, s>>>(rows, D, dm, books, tab);
+    RvqArgs a;
+    a.n = n;
+    a.D = D;
+    a.L = L;
+    a.P = P;
+    a.tab = tab;
+    a.books = books;
+    a.x = x;
+    a.idx = idx;
+    a.idx_bytes = idx_bytes;
+    a.recon = recon;
+    a.partial = want_partial ? partial : nullptr;
+    a.grad = grad;
+    const int E = grad ? L * P * (D + 1) : 0;
+    a.pstride = E + 1;
+    const int grid = rvq_grid(n, want_partial);
+    const size_t lds = (size_t)E * sizeof(float);
+    switch (dm) {
+    case 4: k_rvq_assign<4><<<grid, kRvqThreads, lds, s>>>(a); break;
+    case 8: k_rvq_assign<8><<<grid, kRvqThreads, lds, s>>>(a); break;
+    case 16: k_rvq_assign<16><<<grid, kRvqThreads, lds, s>>>(a); break;
+    default: k_rvq_assign<32><<<grid, kRvqThreads, lds, s>>>(a); break;
+    }
+    if (!want_partial) return;
+    const int entries = E + 1;
+    k_rvq_reduce<<<(entries + 63) / 64, 256, 0, s>>>(partial, grid, a.pstride, entries, red);
+    const int outs = std::max(1, grad ? L * P * D : 1);
+    k_rvq_apply<<<(outs + 255) / 256, 256, 0, s>>>(L, P, D, grad, books, red, 1.0 / ((double)n * P), dbooks, loss);
+}
+
+}  // namespace vcgs

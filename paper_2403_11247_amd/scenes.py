@@ -293,6 +293,36 @@ def mask_and_codebook(n_gauss, seed=3, size=4096, dim=7, stages=2, mask_mu=2.0, 
     return _f32(logits), _f32(books), np.ascontiguousarray(idx.astype(np.int32))
 
 
+def rvq_problem(kind, n, stages, codes, seed=0):
+    """Vectors and starting codebooks for residual vector quantization.
+    kind: "gauss" (per-Gaussian log-scale and quaternion, 7-d), "scaling"
+    (anchor log-scaling, 3-d), "offset" (anchor offsets, k = 10 x 3 = 30-d) or
+    "feature" (anchor features, 32-d).  Stage 1 starts from randomly picked
+    input vectors; stage l > 1 from N(0, (0.35^(l-1) sigma)^2) residual codes.
+    Returns (books (stages, codes, D) float32, x (n, D) float32)."""
+    rng = np.random.default_rng(seed)
+    if kind == "gauss":
+        ls = math.log(0.02) + rng.normal(0.0, 0.3, (n, 3))
+        q = np.array([1.0, 0.0, 0.0, 0.0]) + rng.normal(0.0, 0.5, (n, 4))
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        x = np.concatenate([ls, q], 1)
+    elif kind == "scaling":
+        x = math.log(0.05) + rng.normal(0.0, 0.4, (n, 3))
+    elif kind == "offset":
+        x = rng.normal(0.0, 0.5, (n, 30))
+    elif kind == "feature":
+        x = rng.normal(0.0, 1.0, (n, 32))
+    else:
+        raise ValueError(kind)
+    sigma = x.std(0).mean()
+    D = x.shape[1]
+    books = np.empty((stages, codes, D))
+    books[0] = x[rng.integers(0, n, codes)] if n > 0 else rng.normal(0.0, 1.0, (codes, D))
+    for l in range(1, stages):
+        books[l] = rng.normal(0.0, sigma * 0.35 ** l, (codes, D))
+    return _f32(books), _f32(x)
+
+
 # ---------------------------------------------------------------------------
 # Bundle-adjustment window and serving trace
 # ---------------------------------------------------------------------------

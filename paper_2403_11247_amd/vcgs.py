@@ -71,6 +71,10 @@ class CAnchorGrads(ctypes.Structure):
                 ("W2", c_p), ("b2", c_p), ("books", c_p), ("mask_logit", c_p), ("cam", c_p)]
 
 
+class CRvqBooks(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("stages", ctypes.c_int32), ("codes", ctypes.c_int32), ("books", c_p)]
+
+
 class CServerConfig(ctypes.Structure):
     _fields_ = [("max_views", c_i32), ("slots", c_i32), ("pair_budget", c_i64), ("pairs_per_pixel", c_f),
                 ("bg", c_f * 3)]
@@ -100,7 +104,7 @@ def lib():
                      "vcgs_profile_read", "vcgs_count_enable", "vcgs_count_read", "vcgs_server_create",
                      "vcgs_server_submit", "vcgs_server_progress", "vcgs_server_stats_read",
                      "vcgs_decode_anchors_view", "vcgs_decode_anchors_view_backward", "vcgs_render_forward_hits",
-                     "vcgs_mask_loss", "vcgs_mask_prune"):
+                     "vcgs_mask_loss", "vcgs_mask_prune", "vcgs_rvq_assign"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -448,6 +452,34 @@ def mask_prune(mask_logit, hits=None, mask_eps=0.01, min_hits=1, ctx: Context | 
     _check(lib().vcgs_mask_prune(ctx.h, c_i64(n), _ptr(m), c_f(mask_eps), _ptr(h), ctypes.c_uint32(int(min_hits)),
                                  _ptr(keep), _ptr(idx), ctypes.byref(nk), _stream()))
     return keep, idx[:nk.value]
+
+
+def rvq_assign(books, x, idx_bytes=1, idx=True, recon=True, loss=True, dbooks=None, grad=False,
+               ctx: Context | None = None):
+    """Residual vector quantization (eqs. (14)-(15)) of x (n, D) with
+    codebooks books (L, P, D).  Returns dict(idx (L, n) uint8 or int32, recon
+    (n, D), loss (1,), dbooks (L, P, D)); parts not asked for are None.  With
+    grad=True the code gradient is added into dbooks (created zero if None)."""
+    ctx = ctx or default_context()
+    b = _dev(books)
+    xx = _dev(x)
+    L, P, D = (int(v) for v in b.shape)
+    n = int(xx.shape[0])
+    assert xx.shape == (n, D), "x must be (n, D) with the codebooks' D"
+    out = {"idx": None, "recon": None, "loss": None, "dbooks": None}
+    if idx:
+        out["idx"] = torch.empty((L, n), dtype=torch.uint8 if idx_bytes == 1 else torch.int32, device=b.device)
+    if recon:
+        out["recon"] = torch.empty((n, D), device=b.device)
+    if loss:
+        out["loss"] = torch.empty(1, device=b.device)
+    if grad:
+        out["dbooks"] = torch.zeros_like(b) if dbooks is None else dbooks
+    q = CRvqBooks(D, L, P, _ptr(b))
+    _check(lib().vcgs_rvq_assign(ctx.h, ctypes.byref(q), c_i64(n), _ptr(xx), _ptr(out["idx"]),
+                                 ctypes.c_int32(idx_bytes), _ptr(out["recon"]), _ptr(out["loss"]),
+                                 _ptr(out["dbooks"]), _stream()))
+    return out
 
 
 STAGES = ["decode", "preprocess", "depth_sort", "pair_scan", "emit", "tile_sort", "tile_ranges", "composite",
