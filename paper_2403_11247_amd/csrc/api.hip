@@ -328,7 +328,7 @@ int vcgs_rvq_assign(vcgs_ctx* ctx, const vcgs_rvq_books* q, int64_t n, const flo
     float* tab = sc.get<float>((int64_t)L * P * (rvq_padded_dim(D) + 4));
     const bool grad = dbooks != nullptr;
     float* partial = (loss || grad) ? sc.get<float>(rvq_partial_floats(n, L, P, D, grad)) : nullptr;
-    double* red = (loss || grad) ? sc.get<double>((int64_t)L * P * (D + 1) + 1) : nullptr;
+    double* red = (loss || grad) ? sc.get<double>(rvq_red_doubles(n, L, P, D, grad)) : nullptr;
     if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (R-VQ)");
     launch_rvq(n, D, L, P, q->books, x, idx, idx_bytes, recon, loss, dbooks, tab, partial, red, s);
     const hipError_t e = hipGetLastError();

@@ -189,9 +189,10 @@ void launch_mask_prune(int64_t n, const float* logit, float thr, const uint32_t*
                        uint32_t* n_kept, uint32_t* scan_tmp, hipStream_t s);
 
 // Residual vector quantization (rvq.hip).  tab: L * P * (rvq_padded_dim(D) + 4)
-// floats; partial: rvq_partial_floats(...) floats; red: L * P * (D + 1) + 1 doubles.
+// floats; partial: rvq_partial_floats(...) floats; red: rvq_red_doubles(...) doubles.
 int rvq_padded_dim(int d);
 int64_t rvq_partial_floats(int64_t n, int L, int P, int D, bool grad);
+int64_t rvq_red_doubles(int64_t n, int L, int P, int D, bool grad);
 void launch_rvq(int64_t n, int D, int L, int P, const float* books, const float* x, void* idx, int idx_bytes,
                 float* recon, float* loss, float* dbooks, float* tab, float* partial, double* red, hipStream_t s);
 

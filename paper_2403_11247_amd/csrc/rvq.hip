@@ -179,7 +179,11 @@ __global__ void __launch_bounds__(kRvqThreads) k_rvq_assign(RvqArgs a)
     }
 }
 
-// blocks summed in binary64, block order: 64 entries x 4 slices per block
+// Block partials summed in binary64 in a fixed order: grid.y takes the rows in
+// runs of kRvqRun (4 slices of 8 rows, loads issued together); k_rvq_apply adds
+// the runs in order.
+constexpr int kRvqRun = 32;
+
 __global__ void __launch_bounds__(256) k_rvq_reduce(const float* __restrict__ partial, int grid, int stride,
                                                     int entries, double* __restrict__ red)
 {
@@ -187,26 +191,41 @@ __global__ void __launch_bounds__(256) k_rvq_reduce(const float* __restrict__ pa
     const int lane = threadIdx.x & 63;
     const int s = threadIdx.x >> 6;
     const int e = blockIdx.x * 64 + lane;
+    const int r0 = blockIdx.y * kRvqRun + s;
+    float v[kRvqRun / 4];
+#pragma unroll
+    for (int i = 0; i < kRvqRun / 4; ++i) {
+        const int r = r0 + 4 * i;
+        v[i] = (e < entries && r < grid) ? partial[(int64_t)r * stride + e] : 0.0f;
+    }
     double acc = 0.0;
-    if (e < entries)
-        for (int b = s; b < grid; b += 4) acc += (double)partial[(int64_t)b * stride + e];
+#pragma unroll
+    for (int i = 0; i < kRvqRun / 4; ++i) acc += (double)v[i];
     sm[s][lane] = acc;
     __syncthreads();
-    if (s == 0 && e < entries) red[e] = ((sm[0][lane] + sm[1][lane]) + sm[2][lane]) + sm[3][lane];
+    if (s == 0 && e < entries)
+        red[(int64_t)blockIdx.y * entries + e] = ((sm[0][lane] + sm[1][lane]) + sm[2][lane]) + sm[3][lane];
+}
+
+__device__ __forceinline__ double rvq_red(const double* red, int runs, int entries, int e)
+{
+    double a = 0.0;
+    for (int y = 0; y < runs; ++y) a += red[(int64_t)y * entries + e];
+    return a;
 }
 
 // dL/dC += 2/(N P) (count C - sum r); the loss = sum / (N P)
 __global__ void __launch_bounds__(256) k_rvq_apply(int L, int P, int D, int grad, const float* __restrict__ books,
-                                                   const double* __restrict__ red, double inv_np,
+                                                   const double* __restrict__ red, int runs, double inv_np,
                                                    float* __restrict__ dbooks, float* __restrict__ loss)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int E = grad ? L * P * (D + 1) : 0;
-    if (i == 0 && loss) *loss = (float)(red[E] * inv_np);
+    if (i == 0 && loss) *loss = (float)(rvq_red(red, runs, E + 1, E) * inv_np);
     if (!grad || i >= L * P * D) return;
     const int row = i / D, j = i - row * D;
-    const double cnt = red[row * (D + 1) + D];
-    const double sr = red[row * (D + 1) + j];
+    const double cnt = rvq_red(red, runs, E + 1, row * (D + 1) + D);
+    const double sr = rvq_red(red, runs, E + 1, row * (D + 1) + j);
     dbooks[i] += (float)(2.0 * inv_np * (cnt * (double)books[i] - sr));
 }
 
@@ -220,6 +239,12 @@ int64_t rvq_partial_floats(int64_t n, int L, int P, int D, bool grad)
 {
     const int64_t stride = (grad ? (int64_t)L * P * (D + 1) : 0) + 1;
     return stride * rvq_grid(n, true);
+}
+
+int64_t rvq_red_doubles(int64_t n, int L, int P, int D, bool grad)
+{
+    const int64_t entries = (grad ? (int64_t)L * P * (D + 1) : 0) + 1;
+    return entries * ((rvq_grid(n, true) + kRvqRun - 1) / kRvqRun);
 }
 
 void launch_rvq(int64_t n, int D, int L, int P, const float* books, const float* x, void* idx, int idx_bytes,
@@ -259,9 +284,11 @@ void launch_rvq(int64_t n, int D, int L, int P, const float* books, const float*
     }
     if (!want_partial) return;
     const int entries = E + 1;
-    k_rvq_reduce<<<(entries + 63) / 64, 256, 0, s>>>(partial, grid, a.pstride, entries, red);
+    const int runs = (grid + kRvqRun - 1) / kRvqRun;
+    k_rvq_reduce<<<dim3((entries + 63) / 64, runs), 256, 0, s>>>(partial, grid, a.pstride, entries, red);
     const int outs = std::max(1, grad ? L * P * D : 1);
-    k_rvq_apply<<<(outs + 255) / 256, 256, 0, s>>>(L, P, D, grad, books, red, 1.0 / ((double)n * P), dbooks, loss);
+    k_rvq_apply<<<(outs + 255) / 256, 256, 0, s>>>(L, P, D, grad, books, red, runs, 1.0 / ((double)n * P), dbooks,
+                                                   loss);
 }
 
 }  // namespace vcgs
