@@ -291,6 +291,41 @@ int vcgs_mask_loss(vcgs_ctx* ctx, int64_t n, const float* mask_logit, const uint
 int vcgs_mask_prune(vcgs_ctx* ctx, int64_t n, const float* mask_logit, float mask_eps, const uint32_t* hits,
                     uint32_t min_hits, uint8_t* keep, uint32_t* kept_index, int64_t* n_kept, void* stream);
 
+/* ---- tracking and bundle-adjustment losses (paper Sec. 3.5) ----------- */
+
+/* Silhouette-masked colour + depth loss of eqs. (19) and (21):
+ *   L = sum_p [S(p) > sil_thresh] (l_c(p) + lam_d l_d(p)),
+ *   l_c(p) = sum_c e(C - C*) / (W H),  l_d(p) = e(D - D*) / |R| for D*(p) > 0,
+ * |R| the number of pixels with a depth observation (D* > 0), e(x) = x^2
+ * (norm 2, the paper's form) or |x| (norm 1).  img->alpha is the rendered
+ * silhouette S.  dl_dcolor [3][H][W] and dl_ddepth [H][W] (device, both or
+ * neither) are OVERWRITTEN with the gradient (0 where the mask is off);
+ * loss (device float or NULL) is overwritten.  Deterministic. */
+int vcgs_track_loss(vcgs_ctx* ctx, const vcgs_images* img, const float* target_color, const float* target_depth,
+                    int32_t width, int32_t height, float lam_d, int32_t norm, float sil_thresh, float* dl_dcolor,
+                    float* dl_ddepth, float* loss, void* stream);
+
+/* ICP term of eq. (20), weighted: L = weight sum_i w_i |R p_i + t - q_i|^2.
+ * p_i = mean [3][n] (device, world); q_i = nearest point of depth [H][W]
+ * (device, the observed depth of the frame seen by cam, 0 = none) back-
+ * projected at pixel centres, every stride-th pixel in each direction;
+ * w_i = 1 iff |R p_i + t - q_i| < tau.  The association is held fixed.
+ * loss (device float or NULL) overwritten; dmean [3][n] (device or NULL) and
+ * dpose [6] (device or NULL; (rho, phi) of the left perturbation, as in
+ * vcgs_render_backward) get the gradient ADDED; matched (device uint32 or NULL)
+ * receives the number of Gaussians with w_i = 1.  Deterministic. */
+int vcgs_icp_loss(vcgs_ctx* ctx, int64_t n, const float* mean, const vcgs_camera* cam, const vcgs_pose* pose,
+                  const float* depth, float tau, int32_t stride, float weight, float* dmean, float* dpose,
+                  float* loss, uint32_t* matched, void* stream);
+
+/* SSIM term of bundle adjustment: L = weight (1 - mean SSIM(color, target))
+ * over 3 channels and W H pixels (11 x 11 Gaussian window, sigma 1.5,
+ * C1 = 0.01^2, C2 = 0.03^2, zero padding outside the image).  loss (device
+ * float or NULL) overwritten; dl_dcolor [3][H][W] (device or NULL) gets
+ * dL/dcolor ADDED (so it combines with vcgs_l1_loss or vcgs_track_loss). */
+int vcgs_ssim_loss(vcgs_ctx* ctx, const float* color, const float* target_color, int32_t width, int32_t height,
+                   float weight, float* dl_dcolor, float* loss, void* stream);
+
 /* ---- residual vector quantization (paper Sec. 3.4, eqs. (14)-(15)) ---- */
 
 /* L cascaded codebooks of P codes of dimension D: books is device float

@@ -336,4 +336,69 @@ int vcgs_rvq_assign(vcgs_ctx* ctx, const vcgs_rvq_books* q, int64_t n, const flo
     return VCGS_OK;
 }
 
+int vcgs_track_loss(vcgs_ctx* ctx, const vcgs_images* img, const float* target_color, const float* target_depth,
+                    int32_t width, int32_t height, float lam_d, int32_t norm, float sil_thresh, float* dl_dcolor,
+                    float* dl_ddepth, float* loss, void* stream)
+{
+    if (!ctx || !img) return fail(VCGS_E_INVALID, "ctx or img is NULL");
+    if (width <= 0 || height <= 0 || (int64_t)width * height > ((int64_t)1 << 31))
+        return fail(VCGS_E_INVALID, "image size out of range");
+    if (!img->color || !img->depth || !img->alpha || !target_color || !target_depth)
+        return fail(VCGS_E_INVALID, "an image is NULL (colour, depth, silhouette and both targets are needed)");
+    if (norm != 1 && norm != 2) return fail(VCGS_E_INVALID, "norm must be 1 or 2");
+    if ((dl_dcolor == nullptr) != (dl_ddepth == nullptr))
+        return fail(VCGS_E_INVALID, "dl_dcolor and dl_ddepth go together");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(&ctx->pool);
+    float* partial = sc.get<float>(track_partial_floats(width, height));
+    if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (track loss)");
+    launch_track_loss(width, height, img->color, img->depth, img->alpha, target_color, target_depth, lam_d, norm,
+                      sil_thresh, dl_dcolor, dl_ddepth, loss, partial, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return VCGS_OK;
+}
+
+int vcgs_icp_loss(vcgs_ctx* ctx, int64_t n, const float* mean, const vcgs_camera* cam, const vcgs_pose* pose,
+                  const float* depth, float tau, int32_t stride, float weight, float* dmean, float* dpose,
+                  float* loss, uint32_t* matched, void* stream)
+{
+    if (!ctx || !cam || !pose) return fail(VCGS_E_INVALID, "ctx, cam or pose is NULL");
+    if (n < 0 || n > kMaxSortItems) return fail(VCGS_E_INVALID, "n must be in [0, 2^30)");
+    if (n > 0 && (!mean || !depth)) return fail(VCGS_E_INVALID, "mean or depth is NULL");
+    if (cam->width <= 0 || cam->height <= 0 || !(cam->fx > 0.0f) || !(cam->fy > 0.0f))
+        return fail(VCGS_E_INVALID, "camera needs a positive size and focal lengths");
+    if (!(tau > 0.0f) || stride < 1) return fail(VCGS_E_INVALID, "tau must be > 0 and stride >= 1");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(&ctx->pool);
+    float* partial = sc.get<float>(8 * (int64_t)icp_blocks(n) + 8);
+    if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (ICP)");
+    launch_icp(n, mean, depth, cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy, pose->R, pose->t, tau,
+               stride, weight, dmean, loss, dpose, matched, partial, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return VCGS_OK;
+}
+
+int vcgs_ssim_loss(vcgs_ctx* ctx, const float* color, const float* target_color, int32_t width, int32_t height,
+                   float weight, float* dl_dcolor, float* loss, void* stream)
+{
+    if (!ctx) return fail(VCGS_E_INVALID, "ctx is NULL");
+    if (width <= 0 || height <= 0 || (int64_t)width * height > ((int64_t)1 << 29))
+        return fail(VCGS_E_INVALID, "image size out of range");
+    if (!color || !target_color) return fail(VCGS_E_INVALID, "an image is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(&ctx->pool);
+    float* dm = sc.get<float>(9 * (int64_t)width * height);
+    float* partial = sc.get<float>(ssim_partial_floats(width, height));
+    if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (SSIM)");
+    launch_ssim_loss(width, height, color, target_color, weight, dl_dcolor, loss, dm, partial, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return VCGS_OK;
+}
+
 }  // extern "C"

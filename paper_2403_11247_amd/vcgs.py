@@ -104,7 +104,8 @@ def lib():
                      "vcgs_profile_read", "vcgs_count_enable", "vcgs_count_read", "vcgs_server_create",
                      "vcgs_server_submit", "vcgs_server_progress", "vcgs_server_stats_read",
                      "vcgs_decode_anchors_view", "vcgs_decode_anchors_view_backward", "vcgs_render_forward_hits",
-                     "vcgs_mask_loss", "vcgs_mask_prune", "vcgs_rvq_assign"):
+                     "vcgs_mask_loss", "vcgs_mask_prune", "vcgs_rvq_assign", "vcgs_track_loss",
+                     "vcgs_icp_loss", "vcgs_ssim_loss"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -452,6 +453,55 @@ def mask_prune(mask_logit, hits=None, mask_eps=0.01, min_hits=1, ctx: Context | 
     _check(lib().vcgs_mask_prune(ctx.h, c_i64(n), _ptr(m), c_f(mask_eps), _ptr(h), ctypes.c_uint32(int(min_hits)),
                                  _ptr(keep), _ptr(idx), ctypes.byref(nk), _stream()))
     return keep, idx[:nk.value]
+
+
+def track_loss(color, depth, alpha, target_color, target_depth, lam_d=1.0, norm=2, sil_thresh=0.99,
+               ctx: Context | None = None):
+    """Silhouette-masked colour + depth loss (eqs. (19), (21)); returns
+    (loss (1,), dL/dC (3, H, W), dL/dD (H, W))."""
+    ctx = ctx or default_context()
+    H, W = depth.shape
+    dlc = torch.empty_like(color)
+    dld = torch.empty_like(depth)
+    loss = torch.empty(1, dtype=torch.float32, device=color.device)
+    imgs = CImages(_ptr(_dev(color)), _ptr(_dev(depth)), _ptr(_dev(alpha)))
+    _check(lib().vcgs_track_loss(ctx.h, ctypes.byref(imgs), _ptr(_dev(target_color)), _ptr(_dev(target_depth)),
+                                 c_i32(W), c_i32(H), c_f(lam_d), c_i32(norm), c_f(sil_thresh), _ptr(dlc), _ptr(dld),
+                                 _ptr(loss), _stream()))
+    return loss, dlc, dld
+
+
+def icp_loss(means, camera, pose, depth, tau=0.05, stride=1, weight=1.0, dmeans=None, dpose=None,
+             ctx: Context | None = None):
+    """ICP term of eq. (20) against the observed depth map of ``camera``.
+    Returns (loss (1,), dmeans (3, n) or None, dpose (6,), matched (1,) int32);
+    gradients are added into dmeans / dpose when given (dpose created zero)."""
+    ctx = ctx or default_context()
+    m = _dev(means)
+    n = int(m.shape[1]) if m.dim() == 2 else 0
+    if dpose is None:
+        dpose = torch.zeros(6, device=m.device)
+    loss = torch.empty(1, device=m.device)
+    matched = torch.empty(1, dtype=torch.int32, device=m.device)
+    cam, ps = camera_struct(camera), pose_struct(pose)
+    _check(lib().vcgs_icp_loss(ctx.h, c_i64(n), _ptr(m), ctypes.byref(cam), ctypes.byref(ps), _ptr(_dev(depth)),
+                               c_f(tau), c_i32(stride), c_f(weight), _ptr(dmeans), _ptr(dpose), _ptr(loss),
+                               _ptr(matched), _stream()))
+    return loss, dmeans, dpose, matched
+
+
+def ssim_loss(color, target_color, weight=1.0, dl_dcolor=None, ctx: Context | None = None):
+    """weight * (1 - mean SSIM); returns (loss (1,), dl_dcolor) with the
+    gradient added into dl_dcolor (created zero if None)."""
+    ctx = ctx or default_context()
+    c = _dev(color)
+    _, H, W = c.shape
+    if dl_dcolor is None:
+        dl_dcolor = torch.zeros_like(c)
+    loss = torch.empty(1, device=c.device)
+    _check(lib().vcgs_ssim_loss(ctx.h, _ptr(c), _ptr(_dev(target_color)), c_i32(W), c_i32(H), c_f(weight),
+                                _ptr(dl_dcolor), _ptr(loss), _stream()))
+    return loss, dl_dcolor
 
 
 def rvq_assign(books, x, idx_bytes=1, idx=True, recon=True, loss=True, dbooks=None, grad=False,

@@ -1,0 +1,157 @@
+"""Tracking and BA losses on the GPU (Sec. 3.5 eqs. (19)-(21), SSIM) against
+the oracle: the silhouette-masked colour/depth loss and its image gradients,
+SSIM and its gradient (ragged and full-size images), and the ICP term with its
+nearest-neighbour association, Gaussian-centre and pose gradients (small
+scenes in full, the room at full size on sampled Gaussians).  Queries whose
+association or tau decision lies within binary32 noise are moved out of
+range first, so that both sides decide alike."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import track as otrack
+from paper_2403_11247_amd import scenes
+from tests.gpu_common import FIELDS, dev, gauss_dev, rel_err, say
+
+pytestmark = pytest.mark.gpu
+THRESH32 = float(np.float32(0.99))
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_2403_11247_amd import vcgs
+    vcgs.lib()
+    return vcgs
+
+
+def _frames(V, seed, n=5000, W=200, H=136):
+    g = scenes.random_scene(n, seed=seed, xy=1.3, log_scale=(0.02, 0.12))
+    gd = gauss_dev(g)
+    cam = scenes.Camera(W, H, 160.0, 160.0, W / 2, H / 2)
+    pose = scenes.identity_pose()
+    C, D, A, _ = V.render_forward(*gd, cam, pose, keep_state=False)
+    tpose = scenes.perturb_pose(pose, seed + 1, trans=0.03, rot_deg=1.5)
+    tC, tD, _, _ = V.render_forward(*gd, cam, tpose, keep_state=False)
+    holes = torch.as_tensor(np.random.default_rng(seed).uniform(size=(H, W)) < 0.15, device="cuda")
+    tD = torch.where(holes, torch.zeros_like(tD), tD)
+    torch.cuda.synchronize()
+    return g, gd, cam, pose, tpose, (C, D, A), (tC, tD)
+
+
+@pytest.mark.parametrize("norm", [2, 1])
+def test_track_loss_matches_oracle(V, norm):
+    g, gd, cam, pose, tpose, (C, D, A), (tC, tD) = _frames(V, 1)
+    loss, dlc, dld = V.track_loss(C, D, A, tC, tD, lam_d=0.8, norm=norm)
+    torch.cuda.synchronize()
+    ref, rc, rd = otrack.track_loss(*(t.cpu().numpy() for t in (C, D, A, tC, tD)), lam_d=0.8, norm=norm,
+                                    thresh=THRESH32)
+    on = (A.cpu().numpy() > THRESH32)
+    say(f"track loss norm {norm}: {ref:.5e}, silhouette on {on.mean():.3f}")
+    assert 0.05 < on.mean() < 0.95
+    assert abs(float(loss[0]) - ref) <= 1e-5 * abs(ref)
+    np.testing.assert_allclose(dlc.cpu().numpy(), rc, rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(dld.cpu().numpy(), rd, rtol=1e-5, atol=1e-12)
+
+
+@pytest.mark.parametrize("H,W", [(53, 77), (16, 16), (1, 30), (680, 1200)])
+def test_ssim_matches_oracle(V, H, W):
+    rng = np.random.default_rng(H * W)
+    x = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
+    y = np.clip(x + rng.normal(0, 0.15, x.shape), 0, 1).astype(np.float32)
+    ref, rg, _ = otrack.ssim(x, y)
+    base = np.zeros_like(x)
+    loss, g = V.ssim_loss(dev(x), dev(y), weight=0.3, dl_dcolor=dev(base))
+    torch.cuda.synchronize()
+    assert abs(float(loss[0]) - 0.3 * ref) <= 2e-6, (float(loss[0]), 0.3 * ref)
+    got = g.cpu().numpy().astype(np.float64)
+    scale = np.abs(rg).max() * 0.3
+    assert np.all(np.abs(got - 0.3 * rg) <= 2e-3 * np.abs(0.3 * rg) + 2e-4 * scale), \
+        np.abs(got - 0.3 * rg).max() / scale
+    say(f"ssim {H}x{W}: loss {ref:.5f}")
+
+
+def _pose32(p):
+    """The pose as the kernels see it (binary32)."""
+    return scenes.Pose(np.asarray(p.R, np.float32).astype(np.float64), np.asarray(p.t, np.float32).astype(np.float64))
+
+
+def _unambiguous(means, pose, depth, cam, tau, stride):
+    """Move Gaussians whose association or tau test is within binary32 noise
+    behind the camera (no partner on either side)."""
+    out = otrack.icp(means, pose, depth, cam, tau, stride, chunk=128)
+    amb = (np.abs(out["dist"] - tau) < 1e-5) | (out["second"] - out["dist"] < 1e-5)
+    if amb.any():
+        R = np.asarray(pose.R, np.float64).reshape(3, 3)
+        far = R.T @ (np.array([0.0, 0.0, -100.0]) - np.asarray(pose.t, np.float64))
+        means = means.copy()
+        means[:, amb] = far[:, None]
+        out = otrack.icp(means, pose, depth, cam, tau, stride, chunk=128)
+    return means, out, int(amb.sum())
+
+
+@pytest.mark.parametrize("stride,tau", [(1, 0.05), (3, 0.1)])
+def test_icp_matches_oracle(V, stride, tau):
+    g, gd, cam, pose, tpose, _, (tC, tD) = _frames(V, 2, n=3000, W=160, H=120)
+    tpose = _pose32(tpose)
+    depth = tD.cpu().numpy().astype(np.float64)
+    means, ref, n_amb = _unambiguous(g.mean.astype(np.float64), tpose, depth, cam, tau, stride)
+    m32 = means.astype(np.float32)
+    dm0 = np.random.default_rng(1).normal(size=m32.shape).astype(np.float32)
+    loss, dmeans, dpose, matched = V.icp_loss(dev(m32), cam, tpose, tD, tau=tau,
+                                              stride=stride, weight=0.5, dmeans=dev(dm0))
+    torch.cuda.synchronize()
+    say(f"icp stride {stride} tau {tau}: matched {int(ref['w'].sum())}/{means.shape[1]}, moved {n_amb}")
+    assert int(matched[0]) == int(ref["w"].sum()) > 100
+    assert abs(float(loss[0]) - 0.5 * ref["loss"]) <= 1e-4 * 0.5 * ref["loss"]
+    gm = dmeans.cpu().numpy().astype(np.float64) - dm0
+    sc = np.abs(ref["dmeans"]).max() * 0.5
+    assert np.all(np.abs(gm - 0.5 * ref["dmeans"]) <= 1e-3 * np.abs(0.5 * ref["dmeans"]) + 1e-4 * sc + 1e-6)
+    assert rel_err(dpose.cpu().numpy(), 0.5 * ref["dpose"]) <= 1e-3
+
+
+def test_icp_room_full_size_sampled(V):
+    """400k Gaussians of the room, the 1200x680 observed depth of the true pose,
+    ICP at a perturbed pose, every 2nd pixel: sampled Gaussians' gradients."""
+    from oracle import decode as odec
+    a = scenes.room_anchors(40000, k=10)
+    m = scenes.room_mlp(seed=0)
+    dec = odec.decode(a, m)
+    g = scenes.Gaussians(*[dec[f].astype(np.float32) for f in FIELDS])
+    gd = gauss_dev(g)
+    cam, pose = scenes.room_camera()
+    _, tD, _, _ = V.render_forward(*gd, cam, pose, keep_state=False)
+    tpose = _pose32(scenes.perturb_pose(pose, 7, trans=0.02, rot_deg=1.0))
+    tau, stride = 0.05, 2
+    dmeans = torch.zeros(3, g.n, device="cuda")
+    loss, _, dpose, matched = V.icp_loss(gd[0], cam, tpose, tD, tau=tau, stride=stride, dmeans=dmeans)
+    torch.cuda.synchronize()
+    depth = tD.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(3)
+    # check mostly Gaussians the kernel matched, plus a random draw (the oracle decides both)
+    dm = dmeans.cpu().numpy()
+    hit = np.nonzero(np.abs(dm).sum(0) > 0)[0]
+    assert len(hit) == int(matched[0]) > 1000
+    pick = np.unique(np.concatenate([rng.choice(hit, 300, replace=False), rng.choice(g.n, 100, replace=False)]))
+    ref = otrack.icp(g.mean[:, pick].astype(np.float64), tpose, depth, cam, tau, stride, chunk=16)
+    clear = (np.abs(ref["dist"] - tau) > 1e-5) & (ref["second"] - ref["dist"] > 1e-5)
+    got = dm[:, pick].astype(np.float64)
+    sc = np.abs(ref["dmeans"]).max() + 1e-30
+    ok = np.abs(got - ref["dmeans"]) <= 1e-3 * np.abs(ref["dmeans"]) + 1e-4 * sc
+    assert np.all(ok[:, clear]), np.argwhere(~ok[:, clear])[:5]
+    assert ref["w"][clear].sum() > 250
+    say(f"icp room: matched {int(matched[0])}/{g.n}, loss {float(loss[0]):.4e}, sampled clear {int(clear.sum())}")
+
+
+def test_rejections(V):
+    d = torch.zeros(4, 4, device="cuda")
+    c = torch.zeros(3, 4, 4, device="cuda")
+    with pytest.raises(V.VcgsError):
+        V.track_loss(c, d, d, c, d, norm=3)
+    cam = scenes.Camera(4, 4, 4.0, 4.0, 2.0, 2.0)
+    with pytest.raises(V.VcgsError):
+        V.icp_loss(torch.zeros(3, 5, device="cuda"), cam, scenes.identity_pose(), d, tau=0.0)
+    with pytest.raises(V.VcgsError):
+        V.icp_loss(torch.zeros(3, 5, device="cuda"), cam, scenes.identity_pose(), d, tau=0.1, stride=0)
+    loss, _, dpose, matched = V.icp_loss(torch.zeros(3, 0, device="cuda"), cam, scenes.identity_pose(), d)
+    torch.cuda.synchronize()
+    assert float(loss[0]) == 0.0 and int(matched[0]) == 0 and float(dpose.abs().max()) == 0.0
