@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving replay")
     ap.add_argument("--serve-requests", type=int, default=400, help="requests per arrival rate")
     ap.add_argument("--serve-qps", type=str, default="50,100,200,400")
-    ap.add_argument("--only", choices=("main", "ba", "serve", "view", "mask", "rvq"), default=None,
+    ap.add_argument("--only", choices=("main", "ba", "serve", "view", "mask", "rvq", "track"), default=None,
                     help="run one section only (for profiling)")
     return ap.parse_args()
 
@@ -330,6 +330,58 @@ def rvq_section(args, dev, steps=50, warmup=5):
             "rows": rows}
 
 
+def track_section(args, dev, steps=20, warmup=5):
+    """One tracking iteration (eq. (21)) and one BA-style step on the room:
+    the map is fixed and decoded once; the observed frame is the render at the
+    true pose, its depth normalised by alpha where alpha >= 0.5 and 15% missing.  Tracking: render at a perturbed
+    pose, silhouette-masked squared colour + depth loss, backward to the pose,
+    ICP against the observed depth (every 2nd pixel, tau 5 cm), pose gradient
+    summed.  BA step: render, L1 loss + 0.2 SSIM, backward."""
+    import numpy as np
+    import torch
+    from paper_2403_11247_amd import scenes, vcgs
+    a = scenes.room_anchors(40000, k=10)
+    m = scenes.room_mlp(seed=0)
+    A = [_up(x, dev) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    G = vcgs.decode_anchors(*A)
+    gs = [G[f] for f in F]
+    cam, pose = scenes.room_camera()
+    tC, tD, tA, _ = vcgs.render_forward(*gs, cam, pose, keep_state=False)
+    # a sensor-like depth: the alpha-normalised render where the surface is solid, 15% missing
+    holes = torch.as_tensor(np.random.default_rng(5).uniform(size=(cam.height, cam.width)) < 0.15, device=dev)
+    tD = torch.where(holes | (tA < 0.5), torch.zeros_like(tD), tD / tA.clamp_min(0.5))
+    cur = scenes.perturb_pose(pose, 3, trans=0.02, rot_deg=1.0)
+    stats = {}
+
+    def track_step():
+        C, D, Al, st = vcgs.render_forward(*gs, cam, cur)
+        loss, dlc, dld = vcgs.track_loss(C, D, Al, tC, tD, lam_d=1.0, norm=2)
+        _, dpose = vcgs.render_backward(st, *gs, cam, cur, dlc, dld, None)
+        l_icp, _, dpose, matched = vcgs.icp_loss(gs[0], cam, cur, tD, tau=0.05, stride=2, weight=0.1, dpose=dpose)
+        st.free()
+        stats["matched"] = matched
+        return loss, l_icp, dpose
+
+    def ba_step():
+        C, D, Al, st = vcgs.render_forward(*gs, cam, cur)
+        loss, dlc, dld = vcgs.l1_loss(C, D, tC, tD, 0.5)
+        l_s, dlc = vcgs.ssim_loss(C, tC, weight=0.2, dl_dcolor=dlc)
+        grads, dpose = vcgs.render_backward(st, *gs, cam, cur, dlc, dld, None)
+        st.free()
+        return loss, l_s, grads, dpose
+
+    ms_t = _timed(track_step, steps, warmup)
+    ms_b = _timed(ba_step, steps, warmup)
+    C, D, Al, _ = vcgs.render_forward(*gs, cam, cur, keep_state=False)
+    ms_l = _timed(lambda: vcgs.track_loss(C, D, Al, tC, tD), steps, warmup)
+    ms_i = _timed(lambda: vcgs.icp_loss(gs[0], cam, cur, tD, tau=0.05, stride=2), steps, warmup)
+    ms_s = _timed(lambda: vcgs.ssim_loss(C, tC, 0.2), steps, warmup)
+    return {"workload": "room 400k Gaussians, 1200x680: tracking iteration (render, masked colour+depth loss, "
+                        "backward, ICP every 2nd pixel) and BA step (render, L1 + 0.2 SSIM, backward)",
+            "track_ms": round(ms_t, 4), "ba_ms": round(ms_b, 4), "track_loss_ms": round(ms_l, 4),
+            "icp_ms": round(ms_i, 4), "ssim_ms": round(ms_s, 4), "icp_matched": int(stats["matched"][0])}
+
+
 def serve_section(args, dev):
     """Novel-view requests against a 1M-Gaussian room map (100k anchors at
     2 cm): Poisson arrivals at each rate, sizes uniform over 320x240, 640x480,
@@ -388,9 +440,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    if args.only in ("ba", "serve", "view", "mask", "rvq"):
+    if args.only in ("ba", "serve", "view", "mask", "rvq", "track"):
         res = {"ba": ba_section, "serve": serve_section, "view": view_decode_section,
-               "mask": mask_step_section, "rvq": rvq_section}[args.only](args, dev)
+               "mask": mask_step_section, "rvq": rvq_section, "track": track_section}[args.only](args, dev)
         print(json.dumps({args.only: res}), flush=True)
         return
     if args.only == "main":
@@ -504,6 +556,7 @@ def main():
     out["view_decode_step"] = view_decode_section(args, dev)
     out["mask_step"] = mask_step_section(args, dev)
     out["rvq"] = rvq_section(args, dev)
+    out["tracking"] = track_section(args, dev)
     if not args.no_ba:
         out["ba_window"] = ba_section(args, dev)
     if not args.no_serve:

@@ -330,7 +330,8 @@ int vcgs_rvq_assign(vcgs_ctx* ctx, const vcgs_rvq_books* q, int64_t n, const flo
     float* partial = (loss || grad) ? sc.get<float>(rvq_partial_floats(n, L, P, D, grad)) : nullptr;
     double* red = (loss || grad) ? sc.get<double>(rvq_red_doubles(n, L, P, D, grad)) : nullptr;
     if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (R-VQ)");
-    launch_rvq(n, D, L, P, q->books, x, idx, idx_bytes, recon, loss, dbooks, tab, partial, red, s);
+    if (!launch_rvq(n, D, L, P, q->books, x, idx, idx_bytes, recon, loss, dbooks, tab, partial, red, s))
+        return fail(VCGS_E_UNSUPPORTED, "the device refused the LDS size this R-VQ launch needs");
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return VCGS_OK;
@@ -374,9 +375,10 @@ int vcgs_icp_loss(vcgs_ctx* ctx, int64_t n, const float* mean, const vcgs_camera
     hipStream_t s = (hipStream_t)stream;
     Scratch sc(&ctx->pool);
     float* partial = sc.get<float>(8 * (int64_t)icp_blocks(n) + 8);
+    float* tmin = sc.get<float>(icp_tile_floats(cam->width, cam->height));
     if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (ICP)");
     launch_icp(n, mean, depth, cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy, pose->R, pose->t, tau,
-               stride, weight, dmean, loss, dpose, matched, partial, s);
+               stride, weight, dmean, loss, dpose, matched, partial, tmin, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return VCGS_OK;

@@ -193,7 +193,8 @@ void launch_mask_prune(int64_t n, const float* logit, float thr, const uint32_t*
 int rvq_padded_dim(int d);
 int64_t rvq_partial_floats(int64_t n, int L, int P, int D, bool grad);
 int64_t rvq_red_doubles(int64_t n, int L, int P, int D, bool grad);
-void launch_rvq(int64_t n, int D, int L, int P, const float* books, const float* x, void* idx, int idx_bytes,
+// false: the device refused the LDS the launch needs (nothing was launched)
+bool launch_rvq(int64_t n, int D, int L, int P, const float* books, const float* x, void* idx, int idx_bytes,
                 float* recon, float* loss, float* dbooks, float* tab, float* partial, double* red, hipStream_t s);
 
 // Tracking / BA losses (track.hip).
@@ -205,11 +206,12 @@ void launch_track_loss(int W, int H, const float* C, const float* D, const float
 int64_t ssim_partial_floats(int W, int H);
 void launch_ssim_loss(int W, int H, const float* X, const float* Y, float weight, float* dlc, float* loss, float* dm,
                       float* partial, hipStream_t s);
-// partial: 8 * icp_blocks(n) floats (at least 8)
+// partial: 8 * icp_blocks(n) floats (at least 8); tmin: icp_tile_floats(W, H) floats
 int icp_blocks(int64_t n);
+int64_t icp_tile_floats(int W, int H);
 void launch_icp(int64_t n, const float* mean, const float* depth, int W, int H, float fx, float fy, float cx,
                 float cy, const float R[9], const float t[3], float tau, int stride, float weight, float* dmean,
-                float* loss, float* dpose, uint32_t* matched, float* partial, hipStream_t s);
+                float* loss, float* dpose, uint32_t* matched, float* partial, float* tmin, hipStream_t s);
 
 // Process-wide kernel configuration (vcgs_set_option).
 struct Options {

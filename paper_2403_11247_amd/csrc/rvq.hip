@@ -27,13 +27,16 @@
 
 namespace vcgs {
 
-constexpr int kRvqThreads = 256;
 constexpr int kRvqMaxGridPartial = 512;
-constexpr int kRvqMaxGrid = 8192;
+constexpr int kRvqMaxGrid = 4096;
 
 typedef __attribute__((address_space(4))) const float CFloat;
 
 __host__ __device__ constexpr int rvq_row(int dm) { return dm + 4; }  // |c|^2, -2c (dm), padding
+
+// per-code gradient row: D residual sums and the count, padded to an odd
+// stride so that different codes fall in different LDS banks
+__host__ __device__ constexpr int rvq_gstride(int d) { return (d + 1) | 1; }
 
 int rvq_padded_dim(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32; }
 
@@ -55,37 +58,59 @@ __global__ void __launch_bounds__(256) k_rvq_table(int rows, int D, int dm, cons
 struct RvqArgs {
     int64_t n;
     int D, L, P;
-    const float* tab;    // [L][P][row]
+    const float* tab;    // [L][P][row] in global memory (scalar-operand path)
     const float* books;  // [L][P][D]
     const float* x;      // [n][D]
     void* idx;           // [L][n], 1 or 4 bytes
     int idx_bytes;
     float* recon;        // [n][D] or null
-    float* partial;      // [grid][pstride] or null: code sums and counts [L][P][D+1], then the loss
+    float* partial;      // [grid][pstride] or null: code sums and counts [L][P][rvq_gstride(D)], then the loss
     int grad;            // accumulate code sums
+    int copies;          // 1, 2 or 4 LDS copies of the code sums (lane % copies), summed at the end
     int pstride;
 };
 
-template <int DM>
-__global__ void __launch_bounds__(kRvqThreads) k_rvq_assign(RvqArgs a)
+// NT threads = NT / 256 vector groups of 64 at a time, each searched by four
+// waves over the four quarters of the codebook.  LTAB: the rows (|c|^2, -2c)
+// are built in LDS at the start and read as wave-uniform broadcasts; otherwise
+// they are read from the global table as scalar operands.
+template <int DM, bool LTAB, int NT>
+__global__ void __launch_bounds__(NT) k_rvq_assign(RvqArgs a)
 {
 #pragma clang fp contract(off)
-    extern __shared__ float s_grad[];
-    __shared__ float s_e[2][4][64];
-    __shared__ int s_k[2][4][64];
+    constexpr int SLOTS = NT / 256;
     constexpr int S = rvq_row(DM);
+    extern __shared__ float4 dyn4[];
+    float* dyn = reinterpret_cast<float*>(dyn4);
+    __shared__ float s_e[2][SLOTS][4][64];
+    __shared__ int s_k[2][SLOTS][4][64];
+    __shared__ float s_l[NT / 64];
     const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int slot = wv >> 2, w = wv & 3;
     const int k0 = (w * a.P) >> 2;
     const int k1 = ((w + 1) * a.P) >> 2;
-    const int E = a.grad ? a.L * a.P * (a.D + 1) : 0;
-    for (int i = threadIdx.x; i < E; i += kRvqThreads) s_grad[i] = 0.0f;
+    const int rows = a.L * a.P;
+    float* s_tab = dyn;
+    float* s_grad = dyn + (LTAB ? rows * S : 0);
+    const int E = a.grad ? rows * rvq_gstride(a.D) : 0;
+    if (LTAB) {
+        for (int r = threadIdx.x; r < rows; r += NT) {
+            const float* c = a.books + (int64_t)r * a.D;
+            float* t = s_tab + r * S;
+            float sq = c[0] * c[0];
+            for (int j = 1; j < a.D; ++j) sq = fmaf(c[j], c[j], sq);
+            t[0] = sq;
+            for (int j = 0; j < S - 1; ++j) t[1 + j] = j < a.D ? -2.0f * c[j] : 0.0f;
+        }
+    }
+    for (int i = threadIdx.x; i < E * a.copies; i += NT) s_grad[i] = 0.0f;
     __syncthreads();
     float lsum = 0.0f;
     int phase = 0;
     const int64_t groups = (a.n + 63) >> 6;
-    for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
-        const int64_t v = grp * 64 + lane;
+    for (int64_t base = (int64_t)blockIdx.x * SLOTS; base < groups; base += (int64_t)gridDim.x * SLOTS) {
+        const int64_t v = (base + slot) * 64 + lane;
         const bool valid = v < a.n;
         float xr[DM], xh[DM];
 #pragma unroll
@@ -99,68 +124,103 @@ __global__ void __launch_bounds__(kRvqThreads) k_rvq_assign(RvqArgs a)
             for (int j = 0; j < DM; ++j) r[j] = xr[j] - xh[j];
             float be = __builtin_inff();
             int bk = 0x7fffffff;
-            // wave-uniform rows read through the constant address space: scalar loads
-            const CFloat* t = (const CFloat*)(a.tab + ((int64_t)l * a.P + k0) * S);
-#pragma unroll DM <= 8 ? 4 : 2
-            for (int k = k0; k < k1; ++k, t += S) {
-                float e = t[0];
+            if (LTAB) {
+                const float4* t = reinterpret_cast<const float4*>(s_tab + (l * a.P + k0) * S);
+#pragma unroll 2
+                for (int k = k0; k < k1; ++k, t += S / 4) {
+                    float row[S];
 #pragma unroll
-                for (int j = 0; j < DM; ++j) e = fmaf(t[1 + j], r[j], e);
-                if (e < be) {
-                    be = e;
-                    bk = k;
+                    for (int q = 0; q < S / 4; ++q) {
+                        const float4 f = t[q];
+                        row[4 * q] = f.x;
+                        row[4 * q + 1] = f.y;
+                        row[4 * q + 2] = f.z;
+                        row[4 * q + 3] = f.w;
+                    }
+                    float e = row[0];
+#pragma unroll
+                    for (int j = 0; j < DM; ++j) e = fmaf(row[1 + j], r[j], e);
+                    if (e < be) {
+                        be = e;
+                        bk = k;
+                    }
+                }
+            } else {
+                // wave-uniform rows read through the constant address space: scalar loads
+                const CFloat* t = (const CFloat*)(a.tab + ((int64_t)l * a.P + k0) * S);
+#pragma unroll DM <= 8 ? 4 : 2
+                for (int k = k0; k < k1; ++k, t += S) {
+                    float e = t[0];
+#pragma unroll
+                    for (int j = 0; j < DM; ++j) e = fmaf(t[1 + j], r[j], e);
+                    if (e < be) {
+                        be = e;
+                        bk = k;
+                    }
                 }
             }
             const int buf = phase & 1;
             ++phase;
-            s_e[buf][w][lane] = be;
-            s_k[buf][w][lane] = bk;
+            s_e[buf][slot][w][lane] = be;
+            s_k[buf][slot][w][lane] = bk;
             __syncthreads();
-            be = s_e[buf][0][lane];
-            bk = s_k[buf][0][lane];
+            be = s_e[buf][slot][0][lane];
+            bk = s_k[buf][slot][0][lane];
 #pragma unroll
             for (int u = 1; u < 4; ++u) {
-                const float e2 = s_e[buf][u][lane];
+                const float e2 = s_e[buf][slot][u][lane];
                 if (e2 < be) {
                     be = e2;
-                    bk = s_k[buf][u][lane];
+                    bk = s_k[buf][slot][u][lane];
                 }
             }
             if (bk < 0 || bk >= a.P) bk = 0;  // non-finite distances everywhere
-            const float* c = a.books + ((int64_t)l * a.P + bk) * a.D;
+            if (valid && w == 0 && a.idx) {
+                if (a.idx_bytes == 1)
+                    static_cast<uint8_t*>(a.idx)[(int64_t)l * a.n + v] = (uint8_t)bk;
+                else
+                    static_cast<int32_t*>(a.idx)[(int64_t)l * a.n + v] = bk;
+            }
+            // the picked code, all of it before any accumulation (one wait, then the
+            // atomics issue back to back); from LDS, -0.5 * (-2 c) is exact
             float cv[DM];
+            if (LTAB) {
+                const float4* row4 = reinterpret_cast<const float4*>(s_tab + (l * a.P + bk) * S);
+                float row[S];
 #pragma unroll
-            for (int j = 0; j < DM; ++j) cv[j] = j < a.D ? c[j] : 0.0f;
-            if (valid) {
-                if (w == 0 && a.idx) {
-                    if (a.idx_bytes == 1)
-                        static_cast<uint8_t*>(a.idx)[(int64_t)l * a.n + v] = (uint8_t)bk;
-                    else
-                        static_cast<int32_t*>(a.idx)[(int64_t)l * a.n + v] = bk;
+                for (int q4 = 0; q4 < S / 4; ++q4) {
+                    const float4 f = row4[q4];
+                    row[4 * q4] = f.x;
+                    row[4 * q4 + 1] = f.y;
+                    row[4 * q4 + 2] = f.z;
+                    row[4 * q4 + 3] = f.w;
                 }
-                if (a.partial) {
-                    float* g = s_grad + (l * a.P + bk) * (a.D + 1);
-                    if (w == 0) {
-                        float q = 0.0f;
 #pragma unroll
-                        for (int j = 0; j < DM; ++j) {
-                            if (j < a.D) {
-                                const float d = r[j] - cv[j];
-                                q = fmaf(d, d, q);
-                            }
-                        }
-                        lsum += q;
-                        if (a.grad) atomicAdd(g + a.D, 1.0f);
-                    }
-                    if (a.grad) {
+                for (int j = 0; j < DM; ++j) cv[j] = -0.5f * row[1 + j];
+            } else {
+                const float* cg = a.books + ((int64_t)l * a.P + bk) * a.D;
 #pragma unroll
-                        for (int j = 0; j < DM; ++j)
-                            if (j < a.D && (j & 3) == w) atomicAdd(g + j, r[j]);
-                    }
+                for (int j = 0; j < DM; ++j) cv[j] = j < a.D ? cg[j] : 0.0f;
+            }
+            float* g = s_grad + (lane & (a.copies - 1)) * E + (l * a.P + bk) * rvq_gstride(a.D);
+            float q = 0.0f;
+#pragma unroll
+            for (int j = 0; j < DM; ++j) {
+                if (j < a.D) {
+                    const float d = r[j] - cv[j];
+                    q = fmaf(d, d, q);
+                    xh[j] = xh[j] + cv[j];
                 }
             }
+            if (valid && a.grad) {
 #pragma unroll
-            for (int j = 0; j < DM; ++j) xh[j] = xh[j] + cv[j];
+                for (int j = 0; j < DM; ++j)
+                    if (j < a.D && (j & 3) == w) atomicAdd(g + j, r[j]);
+            }
+            if (valid && a.partial && w == 0) {
+                lsum += q;
+                if (a.grad) atomicAdd(g + a.D, 1.0f);
+            }
         }
         if (valid && a.recon) {
 #pragma unroll
@@ -169,12 +229,21 @@ __global__ void __launch_bounds__(kRvqThreads) k_rvq_assign(RvqArgs a)
         }
     }
     if (a.partial) {
-        __syncthreads();
-        float* p = a.partial + (int64_t)blockIdx.x * a.pstride;
-        for (int i = threadIdx.x; i < E; i += kRvqThreads) p[i] = s_grad[i];
         if (w == 0) {
             for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
-            if (lane == 0) p[E] = lsum;
+        }
+        if (lane == 0) s_l[wv] = lsum;
+        __syncthreads();
+        float* p = a.partial + (int64_t)blockIdx.x * a.pstride;
+        for (int i = threadIdx.x; i < E; i += NT) {
+            float t = s_grad[i];
+            for (int c = 1; c < a.copies; ++c) t += s_grad[c * E + i];
+            p[i] = t;
+        }
+        if (threadIdx.x == 0) {
+            float t = 0.0f;
+            for (int u = 0; u < SLOTS; ++u) t += s_l[4 * u];
+            p[E] = t;
         }
     }
 }
@@ -220,45 +289,104 @@ __global__ void __launch_bounds__(256) k_rvq_apply(int L, int P, int D, int grad
                                                    float* __restrict__ dbooks, float* __restrict__ loss)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    const int E = grad ? L * P * (D + 1) : 0;
+    const int G = rvq_gstride(D);
+    const int E = grad ? L * P * G : 0;
     if (i == 0 && loss) *loss = (float)(rvq_red(red, runs, E + 1, E) * inv_np);
     if (!grad || i >= L * P * D) return;
     const int row = i / D, j = i - row * D;
-    const double cnt = rvq_red(red, runs, E + 1, row * (D + 1) + D);
-    const double sr = rvq_red(red, runs, E + 1, row * (D + 1) + j);
+    const double cnt = rvq_red(red, runs, E + 1, row * G + D);
+    const double sr = rvq_red(red, runs, E + 1, row * G + j);
     dbooks[i] += (float)(2.0 * inv_np * (cnt * (double)books[i] - sr));
 }
 
-int rvq_grid(int64_t n, bool partial)
+constexpr int kRvqStaticLds = 16 * 1024 + 64;
+constexpr int kRvqLdsLimit = 160 * 1024;
+
+static int rvq_threads(int dm) { return dm <= 16 ? 1024 : 512; }
+
+int rvq_grid(int64_t n, int D, bool partial)
 {
-    const int64_t groups = (n + 63) / 64;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(groups, partial ? kRvqMaxGridPartial : kRvqMaxGrid));
+    const int64_t slots = rvq_threads(rvq_padded_dim(D)) / 256;
+    const int64_t blocks = ((n + 63) / 64 + slots - 1) / slots;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, partial ? kRvqMaxGridPartial : kRvqMaxGrid));
 }
 
 int64_t rvq_partial_floats(int64_t n, int L, int P, int D, bool grad)
 {
-    const int64_t stride = (grad ? (int64_t)L * P * (D + 1) : 0) + 1;
-    return stride * rvq_grid(n, true);
+    const int64_t stride = (grad ? (int64_t)L * P * rvq_gstride(D) : 0) + 1;
+    return stride * rvq_grid(n, D, true);
 }
 
 int64_t rvq_red_doubles(int64_t n, int L, int P, int D, bool grad)
 {
-    const int64_t entries = (grad ? (int64_t)L * P * (D + 1) : 0) + 1;
-    return entries * ((rvq_grid(n, true) + kRvqRun - 1) / kRvqRun);
+    const int64_t entries = (grad ? (int64_t)L * P * rvq_gstride(D) : 0) + 1;
+    return entries * ((rvq_grid(n, D, true) + kRvqRun - 1) / kRvqRun);
 }
 
-void launch_rvq(int64_t n, int D, int L, int P, const float* books, const float* x, void* idx, int idx_bytes,
+// LDS beyond 64 KiB per block must be allowed per kernel; false if refused
+template <int DM, bool LTAB>
+static bool rvq_allow_lds()
+{
+    constexpr int NT = DM <= 16 ? 1024 : 512;
+    static int state = 0;  // 0 unknown, 1 allowed, -1 refused
+    if (state == 0)
+        state = hipFuncSetAttribute((const void*)k_rvq_assign<DM, LTAB, NT>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kRvqLdsLimit - kRvqStaticLds) == hipSuccess ? 1 : -1;
+    return state > 0;
+}
+
+template <int DM>
+static bool rvq_allow(bool ltab)
+{
+    return ltab ? rvq_allow_lds<DM, true>() : rvq_allow_lds<DM, false>();
+}
+
+template <int DM>
+static void rvq_launch(bool ltab, int grid, size_t lds, const RvqArgs& a, hipStream_t s)
+{
+    constexpr int NT = DM <= 16 ? 1024 : 512;
+    if (ltab)
+        k_rvq_assign<DM, true, NT><<<grid, NT, lds, s>>>(a);
+    else
+        k_rvq_assign<DM, false, NT><<<grid, NT, lds, s>>>(a);
+}
+
+bool launch_rvq(int64_t n, int D, int L, int P, const float* books, const float* x, void* idx, int idx_bytes,
                 float* recon, float* loss, float* dbooks, float* tab, float* partial, double* red, hipStream_t s)
 {
     const bool want_partial = loss || dbooks;
     const int grad = dbooks ? 1 : 0;
     if (n <= 0) {
         if (loss) launch_fill_f32(loss, 0.0f, 1, s);
-        return;
+        return true;
     }
     const int dm = rvq_padded_dim(D);
     const int rows = L * P;
-    k_rvq_table<<<(rows + 255) / 256, 256, 0, s>>>(rows, D, dm, books, tab);
+    const int E = grad ? rows * rvq_gstride(D) : 0;
+    const size_t tab_bytes = (size_t)rows * rvq_row(dm) * sizeof(float);
+    auto allow = [&](bool lt) {
+        switch (dm) {
+        case 4: return rvq_allow<4>(lt);
+        case 8: return rvq_allow<8>(lt);
+        case 16: return rvq_allow<16>(lt);
+        default: return rvq_allow<32>(lt);
+        }
+    };
+    const size_t lds_limit = (size_t)(kRvqLdsLimit - kRvqStaticLds);
+    bool ltab = (size_t)E * sizeof(float) + tab_bytes <= lds_limit;
+    // lanes of a wave that picked the same code serialise on its LDS row: spread
+    // them over up to four copies when they fit beside the table
+    int copies = 1;
+    while (ltab && E > 0 && copies < 4 && (size_t)E * 2 * copies * sizeof(float) + tab_bytes <= lds_limit) copies *= 2;
+    if (ltab && (size_t)E * copies * sizeof(float) + tab_bytes > 64 * 1024) ltab = allow(true);
+    if (!ltab) copies = 1;
+    if (!ltab && (size_t)E * sizeof(float) > 64 * 1024 - kRvqStaticLds && !allow(false)) {
+        (void)hipGetLastError();
+        return false;
+    }
+    (void)hipGetLastError();
+    if (!ltab) k_rvq_table<<<(rows + 255) / 256, 256, 0, s>>>(rows, D, dm, books, tab);
     RvqArgs a;
     a.n = n;
     a.D = D;
@@ -272,23 +400,24 @@ void launch_rvq(int64_t n, int D, int L, int P, const float* books, const float*
     a.recon = recon;
     a.partial = want_partial ? partial : nullptr;
     a.grad = grad;
-    const int E = grad ? L * P * (D + 1) : 0;
+    a.copies = copies;
     a.pstride = E + 1;
-    const int grid = rvq_grid(n, want_partial);
-    const size_t lds = (size_t)E * sizeof(float);
+    const int grid = rvq_grid(n, D, want_partial);
+    const size_t lds = (size_t)E * copies * sizeof(float) + (ltab ? tab_bytes : 0);
     switch (dm) {
-    case 4: k_rvq_assign<4><<<grid, kRvqThreads, lds, s>>>(a); break;
-    case 8: k_rvq_assign<8><<<grid, kRvqThreads, lds, s>>>(a); break;
-    case 16: k_rvq_assign<16><<<grid, kRvqThreads, lds, s>>>(a); break;
-    default: k_rvq_assign<32><<<grid, kRvqThreads, lds, s>>>(a); break;
+    case 4: rvq_launch<4>(ltab, grid, lds, a, s); break;
+    case 8: rvq_launch<8>(ltab, grid, lds, a, s); break;
+    case 16: rvq_launch<16>(ltab, grid, lds, a, s); break;
+    default: rvq_launch<32>(ltab, grid, lds, a, s); break;
     }
-    if (!want_partial) return;
+    if (!want_partial) return true;
     const int entries = E + 1;
     const int runs = (grid + kRvqRun - 1) / kRvqRun;
     k_rvq_reduce<<<dim3((entries + 63) / 64, runs), 256, 0, s>>>(partial, grid, a.pstride, entries, red);
     const int outs = std::max(1, grad ? L * P * D : 1);
     k_rvq_apply<<<(outs + 255) / 256, 256, 0, s>>>(L, P, D, grad, books, red, runs, 1.0 / ((double)n * P), dbooks,
                                                    loss);
+    return true;
 }
 
 }  // namespace vcgs

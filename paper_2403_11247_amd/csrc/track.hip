@@ -20,7 +20,9 @@
 // x's projection along u (likewise along v), so scanning that window of the
 // depth map finds exactly the nearest observed point whenever one lies within
 // tau; beyond tau w = 0 and the point does not matter.  When x_z <= tau the
-// bound does not hold and the whole image is scanned.
+// bound does not hold and the window is the whole image.  Inside the window
+// only the 16 x 16 tiles whose observed depth range meets (x_z - tau, x_z + tau)
+// are scanned: a point of any other tile is at least tau away along z alone.
 #include "internal.h"
 
 namespace vcgs {
@@ -329,9 +331,36 @@ void launch_ssim_loss(int W, int H, const float* X, const float* Y, float weight
 
 // ---- ICP ----------------------------------------------------------------------
 
+constexpr int kIcpTile = 16;
+
+// smallest and largest observed depth per 16 x 16 tile (+inf, -inf without observations)
+__global__ void __launch_bounds__(256) k_icp_tile_range(const float* __restrict__ depth, int W, int H,
+                                                        float2* __restrict__ trange)
+{
+    __shared__ float smin[256], smax[256];
+    const int u = blockIdx.x * kIcpTile + (threadIdx.x & 15), v = blockIdx.y * kIcpTile + (threadIdx.x >> 4);
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+    if (u < W && v < H) {
+        const float z = depth[(int64_t)v * W + u];
+        if (z > 0.0f) lo = hi = z;
+    }
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smin[threadIdx.x] = fminf(smin[threadIdx.x], smin[threadIdx.x + w]);
+            smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) trange[blockIdx.y * gridDim.x + blockIdx.x] = make_float2(smin[0], smax[0]);
+}
+
 struct IcpArgs {
     int64_t n;
     const float* mean;  // [3][n]
+    const float2* trange;  // [ceil(H/16)][ceil(W/16)] observed depth range per tile
     const float* depth; // [H][W] observed
     int W, H, stride;
     float fx, fy, cx, cy;
@@ -355,6 +384,31 @@ __global__ void __launch_bounds__(kTrackThreads) k_icp(IcpArgs a)
         const float y = fmaf(a.R[3], mx, fmaf(a.R[4], my, fmaf(a.R[5], mz, a.t[1])));
         const float z = fmaf(a.R[6], mx, fmaf(a.R[7], my, fmaf(a.R[8], mz, a.t[2])));
         if (!(z + a.tau > 0.0f)) continue;  // every observed point has depth > 0
+        float best = tau2, qx = 0.0f, qy = 0.0f, qz = 0.0f;
+        bool hit = false;
+        // nearest observed point in the pixel rectangle [ulo, uhi] x [vlo, vhi] (stride-aligned)
+        auto scan = [&](int ulo, int uhi, int vlo, int vhi) {
+            ulo = (ulo + s - 1) / s * s;
+            vlo = (vlo + s - 1) / s * s;
+            for (int v = vlo; v <= vhi; v += s) {
+                const float* row = a.depth + (int64_t)v * a.W;
+                const float py = ((float)v + 0.5f - a.cy) / a.fy;
+                for (int u = ulo; u <= uhi; u += s) {
+                    const float d = row[u];
+                    if (!(d > 0.0f)) continue;
+                    const float px = ((float)u + 0.5f - a.cx) / a.fx;
+                    const float ex = x - px * d, ey = y - py * d, ez = z - d;
+                    const float d2 = ex * ex + ey * ey + ez * ez;
+                    if (d2 < best) {
+                        best = d2;
+                        qx = px * d;
+                        qy = py * d;
+                        qz = d;
+                        hit = true;
+                    }
+                }
+            }
+        };
         int ulo = 0, uhi = a.W - 1, vlo = 0, vhi = a.H - 1;
         if (z > a.tau) {
             const float iz = 1.0f / z;
@@ -366,27 +420,15 @@ __global__ void __launch_bounds__(kTrackThreads) k_icp(IcpArgs a)
             vlo = (int)fmaxf(0.0f, floorf(vc - rv));
             vhi = (int)fminf((float)(a.H - 1), ceilf(vc + rv));
         }
-        ulo = (ulo + s - 1) / s * s;
-        vlo = (vlo + s - 1) / s * s;
-        float best = tau2, qx = 0.0f, qy = 0.0f, qz = 0.0f;
-        bool hit = false;
-        for (int v = vlo; v <= vhi; v += s) {
-            const float* row = a.depth + (int64_t)v * a.W;
-            const float py = ((float)v + 0.5f - a.cy) / a.fy;
-            for (int u = ulo; u <= uhi; u += s) {
-                const float d = row[u];
-                if (!(d > 0.0f)) continue;
-                const float px = ((float)u + 0.5f - a.cx) / a.fx;
-                const float ex = x - px * d, ey = y - py * d, ez = z - d;
-                const float d2 = ex * ex + ey * ey + ez * ez;
-                if (d2 < best) {
-                    best = d2;
-                    qx = px * d;
-                    qy = py * d;
-                    qz = d;
-                    hit = true;
+        if (ulo <= uhi && vlo <= vhi) {
+            const int tx = (a.W + kIcpTile - 1) / kIcpTile;
+            for (int j = vlo / kIcpTile; j <= vhi / kIcpTile; ++j)
+                for (int i = ulo / kIcpTile; i <= uhi / kIcpTile; ++i) {
+                    const float2 r = a.trange[j * tx + i];
+                    if (r.x < z + a.tau && r.y > z - a.tau)
+                        scan(max(ulo, i * kIcpTile), min(uhi, i * kIcpTile + kIcpTile - 1), max(vlo, j * kIcpTile),
+                             min(vhi, j * kIcpTile + kIcpTile - 1));
                 }
-            }
         }
         if (!hit) continue;
         const float ex = x - qx, ey = y - qy, ez = z - qz;
@@ -442,11 +484,17 @@ __global__ void __launch_bounds__(256) k_icp_finish(const float* __restrict__ pa
 
 int icp_blocks(int64_t n) { return track_blocks(n); }
 
+int64_t icp_tile_floats(int W, int H)
+{
+    return 2 * (int64_t)((W + kIcpTile - 1) / kIcpTile) * ((H + kIcpTile - 1) / kIcpTile);
+}
+
 void launch_icp(int64_t n, const float* mean, const float* depth, int W, int H, float fx, float fy, float cx,
                 float cy, const float R[9], const float t[3], float tau, int stride, float weight, float* dmean,
-                float* loss, float* dpose, uint32_t* matched, float* partial, hipStream_t s)
+                float* loss, float* dpose, uint32_t* matched, float* partial, float* tmin, hipStream_t s)
 {
     IcpArgs a;
+    a.trange = reinterpret_cast<const float2*>(tmin);
     a.n = n;
     a.mean = mean;
     a.depth = depth;
@@ -464,7 +512,11 @@ void launch_icp(int64_t n, const float* mean, const float* depth, int W, int H, 
     a.dmean = dmean;
     a.partial = partial;
     const int nb = icp_blocks(n);
-    if (n > 0) k_icp<<<nb, kTrackThreads, 0, s>>>(a);
+    if (n > 0) {
+        k_icp_tile_range<<<dim3((W + kIcpTile - 1) / kIcpTile, (H + kIcpTile - 1) / kIcpTile), 256, 0, s>>>(
+            depth, W, H, reinterpret_cast<float2*>(tmin));
+        k_icp<<<nb, kTrackThreads, 0, s>>>(a);
+    }
     else launch_fill_f32(partial, 0.0f, 8, s);
     k_icp_finish<<<1, 256, 0, s>>>(partial, n > 0 ? nb : 1, weight, loss, dpose, matched);
 }

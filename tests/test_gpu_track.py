@@ -109,6 +109,37 @@ def test_icp_matches_oracle(V, stride, tau):
     assert rel_err(dpose.cpu().numpy(), 0.5 * ref["dpose"]) <= 1e-3
 
 
+def test_icp_near_the_camera_plane(V):
+    """Gaussians with camera depth within tau of zero (the projection bound
+    fails; tiles are pruned by their smallest depth) against a depth map with a
+    patch of very close observations."""
+    rng = np.random.default_rng(11)
+    W, H = 96, 64
+    cam = scenes.Camera(W, H, 60.0, 60.0, W / 2, H / 2)
+    depth = np.full((H, W), 2.0, np.float32)
+    depth[20:30, 40:52] = rng.uniform(0.02, 0.08, (10, 12))
+    depth[rng.uniform(size=(H, W)) < 0.1] = 0.0
+    tau, stride = 0.05, 1
+    pts = otrack.backproject(depth, cam)
+    near = pts[(pts[:, 2] < 0.1)][rng.integers(0, 100, 150)] + rng.normal(0, 0.02, (150, 3))
+    near[:, 2] = rng.uniform(-0.04, 0.05, 150)
+    far = pts[rng.integers(0, len(pts), 300)] + rng.normal(0, 0.02, (300, 3))
+    means = np.concatenate([near, far]).T
+    pose = _pose32(scenes.identity_pose())
+    means, ref, n_amb = _unambiguous(means, pose, depth.astype(np.float64), cam, tau, stride)
+    loss, dmeans, dpose, matched = V.icp_loss(dev(means.astype(np.float32)), cam, pose, dev(depth), tau=tau,
+                                              stride=stride, dmeans=torch.zeros(3, means.shape[1], device="cuda"))
+    torch.cuda.synchronize()
+    w_near = int(ref["w"][:150].sum())
+    say(f"icp near plane: matched {int(ref['w'].sum())} ({w_near} near), moved {n_amb}")
+    assert w_near > 10
+    assert int(matched[0]) == int(ref["w"].sum())
+    assert abs(float(loss[0]) - ref["loss"]) <= 1e-4 * ref["loss"]
+    sc = np.abs(ref["dmeans"]).max()
+    got = dmeans.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref["dmeans"]) <= 1e-3 * np.abs(ref["dmeans"]) + 1e-4 * sc + 1e-6)
+
+
 def test_icp_room_full_size_sampled(V):
     """400k Gaussians of the room, the 1200x680 observed depth of the true pose,
     ICP at a perturbed pose, every 2nd pixel: sampled Gaussians' gradients."""
