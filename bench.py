@@ -553,10 +553,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 2 * src.numel() * 4
-    out["view_decode_step"] = view_decode_section(args, dev)
-    out["mask_step"] = mask_step_section(args, dev)
-    out["rvq"] = rvq_section(args, dev)
-    out["tracking"] = track_section(args, dev)
+    if args.only != "main":
+        out["view_decode_step"] = view_decode_section(args, dev)
+        out["mask_step"] = mask_step_section(args, dev)
+        out["rvq"] = rvq_section(args, dev)
+        out["tracking"] = track_section(args, dev)
     if not args.no_ba:
         out["ba_window"] = ba_section(args, dev)
     if not args.no_serve:
