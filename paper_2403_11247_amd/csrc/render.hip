@@ -430,13 +430,14 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
                 const float a = f.alpha;
                 const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
                 const float x[5] = {rc.y, rc.z, rc.w, rz, 1.0f};
+                // a masked to 0 leaves acc unchanged exactly (acc + 0 d), one select for five channels
+                const float am = c ? a : 0.0f;
                 float dla = 0.0f;
 #pragma unroll
                 for (int ch = 0; ch < 5; ++ch) {
                     const float d = x[ch] - acc[j][ch];
                     dla += up[j][ch] * d;
-                    const float an = acc[j][ch] + a * d;
-                    acc[j][ch] = c ? an : acc[j][ch];
+                    acc[j][ch] = fmaf(am, d, acc[j][ch]);
                 }
                 dla *= Ti;
                 const float w = c ? a * Ti : 0.0f;
@@ -445,14 +446,15 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
                 p[8] += w * up[j][2];
                 p[9] += w * up[j][3];
                 const bool g = c && !f.clamped;
-                const float dp = g ? dla * a : 0.0f;  // dL/dpower, power = -1/2 d^T Q d
+                const float dg = g ? dla : 0.0f;
+                const float dp = dg * a;  // dL/dpower, power = -1/2 d^T Q d
                 const float q1 = i1 * f.p1, q2 = i2 * f.p2;
                 p[0] += dp * (q1 * rb.x - q2 * rb.y);   // d power / d u = (Q d)_x
                 p[1] += dp * (q1 * rb.y + q2 * rb.x);   // d power / d v = (Q d)_y
                 p[2] += dp * (-0.5f * dx * dx);
                 p[3] += dp * (-dx * dyj);
                 p[4] += dp * (-0.5f * dyj * dyj);
-                p[5] += g ? dla * f.G : 0.0f;
+                p[5] += dg * f.G;
                 T[j] = c ? Ti : T[j];
                 contrib = contrib || c;
             }

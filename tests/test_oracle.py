@@ -593,6 +593,11 @@ def test_mask_loss_gradient_and_closed_form():
     # sigmoid(0) = 1/2 whatever the window
     assert abs(omask.mask_loss(np.zeros(50), np.ones(50, bool), 2.0)[0] - 1.0) < 1e-15
     assert omask.mask_loss(m, np.zeros(200, bool))[0] == 0.0
+    # only the frustum counts: logits outside it change neither the loss nor any gradient
+    m2 = m.copy()
+    m2[~inf] = rng.normal(5.0, 3.0, int((~inf).sum()))
+    l2, g2 = omask.mask_loss(m2, inf, weight=0.3)
+    assert l2 == loss and np.array_equal(g2, grad) and np.all(grad[~inf] == 0)
 
 
 def test_prune_keeps_order_and_conditions():

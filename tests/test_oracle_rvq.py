@@ -131,3 +131,20 @@ def test_empty_input():
     books = np.ones((2, 8, 3), np.float32)
     out = rvq.rvq(books, np.zeros((0, 3), np.float32))
     assert out["loss"] == 0.0 and np.all(out["dbooks"] == 0.0) and out["idx"].shape == (2, 0)
+
+
+def test_equal_distances_pick_the_first_code():
+    """Duplicated codes tie exactly; the pick is the lowest index, as numpy's
+    argmin returns the first of equal minima."""
+    rng = np.random.default_rng(12)
+    P, D = 32, 5
+    books = rng.normal(0.0, 1.0, (1, P, D)).astype(np.float32)
+    books[0, 20] = books[0, 3]
+    books[0, 29] = books[0, 11]
+    x = np.concatenate([books[0, [3, 11]] + rng.normal(0.0, 1e-3, (2, D)),
+                        rng.normal(0.0, 1.0, (200, D))]).astype(np.float32)
+    out = rvq.rvq(books, x)
+    d = ((books[0][None].astype(np.float64) - x[:, None].astype(np.float64)) ** 2).sum(-1)
+    assert out["idx"][0][0] == 3 and out["idx"][0][1] == 11
+    assert not np.isin(out["idx"][0], [20, 29]).any()
+    assert np.array_equal(out["idx"][0], d.argmin(1))

@@ -85,6 +85,33 @@ def test_icp_nearest_neighbours_match_kdtree():
         assert out["w"].sum() > 10
 
 
+def test_backprojection_lands_on_pixel_centres():
+    """Projecting the back-projected points with the pinhole model gives the
+    pixel centres (u + 0.5, v + 0.5) and the observed depths."""
+    rng = np.random.default_rng(13)
+    cam = scenes.Camera(37, 23, 31.0, 29.0, 17.3, 12.1)
+    depth = rng.uniform(0.5, 4.0, (23, 37))
+    depth[rng.uniform(size=depth.shape) < 0.3] = 0.0
+    for stride in (1, 2, 5):
+        pts = track.backproject(depth, cam, stride)
+        v, u = np.nonzero(depth[::stride, ::stride] > 0)
+        np.testing.assert_allclose(cam.fx * pts[:, 0] / pts[:, 2] + cam.cx, u * stride + 0.5, rtol=0, atol=1e-9)
+        np.testing.assert_allclose(cam.fy * pts[:, 1] / pts[:, 2] + cam.cy, v * stride + 0.5, rtol=0, atol=1e-9)
+        np.testing.assert_allclose(pts[:, 2], depth[::stride, ::stride][v, u], rtol=1e-15)
+
+
+def test_icp_weights_are_the_tau_test_on_kdtree_distances():
+    rng = np.random.default_rng(14)
+    cam = scenes.Camera(40, 30, 35.0, 35.0, 20.0, 15.0)
+    depth = rng.uniform(1.0, 3.0, (30, 40))
+    means = rng.uniform([-1, -1, 1], [1, 1, 3], (500, 3)).T
+    for tau in (0.03, 0.1, 0.3):
+        out = track.icp(means, scenes.identity_pose(), depth, cam, tau)
+        dist, _ = cKDTree(out["pts"]).query(means.T)
+        assert np.array_equal(out["w"] > 0, dist < tau)
+        assert 0 < out["w"].sum() < means.shape[1]
+
+
 def test_icp_shifted_plane_closed_form():
     cam, depth = _plane_case()
     pts = track.backproject(depth, cam)
