@@ -203,6 +203,16 @@ int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* 
                       const vcgs_images* outs, vcgs_gaussian_buffers* grads, float* dl_dpose, float* loss,
                       int flags, void* stream);
 
+/* vcgs_render_batch that also adds, for every Gaussian, the number of pixels
+ * of all the window's views whose composite blends it to hits [n] (device
+ * uint32, accumulated as in vcgs_render_forward_hits: the mask step's hit
+ * counts of a keyframe window in one pass, paper Sec. 3.3 eq. (13)).  A
+ * captured graph adds them again on every replay. */
+int vcgs_render_batch_hits(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
+                           const float* const* target_color, const float* const* target_depth, float w_depth,
+                           const vcgs_images* outs, vcgs_gaussian_buffers* grads, float* dl_dpose, float* loss,
+                           int flags, uint32_t* hits, void* stream);
+
 /* Waits for the last vcgs_render_batch of ctx to finish.  Returns VCGS_OK, or
  * VCGS_E_CAPACITY if its pair buffers overflowed (its results are then
  * incomplete).  pairs (optional) receives the pass's pair count. */

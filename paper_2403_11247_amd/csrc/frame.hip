@@ -440,10 +440,10 @@ int vcgs_render_backward(vcgs_ctx* ctx, const vcgs_state* st_, const vcgs_gaussi
     return VCGS_OK;
 }
 
-int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
-                      const float* const* target_color, const float* const* target_depth, float w_depth,
-                      const vcgs_images* outs, vcgs_gaussian_buffers* grads, float* dl_dpose, float* loss,
-                      int flags, void* stream)
+static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
+                             const float* const* target_color, const float* const* target_depth, float w_depth,
+                             const vcgs_images* outs, vcgs_gaussian_buffers* grads, float* dl_dpose, float* loss,
+                             int flags, uint32_t* hits, void* stream)
 {
     if (!ctx || !views || !outs || !bg) return fail(VCGS_E_INVALID, "ctx, views, outs or bg is NULL");
     const int V = views->n_views;
@@ -468,7 +468,7 @@ int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* 
 
     // signature of the prepared plan: shapes, intrinsics and every pointer a graph would bake in
     std::vector<const void*> ptrs = {g->mean, g->scale, g->quat, g->opacity, g->color, gb.mean, gb.scale, gb.quat,
-                                     gb.opacity, gb.color, dl_dpose, loss};
+                                     gb.opacity, gb.color, dl_dpose, loss, hits};
     for (int v = 0; v < V; ++v) {
         ptrs.push_back(outs[v].color);
         ptrs.push_back(outs[v].depth);
@@ -507,6 +507,7 @@ int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* 
         for (int v = 0; v < V; ++v) plan->cams[v] = views->cams[v];
         Frame& f = plan->f;
         build_tables(V, g->n, views->cams, views->poses, bg, f);
+        f.vt.hits = hits;
         f.pt_dev = plan->get_e<ProjTab>(1);
         f.rec = plan->get_e<Splat>(f.E);
         f.depth_key = plan->get_e<uint32_t>(f.E);
@@ -607,6 +608,25 @@ int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* 
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return VCGS_OK;
+}
+
+int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
+                      const float* const* target_color, const float* const* target_depth, float w_depth,
+                      const vcgs_images* outs, vcgs_gaussian_buffers* grads, float* dl_dpose, float* loss,
+                      int flags, void* stream)
+{
+    return render_batch_impl(ctx, g, views, bg, target_color, target_depth, w_depth, outs, grads, dl_dpose, loss,
+                             flags, nullptr, stream);
+}
+
+int vcgs_render_batch_hits(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
+                           const float* const* target_color, const float* const* target_depth, float w_depth,
+                           const vcgs_images* outs, vcgs_gaussian_buffers* grads, float* dl_dpose, float* loss,
+                           int flags, uint32_t* hits, void* stream)
+{
+    if (!hits) return fail(VCGS_E_INVALID, "hits is NULL");
+    return render_batch_impl(ctx, g, views, bg, target_color, target_depth, w_depth, outs, grads, dl_dpose, loss,
+                             flags, hits, stream);
 }
 
 int vcgs_batch_check(vcgs_ctx* ctx, int64_t* pairs)

@@ -105,7 +105,7 @@ def lib():
                      "vcgs_server_submit", "vcgs_server_progress", "vcgs_server_stats_read",
                      "vcgs_decode_anchors_view", "vcgs_decode_anchors_view_backward", "vcgs_render_forward_hits",
                      "vcgs_mask_loss", "vcgs_mask_prune", "vcgs_rvq_assign", "vcgs_track_loss",
-                     "vcgs_icp_loss", "vcgs_ssim_loss"):
+                     "vcgs_icp_loss", "vcgs_ssim_loss", "vcgs_render_batch_hits"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -627,8 +627,10 @@ class BatchWindow:
                                                                              "color")])
         self.pairs = None
 
-    def run(self, means, scales, quats, opacities, colors, poses, targets=None):
-        """targets: list of (colour (3,H,W), depth (H,W)) per view when backward."""
+    def run(self, means, scales, quats, opacities, colors, poses, targets=None, hits=None):
+        """targets: list of (colour (3,H,W), depth (H,W)) per view when backward.
+        hits: optional int32 (n,) device tensor to which every Gaussian's number
+        of blended pixels over the window's views is added (mask step)."""
         g, keep = _gauss(means, scales, quats, opacities, colors)
         assert g.n == self.n and len(poses) == self.V
         views = CViews(self.V, ctypes.cast(self.c_cams, c_p),
@@ -640,16 +642,24 @@ class BatchWindow:
             self._tkeep = [(_dev(t[0]), _dev(t[1])) for t in targets]
             tc = (c_p * self.V)(*[_ptr(t[0]) for t in self._tkeep])
             td = (c_p * self.V)(*[_ptr(t[1]) for t in self._tkeep])
-        for attempt in range(2):
-            _check(lib().vcgs_render_batch(
-                self.ctx.h, ctypes.byref(g), ctypes.byref(views), self.bg, tc, td, c_f(self.w_depth), self.c_outs,
+        if hits is not None:
+            assert hits.is_cuda and hits.dtype == torch.int32 and hits.numel() == self.n and hits.is_contiguous()
+            saved = hits.clone()
+        args = (self.ctx.h, ctypes.byref(g), ctypes.byref(views), self.bg, tc, td, c_f(self.w_depth), self.c_outs,
                 ctypes.byref(self.c_grads) if self.backward else None,
                 _ptr(self.dpose) if self.backward else None, _ptr(self.loss) if self.backward else None,
-                c_i32(self.flags), _stream()))
+                c_i32(self.flags))
+        for attempt in range(2):
+            if hits is None:
+                _check(lib().vcgs_render_batch(*args, _stream()))
+            else:
+                _check(lib().vcgs_render_batch_hits(*args, _ptr(hits), _stream()))
             pairs = c_i64()
             rc = lib().vcgs_batch_check(self.ctx.h, ctypes.byref(pairs))
             self.pairs = pairs.value
             if rc == VCGS_E_CAPACITY and attempt == 0:
+                if hits is not None:
+                    hits.copy_(saved)  # the overflowed pass added incomplete counts
                 continue  # the library resized its pair buffers; run the pass again
             _check(rc)
             break

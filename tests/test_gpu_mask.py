@@ -114,3 +114,54 @@ def test_prune_matches_oracle(V):
     assert np.array_equal(idx.cpu().numpy().astype(np.uint32), idx_ref)
     keep, idx = V.mask_prune(dev(m[:0]))
     assert idx.numel() == 0
+
+
+def _single_view_hits(V, gd, cams, poses, n):
+    h = torch.zeros(n, dtype=torch.int32, device="cuda")
+    for c, p in zip(cams, poses):
+        V.render_forward(*gd, c, p, keep_state=False, hits=h)
+    torch.cuda.synchronize()
+    return h
+
+
+@pytest.mark.parametrize("graph,backward", [(False, False), (True, False), (True, True)])
+def test_window_hit_counts_equal_the_views_summed(V, graph, backward):
+    """A window's hit counts (one pass over 5 views) equal the per-view counts
+    summed, bit for bit; a replayed graph adds them again."""
+    g = scenes.random_scene(3000, seed=21, xy=1.2)
+    gd = gauss_dev(g)
+    cams = [scenes.Camera(w, h, 0.8 * w, 0.8 * w, w / 2.0, h / 2.0)
+            for (w, h) in [(64, 48), (100, 70), (128, 96), (33, 17), (80, 80)]]
+    poses = [scenes.perturb_pose(scenes.identity_pose(), 40 + i, trans=0.1, rot_deg=4.0) for i in range(5)]
+    want = _single_view_hits(V, gd, cams, poses, g.n)
+    assert int(want.sum()) > 1000
+    rng = np.random.default_rng(2)
+    tg = [(dev(rng.uniform(0, 1, (3, c.height, c.width))), dev(rng.uniform(1.5, 4.5, (c.height, c.width))))
+          for c in cams] if backward else None
+    win = V.BatchWindow(g.n, cams, backward=backward, graph=graph)
+    h = torch.zeros(g.n, dtype=torch.int32, device="cuda")
+    win.run(*gd, poses, tg, hits=h)
+    torch.cuda.synchronize()
+    assert torch.equal(h, want)
+    win.run(*gd, poses, tg, hits=h)
+    torch.cuda.synchronize()
+    assert torch.equal(h, 2 * want)
+
+
+def test_window_hit_counts_survive_a_capacity_rerun(V):
+    """Sized on distant poses, then rendered close up: the overflowed pass is
+    rerun and the counts are those of the complete pass only."""
+    g = scenes.random_scene(3000, seed=7, xy=1.0, log_scale=(0.05, 0.2))
+    gd = gauss_dev(g)
+    cams = [scenes.Camera(w, h, 0.8 * w, 0.8 * w, w / 2.0, h / 2.0) for (w, h) in [(200, 150), (160, 120)]]
+    far = [scenes.Pose(np.eye(3, dtype=np.float32), np.array([0, 0, 20.0], np.float32))] * 2
+    near = [scenes.Pose(np.eye(3, dtype=np.float32), np.array([0, 0, -1.2], np.float32))] * 2
+    for graph in (False, True):
+        win = V.BatchWindow(g.n, cams, backward=False, graph=graph)
+        win.run(*gd, far)
+        small = win.pairs
+        h = torch.zeros(g.n, dtype=torch.int32, device="cuda")
+        win.run(*gd, near, hits=h)
+        torch.cuda.synchronize()
+        assert win.pairs > small + small // 8 + 4096, (small, win.pairs)
+        assert torch.equal(h, _single_view_hits(V, gd, cams, near, g.n))
