@@ -371,44 +371,28 @@ struct IcpArgs {
     float* partial;     // [grid][8]: loss, rho(3), phi(3), matched
 };
 
+constexpr int kIcpGroup = 16;  // lanes that search for one Gaussian
+
+// 16 lanes per Gaussian: the tiles of its window are tested 16 at a time, and
+// the stride-aligned pixels of each tile that passes are spread over the lanes.
+// The nearest point is taken by (distance^2, pixel index), lowest first, so an
+// exact tie goes to the first pixel in raster order whatever the visiting order.
 __global__ void __launch_bounds__(kTrackThreads) k_icp(IcpArgs a)
 {
     __shared__ float sm[8][kTrackThreads];
     float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     const float tau2 = a.tau * a.tau;
     const int s = a.stride;
-    for (int64_t i = (int64_t)blockIdx.x * kTrackThreads + threadIdx.x; i < a.n;
-         i += (int64_t)gridDim.x * kTrackThreads) {
+    const int gl = threadIdx.x & (kIcpGroup - 1);
+    const int gbase = (threadIdx.x & 63) & ~(kIcpGroup - 1);  // first lane of the group in its wave
+    const int tx = (a.W + kIcpTile - 1) / kIcpTile;
+    constexpr int GPB = kTrackThreads / kIcpGroup;
+    for (int64_t i = (int64_t)blockIdx.x * GPB + threadIdx.x / kIcpGroup; i < a.n; i += (int64_t)gridDim.x * GPB) {
         const float mx = a.mean[i], my = a.mean[a.n + i], mz = a.mean[2 * a.n + i];
         const float x = fmaf(a.R[0], mx, fmaf(a.R[1], my, fmaf(a.R[2], mz, a.t[0])));
         const float y = fmaf(a.R[3], mx, fmaf(a.R[4], my, fmaf(a.R[5], mz, a.t[1])));
         const float z = fmaf(a.R[6], mx, fmaf(a.R[7], my, fmaf(a.R[8], mz, a.t[2])));
-        if (!(z + a.tau > 0.0f)) continue;  // every observed point has depth > 0
-        float best = tau2, qx = 0.0f, qy = 0.0f, qz = 0.0f;
-        bool hit = false;
-        // nearest observed point in the pixel rectangle [ulo, uhi] x [vlo, vhi] (stride-aligned)
-        auto scan = [&](int ulo, int uhi, int vlo, int vhi) {
-            ulo = (ulo + s - 1) / s * s;
-            vlo = (vlo + s - 1) / s * s;
-            for (int v = vlo; v <= vhi; v += s) {
-                const float* row = a.depth + (int64_t)v * a.W;
-                const float py = ((float)v + 0.5f - a.cy) / a.fy;
-                for (int u = ulo; u <= uhi; u += s) {
-                    const float d = row[u];
-                    if (!(d > 0.0f)) continue;
-                    const float px = ((float)u + 0.5f - a.cx) / a.fx;
-                    const float ex = x - px * d, ey = y - py * d, ez = z - d;
-                    const float d2 = ex * ex + ey * ey + ez * ez;
-                    if (d2 < best) {
-                        best = d2;
-                        qx = px * d;
-                        qy = py * d;
-                        qz = d;
-                        hit = true;
-                    }
-                }
-            }
-        };
+        if (!(z + a.tau > 0.0f)) continue;  // every observed point has depth > 0 (uniform in the group)
         int ulo = 0, uhi = a.W - 1, vlo = 0, vhi = a.H - 1;
         if (z > a.tau) {
             const float iz = 1.0f / z;
@@ -420,17 +404,57 @@ __global__ void __launch_bounds__(kTrackThreads) k_icp(IcpArgs a)
             vlo = (int)fmaxf(0.0f, floorf(vc - rv));
             vhi = (int)fminf((float)(a.H - 1), ceilf(vc + rv));
         }
+        float best = __builtin_inff();
+        int bpix = 0x7fffffff;
         if (ulo <= uhi && vlo <= vhi) {
-            const int tx = (a.W + kIcpTile - 1) / kIcpTile;
-            for (int j = vlo / kIcpTile; j <= vhi / kIcpTile; ++j)
-                for (int i = ulo / kIcpTile; i <= uhi / kIcpTile; ++i) {
-                    const float2 r = a.trange[j * tx + i];
-                    if (r.x < z + a.tau && r.y > z - a.tau)
-                        scan(max(ulo, i * kIcpTile), min(uhi, i * kIcpTile + kIcpTile - 1), max(vlo, j * kIcpTile),
-                             min(vhi, j * kIcpTile + kIcpTile - 1));
+            const int ti0 = ulo / kIcpTile, ti1 = uhi / kIcpTile, tj0 = vlo / kIcpTile, tj1 = vhi / kIcpTile;
+            const int ntx = ti1 - ti0 + 1, ntile = ntx * (tj1 - tj0 + 1);
+            for (int tb = 0; tb < ntile; tb += kIcpGroup) {
+                const int t = tb + gl;
+                bool pass = false;
+                if (t < ntile) {
+                    const float2 r = a.trange[(tj0 + t / ntx) * tx + ti0 + t % ntx];
+                    pass = r.x < z + a.tau && r.y > z - a.tau;
                 }
+                uint32_t m = (uint32_t)(__ballot(pass) >> gbase) & 0xFFFFu;
+                while (m) {
+                    const int k = __builtin_ctz(m);
+                    m &= m - 1u;
+                    const int ti = ti0 + (tb + k) % ntx, tj = tj0 + (tb + k) / ntx;
+                    const int u0 = (max(ulo, ti * kIcpTile) + s - 1) / s * s, u1 = min(uhi, ti * kIcpTile + kIcpTile - 1);
+                    const int v0 = (max(vlo, tj * kIcpTile) + s - 1) / s * s, v1 = min(vhi, tj * kIcpTile + kIcpTile - 1);
+                    if (u0 > u1 || v0 > v1) continue;
+                    const int nu = (u1 - u0) / s + 1, np = nu * ((v1 - v0) / s + 1);
+                    for (int idx = gl; idx < np; idx += kIcpGroup) {
+                        const int u = u0 + (idx % nu) * s, v = v0 + (idx / nu) * s;
+                        const int pix = v * a.W + u;
+                        const float d = a.depth[pix];
+                        if (!(d > 0.0f)) continue;
+                        const float px = ((float)u + 0.5f - a.cx) / a.fx, py = ((float)v + 0.5f - a.cy) / a.fy;
+                        const float ex = x - px * d, ey = y - py * d, ez = z - d;
+                        const float d2 = ex * ex + ey * ey + ez * ez;
+                        if (d2 < tau2 && (d2 < best || (d2 == best && pix < bpix))) {
+                            best = d2;
+                            bpix = pix;
+                        }
+                    }
+                }
+            }
         }
-        if (!hit) continue;
+        // lexicographic minimum over the group's 16 lanes
+#pragma unroll
+        for (int off = kIcpGroup / 2; off > 0; off >>= 1) {
+            const float ob = __shfl_xor(best, off, kIcpGroup);
+            const int op = __shfl_xor(bpix, off, kIcpGroup);
+            if (ob < best || (ob == best && op < bpix)) {
+                best = ob;
+                bpix = op;
+            }
+        }
+        if (gl != 0 || !(best < tau2)) continue;
+        const int u = bpix % a.W, v = bpix / a.W;
+        const float d = a.depth[bpix];
+        const float qx = ((float)u + 0.5f - a.cx) / a.fx * d, qy = ((float)v + 0.5f - a.cy) / a.fy * d, qz = d;
         const float ex = x - qx, ey = y - qy, ez = z - qz;
         const float gx = 2.0f * a.weight * ex, gy = 2.0f * a.weight * ey, gz = 2.0f * a.weight * ez;
         acc[0] += ex * ex + ey * ey + ez * ez;
@@ -482,7 +506,12 @@ __global__ void __launch_bounds__(256) k_icp_finish(const float* __restrict__ pa
     }
 }
 
-int icp_blocks(int64_t n) { return track_blocks(n); }
+// one 16-lane group per Gaussian
+int icp_blocks(int64_t n)
+{
+    constexpr int64_t GPB = kTrackThreads / kIcpGroup;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + GPB - 1) / GPB, 1 << 16));
+}
 
 int64_t icp_tile_floats(int W, int H)
 {
