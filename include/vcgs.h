@@ -23,6 +23,7 @@
 #ifndef VCGS_H
 #define VCGS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -93,6 +94,19 @@ void vcgs_destroy(vcgs_ctx* ctx);
 const char* vcgs_last_error(void);
 /* Library version string. */
 const char* vcgs_version(void);
+
+/* Device memory of the context's workspaces, render states, batch plans and
+ * servers: from hipMalloc / hipFree (the default, alloc = free = NULL), or
+ * from the caller's functions, e.g. a framework's caching allocator.  alloc
+ * returns a device pointer of at least `bytes` (NULL = out of memory); free
+ * takes it back.  The library returns memory only after the work that used it
+ * has finished (it synchronises first), so the caller may reuse it at once.
+ * Call it before the context holds memory: it drops the context's batch plans
+ * and cached blocks, and fails with VCGS_E_INVALID while a render state or a
+ * server of the context is alive. */
+typedef void* (*vcgs_alloc_fn)(size_t bytes, void* user);
+typedef void (*vcgs_free_fn)(void* ptr, void* user);
+int vcgs_set_allocator(vcgs_ctx* ctx, vcgs_alloc_fn alloc, vcgs_free_fn free_fn, void* user);
 
 /* ---- plain render ----------------------------------------------------- */
 

@@ -30,6 +30,7 @@ int vcgs_create(int device, vcgs_ctx** out)
     HIP_TRY(hipSetDevice(device));
     vcgs_ctx* c = new vcgs_ctx();
     c->device = device;
+    c->pool.dev = &c->dalloc;
     if (hipHostMalloc((void**)&c->host_u32, 64, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->host_tab, sizeof(ProjTab), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->graph_done, hipEventDisableTiming) != hipSuccess) {
@@ -400,6 +401,21 @@ int vcgs_ssim_loss(vcgs_ctx* ctx, const float* color, const float* target_color,
     launch_ssim_loss(width, height, color, target_color, weight, dl_dcolor, loss, dm, partial, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return VCGS_OK;
+}
+
+int vcgs_set_allocator(vcgs_ctx* ctx, vcgs_alloc_fn alloc, vcgs_free_fn free_fn, void* user)
+{
+    if (!ctx) return fail(VCGS_E_INVALID, "ctx is NULL");
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(VCGS_E_INVALID, "alloc and free go together");
+    if (ctx->servers > 0) return fail(VCGS_E_INVALID, "a server of this context is alive");
+    HIP_TRY(hipSetDevice(ctx->device));
+    destroy_plans(ctx);
+    ctx->pool.release_cache();
+    if (!ctx->pool.sizes.empty()) return fail(VCGS_E_INVALID, "workspaces are in use (a render state is alive)");
+    ctx->dalloc.alloc_fn = alloc;
+    ctx->dalloc.free_fn = free_fn;
+    ctx->dalloc.user = user;
     return VCGS_OK;
 }
 

@@ -26,11 +26,38 @@ inline int fail(int code, const std::string& msg)
         if (e_ != hipSuccess) return ::vcgs::fail(VCGS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Where device memory comes from: hipMalloc / hipFree, or the caller's
+// functions (vcgs_set_allocator), e.g. a framework's caching allocator.
+struct DevAlloc {
+    void* (*alloc_fn)(size_t, void*) = nullptr;
+    void (*free_fn)(void*, void*) = nullptr;
+    void* user = nullptr;
+    void* get(size_t bytes)
+    {
+        if (alloc_fn) return alloc_fn(bytes, user);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void put(void* p)
+    {
+        if (!p) return;
+        if (free_fn)
+            free_fn(p, user);
+        else
+            (void)hipFree(p);
+    }
+};
+
 // Caching allocator.  Blocks freed by the library go back to a size-keyed
 // free list and are reused by later requests; all work of a context is
 // ordered on the caller's stream, so a block released by one call is only
 // touched again by work enqueued after it.
 struct Pool {
+    DevAlloc* dev = nullptr;  // the context's source of device memory
     std::multimap<size_t, void*> free_blocks;
     std::map<void*, size_t> sizes;
     size_t cached = 0;
@@ -54,14 +81,11 @@ struct Pool {
             free_blocks.erase(it);
             return p;
         }
-        void* p = nullptr;
-        if (hipMalloc(&p, want) != hipSuccess) {
-            (void)hipGetLastError();
+        void* p = dev->get(want);
+        if (!p) {
             release_cache();
-            if (hipMalloc(&p, want) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
-            }
+            p = dev->get(want);
+            if (!p) return nullptr;
         }
         sizes[p] = want;
         return p;
@@ -81,7 +105,7 @@ struct Pool {
         if (free_blocks.empty()) return;
         (void)hipDeviceSynchronize();
         for (auto& kv : free_blocks) {
-            (void)hipFree(kv.second);
+            dev->put(kv.second);
             sizes.erase(kv.second);
         }
         free_blocks.clear();
@@ -91,7 +115,7 @@ struct Pool {
     void destroy()
     {
         (void)hipDeviceSynchronize();
-        for (auto& kv : sizes) (void)hipFree(kv.first);
+        for (auto& kv : sizes) dev->put(kv.first);
         sizes.clear();
         free_blocks.clear();
         cached = 0;
@@ -195,7 +219,8 @@ struct BatchPlan;
 
 struct vcgs_ctx {
     int device = 0;
-    vcgs::Pool pool;
+    vcgs::DevAlloc dalloc;
+    vcgs::Pool pool;  // pool.dev = &dalloc
     vcgs::Prof prof;
     uint32_t* host_u32 = nullptr;  // pinned readback slot
     vcgs::ProjTab* host_tab = nullptr;  // pinned staging of the per-view table
@@ -204,6 +229,7 @@ struct vcgs_ctx {
     std::vector<vcgs::BatchPlan*> plans;  // prepared batched windows, most recent last
     vcgs::BatchPlan* last_plan = nullptr;
     hipStream_t last_stream = nullptr;
+    int servers = 0;  // live servers (their slot buffers come from dalloc)
 };
 
 namespace vcgs {

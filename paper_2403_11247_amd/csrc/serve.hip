@@ -50,6 +50,7 @@ Prof& quiet_prof()
 
 struct vcgs_server {
     vcgs_ctx* ctx = nullptr;
+    bool counted = false;  // included in ctx->servers
     vcgs_gaussians map{};
     vcgs_server_config cfg{};
     std::deque<Req> queue;
@@ -87,18 +88,17 @@ struct vcgs_server {
 
     void* dalloc(size_t bytes, std::vector<void*>& list)
     {
-        void* p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
-            (void)hipGetLastError();
+        void* p = ctx->dalloc.get(std::max<size_t>(bytes, 256));
+        if (!p) {
             oom = true;
             return nullptr;
         }
         list.push_back(p);
         return p;
     }
-    static void dfree(std::vector<void*>& list)
+    void dfree(std::vector<void*>& list)
     {
-        for (void* p : list) (void)hipFree(p);
+        for (void* p : list) ctx->dalloc.put(p);
         list.clear();
     }
     // (Re)allocates a slot's pair buffers; the slot must be idle.  On failure
@@ -232,6 +232,10 @@ struct vcgs_server {
 
     void release()
     {
+        if (counted) {
+            --ctx->servers;
+            counted = false;
+        }
         for (Slot& sl : slots) {
             if (sl.s) (void)hipStreamSynchronize(sl.s);
             dfree(sl.blocks_e);
@@ -266,6 +270,8 @@ int vcgs_server_create(vcgs_ctx* ctx, const vcgs_gaussians* map, const vcgs_serv
     HIP_TRY(hipSetDevice(ctx->device));
     vcgs_server* srv = new vcgs_server();
     srv->ctx = ctx;
+    ++ctx->servers;
+    srv->counted = true;
     srv->map = *map;
     srv->cfg = *cfg;
     srv->ppp = cfg->pairs_per_pixel;

@@ -105,7 +105,7 @@ def lib():
                      "vcgs_server_submit", "vcgs_server_progress", "vcgs_server_stats_read",
                      "vcgs_decode_anchors_view", "vcgs_decode_anchors_view_backward", "vcgs_render_forward_hits",
                      "vcgs_mask_loss", "vcgs_mask_prune", "vcgs_rvq_assign", "vcgs_track_loss",
-                     "vcgs_icp_loss", "vcgs_ssim_loss", "vcgs_render_batch_hits"):
+                     "vcgs_icp_loss", "vcgs_ssim_loss", "vcgs_render_batch_hits", "vcgs_set_allocator"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -157,6 +157,29 @@ class Context:
         _check(lib().vcgs_create(dev, ctypes.byref(h)))
         self.h = h
         self.device = dev
+
+    ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+    FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+    def use_torch_allocator(self):
+        """Take the context's device memory from torch's caching allocator
+        (vcgs_set_allocator); call before the context holds memory."""
+        dev = self.device
+
+        def alloc(nbytes, _user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev)
+            except Exception:
+                return None
+
+        def free(ptr, _user):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        fa, ff = Context.ALLOC_FN(alloc), Context.FREE_FN(free)
+        # the library may still call the functions it holds (e.g. to return cached
+        # blocks while switching): every registered thunk stays alive with the context
+        self._fns = getattr(self, "_fns", []) + [fa, ff]
+        _check(lib().vcgs_set_allocator(self.h, fa, ff, None))
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
