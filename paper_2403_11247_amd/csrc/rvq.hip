@@ -328,12 +328,14 @@ template <int DM, bool LTAB>
 static bool rvq_allow_lds()
 {
     constexpr int NT = DM <= 16 ? 1024 : 512;
-    static int state = 0;  // 0 unknown, 1 allowed, -1 refused
-    if (state == 0)
-        state = hipFuncSetAttribute((const void*)k_rvq_assign<DM, LTAB, NT>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    kRvqLdsLimit - kRvqStaticLds) == hipSuccess ? 1 : -1;
-    return state > 0;
+    static int state[64] = {};  // per device: 0 unknown, 1 allowed, -1 refused
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    if (state[dev] == 0)
+        state[dev] = hipFuncSetAttribute((const void*)k_rvq_assign<DM, LTAB, NT>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         kRvqLdsLimit - kRvqStaticLds) == hipSuccess ? 1 : -1;
+    return state[dev] > 0;
 }
 
 template <int DM>
