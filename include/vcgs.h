@@ -354,7 +354,7 @@ int vcgs_ssim_loss(vcgs_ctx* ctx, const float* color, const float* target_color,
 
 /* L cascaded codebooks of P codes of dimension D: books is device float
  * [L][P][D] (row-major).  Limits: 1 <= D <= 32, 1 <= L <= 8, 1 <= P <= 256;
- * with a code gradient also L * P * (D + 1) <= 15360. */
+ * with a code gradient also L * P * ((D + 1) | 1) <= 16384. */
 typedef struct {
     int32_t dim;
     int32_t stages;
@@ -373,8 +373,10 @@ typedef struct {
  *          of |r - C[i]|^2;
  *   dbooks float [L][P][D]: the loss's gradient to the codes is ADDED (the
  *          residual is under a stop-gradient, so x gets none).
- * Code sums inside a block are float atomics: dbooks is reproducible to
- * rounding, not bit for bit; idx and recon are exact. */
+ * Code sums inside a block are exact 64-bit fixed point (2^-32 units; a
+ * block's sum of one residual component must stay below 2^31 in magnitude),
+ * so every output, dbooks included, is bit-reproducible; idx and recon are
+ * exact. */
 int vcgs_rvq_assign(vcgs_ctx* ctx, const vcgs_rvq_books* q, int64_t n, const float* x, void* idx, int32_t idx_bytes,
                     float* recon, float* loss, float* dbooks, void* stream);
 

@@ -317,8 +317,8 @@ int vcgs_rvq_assign(vcgs_ctx* ctx, const vcgs_rvq_books* q, int64_t n, const flo
     const int D = q->dim, L = q->stages, P = q->codes;
     if (D < 1 || D > 32 || L < 1 || L > 8 || P < 1 || P > 256)
         return fail(VCGS_E_INVALID, "R-VQ needs 1 <= dim <= 32, 1 <= stages <= 8, 1 <= codes <= 256");
-    if (dbooks && (int64_t)L * P * (D + 1) > 15360)
-        return fail(VCGS_E_INVALID, "stages * codes * (dim + 1) exceeds 15360 with a code gradient");
+    if (dbooks && (int64_t)L * P * ((D + 1) | 1) > 16384)
+        return fail(VCGS_E_INVALID, "stages * codes * ((dim + 1) | 1) exceeds 16384 with a code gradient");
     if (!q->books) return fail(VCGS_E_INVALID, "books is NULL");
     if (n < 0 || n > ((int64_t)1 << 40)) return fail(VCGS_E_INVALID, "n out of range");
     if (n > 0 && !x) return fail(VCGS_E_INVALID, "x is NULL");

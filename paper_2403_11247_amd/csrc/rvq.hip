@@ -20,9 +20,11 @@
 // Decision arithmetic (binary32, no contraction beyond the explicit fmaf):
 //   |c|^2 = c_0 c_0, then fmaf(c_j, c_j, .);  e = |c|^2, then fmaf(-2 c_j, r_j, .);
 //   xhat_j += c_j and r_j = x_j - xhat_j.
-// Code gradients: per-block sums of residuals and counts per code in LDS (float
-// atomics, so the order inside a block is not fixed), blocks summed in binary64
-// in block order, then dL/dC = 2/(N P) (count * C - sum r).
+// Code gradients: per-block sums of residuals and counts per code in LDS as
+// 64-bit fixed point (2^-32 units; integer atomics are exact, so the sums do
+// not depend on the order the lanes arrive in, and they run far faster than
+// float atomics on LDS), blocks summed in binary64 in block order, then
+// dL/dC = 2/(N P) (count * C - sum r).
 #include "internal.h"
 
 namespace vcgs {
@@ -33,6 +35,15 @@ constexpr int kRvqMaxGrid = 4096;
 typedef __attribute__((address_space(4))) const float CFloat;
 
 __host__ __device__ constexpr int rvq_row(int dm) { return dm + 4; }  // |c|^2, -2c (dm), padding
+
+// fixed point of the code sums: 2^-32 units in two's complement (a block's sum
+// of one residual component must stay below 2^31 in magnitude)
+constexpr unsigned long long kRvqOne = 1ull << 32;
+constexpr double kRvqUnit = 1.0 / 4294967296.0;
+__device__ __forceinline__ unsigned long long rvq_fixed(float v)
+{
+    return (unsigned long long)__float2ll_rn(v * 4294967296.0f);  // scaling by 2^32 is exact
+}
 
 // per-code gradient row: D residual sums and the count, padded to an odd
 // stride so that different codes fall in different LDS banks
@@ -66,7 +77,6 @@ struct RvqArgs {
     float* recon;        // [n][D] or null
     float* partial;      // [grid][pstride] or null: code sums and counts [L][P][rvq_gstride(D)], then the loss
     int grad;            // accumulate code sums
-    int copies;          // 1, 2 or 4 LDS copies of the code sums (lane % copies), summed at the end
     int pstride;
 };
 
@@ -92,7 +102,7 @@ __global__ void __launch_bounds__(NT) k_rvq_assign(RvqArgs a)
     const int k1 = ((w + 1) * a.P) >> 2;
     const int rows = a.L * a.P;
     float* s_tab = dyn;
-    float* s_grad = dyn + (LTAB ? rows * S : 0);
+    unsigned long long* s_grad = reinterpret_cast<unsigned long long*>(dyn + (LTAB ? rows * S : 0));
     const int E = a.grad ? rows * rvq_gstride(a.D) : 0;
     if (LTAB) {
         for (int r = threadIdx.x; r < rows; r += NT) {
@@ -104,7 +114,7 @@ __global__ void __launch_bounds__(NT) k_rvq_assign(RvqArgs a)
             for (int j = 0; j < S - 1; ++j) t[1 + j] = j < a.D ? -2.0f * c[j] : 0.0f;
         }
     }
-    for (int i = threadIdx.x; i < E * a.copies; i += NT) s_grad[i] = 0.0f;
+    for (int i = threadIdx.x; i < E; i += NT) s_grad[i] = 0ull;
     __syncthreads();
     float lsum = 0.0f;
     int phase = 0;
@@ -202,7 +212,7 @@ __global__ void __launch_bounds__(NT) k_rvq_assign(RvqArgs a)
 #pragma unroll
                 for (int j = 0; j < DM; ++j) cv[j] = j < a.D ? cg[j] : 0.0f;
             }
-            float* g = s_grad + (lane & (a.copies - 1)) * E + (l * a.P + bk) * rvq_gstride(a.D);
+            unsigned long long* g = s_grad + (l * a.P + bk) * rvq_gstride(a.D);
             float q = 0.0f;
 #pragma unroll
             for (int j = 0; j < DM; ++j) {
@@ -215,11 +225,11 @@ __global__ void __launch_bounds__(NT) k_rvq_assign(RvqArgs a)
             if (valid && a.grad) {
 #pragma unroll
                 for (int j = 0; j < DM; ++j)
-                    if (j < a.D && (j & 3) == w) atomicAdd(g + j, r[j]);
+                    if (j < a.D && (j & 3) == w) atomicAdd(g + j, rvq_fixed(r[j]));
             }
             if (valid && a.partial && w == 0) {
                 lsum += q;
-                if (a.grad) atomicAdd(g + a.D, 1.0f);
+                if (a.grad) atomicAdd(g + a.D, kRvqOne);
             }
         }
         if (valid && a.recon) {
@@ -235,11 +245,7 @@ __global__ void __launch_bounds__(NT) k_rvq_assign(RvqArgs a)
         if (lane == 0) s_l[wv] = lsum;
         __syncthreads();
         float* p = a.partial + (int64_t)blockIdx.x * a.pstride;
-        for (int i = threadIdx.x; i < E; i += NT) {
-            float t = s_grad[i];
-            for (int c = 1; c < a.copies; ++c) t += s_grad[c * E + i];
-            p[i] = t;
-        }
+        for (int i = threadIdx.x; i < E; i += NT) p[i] = (float)((double)(long long)s_grad[i] * kRvqUnit);
         if (threadIdx.x == 0) {
             float t = 0.0f;
             for (int u = 0; u < SLOTS; ++u) t += s_l[4 * u];
@@ -367,6 +373,7 @@ bool launch_rvq(int64_t n, int D, int L, int P, const float* books, const float*
     const int rows = L * P;
     const int E = grad ? rows * rvq_gstride(D) : 0;
     const size_t tab_bytes = (size_t)rows * rvq_row(dm) * sizeof(float);
+    const size_t acc_bytes = (size_t)E * sizeof(unsigned long long);
     auto allow = [&](bool lt) {
         switch (dm) {
         case 4: return rvq_allow<4>(lt);
@@ -376,14 +383,9 @@ bool launch_rvq(int64_t n, int D, int L, int P, const float* books, const float*
         }
     };
     const size_t lds_limit = (size_t)(kRvqLdsLimit - kRvqStaticLds);
-    bool ltab = (size_t)E * sizeof(float) + tab_bytes <= lds_limit;
-    // lanes of a wave that picked the same code serialise on its LDS row: spread
-    // them over up to four copies when they fit beside the table
-    int copies = 1;
-    while (ltab && E > 0 && copies < 4 && (size_t)E * 2 * copies * sizeof(float) + tab_bytes <= lds_limit) copies *= 2;
-    if (ltab && (size_t)E * copies * sizeof(float) + tab_bytes > 64 * 1024) ltab = allow(true);
-    if (!ltab) copies = 1;
-    if (!ltab && (size_t)E * sizeof(float) > 64 * 1024 - kRvqStaticLds && !allow(false)) {
+    bool ltab = acc_bytes + tab_bytes <= lds_limit;
+    if (ltab && acc_bytes + tab_bytes > 64 * 1024 - kRvqStaticLds) ltab = allow(true);
+    if (!ltab && acc_bytes > 64 * 1024 - kRvqStaticLds && !allow(false)) {
         (void)hipGetLastError();
         return false;
     }
@@ -402,10 +404,9 @@ bool launch_rvq(int64_t n, int D, int L, int P, const float* books, const float*
     a.recon = recon;
     a.partial = want_partial ? partial : nullptr;
     a.grad = grad;
-    a.copies = copies;
     a.pstride = E + 1;
     const int grid = rvq_grid(n, D, want_partial);
-    const size_t lds = (size_t)E * copies * sizeof(float) + (ltab ? tab_bytes : 0);
+    const size_t lds = acc_bytes + (ltab ? tab_bytes : 0);
     switch (dm) {
     case 4: rvq_launch<4>(ltab, grid, lds, a, s); break;
     case 8: rvq_launch<8>(ltab, grid, lds, a, s); break;

@@ -96,3 +96,14 @@ def test_empty_and_rejections(V):
         V.rvq_assign(torch.ones(8, 256, 32, device="cuda"), torch.zeros(4, 32, device="cuda"), grad=True)
     with pytest.raises(V.VcgsError):
         V.rvq_assign(torch.ones(1, 8, 33, device="cuda"), torch.zeros(4, 33, device="cuda"))
+
+
+def test_code_gradient_is_bit_reproducible(V):
+    """The per-block code sums are exact integers, so repeated calls give the
+    same bits for every output, the code gradient included."""
+    books, x = scenes.rvq_problem("gauss", 200_000, 6, 64, seed=4)
+    outs = [V.rvq_assign(dev(books), dev(x), grad=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    for o in outs[1:]:
+        for k in ("idx", "recon", "loss", "dbooks"):
+            assert torch.equal(o[k], outs[0][k]), k
