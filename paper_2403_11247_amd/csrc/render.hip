@@ -125,7 +125,9 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     constexpr int SW = PPL == 1 ? 8 : 16;  // width of a wave's pixel block (8x8 quadrants at 1 pixel per lane)
     constexpr int LR = 64 / SW;            // rows of lanes
     constexpr int SH = LR * PPL;           // height of a wave's pixel block
-    __shared__ float4 slab[4][64][4];
+    // splat records staged component-major (conflict-free stores, broadcast reads); only z of the 4th row is used
+    __shared__ float4 slab[4][3][64];
+    __shared__ float slab_z[4][64];
     __shared__ uint32_t slab_gid[4][64];  // entries of the slab (kept only for hit counts)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gw = (sched ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + wave;
@@ -201,10 +203,10 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
             const uint32_t e = gids[idx];
             const Splat sp = rec[e];
             keep = !cull || reaches_rect(sp, rx0, rx1, ry0, ry1);
-            slab[wave][lane][0] = sp.a;
-            slab[wave][lane][1] = sp.b;
-            slab[wave][lane][2] = sp.c;
-            slab[wave][lane][3] = sp.d;
+            slab[wave][0][lane] = sp.a;
+            slab[wave][1][lane] = sp.b;
+            slab[wave][2][lane] = sp.c;
+            slab_z[wave][lane] = sp.d.x;
             if (hits) slab_gid[wave][lane] = e;
         }
         uint64_t todo = __ballot(keep);
@@ -217,10 +219,10 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
             const bool two = todo != 0ull;
             const int k2 = two ? __builtin_ctzll(todo) : k1;
             todo &= todo - 1ull;
-            const float4 a1 = slab[wave][k1][0], b1 = slab[wave][k1][1], r1 = slab[wave][k1][2];
-            const float z1 = slab[wave][k1][3].x;
-            const float4 a2 = slab[wave][k2][0], b2 = slab[wave][k2][1], r2 = slab[wave][k2][2];
-            const float z2 = slab[wave][k2][3].x;
+            const float4 a1 = slab[wave][0][k1], b1 = slab[wave][1][k1], r1 = slab[wave][2][k1];
+            const float z1 = slab_z[wave][k1];
+            const float4 a2 = slab[wave][0][k2], b2 = slab[wave][1][k2], r2 = slab[wave][2][k2];
+            const float z2 = slab_z[wave][k2];
             const float dx1 = (pxf - a1.x) - a1.z, dx2 = (pxf - a2.x) - a2.z;
             uint32_t h1 = 0u, h2 = 0u;
 #pragma unroll
@@ -337,7 +339,9 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
     constexpr int SW = PPL == 1 ? 8 : 16;
     constexpr int LR = 64 / SW;
     constexpr int SH = LR * PPL;
-    __shared__ float4 slab[4][64][4];
+    // splat records staged component-major (conflict-free stores, broadcast reads); only z of the 4th row is used
+    __shared__ float4 slab[4][3][64];
+    __shared__ float slab_z[4][64];
     __shared__ uint32_t slab_gid[4][64];
     // per-Gaussian row sums (4 rows x 10 values) waiting to be added to g2
     __shared__ float pend[4][kPend][4][10];
@@ -399,10 +403,10 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
             const uint32_t g = gids[start + li];
             const Splat sp = rec[g];
             keep = !cull || reaches_rect(sp, rx0, rx1, ry0, ry1);
-            slab[wave][lane][0] = sp.a;
-            slab[wave][lane][1] = sp.b;
-            slab[wave][lane][2] = sp.c;
-            slab[wave][lane][3] = sp.d;
+            slab[wave][0][lane] = sp.a;
+            slab[wave][1][lane] = sp.b;
+            slab[wave][2][lane] = sp.c;
+            slab_z[wave][lane] = sp.d.x;
             slab_gid[wave][lane] = g;
         }
         uint64_t hits = __ballot(keep);
@@ -411,8 +415,8 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
             const int k = 63 - __builtin_clzll(hits);
             hits &= ~(1ull << k);
             const uint32_t local = (uint32_t)(bs + k);
-            const float4 ra = slab[wave][k][0], rb = slab[wave][k][1], rc = slab[wave][k][2];
-            const float rz = slab[wave][k][3].x;
+            const float4 ra = slab[wave][0][k], rb = slab[wave][1][k], rc = slab[wave][2][k];
+            const float rz = slab_z[wave][k];
             const float i1 = -2.0f * kLn2 * rb.z, i2 = -2.0f * kLn2 * rb.w;  // eigenvalues of Q
             const float dx = (pxf - ra.x) - ra.z;
             float p[10];
