@@ -303,6 +303,54 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
         const int64_t a0 = grp * 16;
         const int64_t an = a0 + (lane & 15);
         const bool avalid = an < a.na;
+        {
+            // per-anchor sums over offsets (anchor position, scaling) and the offsets'
+            // gradients: the (anchor, offset) pairs spread over the 64 lanes, their
+            // contributions staged in the wave's y buffer (free until layer 2), then
+            // added per anchor in offset order by 16 lanes
+            float* stg = &ys[wave][0][0];  // 16 * LO >= 16 * k * 6 floats
+            for (int e = lane; e < 16 * a.k; e += 64) {
+                const int al = e / a.k, off = e - al * a.k;
+                const int64_t anc = a0 + al;
+                float dm[3] = {0.0f, 0.0f, 0.0f}, dl[3] = {0.0f, 0.0f, 0.0f};
+                if (anc < a.na) {
+                    const int64_t g = anc * a.k + off;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        dm[i] = dG.mean ? dG.mean[i * n + g] : 0.0f;
+                        dl[i] = dm[i] * a.offset[g * 3 + i];
+                    }
+                    if (out.offset) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) out.offset[g * 3 + i] = dm[i] * a.scaling[i * a.na + anc];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    stg[e * 6 + i] = dm[i];
+                    stg[e * 6 + 3 + i] = dl[i];
+                }
+            }
+            wsync();
+            if (lane < 16 && a0 + lane < a.na) {
+                const int64_t anc = a0 + lane;
+                float dx[3] = {0.0f, 0.0f, 0.0f}, dls[3] = {0.0f, 0.0f, 0.0f};
+                for (int off = 0; off < a.k; ++off) {
+                    const float* q = stg + (lane * a.k + off) * 6;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        dx[i] += q[i];
+                        dls[i] += q[3 + i];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if (out.scaling) out.scaling[i * a.na + anc] = dls[i];
+                    if (out.xa) out.xa[i * a.na + anc] = dx[i];
+                }
+            }
+            wsync();
+        }
         v4f d1[2];
         float vin;
         layer1(w1, a, an, avalid, lane, d1, vin);
@@ -386,28 +434,6 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
             } else {
 #pragma unroll
                 for (int i = 0; i < 7; ++i) dy[4 + i] = dv[i];
-            }
-        }
-        // per-anchor sums over offsets: scaling, anchor position; and offsets
-        if (lane < 16) {
-            const int64_t anc = a0 + lane;
-            if (anc < a.na) {
-                float dl[3] = {0, 0, 0}, dx[3] = {0, 0, 0};
-                for (int off = 0; off < a.k; ++off) {
-                    const int64_t g = anc * a.k + off;
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const float dm = dG.mean ? dG.mean[i * n + g] : 0.0f;
-                        dx[i] += dm;
-                        dl[i] += dm * a.offset[g * 3 + i];
-                        if (out.offset) out.offset[g * 3 + i] = dm * a.scaling[i * a.na + anc];
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    if (out.scaling) out.scaling[i * a.na + anc] = dl[i];
-                    if (out.xa) out.xa[i * a.na + anc] = dx[i];
-                }
             }
         }
         wsync();
