@@ -500,6 +500,19 @@ def main():
     prof = vcgs.profile_read()
     vcgs.profile_enable(False)
 
+    # per-step latency distribution, after the timed region: HIP events around single steps
+    lat_ev = []
+    for _ in range(max(args.steps, 50)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step()
+        e1.record()
+        lat_ev.append((e0, e1))
+    torch.cuda.synchronize()
+    lat = sorted(a_.elapsed_time(b_) for a_, b_ in lat_ev)
+    step_latency = {"p50": round(lat[len(lat) // 2], 4), "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
+                    "steps": len(lat)}
+
     ms = (t1 - t0) * 1e3 / args.steps
     mpix = cam.width * cam.height / (ms * 1e-3) / 1e6
     per_step = {k: v[0] / max(args.steps, 1) for k, v in prof.items() if v[1] > 0}
@@ -542,6 +555,7 @@ def main():
            "autotune": {"best": tuned, "candidates": len(tune_table),
                         "spread_ms": [round(min(t for _, t in tune_table) * 1e3, 3),
                                       round(max(t for _, t in tune_table) * 1e3, 3)] if tune_table else None},
+           "step_latency_ms": step_latency,
            "stages_ms": {k: round(v, 4) for k, v in per_step.items()},
            "stages_hbm_frac": hbm_stages,
            "counts": counts}
