@@ -107,3 +107,27 @@ def test_code_gradient_is_bit_reproducible(V):
     for o in outs[1:]:
         for k in ("idx", "recon", "loss", "dbooks"):
             assert torch.equal(o[k], outs[0][k]), k
+
+
+def test_codebooks_learn_from_the_code_gradient(V):
+    """Codebooks trained on eq. (15) with the GPU gradient (Adam, 60 steps)
+    lower the quantisation loss and the reconstruction error of the
+    per-Gaussian (log-scale, rotation) vectors; the assignment follows them."""
+    books, x = scenes.rvq_problem("gauss", 50_000, 4, 64, seed=8)
+    b = dev(books)
+    xx = dev(x)
+    opt = torch.optim.Adam([b.requires_grad_()], lr=2e-3)
+    first = None
+    for it in range(60):
+        out = V.rvq_assign(b.detach(), xx, grad=True)
+        loss = float(out["loss"][0])
+        first = loss if first is None else first
+        opt.zero_grad()
+        b.grad = out["dbooks"]
+        opt.step()
+    final = V.rvq_assign(b.detach(), xx)
+    err0 = float(((V.rvq_assign(dev(books), xx)["recon"] - xx) ** 2).mean())
+    err1 = float(((final["recon"] - xx) ** 2).mean())
+    say(f"rvq fit: loss {first:.4e} -> {float(final['loss'][0]):.4e}, recon mse {err0:.3e} -> {err1:.3e}")
+    assert float(final["loss"][0]) < 0.8 * first
+    assert err1 < 0.5 * err0
