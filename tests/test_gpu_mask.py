@@ -165,3 +165,39 @@ def test_window_hit_counts_survive_a_capacity_rerun(V):
         torch.cuda.synchronize()
         assert win.pairs > small + small // 8 + 4096, (small, win.pairs)
         assert torch.equal(h, _single_view_hits(V, gd, cams, near, g.n))
+
+
+def test_pruning_by_window_hits_keeps_the_window_images(V):
+    """Gaussians that no pixel of a window blends are pruned (min_hits = 1);
+    re-rendering the window with the kept ones changes nothing except at
+    pixels where a pruned Gaussian only stopped the compositing (T < 1e-4),
+    which moves a value by ~1e-4 at most."""
+    from oracle import decode as odec
+    a = scenes.room_anchors(8000, k=10, seed=5)
+    m = scenes.room_mlp(seed=5)
+    d = odec.decode(a, m)
+    g = scenes.Gaussians(*[d[f].astype(np.float32) for f in FIELDS])
+    gd = gauss_dev(g)
+    cams, poses = scenes.ba_window(4, sizes=[(160, 120), (200, 150)])
+    win = V.BatchWindow(g.n, cams, backward=False)
+    hits = torch.zeros(g.n, dtype=torch.int32, device="cuda")
+    win.run(*gd, poses, hits=hits)
+    before = [tuple(t.clone() for t in o) for o in win.outs]
+    mlog = torch.full((g.n,), 5.0, device="cuda")  # every mask on: the hit counts decide
+    keep, idx = V.mask_prune(mlog, hits, 0.01, 1)
+    torch.cuda.synchronize()
+    kept = idx.long()
+    assert 0.1 * g.n < kept.numel() < g.n
+    gk = [t.index_select(t.dim() - 1, kept).contiguous() for t in gd]
+    win2 = V.BatchWindow(kept.numel(), cams, backward=False)
+    win2.run(*gk, poses)
+    torch.cuda.synchronize()
+    same = total = 0
+    for (C0, D0, A0), (C1, D1, A1) in zip(before, win2.outs):
+        assert float((C0 - C1).abs().max()) <= 2e-4 and float((A0 - A1).abs().max()) <= 2e-4
+        assert float((D0 - D1).abs().max()) <= 1e-3 * float(D0.abs().max())
+        eq = (C0 == C1).all(0) & (D0 == D1) & (A0 == A1)
+        same += int(eq.sum())
+        total += eq.numel()
+    say(f"pruned {g.n - kept.numel()} of {g.n}; identical pixels {same}/{total}")
+    assert same >= 0.99 * total
