@@ -189,7 +189,14 @@ typedef struct {
     const vcgs_pose* poses;
 } vcgs_views;
 
-enum { VCGS_BATCH_GRAPH = 1 };
+/* VCGS_BATCH_GRAPH: capture the pass in a hipGraph and replay it.
+ * VCGS_BATCH_PER_VIEW: every view has its own Gaussian set (e.g. the
+ * view-dependent decode of paper eqs. (8)-(9), decoded once per keyframe):
+ * g->n is the count per view and each attribute array holds the views' sets
+ * one after another, component-major over all of them (mean [3][V*n], view v
+ * at columns [v*n, (v+1)*n)); grads have the same layout and receive each
+ * view's gradients separately instead of their sum. */
+enum { VCGS_BATCH_GRAPH = 1, VCGS_BATCH_PER_VIEW = 2 };
 
 /* Render n_views views of the same Gaussians in one pass (the keyframes of a
  * local bundle-adjustment window, paper Sec. 3.5, or the requests of one

@@ -507,6 +507,7 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
         for (int v = 0; v < V; ++v) plan->cams[v] = views->cams[v];
         Frame& f = plan->f;
         build_tables(V, g->n, views->cams, views->poses, bg, f);
+        f.pt.per_view = (flags & VCGS_BATCH_PER_VIEW) ? 1 : 0;
         f.vt.hits = hits;
         f.pt_dev = plan->get_e<ProjTab>(1);
         f.rec = plan->get_e<Splat>(f.E);

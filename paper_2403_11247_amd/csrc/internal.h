@@ -40,7 +40,8 @@ struct PoseK {
 // (view e / n, Gaussian e % n); global tile ids are view-major.
 struct ProjTab {
     int n_views;
-    int64_t n;  // Gaussians per view
+    int per_view;  // 0: one Gaussian set for all views; 1: view v reads its own set [v*n, (v+1)*n)
+    int64_t n;     // Gaussians per view
     CamK cam[kMaxViews];
     PoseK pose[kMaxViews];
 };

@@ -609,6 +609,7 @@ class CViews(ctypes.Structure):
 
 VCGS_E_CAPACITY = -3
 VCGS_BATCH_GRAPH = 1
+VCGS_BATCH_PER_VIEW = 2
 
 
 class BatchWindow:
@@ -620,7 +621,7 @@ class BatchWindow:
     returns the summed Gaussian gradients and per-view pose gradients."""
 
     def __init__(self, n, cameras, backward=True, graph=False, w_depth=0.5, bg=(0.0, 0.0, 0.0), ctx=None,
-                 device=None):
+                 device=None, per_view=False):
         self.ctx = ctx or default_context()
         self.dev = torch.device("cuda", self.ctx.device if device is None else device)
         self.cameras = list(cameras)
@@ -628,7 +629,9 @@ class BatchWindow:
         assert 1 <= self.V <= 16
         self.n = int(n)
         self.backward = backward
-        self.flags = VCGS_BATCH_GRAPH if graph else 0
+        self.flags = (VCGS_BATCH_GRAPH if graph else 0) | (VCGS_BATCH_PER_VIEW if per_view else 0)
+        self.per_view = per_view
+        cols = self.n * (self.V if per_view else 1)  # attribute columns: the views' own sets side by side
         self.w_depth = float(w_depth)
         self.bg = (c_f * 3)(*[float(b) for b in bg])
         self.outs = []
@@ -639,11 +642,11 @@ class BatchWindow:
         self.c_outs = (CImages * self.V)(*[CImages(_ptr(o[0]), _ptr(o[1]), _ptr(o[2])) for o in self.outs])
         self.c_cams = (CCamera * self.V)(*[camera_struct(c) for c in self.cameras])
         if backward:
-            self.grads = {"mean": torch.empty((3, self.n), device=self.dev),
-                          "scale": torch.empty((3, self.n), device=self.dev),
-                          "quat": torch.empty((4, self.n), device=self.dev),
-                          "opacity": torch.empty(self.n, device=self.dev),
-                          "color": torch.empty((3, self.n), device=self.dev)}
+            self.grads = {"mean": torch.empty((3, cols), device=self.dev),
+                          "scale": torch.empty((3, cols), device=self.dev),
+                          "quat": torch.empty((4, cols), device=self.dev),
+                          "opacity": torch.empty(cols, device=self.dev),
+                          "color": torch.empty((3, cols), device=self.dev)}
             self.dpose = torch.empty((self.V, 6), device=self.dev)
             self.loss = torch.empty(self.V, device=self.dev)
             self.c_grads = CGaussianBuffers(*[_ptr(self.grads[k]) for k in ("mean", "scale", "quat", "opacity",
@@ -655,6 +658,9 @@ class BatchWindow:
         hits: optional int32 (n,) device tensor to which every Gaussian's number
         of blended pixels over the window's views is added (mask step)."""
         g, keep = _gauss(means, scales, quats, opacities, colors)
+        if self.per_view:
+            assert g.n == self.n * self.V, "per-view sets: attributes hold n Gaussians per view, views side by side"
+            g.n = self.n
         assert g.n == self.n and len(poses) == self.V
         views = CViews(self.V, ctypes.cast(self.c_cams, c_p),
                        ctypes.cast((CPose * self.V)(*[pose_struct(p) for p in poses]), c_p))
