@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving replay")
     ap.add_argument("--serve-requests", type=int, default=400, help="requests per arrival rate")
     ap.add_argument("--serve-qps", type=str, default="50,100,200,400")
-    ap.add_argument("--only", choices=("main", "ba", "serve", "view", "mask", "rvq", "track"), default=None,
+    ap.add_argument("--only", choices=("main", "ba", "ba_view", "serve", "view", "mask", "rvq", "track"), default=None,
                     help="run one section only (for profiling)")
     return ap.parse_args()
 
@@ -235,6 +235,71 @@ def ba_section(args, dev):
             "autotune": {"best": best, "candidates": len(table),
                          "best_ms": round(min(t for _, t in table) * 1e3, 3) if table else None,
                          "worst_ms": round(worst * 1e3, 3) if worst else None}}
+
+
+def ba_view_section(args, dev):
+    """The BA window with the view-dependent decode (eqs. (8)-(9)): each of 12
+    keyframes decodes its own 500k-Gaussian set from the same anchors and MLP
+    (written straight into its block of the stacked per-view set), one batched
+    forward + L1 + backward pass over the stacked sets (per-view mode, replayed
+    hipGraph), then the decode backward per keyframe; against the plain loop of
+    decode, render, loss, backward and decode backward per keyframe."""
+    import torch
+    from paper_2403_11247_amd import scenes, vcgs
+    a = scenes.room_anchors(50000, k=10, spacing=0.05, seed=1)
+    m = scenes.room_mlp_view(seed=1)
+    A = [_up(x, dev) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    n = a.xa.shape[1] * 10
+    cams, poses = scenes.ba_window(12)
+    V = len(cams)
+    centres = [vcgs.camera_centre(p) for p in poses]
+    targets = []
+    for c, p in zip(cams, poses):
+        tp = scenes.perturb_pose(p, 200 + len(targets))
+        G = vcgs.decode_anchors(*A, cam_centre=vcgs.camera_centre(tp))
+        C, D, _, _ = vcgs.render_forward(*[G[f] for f in F], c, tp, keep_state=False)
+        targets.append((C, D))
+    shapes = {"mean": (3, n), "scale": (3, n), "quat": (4, n), "opacity": (n,), "color": (3, n)}
+    stacked = {f: torch.empty((V,) + sh, device=dev) for f, sh in shapes.items()}
+    win = vcgs.BatchWindow(n, cams, backward=True, graph=True, per_view=True)
+    dpose = torch.empty((V, 6), device=dev)
+
+    def batched():
+        for v in range(V):
+            vcgs.decode_anchors(*A, cam_centre=centres[v], out={f: stacked[f][v] for f in F})
+        win.run(*[stacked[f] for f in F], poses, targets)
+        for v in range(V):
+            ag = vcgs.decode_anchors_backward(*A, {f: win.grads[f][v] for f in F}, cam_centre=centres[v])
+            dpose[v].copy_(win.dpose[v] + vcgs.pose_grad_from_centre(poses[v], ag["cam"]))
+        return dpose
+
+    ref = torch.empty((V, 6), device=dev)
+
+    def plain():
+        for v, (c, p, tg) in enumerate(zip(cams, poses, targets)):
+            G = vcgs.decode_anchors(*A, cam_centre=centres[v])
+            gs = [G[f] for f in F]
+            C, D, _, st = vcgs.render_forward(*gs, c, p)
+            _, dlc, dld = vcgs.l1_loss(C, D, tg[0], tg[1], 0.5)
+            gr, dp = vcgs.render_backward(st, *gs, c, p, dlc, dld, None)
+            ag = vcgs.decode_anchors_backward(*A, gr, cam_centre=centres[v])
+            ref[v].copy_(dp + vcgs.pose_grad_from_centre(p, ag["cam"]))
+            st.free()
+        return ref
+
+    ms_plain = _timed(plain, args.ba_steps, 2)
+    ms_batch = _timed(batched, args.ba_steps, 2)
+    plain()
+    batched()
+    torch.cuda.synchronize()
+    p_err = float((dpose - ref).abs().max() / ref.abs().max().clamp_min(1e-30))
+    pix = sum(int(c.width) * int(c.height) for c in cams)
+    return {"workload": "room 50k anchors x 10 with the view-dependent decode, 12 keyframes 4x320x240 + "
+                        "4x640x480 + 4x1200x680: decode per keyframe, fwd + L1 + bwd, decode bwd per keyframe, "
+                        "pose gradient through render and decode",
+            "gaussians_per_view": n, "pixels": pix,
+            "plain_ms": round(ms_plain, 3), "batch_graph_ms": round(ms_batch, 3),
+            "speedup_vs_plain": round(ms_plain / ms_batch, 2), "pose_grad_rel_err_vs_plain": p_err}
 
 
 def view_decode_section(args, dev, steps=20, warmup=5):
@@ -440,9 +505,10 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    if args.only in ("ba", "serve", "view", "mask", "rvq", "track"):
+    if args.only in ("ba", "ba_view", "serve", "view", "mask", "rvq", "track"):
         res = {"ba": ba_section, "serve": serve_section, "view": view_decode_section,
-               "mask": mask_step_section, "rvq": rvq_section, "track": track_section}[args.only](args, dev)
+               "mask": mask_step_section, "rvq": rvq_section, "track": track_section,
+               "ba_view": ba_view_section}[args.only](args, dev)
         print(json.dumps({args.only: res}), flush=True)
         return
     if args.only == "main":
@@ -574,6 +640,8 @@ def main():
         out["tracking"] = track_section(args, dev)
     if not args.no_ba:
         out["ba_window"] = ba_section(args, dev)
+        if args.only != "main":
+            out["ba_window_view_decode"] = ba_view_section(args, dev)
     if not args.no_serve:
         out["serving"] = serve_section(args, dev)
     if not args.no_cpu_baseline:

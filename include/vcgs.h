@@ -193,9 +193,9 @@ typedef struct {
  * VCGS_BATCH_PER_VIEW: every view has its own Gaussian set (e.g. the
  * view-dependent decode of paper eqs. (8)-(9), decoded once per keyframe):
  * g->n is the count per view and each attribute array holds the views' sets
- * one after another, component-major over all of them (mean [3][V*n], view v
- * at columns [v*n, (v+1)*n)); grads have the same layout and receive each
- * view's gradients separately instead of their sum. */
+ * one after another, each an ordinary SoA set (mean [V][3][n], quat
+ * [V][4][n], opacity [V][n], ...); grads have the same layout and receive
+ * each view's gradients separately instead of their sum. */
 enum { VCGS_BATCH_GRAPH = 1, VCGS_BATCH_PER_VIEW = 2 };
 
 /* Render n_views views of the same Gaussians in one pass (the keyframes of a

@@ -150,13 +150,14 @@ __global__ void __launch_bounds__(256) k_preprocess(const ProjTab* __restrict__ 
     const int v = (int)(e / n);
     const int64_t g = e - (int64_t)v * n;
     const CamK& cam = tab.cam[v];
-    // attribute index and component stride: the shared set, or view v's own set
-    const int64_t ga = tab.per_view ? e : g;
-    const int64_t st = tab.per_view ? n * tab.n_views : n;
-    const float o = opac[ga];
-    const KeyOut k = key_path(mean[ga], mean[st + ga], mean[2 * st + ga], scale[ga], scale[st + ga],
-                              scale[2 * st + ga], quat[ga], quat[st + ga], quat[2 * st + ga], quat[3 * st + ga], o,
-                              cam, tab.pose[v]);
+    // the shared set, or view v's own set (views' SoA sets stored one after another)
+    const int64_t vb = tab.per_view ? (int64_t)v * n : 0;  // view offset per attribute component
+    const float* vm = mean + 3 * vb;
+    const float* vs = scale + 3 * vb;
+    const float* vq = quat + 4 * vb;
+    const float o = opac[vb + g];
+    const KeyOut k = key_path(vm[g], vm[n + g], vm[2 * n + g], vs[g], vs[n + g], vs[2 * n + g], vq[g], vq[n + g],
+                              vq[2 * n + g], vq[3 * n + g], o, cam, tab.pose[v]);
     if (!k.vis) {
         depth_key[e] = 0xFFFFFFFFu;
         count[e] = 0u;
@@ -175,7 +176,8 @@ __global__ void __launch_bounds__(256) k_preprocess(const ProjTab* __restrict__ 
     Splat sp;
     sp.a = make_float4(k.u, k.v, (float)(k.ud - (double)k.u), (float)(k.vd - (double)k.v));
     sp.b = make_float4(ex, ey, kNegHalfLog2e / k.lam, kNegHalfLog2e / lmin);
-    sp.c = make_float4(o, color[ga], color[st + ga], color[2 * st + ga]);
+    const float* vc = color + 3 * vb;
+    sp.c = make_float4(o, vc[g], vc[n + g], vc[2 * n + g]);
     sp.d = make_float4(k.Z, 0.0f, 0.0f, 0.0f);
     rec[e] = sp;
     depth_key[e] = __float_as_uint(k.Z);
@@ -217,8 +219,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
     const CamK& cam = tab.cam[vw];
     const PoseK& P = tab.pose[vw];
     const int64_t e = (int64_t)vw * n + g;
-    const int64_t ga = tab.per_view ? e : g;
-    const int64_t st = tab.per_view ? n * tab.n_views : n;
+    const int64_t vb = tab.per_view ? (int64_t)vw * n : 0;  // view offset per attribute component
     float pose6[6] = {0, 0, 0, 0, 0, 0};
     if (g < n) {
         const bool vis = count[e] != 0u;
@@ -236,17 +237,18 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
         dop += gg[5];
         dcol[0] += gg[6]; dcol[1] += gg[7]; dcol[2] += gg[8];
         if (vis) {
-            const float x = mean[ga], y = mean[st + ga], z = mean[2 * st + ga];
+            const float x = mean[3 * vb + g], y = mean[3 * vb + n + g], z = mean[3 * vb + 2 * n + g];
             const float X = P.R[0] * x + P.R[1] * y + P.R[2] * z + P.t[0];
             const float Y = P.R[3] * x + P.R[4] * y + P.R[5] * z + P.t[1];
             const float Z = P.R[6] * x + P.R[7] * y + P.R[8] * z + P.t[2];
-            float qw = quat[ga], qx = quat[st + ga], qy = quat[2 * st + ga], qz = quat[3 * st + ga];
+            float qw = quat[4 * vb + g], qx = quat[4 * vb + n + g], qy = quat[4 * vb + 2 * n + g],
+                  qz = quat[4 * vb + 3 * n + g];
             const float n2 = qw * qw + qx * qx + qy * qy + qz * qz;
             const bool qok = n2 > 0.0f;
             const float qn = qok ? sqrtf(n2) : 1.0f;
             if (qok) { const float iq = 1.0f / qn; qw *= iq; qx *= iq; qy *= iq; qz *= iq; }
             else { qw = 1.0f; qx = qy = qz = 0.0f; }
-            const float s[3] = {scale[ga], scale[st + ga], scale[2 * st + ga]};
+            const float s[3] = {scale[3 * vb + g], scale[3 * vb + n + g], scale[3 * vb + 2 * n + g]};
             float r[9];
             r[0] = 1.f - 2.f * (qy * qy + qz * qz); r[1] = 2.f * (qx * qy - qw * qz); r[2] = 2.f * (qx * qz + qw * qy);
             r[3] = 2.f * (qx * qy + qw * qz); r[4] = 1.f - 2.f * (qx * qx + qz * qz); r[5] = 2.f * (qy * qz - qw * qx);
@@ -403,12 +405,22 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
     // a view's own set takes its gradients here; a shared set after all views
     if (tab.per_view || vw == tab.n_views - 1) {
         if (g < n) {
-            if (d_opac) d_opac[ga] = dop;
-            if (d_color) { d_color[ga] = dcol[0]; d_color[st + ga] = dcol[1]; d_color[2 * st + ga] = dcol[2]; }
-            if (d_mean) { d_mean[ga] = dmu[0]; d_mean[st + ga] = dmu[1]; d_mean[2 * st + ga] = dmu[2]; }
-            if (d_scale) { d_scale[ga] = dsc[0]; d_scale[st + ga] = dsc[1]; d_scale[2 * st + ga] = dsc[2]; }
+            if (d_opac) d_opac[vb + g] = dop;
+            if (d_color) {
+                float* p = d_color + 3 * vb;
+                p[g] = dcol[0]; p[n + g] = dcol[1]; p[2 * n + g] = dcol[2];
+            }
+            if (d_mean) {
+                float* p = d_mean + 3 * vb;
+                p[g] = dmu[0]; p[n + g] = dmu[1]; p[2 * n + g] = dmu[2];
+            }
+            if (d_scale) {
+                float* p = d_scale + 3 * vb;
+                p[g] = dsc[0]; p[n + g] = dsc[1]; p[2 * n + g] = dsc[2];
+            }
             if (d_quat) {
-                d_quat[ga] = dqt[0]; d_quat[st + ga] = dqt[1]; d_quat[2 * st + ga] = dqt[2]; d_quat[3 * st + ga] = dqt[3];
+                float* p = d_quat + 4 * vb;
+                p[g] = dqt[0]; p[n + g] = dqt[1]; p[2 * n + g] = dqt[2]; p[3 * n + g] = dqt[3];
             }
         }
         dop = 0.0f;

@@ -394,17 +394,22 @@ def pose_grad_from_centre(pose, dcam):
 
 
 def decode_anchors(xa, feat, scaling, offset, W1, b1, W2, b2, books=None, idx=None, mask_logit=None, mask_eps=0.01,
-                   cam_centre=None, ctx: Context | None = None):
+                   cam_centre=None, ctx: Context | None = None, out=None):
     """Decode anchors into na*k Gaussians (dict mean/scale/quat/opacity/color, SoA).
-    With cam_centre (3 values) the decode is view-dependent and W1 is (32, 36)."""
+    With cam_centre (3 values) the decode is view-dependent and W1 is (32, 36).
+    out: optional dict of contiguous float32 device tensors of those shapes to
+    write into (e.g. one view's block of a stacked per-view set)."""
     ctx = ctx or default_context()
     a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx,
                                             32 if cam_centre is None else 36)
     n = na * k
     dv = feat.device
-    out = {"mean": torch.empty((3, n), device=dv), "scale": torch.empty((3, n), device=dv),
-           "quat": torch.empty((4, n), device=dv), "opacity": torch.empty(n, device=dv),
-           "color": torch.empty((3, n), device=dv)}
+    shapes = {"mean": (3, n), "scale": (3, n), "quat": (4, n), "opacity": (n,), "color": (3, n)}
+    if out is None:
+        out = {f: torch.empty(sh, device=dv) for f, sh in shapes.items()}
+    elif not all(tuple(out[f].shape) == sh and out[f].is_contiguous() and out[f].is_cuda
+                 and out[f].dtype == torch.float32 for f, sh in shapes.items()):
+        raise VcgsError("decode_anchors: out tensors must be contiguous float32 device tensors of the decoded shapes")
     ob = CGaussianBuffers(*[_ptr(out[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
     ml = None if mask_logit is None else _dev(mask_logit)
     if cam_centre is None:
@@ -631,7 +636,7 @@ class BatchWindow:
         self.backward = backward
         self.flags = (VCGS_BATCH_GRAPH if graph else 0) | (VCGS_BATCH_PER_VIEW if per_view else 0)
         self.per_view = per_view
-        cols = self.n * (self.V if per_view else 1)  # attribute columns: the views' own sets side by side
+        lead = (self.V,) if per_view else ()  # the views' own sets stacked: (V, 3, n), ...
         self.w_depth = float(w_depth)
         self.bg = (c_f * 3)(*[float(b) for b in bg])
         self.outs = []
@@ -642,11 +647,11 @@ class BatchWindow:
         self.c_outs = (CImages * self.V)(*[CImages(_ptr(o[0]), _ptr(o[1]), _ptr(o[2])) for o in self.outs])
         self.c_cams = (CCamera * self.V)(*[camera_struct(c) for c in self.cameras])
         if backward:
-            self.grads = {"mean": torch.empty((3, cols), device=self.dev),
-                          "scale": torch.empty((3, cols), device=self.dev),
-                          "quat": torch.empty((4, cols), device=self.dev),
-                          "opacity": torch.empty(cols, device=self.dev),
-                          "color": torch.empty((3, cols), device=self.dev)}
+            self.grads = {"mean": torch.empty(lead + (3, self.n), device=self.dev),
+                          "scale": torch.empty(lead + (3, self.n), device=self.dev),
+                          "quat": torch.empty(lead + (4, self.n), device=self.dev),
+                          "opacity": torch.empty(lead + (self.n,), device=self.dev),
+                          "color": torch.empty(lead + (3, self.n), device=self.dev)}
             self.dpose = torch.empty((self.V, 6), device=self.dev)
             self.loss = torch.empty(self.V, device=self.dev)
             self.c_grads = CGaussianBuffers(*[_ptr(self.grads[k]) for k in ("mean", "scale", "quat", "opacity",
@@ -657,10 +662,14 @@ class BatchWindow:
         """targets: list of (colour (3,H,W), depth (H,W)) per view when backward.
         hits: optional int32 (n,) device tensor to which every Gaussian's number
         of blended pixels over the window's views is added (mask step)."""
-        g, keep = _gauss(means, scales, quats, opacities, colors)
         if self.per_view:
-            assert g.n == self.n * self.V, "per-view sets: attributes hold n Gaussians per view, views side by side"
-            g.n = self.n
+            ts = [_dev(x) for x in (means, scales, quats, opacities, colors)]
+            shapes = [(self.V, 3, self.n), (self.V, 3, self.n), (self.V, 4, self.n), (self.V, self.n),
+                      (self.V, 3, self.n)]
+            assert all(tuple(t.shape) == sh for t, sh in zip(ts, shapes)), "per-view sets are stacked (V, ., n)"
+            g, keep = CGaussians(self.n, *[_ptr(t) for t in ts]), ts
+        else:
+            g, keep = _gauss(means, scales, quats, opacities, colors)
         assert g.n == self.n and len(poses) == self.V
         views = CViews(self.V, ctypes.cast(self.c_cams, c_p),
                        ctypes.cast((CPose * self.V)(*[pose_struct(p) for p in poses]), c_p))

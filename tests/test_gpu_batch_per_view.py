@@ -27,9 +27,9 @@ def _targets(cams, seed):
             for c in cams]
 
 
-def _cat(sets):
-    """Per-view attribute sets side by side (columns), as VCGS_BATCH_PER_VIEW reads them."""
-    return [torch.cat([s[i] for s in sets], dim=-1).contiguous() for i in range(5)]
+def _stack(sets):
+    """Per-view attribute sets stacked (V, ., n), as VCGS_BATCH_PER_VIEW reads them."""
+    return [torch.stack([s[i] for s in sets]).contiguous() for i in range(5)]
 
 
 def _plain(V, gd, cam, pose, tg):
@@ -57,14 +57,14 @@ def test_own_sets_match_plain_renders(V, graph):
     tg = _targets(cams, 9)
     win = V.BatchWindow(g.n, cams, backward=True, graph=graph, per_view=True)
     for _ in range(2):
-        win.run(*_cat(sets), poses, tg)
+        win.run(*_stack(sets), poses, tg)
     torch.cuda.synchronize()
     for v in range(3):
         imgs, grads, dpose = _plain(V, sets[v], cams[v], poses[v], tg[v])
         for a, b in zip(win.outs[v], imgs):
             assert torch.equal(a, b), v
         for k in FIELDS:
-            got = win.grads[k][..., v * g.n:(v + 1) * g.n]
+            got = win.grads[k][v]
             assert rel_err(got.cpu().numpy(), grads[k].cpu().numpy()) <= 1e-5, (v, k)
         assert rel_err(win.dpose[v].cpu().numpy(), dpose.cpu().numpy()) <= 1e-5, v
     say("per-view sets: images bit-exact, gradients per view")
@@ -80,14 +80,20 @@ def test_view_dependent_decode_in_a_ba_window(V):
     decoded = [V.decode_anchors(*A, cam_centre=c) for c in centres]
     sets = [tuple(d[f] for f in FIELDS) for d in decoded]
     n = int(sets[0][3].shape[0])
+    # decode straight into each keyframe's block of the stacked set: the same bits
+    stacked = [torch.empty((4,) + tuple(t.shape), device=t.device) for t in sets[0]]
+    for v, c in enumerate(centres):
+        V.decode_anchors(*A, cam_centre=c, out={f: stacked[i][v] for i, f in enumerate(FIELDS)})
+    for x, y in zip(stacked, _stack(sets)):
+        assert torch.equal(x, y)
     win = V.BatchWindow(n, cams, backward=True, graph=True, per_view=True)
-    win.run(*_cat(sets), poses, tg)
+    win.run(*stacked, poses, tg)
     torch.cuda.synchronize()
     for v in range(4):
         imgs, grads, dpose = _plain(V, sets[v], cams[v], poses[v], tg[v])
         for x, y in zip(win.outs[v], imgs):
             assert torch.equal(x, y), v
-        wg = {k: win.grads[k][..., v * n:(v + 1) * n].contiguous() for k in FIELDS}
+        wg = {k: win.grads[k][v] for k in FIELDS}
         ag_win = V.decode_anchors_backward(*A, wg, cam_centre=centres[v])
         ag_ref = V.decode_anchors_backward(*A, grads, cam_centre=centres[v])
         torch.cuda.synchronize()
