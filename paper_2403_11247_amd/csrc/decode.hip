@@ -204,11 +204,15 @@ __global__ void __launch_bounds__(256) k_decode_fwd(DecodeArgs a, float* __restr
 
 static int out_tiles(int k) { return (k * 11 + 15) / 16; }
 
+// Forward grid cap: each wave loads the MLP weights once into registers, so
+// a wave that strides over several 16-anchor groups amortises that load.
+constexpr int kFwdMaxBlocks = 256;
+
 void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hipStream_t s)
 {
     if (a.na <= 0) return;
     const int64_t groups = (a.na + 15) / 16;
-    const int blocks = (int)std::min<int64_t>((groups + 3) / 4, 4096);
+    const int blocks = (int)std::min<int64_t>((groups + 3) / 4, kFwdMaxBlocks);
 #define VCGS_DEC_FWD(OT)                                                                                        \
     case OT:                                                                                                    \
         k_decode_fwd<OT><<<blocks, 256, 0, s>>>(a, out.mean, out.scale, out.quat, out.opacity, out.color);      \
@@ -227,16 +231,22 @@ void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hi
 constexpr int kBwdWaves = 4;
 constexpr int kBwdMaxBlocks = 256;
 
-// partial layout per block: dW2 [O][32] | db2 [O] | dW1 [32][32] | db1 [32]
 // Partial row of one block: dW2 [O][32], db2 [O], dW1 [32][in_dim], db1 [32], dL/dcam [3].
 __host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim)
 {
     return (int64_t)k * 11 * kF + k * 11 + (int64_t)kF * in_dim + kF + 3;
 }
 
-// The per-wave y buffers of a block double as the block's reduction buffer:
-// floats for both uses with OT output tiles.
-constexpr int bwd_red_floats(int OT) { return 16 * OT * (kF + 1) + kF * (kF + 4) + kF + 3; }
+// Block reduction buffer, padded so that every lane owns a slot for each of
+// its accumulators (no bounds tests, hence no per-slot branches): dW2 [OT*16][32],
+// db2 [192], dW1 [32][48], db1 [64], dL/dcam [64].  The per-wave y buffers of
+// a block double as it.
+constexpr int kRedB2 = 192, kRedW1Cols = 48;
+constexpr int red_b2(int OT) { return OT * 16 * kF; }
+constexpr int red_w1(int OT) { return red_b2(OT) + kRedB2; }
+constexpr int red_b1(int OT) { return red_w1(OT) + kF * kRedW1Cols; }
+constexpr int red_cam(int OT) { return red_b1(OT) + 64; }
+constexpr int bwd_red_floats(int OT) { return red_cam(OT) + 64; }
 constexpr int bwd_smem_floats(int OT)
 {
     return kBwdWaves * 16 * lds_o(OT) > bwd_red_floats(OT) ? kBwdWaves * 16 * lds_o(OT) : bwd_red_floats(OT);
@@ -535,61 +545,73 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
     }
     // block reduction in wave order, then one partial row per block
     __syncthreads();
-    float* red = smem;  // bwd_smem_floats(OT) >= decode_bwd_partial_floats(k, in_dim) floats
-    const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim);
-    const int oW1 = O * kF + O, oB1 = oW1 + kF * a.in_dim, oCam = oB1 + kF;
+    float* red = smem;  // bwd_smem_floats(OT) >= bwd_red_floats(OT)
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) accCam[i] += __shfl_xor(accCam[i], o, 64);
+    float cam = lane == 0 ? accCam[0] : (lane == 1 ? accCam[1] : (lane == 2 ? accCam[2] : 0.0f));
+    // Wave w adds the sum of waves 0..w-1 into its accumulators, then stores
+    // them: all its loads are issued before any store.
     for (int w = 0; w < kBwdWaves; ++w) {
         if (wave == w) {
+            if (w > 0) {
+#pragma unroll
+                for (int t = 0; t < OT; ++t)
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            accW2[t][nt][i] += red[(t * 16 + 4 * (lane >> 4) + i) * kF + nt * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < (kMaxO + 63) / 64; ++j) accB2[j] += red[red_b2(OT) + lane + 64 * j];
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int ft = 0; ft < 3; ++ft)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            accW1[nt][ft][i] +=
+                                red[red_w1(OT) + (nt * 16 + 4 * (lane >> 4) + i) * kRedW1Cols + ft * 16 + (lane & 15)];
+                accB1 += red[red_b1(OT) + lane];
+                cam += red[red_cam(OT) + lane];
+            }
 #pragma unroll
             for (int t = 0; t < OT; ++t)
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int m = t * 16 + 4 * (lane >> 4) + i;
-                        const int nn = nt * 16 + (lane & 15);
-                        if (m < O) {
-                            float* p = red + m * kF + nn;
-                            *p = (w == 0 ? 0.0f : *p) + accW2[t][nt][i];
-                        }
-                    }
+                    for (int i = 0; i < 4; ++i)
+                        red[(t * 16 + 4 * (lane >> 4) + i) * kF + nt * 16 + (lane & 15)] = accW2[t][nt][i];
 #pragma unroll
-            for (int j = 0; j < (kMaxO + 63) / 64; ++j) {
-                const int m = lane + 64 * j;
-                if (m < O) {
-                    float* p = red + O * kF + m;
-                    *p = (w == 0 ? 0.0f : *p) + accB2[j];
-                }
-            }
+            for (int j = 0; j < (kMaxO + 63) / 64; ++j) red[red_b2(OT) + lane + 64 * j] = accB2[j];
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
                 for (int ft = 0; ft < 3; ++ft)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int nn = nt * 16 + 4 * (lane >> 4) + i;
-                        const int f = ft * 16 + (lane & 15);
-                        if (f < a.in_dim) {
-                            float* p = red + oW1 + nn * a.in_dim + f;
-                            *p = (w == 0 ? 0.0f : *p) + accW1[nt][ft][i];
-                        }
-                    }
-            if (lane < kF) {
-                float* p = red + oB1 + lane;
-                *p = (w == 0 ? 0.0f : *p) + accB1;
-            }
-            if (lane < 3) {
-                float* p = red + oCam + lane;
-                *p = (w == 0 ? 0.0f : *p) + accCam[lane];
-            }
+                    for (int i = 0; i < 4; ++i)
+                        red[red_w1(OT) + (nt * 16 + 4 * (lane >> 4) + i) * kRedW1Cols + ft * 16 + (lane & 15)] =
+                            accW1[nt][ft][i];
+            red[red_b1(OT) + lane] = accB1;
+            red[red_cam(OT) + lane] = cam;
         }
         __syncthreads();
     }
-    for (int64_t i = threadIdx.x; i < PF; i += blockDim.x) partial[blockIdx.x * PF + i] = red[i];
+    // compact partial row: dW2 [O][32] | db2 [O] | dW1 [32][in_dim] | db1 [32] | dcam [3]
+    const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim);
+    const int oB2 = O * kF, oW1 = oB2 + O, oB1 = oW1 + kF * a.in_dim, oCam = oB1 + kF;
+    for (int i = threadIdx.x; i < PF; i += blockDim.x) {
+        int src;
+        if (i < oB2) src = i;
+        else if (i < oW1) src = red_b2(OT) + (i - oB2);
+        else if (i < oB1) {
+            const int j = i - oW1, nn = j / a.in_dim;
+            src = red_w1(OT) + nn * kRedW1Cols + (j - nn * a.in_dim);
+        } else if (i < oCam) src = red_b1(OT) + (i - oB1);
+        else src = red_cam(OT) + (i - oCam);
+        partial[blockIdx.x * PF + i] = red[src];
+    }
 }
 
 // Sum of the per-block partial rows: each block owns 64 consecutive outputs;
