@@ -148,7 +148,7 @@ static int decode_bwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
     if (!cam) o.cam = nullptr;
     if (d.na == 0) return VCGS_OK;
     Scratch sc(&ctx->pool);
-    const int nb = decode_bwd_blocks(d.na);
+    const int nb = decode_bwd_blocks(d.na, d.k);
     float* partial = sc.get<float>((int64_t)nb * decode_bwd_partial_floats(d.k, d.in_dim));
     if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (decode backward)");
     ctx->prof.begin(VCGS_STAGE_DECODE_BWD, s);

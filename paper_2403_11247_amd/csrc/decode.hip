@@ -18,7 +18,9 @@
 // transposed products (dh = W2^T dy, df = W1^T dpre, and the weight gradients
 // dW2 = dy h^T, dW1 = dpre f^T summed over anchors) on MFMA as well.  Weight
 // gradients are summed per wave in registers, per block in a fixed wave order,
-// and across blocks in block order (deterministic).
+// and across blocks in a fixed order (deterministic).  The backward reads the
+// weights from a block-shared LDS copy instead of registers, which leaves room
+// for two waves per SIMD.
 #include "internal.h"
 
 namespace vcgs {
@@ -111,6 +113,33 @@ __device__ __forceinline__ void layer1(const float (&w1)[2][9], const DecodeArgs
         vin = valid ? view_input(a, an, lane >> 4) : 0.0f;
         d1[0] = mfma4(w1[0][8], vin, d1[0]);
         d1[1] = mfma4(w1[1][8], vin, d1[1]);
+    }
+}
+
+// Block-shared copies of the MLP weights for the backward, read at their point
+// of use rather than held in registers: W2 rows padded to kW2S floats (rows at
+// or beyond O zero), W1 rows padded to kW1S floats (columns at or beyond in_dim zero).
+constexpr int kW2S = 36;
+constexpr int kW1S = 52;
+
+__device__ __forceinline__ void layer1_lds(const float* w1s, const DecodeArgs& a, int64_t an, bool valid, int lane,
+                                           v4f (&d1)[2], float& vin)
+{
+    d1[0] = v4f{0.f, 0.f, 0.f, 0.f};
+    d1[1] = v4f{0.f, 0.f, 0.f, 0.f};
+    const float* r0 = w1s + (lane & 15) * kW1S + (lane >> 4);
+    const float* r1 = r0 + 16 * kW1S;
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        const float b = valid ? a.feat[an * kF + ks * 4 + (lane >> 4)] : 0.0f;
+        d1[0] = mfma4(r0[ks * 4], b, d1[0]);
+        d1[1] = mfma4(r1[ks * 4], b, d1[1]);
+    }
+    vin = 0.0f;
+    if (a.in_dim > kF) {  // uniform
+        vin = valid ? view_input(a, an, lane >> 4) : 0.0f;
+        d1[0] = mfma4(r0[32], vin, d1[0]);
+        d1[1] = mfma4(r1[32], vin, d1[1]);
     }
 }
 
@@ -229,7 +258,9 @@ void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hi
 // Backward
 // ---------------------------------------------------------------------------
 constexpr int kBwdWaves = 4;
-constexpr int kBwdMaxBlocks = 256;
+// Grid cap: two blocks per CU where registers and LDS allow two waves per SIMD
+// (up to 8 output tiles), else one.
+constexpr int kBwdMaxBlocks = 512;
 
 // Partial row of one block: dW2 [O][32], db2 [O], dW1 [32][in_dim], db1 [32], dL/dcam [3].
 __host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim)
@@ -252,14 +283,15 @@ constexpr int bwd_smem_floats(int OT)
     return kBwdWaves * 16 * lds_o(OT) > bwd_red_floats(OT) ? kBwdWaves * 16 * lds_o(OT) : bwd_red_floats(OT);
 }
 
-int decode_bwd_blocks(int64_t na)
+int decode_bwd_blocks(int64_t na, int k)
 {
     const int64_t groups = (na + 15) / 16;
-    return (int)std::max<int64_t>(1, std::min<int64_t>((groups + kBwdWaves - 1) / kBwdWaves, kBwdMaxBlocks));
+    const int cap = out_tiles(k) <= 8 ? kBwdMaxBlocks : kBwdMaxBlocks / 2;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((groups + kBwdWaves - 1) / kBwdWaves, cap));
 }
 
 template <int OT>
-__global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcgs_gaussian_buffers dG,
+__global__ void __launch_bounds__(64 * kBwdWaves, 2) k_decode_bwd(DecodeArgs a, vcgs_gaussian_buffers dG,
                                                                vcgs_anchor_grads out, float* __restrict__ partial)
 {
     // Each wave's [16 anchors][k * 11] outputs y are overwritten in place by
@@ -276,27 +308,21 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
     const int O = a.k * 11;
     const int64_t n = a.na * a.k;
     const bool view = a.in_dim > kF;  // uniform
-    float w1[2][9], b1v[2][4], w2[OT][8], b2v[OT][4];
-    load_weights<OT>(a, lane, w1, b1v, w2, b2v);
-    // transposed operands: W2^T (rows n, k = m) and W1^T in the accumulator-ordered K
-    float w2t[2][OT * 4];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int ks = 0; ks < OT * 4; ++ks) {
-            const int m = ks * 4 + (lane >> 4);
-            w2t[nt][ks] = m < O ? a.W2[m * kF + nt * 16 + (lane & 15)] : 0.0f;
-        }
-    // input tile 2 holds the four view inputs (rows 32..35), zero without them
-    float w1t[3][8];
-#pragma unroll
-    for (int ft = 0; ft < 3; ++ft)
-#pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            const int nn = (st >> 2) * 16 + 4 * (lane >> 4) + (st & 3);
-            const int f = ft * 16 + (lane & 15);
-            w1t[ft][st] = f < a.in_dim ? a.W1[nn * a.in_dim + f] : 0.0f;
-        }
+    __shared__ __align__(16) float w2s[OT * 16 * kW2S];
+    __shared__ float w1s[kF * kW1S];
+    __shared__ float b2s[OT * 16];
+    __shared__ float b1s[kF];
+    for (int i = threadIdx.x; i < OT * 16 * kW2S; i += blockDim.x) {
+        const int m = i / kW2S, c = i - m * kW2S;
+        w2s[i] = (m < O && c < kF) ? a.W2[m * kF + c] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < kF * kW1S; i += blockDim.x) {
+        const int r = i / kW1S, c = i - r * kW1S;
+        w1s[i] = c < a.in_dim ? a.W1[r * a.in_dim + c] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < OT * 16; i += blockDim.x) b2s[i] = i < O ? a.b2[i] : 0.0f;
+    if (threadIdx.x < kF) b1s[threadIdx.x] = a.b1[threadIdx.x];
+    __syncthreads();
     v4f accW2[OT][2], accW1[2][3];
 #pragma unroll
     for (int t = 0; t < OT; ++t) accW2[t][0] = accW2[t][1] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -363,14 +389,14 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
         }
         v4f d1[2];
         float vin;
-        layer1(w1, a, an, avalid, lane, d1, vin);
+        layer1_lds(w1s, a, an, avalid, lane, d1, vin);
         if (view) vs[wave][lane & 15][lane >> 4] = vin;
         float pre[2][4], h[2][4];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                pre[mt][i] = d1[mt][i] + b1v[mt][i];
+                pre[mt][i] = d1[mt][i] + b1s[mt * 16 + 4 * (lane >> 4) + i];
                 h[mt][i] = avalid ? fmaxf(pre[mt][i], 0.0f) : 0.0f;
             }
         wsync();
@@ -381,12 +407,13 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
 #pragma unroll
         for (int t = 0; t < OT; ++t) {
             v4f d2 = {0.f, 0.f, 0.f, 0.f};
+            const float* wr = w2s + (t * 16 + (lane & 15)) * kW2S + 4 * (lane >> 4);
 #pragma unroll
-            for (int st = 0; st < 8; ++st) d2 = mfma4(w2[t][st], h[st >> 2][st & 3], d2);
+            for (int st = 0; st < 8; ++st) d2 = mfma4(wr[(st >> 2) * 16 + (st & 3)], h[st >> 2][st & 3], d2);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int m = t * 16 + 4 * (lane >> 4) + i;
-                if (m < O) ys[wave][lane & 15][m] = d2[i] + b2v[t][i];
+                if (m < O) ys[wave][lane & 15][m] = d2[i] + b2s[m];
             }
         }
         wsync();
@@ -477,8 +504,9 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
         for (int ks = 0; ks < OT * 4; ++ks) {
             const int m = ks * 4 + (lane >> 4);
             const float bv = m < O ? dys[wave][lane & 15][m] : 0.0f;
-            dh[0] = mfma4(w2t[0][ks], bv, dh[0]);
-            dh[1] = mfma4(w2t[1][ks], bv, dh[1]);
+            const float* wr = w2s + (ks * 4 + (lane >> 4)) * kW2S + (lane & 15);
+            dh[0] = mfma4(wr[0], bv, dh[0]);
+            dh[1] = mfma4(wr[16], bv, dh[1]);
         }
         float dpre[2][4];
 #pragma unroll
@@ -489,9 +517,10 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
         v4f df[3] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
-            df[0] = mfma4(w1t[0][st], dpre[st >> 2][st & 3], df[0]);
-            df[1] = mfma4(w1t[1][st], dpre[st >> 2][st & 3], df[1]);
-            if (view) df[2] = mfma4(w1t[2][st], dpre[st >> 2][st & 3], df[2]);
+            const float* wr = w1s + ((st >> 2) * 16 + 4 * (lane >> 4) + (st & 3)) * kW1S + (lane & 15);
+            df[0] = mfma4(wr[0], dpre[st >> 2][st & 3], df[0]);
+            df[1] = mfma4(wr[16], dpre[st >> 2][st & 3], df[1]);
+            if (view) df[2] = mfma4(wr[32], dpre[st >> 2][st & 3], df[2]);
         }
         if (view && lane < 16 && avalid) {
             // lanes 0-15 hold rows 32..35 (dL/d distance, dL/d direction) of anchor `lane`:
@@ -615,24 +644,27 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_decode_bwd(DecodeArgs a, vcg
 }
 
 // Sum of the per-block partial rows: each block owns 64 consecutive outputs;
-// its 4 waves add interleaved quarters of the rows and combine in wave order.
-__global__ void __launch_bounds__(256) k_decode_bwd_reduce(const float* __restrict__ partial, int nblocks, int64_t PF,
+// its 16 waves add interleaved sixteenths of the rows and combine in wave order.
+constexpr int kRedWaves = 16;
+__global__ void __launch_bounds__(64 * kRedWaves) k_decode_bwd_reduce(const float* __restrict__ partial, int nblocks, int64_t PF,
                                                            int O, int in_dim, float* __restrict__ dW2,
                                                            float* __restrict__ db2, float* __restrict__ dW1,
                                                            float* __restrict__ db1, float* __restrict__ dcam)
 {
-    __shared__ float acc[4][64];
+    __shared__ float acc[kRedWaves][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     float s = 0.0f;
     if (i < PF) {
-#pragma unroll 8
-        for (int b = wave; b < nblocks; b += 4) s += partial[(int64_t)b * PF + i];
+#pragma unroll 4
+        for (int b = wave; b < nblocks; b += kRedWaves) s += partial[(int64_t)b * PF + i];
     }
     acc[wave][lane] = s;
     __syncthreads();
     if (wave != 0 || i >= PF) return;
-    s = ((acc[0][lane] + acc[1][lane]) + acc[2][lane]) + acc[3][lane];
+    s = acc[0][lane];
+#pragma unroll
+    for (int w = 1; w < kRedWaves; ++w) s += acc[w][lane];
     const int64_t oW2 = (int64_t)O * kF, oB2 = oW2 + O, oW1 = oB2 + (int64_t)kF * in_dim, oB1 = oW1 + kF;
     if (i < oW2) { if (dW2) dW2[i] = s; }
     else if (i < oB2) { if (db2) db2[i - oW2] = s; }
@@ -657,7 +689,7 @@ void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, con
     }
 #undef VCGS_DEC_BWD
     const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim);
-    k_decode_bwd_reduce<<<(unsigned)((PF + 63) / 64), 256, 0, s>>>(partial, nblocks, PF, a.k * 11, a.in_dim, out.W2,
+    k_decode_bwd_reduce<<<(unsigned)((PF + 63) / 64), 64 * kRedWaves, 0, s>>>(partial, nblocks, PF, a.k * 11, a.in_dim, out.W2,
                                                                    out.b2, out.W1, out.b1, out.cam);
 }
 

@@ -238,7 +238,7 @@ struct DecodeArgs {
     float cam[3];
 };
 void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hipStream_t s);
-int decode_bwd_blocks(int64_t na);
+int decode_bwd_blocks(int64_t na, int k);
 __host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim);
 void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, const vcgs_anchor_grads& out,
                        float* partial, int nblocks, hipStream_t s);
