@@ -477,6 +477,28 @@ int vcgs_decode_anchors_view_backward(vcgs_ctx* ctx, const vcgs_anchors* a, cons
                                       const float cam_centre[3], const vcgs_gaussian_buffers* dG,
                                       vcgs_anchor_grads* out, void* stream);
 
+/* The view-dependent decode (paper eqs. (8)-(9)) for n_views camera centres
+ * in one launch, e.g. the keyframes of a bundle-adjustment window (Sec. 3.5).
+ * cam_centres: host, [n_views][3]; 1 <= n_views <= VCGS_DECODE_MAX_VIEWS.
+ * View v's Gaussians are written to block v of a stacked per-view set: out
+ * arrays hold n_views * na*k Gaussians, each view an ordinary SoA set
+ * (mean [V][3][na*k], quat [V][4][na*k], opacity [V][na*k], ...), the layout
+ * that vcgs_render_batch reads with VCGS_BATCH_PER_VIEW.  Each view's block
+ * equals vcgs_decode_anchors_view for that centre, bit for bit. */
+#define VCGS_DECODE_MAX_VIEWS 16
+int vcgs_decode_anchors_views(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
+                              const float* mask_logit, float mask_eps, int n_views, const float* cam_centres,
+                              vcgs_gaussian_buffers* out, void* stream);
+
+/* Gradients of vcgs_decode_anchors_views: dG stacked per view as above.  The
+ * anchor, MLP, codebook and mask gradients in out are the sums over the views
+ * (one launch, deterministic); out->cam (if non-NULL) receives dL/d(camera
+ * centre) per view, [n_views][3]. */
+int vcgs_decode_anchors_views_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
+                                       const vcgs_codebook* cb, const float* mask_logit, float mask_eps,
+                                       int n_views, const float* cam_centres, const vcgs_gaussian_buffers* dG,
+                                       vcgs_anchor_grads* out, void* stream);
+
 /* ---- kernel configuration ---------------------------------------------- */
 
 /* Process-wide settings read by every later launch (all contexts):

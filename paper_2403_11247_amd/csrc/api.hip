@@ -78,13 +78,17 @@ int vcgs_l1_loss(vcgs_ctx* ctx, const vcgs_images* img, const float* target_colo
     return VCGS_OK;
 }
 
+// cam: NULL, or views camera centres (host, [views][3]) for the view-dependent decode.
 static int make_decode_args(const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
-                            const float* mask_logit, float mask_eps, DecodeArgs* d, const float* cam = nullptr)
+                            const float* mask_logit, float mask_eps, DecodeArgs* d, const float* cam = nullptr,
+                            int views = 1)
 {
+    if (views < 1 || views > kDecodeMaxViews || (!cam && views != 1))
+        return fail(VCGS_E_INVALID, "views must be in [1, 16] (and 1 without camera centres)");
     d->in_dim = cam ? 36 : 32;
-    d->cam[0] = cam ? cam[0] : 0.0f;
-    d->cam[1] = cam ? cam[1] : 0.0f;
-    d->cam[2] = cam ? cam[2] : 0.0f;
+    d->views = views;
+    for (int v = 0; v < kDecodeMaxViews; ++v)
+        for (int i = 0; i < 3; ++i) d->cam[v][i] = (cam && v < views) ? cam[3 * v + i] : 0.0f;
     if (!a || !mlp) return fail(VCGS_E_INVALID, "anchors or mlp is NULL");
     if (a->n_anchor < 0) return fail(VCGS_E_INVALID, "negative anchor count");
     if (a->feat_dim != 32) return fail(VCGS_E_UNSUPPORTED, "feat_dim must be 32");
@@ -114,12 +118,12 @@ static int make_decode_args(const vcgs_anchors* a, const vcgs_mlp* mlp, const vc
 }
 
 static int decode_fwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
-                      const float* mask_logit, float mask_eps, const float* cam, vcgs_gaussian_buffers* out,
-                      void* stream)
+                      const float* mask_logit, float mask_eps, const float* cam, int views,
+                      vcgs_gaussian_buffers* out, void* stream)
 {
     if (!ctx || !out) return fail(VCGS_E_INVALID, "ctx or out is NULL");
     DecodeArgs d;
-    int rc = make_decode_args(a, mlp, cb, mask_logit, mask_eps, &d, cam);
+    int rc = make_decode_args(a, mlp, cb, mask_logit, mask_eps, &d, cam, views);
     if (rc != VCGS_OK) return rc;
     if (d.na > 0 && (!out->mean || !out->scale || !out->quat || !out->opacity || !out->color))
         return fail(VCGS_E_INVALID, "an output pointer is NULL");
@@ -133,12 +137,12 @@ static int decode_fwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
 }
 
 static int decode_bwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
-                      const float* mask_logit, float mask_eps, const float* cam, const vcgs_gaussian_buffers* dG,
-                      vcgs_anchor_grads* out, void* stream)
+                      const float* mask_logit, float mask_eps, const float* cam, int views,
+                      const vcgs_gaussian_buffers* dG, vcgs_anchor_grads* out, void* stream)
 {
     if (!ctx || !out || !dG) return fail(VCGS_E_INVALID, "ctx, dG or out is NULL");
     DecodeArgs d;
-    int rc = make_decode_args(a, mlp, cb, mask_logit, mask_eps, &d, cam);
+    int rc = make_decode_args(a, mlp, cb, mask_logit, mask_eps, &d, cam, views);
     if (rc != VCGS_OK) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
@@ -149,7 +153,7 @@ static int decode_bwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
     if (d.na == 0) return VCGS_OK;
     Scratch sc(&ctx->pool);
     const int nb = decode_bwd_blocks(d.na, d.k);
-    float* partial = sc.get<float>((int64_t)nb * decode_bwd_partial_floats(d.k, d.in_dim));
+    float* partial = sc.get<float>((int64_t)nb * decode_bwd_partial_floats(d.k, d.in_dim, d.views));
     if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (decode backward)");
     ctx->prof.begin(VCGS_STAGE_DECODE_BWD, s);
     launch_decode_bwd(d, *dG, o, partial, nb, s);
@@ -162,14 +166,14 @@ static int decode_bwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
 int vcgs_decode_anchors(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
                         const float* mask_logit, float mask_eps, vcgs_gaussian_buffers* out, void* stream)
 {
-    return decode_fwd(ctx, a, mlp, cb, mask_logit, mask_eps, nullptr, out, stream);
+    return decode_fwd(ctx, a, mlp, cb, mask_logit, mask_eps, nullptr, 1, out, stream);
 }
 
 int vcgs_decode_anchors_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
                                  const float* mask_logit, float mask_eps, const vcgs_gaussian_buffers* dG,
                                  vcgs_anchor_grads* out, void* stream)
 {
-    return decode_bwd(ctx, a, mlp, cb, mask_logit, mask_eps, nullptr, dG, out, stream);
+    return decode_bwd(ctx, a, mlp, cb, mask_logit, mask_eps, nullptr, 1, dG, out, stream);
 }
 
 int vcgs_decode_anchors_view(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
@@ -177,7 +181,15 @@ int vcgs_decode_anchors_view(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_ml
                              vcgs_gaussian_buffers* out, void* stream)
 {
     if (!cam_centre) return fail(VCGS_E_INVALID, "cam_centre is NULL");
-    return decode_fwd(ctx, a, mlp, cb, mask_logit, mask_eps, cam_centre, out, stream);
+    return decode_fwd(ctx, a, mlp, cb, mask_logit, mask_eps, cam_centre, 1, out, stream);
+}
+
+int vcgs_decode_anchors_views(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
+                              const float* mask_logit, float mask_eps, int n_views, const float* cam_centres,
+                              vcgs_gaussian_buffers* out, void* stream)
+{
+    if (!cam_centres) return fail(VCGS_E_INVALID, "cam_centres is NULL");
+    return decode_fwd(ctx, a, mlp, cb, mask_logit, mask_eps, cam_centres, n_views, out, stream);
 }
 
 int vcgs_decode_anchors_view_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
@@ -186,7 +198,16 @@ int vcgs_decode_anchors_view_backward(vcgs_ctx* ctx, const vcgs_anchors* a, cons
                                       vcgs_anchor_grads* out, void* stream)
 {
     if (!cam_centre) return fail(VCGS_E_INVALID, "cam_centre is NULL");
-    return decode_bwd(ctx, a, mlp, cb, mask_logit, mask_eps, cam_centre, dG, out, stream);
+    return decode_bwd(ctx, a, mlp, cb, mask_logit, mask_eps, cam_centre, 1, dG, out, stream);
+}
+
+int vcgs_decode_anchors_views_backward(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
+                                       const vcgs_codebook* cb, const float* mask_logit, float mask_eps,
+                                       int n_views, const float* cam_centres, const vcgs_gaussian_buffers* dG,
+                                       vcgs_anchor_grads* out, void* stream)
+{
+    if (!cam_centres) return fail(VCGS_E_INVALID, "cam_centres is NULL");
+    return decode_bwd(ctx, a, mlp, cb, mask_logit, mask_eps, cam_centres, n_views, dG, out, stream);
 }
 
 int vcgs_mask_loss(vcgs_ctx* ctx, int64_t n, const float* mask_logit, const uint32_t* in_frustum_count,

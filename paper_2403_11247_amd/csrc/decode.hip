@@ -87,43 +87,25 @@ __device__ __forceinline__ Decoded decode_one(const DecodeArgs& a, const float* 
     return d;
 }
 
-// View input c of anchor an (eq. (9)): c = 0 the distance, 1..3 the unit direction.
-__device__ __forceinline__ float view_input(const DecodeArgs& a, int64_t an, int c)
+// View input c of anchor an for the camera centre cam (eq. (9)): c = 0 the
+// distance, 1..3 the unit direction.
+__device__ __forceinline__ float view_input(const DecodeArgs& a, const float* cam, int64_t an, int c)
 {
-    const float vx = a.xa[an] - a.cam[0], vy = a.xa[a.na + an] - a.cam[1], vz = a.xa[2 * a.na + an] - a.cam[2];
+    const float vx = a.xa[an] - cam[0], vy = a.xa[a.na + an] - cam[1], vz = a.xa[2 * a.na + an] - cam[2];
     const float dist = sqrtf(vx * vx + vy * vy + vz * vz);
     return c == 0 ? dist : (c == 1 ? vx : (c == 2 ? vy : vz)) / dist;
 }
 
-// First layer for 16 anchors; returns the pre-activations in accumulator layout
-// and, with the view input, this lane's view value (anchor lane % 16, input lane / 16).
-__device__ __forceinline__ void layer1(const float (&w1)[2][9], const DecodeArgs& a, int64_t an, bool valid,
-                                       int lane, v4f (&d1)[2], float& vin)
-{
-    d1[0] = v4f{0.f, 0.f, 0.f, 0.f};
-    d1[1] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-        const float b = valid ? a.feat[an * kF + ks * 4 + (lane >> 4)] : 0.0f;
-        d1[0] = mfma4(w1[0][ks], b, d1[0]);
-        d1[1] = mfma4(w1[1][ks], b, d1[1]);
-    }
-    vin = 0.0f;
-    if (a.in_dim > kF) {  // uniform
-        vin = valid ? view_input(a, an, lane >> 4) : 0.0f;
-        d1[0] = mfma4(w1[0][8], vin, d1[0]);
-        d1[1] = mfma4(w1[1][8], vin, d1[1]);
-    }
-}
-
-// Block-shared copies of the MLP weights for the backward, read at their point
-// of use rather than held in registers: W2 rows padded to kW2S floats (rows at
-// or beyond O zero), W1 rows padded to kW1S floats (columns at or beyond in_dim zero).
+// Block-shared copies of the MLP weights, read at their point of use rather
+// than held in registers: W2 rows padded to kW2S floats (rows at or beyond O
+// zero), W1 rows padded to kW1S floats (columns at or beyond in_dim zero).
 constexpr int kW2S = 36;
 constexpr int kW1S = 52;
 
-__device__ __forceinline__ void layer1_lds(const float* w1s, const DecodeArgs& a, int64_t an, bool valid, int lane,
-                                           v4f (&d1)[2], float& vin)
+// First layer for 16 anchors; returns the pre-activations in accumulator layout
+// and, with the view input, this lane's view value (anchor lane % 16, input lane / 16).
+__device__ __forceinline__ void layer1_lds(const float* w1s, const DecodeArgs& a, const float* cam, int64_t an,
+                                           bool valid, int lane, v4f (&d1)[2], float& vin)
 {
     d1[0] = v4f{0.f, 0.f, 0.f, 0.f};
     d1[1] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -137,79 +119,102 @@ __device__ __forceinline__ void layer1_lds(const float* w1s, const DecodeArgs& a
     }
     vin = 0.0f;
     if (a.in_dim > kF) {  // uniform
-        vin = valid ? view_input(a, an, lane >> 4) : 0.0f;
+        vin = valid ? view_input(a, cam, an, lane >> 4) : 0.0f;
         d1[0] = mfma4(r0[32], vin, d1[0]);
         d1[1] = mfma4(r1[32], vin, d1[1]);
     }
 }
 
+// View v's block of a stacked per-view Gaussian set of n Gaussians per view.
+__device__ __forceinline__ vcgs_gaussian_buffers view_block(const vcgs_gaussian_buffers& g, int v, int64_t n)
+{
+    vcgs_gaussian_buffers r;
+    r.mean = g.mean ? g.mean + 3 * v * n : nullptr;
+    r.scale = g.scale ? g.scale + 3 * v * n : nullptr;
+    r.quat = g.quat ? g.quat + 4 * v * n : nullptr;
+    r.opacity = g.opacity ? g.opacity + v * n : nullptr;
+    r.color = g.color ? g.color + 3 * v * n : nullptr;
+    return r;
+}
+
+// Per-anchor outputs of the backward: the first view stores, later views add.
+__device__ __forceinline__ void put(float* p, bool first, float x) { *p = first ? x : *p + x; }
+
+// Block-wide copy of the weights into LDS (ends with a block barrier).
 template <int OT>
-__device__ __forceinline__ void load_weights(const DecodeArgs& a, int lane, float (&w1)[2][9], float (&b1v)[2][4],
-                                             float (&w2)[OT][8], float (&b2v)[OT][4])
+__device__ __forceinline__ void fill_weights(const DecodeArgs& a, float* w2s, float* w1s, float* b2s, float* b1s)
 {
     const int O = a.k * 11;
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int ks = 0; ks < 9; ++ks)
-            w1[mt][ks] = (ks < 8 || a.in_dim > kF) ? a.W1[(mt * 16 + (lane & 15)) * a.in_dim + ks * 4 + (lane >> 4)]
-                                                   : 0.0f;
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) b1v[mt][i] = a.b1[mt * 16 + 4 * (lane >> 4) + i];
+    for (int i = threadIdx.x; i < OT * 16 * kW2S; i += blockDim.x) {
+        const int m = i / kW2S, c = i - m * kW2S;
+        w2s[i] = (m < O && c < kF) ? a.W2[m * kF + c] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < kF * kW1S; i += blockDim.x) {
+        const int r = i / kW1S, c = i - r * kW1S;
+        w1s[i] = c < a.in_dim ? a.W1[r * a.in_dim + c] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < OT * 16; i += blockDim.x) b2s[i] = i < O ? a.b2[i] : 0.0f;
+    if (threadIdx.x < kF) b1s[threadIdx.x] = a.b1[threadIdx.x];
+    __syncthreads();
+}
+
+// Second layer for 16 anchors from the LDS weights: y = W2 h + b2 into the
+// wave's [16 anchors][O] buffer.
+template <int OT, int LO>
+__device__ __forceinline__ void layer2_lds(const float* w2s, const float* b2s, const float (&h)[2][4], int O, int lane,
+                                           float (*yw)[LO])
+{
 #pragma unroll
     for (int t = 0; t < OT; ++t) {
-        const int m = t * 16 + (lane & 15);
+        v4f d2 = {0.f, 0.f, 0.f, 0.f};
+        const float* wr = w2s + (t * 16 + (lane & 15)) * kW2S + 4 * (lane >> 4);
 #pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            const int n = (st >> 2) * 16 + 4 * (lane >> 4) + (st & 3);
-            w2[t][st] = m < O ? a.W2[m * kF + n] : 0.0f;
-        }
+        for (int st = 0; st < 8; ++st) d2 = mfma4(wr[(st >> 2) * 16 + (st & 3)], h[st >> 2][st & 3], d2);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int mm = t * 16 + 4 * (lane >> 4) + i;
-            b2v[t][i] = mm < O ? a.b2[mm] : 0.0f;
+            const int m = t * 16 + 4 * (lane >> 4) + i;
+            if (m < O) yw[lane & 15][m] = d2[i] + b2s[m];
         }
     }
 }
 
 template <int OT>
-__global__ void __launch_bounds__(256) k_decode_fwd(DecodeArgs a, float* __restrict__ mean, float* __restrict__ scale,
-                                                    float* __restrict__ quat, float* __restrict__ opac,
-                                                    float* __restrict__ color)
+__global__ void __launch_bounds__(256) k_decode_fwd(DecodeArgs a, float* __restrict__ mean0, float* __restrict__ scale0,
+                                                    float* __restrict__ quat0, float* __restrict__ opac0,
+                                                    float* __restrict__ color0)
 {
     constexpr int LO = lds_o(OT);
     __shared__ float ys[4][16][LO];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int O = a.k * 11;
-    float w1[2][9], b1v[2][4], w2[OT][8], b2v[OT][4];
-    load_weights<OT>(a, lane, w1, b1v, w2, b2v);
+    __shared__ __align__(16) float w2s[OT * 16 * kW2S];
+    __shared__ float w1s[kF * kW1S];
+    __shared__ float b2s[OT * 16];
+    __shared__ float b1s[kF];
+    fill_weights<OT>(a, w2s, w1s, b2s, b1s);
     const int64_t n = a.na * a.k;
     const int64_t groups = (a.na + 15) / 16;
-    for (int64_t grp = (int64_t)blockIdx.x * 4 + wave; grp < groups; grp += (int64_t)gridDim.x * 4) {
+    // work items: (view, 16-anchor group), view-major
+    for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < groups * a.views; it += (int64_t)gridDim.x * 4) {
+        const int v = (int)(it / groups);
+        const int64_t grp = it - v * groups;
         const int64_t a0 = grp * 16;
         const int64_t an = a0 + (lane & 15);
+        float* mean = mean0 + 3 * v * n;
+        float* scale = scale0 + 3 * v * n;
+        float* quat = quat0 + 4 * v * n;
+        float* opac = opac0 + v * n;
+        float* color = color0 + 3 * v * n;
         v4f d1[2];
         float vin;
-        layer1(w1, a, an, an < a.na, lane, d1, vin);
+        layer1_lds(w1s, a, a.cam[v], an, an < a.na, lane, d1, vin);
         float h[2][4];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) h[mt][i] = fmaxf(d1[mt][i] + b1v[mt][i], 0.0f);
+            for (int i = 0; i < 4; ++i) h[mt][i] = fmaxf(d1[mt][i] + b1s[mt * 16 + 4 * (lane >> 4) + i], 0.0f);
         wsync();
-#pragma unroll
-        for (int t = 0; t < OT; ++t) {
-            v4f d2 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int st = 0; st < 8; ++st) d2 = mfma4(w2[t][st], h[st >> 2][st & 3], d2);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int m = t * 16 + 4 * (lane >> 4) + i;
-                if (m < O) ys[wave][lane & 15][m] = d2[i] + b2v[t][i];
-            }
-        }
+        layer2_lds<OT, LO>(w2s, b2s, h, O, lane, ys[wave]);
         wsync();
         for (int e = lane; e < 16 * a.k; e += 64) {
             const int al = e / a.k, off = e - al * a.k;
@@ -233,15 +238,16 @@ __global__ void __launch_bounds__(256) k_decode_fwd(DecodeArgs a, float* __restr
 
 static int out_tiles(int k) { return (k * 11 + 15) / 16; }
 
-// Forward grid cap: each wave loads the MLP weights once into registers, so
-// a wave that strides over several 16-anchor groups amortises that load.
-constexpr int kFwdMaxBlocks = 256;
+// Forward grid cap: three blocks per CU (LDS bound); each block copies the
+// weights into LDS once, so waves that stride over several 16-anchor groups
+// amortise that copy.
+constexpr int kFwdMaxBlocks = 768;
 
 void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hipStream_t s)
 {
     if (a.na <= 0) return;
-    const int64_t groups = (a.na + 15) / 16;
-    const int blocks = (int)std::min<int64_t>((groups + 3) / 4, kFwdMaxBlocks);
+    const int64_t items = (a.na + 15) / 16 * a.views;
+    const int blocks = (int)std::min<int64_t>((items + 3) / 4, kFwdMaxBlocks);
 #define VCGS_DEC_FWD(OT)                                                                                        \
     case OT:                                                                                                    \
         k_decode_fwd<OT><<<blocks, 256, 0, s>>>(a, out.mean, out.scale, out.quat, out.opacity, out.color);      \
@@ -262,10 +268,10 @@ constexpr int kBwdWaves = 4;
 // (up to 8 output tiles), else one.
 constexpr int kBwdMaxBlocks = 512;
 
-// Partial row of one block: dW2 [O][32], db2 [O], dW1 [32][in_dim], db1 [32], dL/dcam [3].
-__host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim)
+// Partial row of one block: dW2 [O][32], db2 [O], dW1 [32][in_dim], db1 [32], dL/dcam [views][3].
+__host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim, int views)
 {
-    return (int64_t)k * 11 * kF + k * 11 + (int64_t)kF * in_dim + kF + 3;
+    return (int64_t)k * 11 * kF + k * 11 + (int64_t)kF * in_dim + kF + 3 * views;
 }
 
 // Block reduction buffer, padded so that every lane owns a slot for each of
@@ -312,17 +318,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves, 2) k_decode_bwd(DecodeArgs a, 
     __shared__ float w1s[kF * kW1S];
     __shared__ float b2s[OT * 16];
     __shared__ float b1s[kF];
-    for (int i = threadIdx.x; i < OT * 16 * kW2S; i += blockDim.x) {
-        const int m = i / kW2S, c = i - m * kW2S;
-        w2s[i] = (m < O && c < kF) ? a.W2[m * kF + c] : 0.0f;
-    }
-    for (int i = threadIdx.x; i < kF * kW1S; i += blockDim.x) {
-        const int r = i / kW1S, c = i - r * kW1S;
-        w1s[i] = c < a.in_dim ? a.W1[r * a.in_dim + c] : 0.0f;
-    }
-    for (int i = threadIdx.x; i < OT * 16; i += blockDim.x) b2s[i] = i < O ? a.b2[i] : 0.0f;
-    if (threadIdx.x < kF) b1s[threadIdx.x] = a.b1[threadIdx.x];
-    __syncthreads();
+    fill_weights<OT>(a, w2s, w1s, b2s, b1s);
     v4f accW2[OT][2], accW1[2][3];
 #pragma unroll
     for (int t = 0; t < OT; ++t) accW2[t][0] = accW2[t][1] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -332,254 +328,257 @@ __global__ void __launch_bounds__(64 * kBwdWaves, 2) k_decode_bwd(DecodeArgs a, 
         for (int ft = 0; ft < 3; ++ft) accW1[nt][ft] = v4f{0.f, 0.f, 0.f, 0.f};
     float accB2[(kMaxO + 63) / 64] = {0.f, 0.f, 0.f};
     float accB1 = 0.0f;
-    float accCam[3] = {0.f, 0.f, 0.f};  // dL/d camera centre of this lane's anchors
+    __shared__ float camw[kBwdWaves][kDecodeMaxViews * 3];  // dL/d camera centre per wave and view
+    if (lane < kDecodeMaxViews * 3) camw[wave][lane] = 0.0f;
 
+    // each wave takes a 16-anchor group through every view in turn, so the
+    // per-anchor outputs add up over the views without races
     const int64_t groups = (a.na + 15) / 16;
     for (int64_t grp = (int64_t)blockIdx.x * kBwdWaves + wave; grp < groups; grp += (int64_t)gridDim.x * kBwdWaves) {
-        const int64_t a0 = grp * 16;
-        const int64_t an = a0 + (lane & 15);
-        const bool avalid = an < a.na;
-        {
-            // per-anchor sums over offsets (anchor position, scaling) and the offsets'
-            // gradients: the (anchor, offset) pairs spread over the 64 lanes, their
-            // contributions staged in the wave's y buffer (free until layer 2), then
-            // added per anchor in offset order by 16 lanes
-            float* stg = &ys[wave][0][0];  // 16 * LO >= 16 * k * 6 floats
+        for (int v = 0; v < a.views; ++v) {
+            const bool first = v == 0;
+            const vcgs_gaussian_buffers dGv = view_block(dG, v, n);
+            const int64_t a0 = grp * 16;
+            const int64_t an = a0 + (lane & 15);
+            const bool avalid = an < a.na;
+            {
+                // per-anchor sums over offsets (anchor position, scaling) and the offsets'
+                // gradients: the (anchor, offset) pairs spread over the 64 lanes, their
+                // contributions staged in the wave's y buffer (free until layer 2), then
+                // added per anchor in offset order by 16 lanes
+                float* stg = &ys[wave][0][0];  // 16 * LO >= 16 * k * 6 floats
+                for (int e = lane; e < 16 * a.k; e += 64) {
+                    const int al = e / a.k, off = e - al * a.k;
+                    const int64_t anc = a0 + al;
+                    float dm[3] = {0.0f, 0.0f, 0.0f}, dl[3] = {0.0f, 0.0f, 0.0f};
+                    if (anc < a.na) {
+                        const int64_t g = anc * a.k + off;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            dm[i] = dGv.mean ? dGv.mean[i * n + g] : 0.0f;
+                            dl[i] = dm[i] * a.offset[g * 3 + i];
+                        }
+                        if (out.offset) {
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) put(out.offset + g * 3 + i, first, dm[i] * a.scaling[i * a.na + anc]);
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        stg[e * 6 + i] = dm[i];
+                        stg[e * 6 + 3 + i] = dl[i];
+                    }
+                }
+                wsync();
+                if (lane < 16 && a0 + lane < a.na) {
+                    const int64_t anc = a0 + lane;
+                    float dx[3] = {0.0f, 0.0f, 0.0f}, dls[3] = {0.0f, 0.0f, 0.0f};
+                    for (int off = 0; off < a.k; ++off) {
+                        const float* q = stg + (lane * a.k + off) * 6;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            dx[i] += q[i];
+                            dls[i] += q[3 + i];
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        if (out.scaling) put(out.scaling + i * a.na + anc, first, dls[i]);
+                        if (out.xa) put(out.xa + i * a.na + anc, first, dx[i]);
+                    }
+                }
+                wsync();
+            }
+            v4f d1[2];
+            float vin;
+            layer1_lds(w1s, a, a.cam[v], an, avalid, lane, d1, vin);
+            if (view) vs[wave][lane & 15][lane >> 4] = vin;
+            float pre[2][4], h[2][4];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    pre[mt][i] = d1[mt][i] + b1s[mt * 16 + 4 * (lane >> 4) + i];
+                    h[mt][i] = avalid ? fmaxf(pre[mt][i], 0.0f) : 0.0f;
+                }
+            wsync();
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) hs[wave][lane & 15][mt * 16 + 4 * (lane >> 4) + i] = h[mt][i];
+            layer2_lds<OT, LO>(w2s, b2s, h, O, lane, ys[wave]);
+            wsync();
+            // dL/dy per (anchor, offset); codebook and mask gradients
             for (int e = lane; e < 16 * a.k; e += 64) {
                 const int al = e / a.k, off = e - al * a.k;
                 const int64_t anc = a0 + al;
-                float dm[3] = {0.0f, 0.0f, 0.0f}, dl[3] = {0.0f, 0.0f, 0.0f};
-                if (anc < a.na) {
-                    const int64_t g = anc * a.k + off;
+                float* dy = &dys[wave][al][off * 11];
+                if (anc >= a.na) {
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        dm[i] = dG.mean ? dG.mean[i * n + g] : 0.0f;
-                        dl[i] = dm[i] * a.offset[g * 3 + i];
-                    }
-                    if (out.offset) {
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) out.offset[g * 3 + i] = dm[i] * a.scaling[i * a.na + anc];
-                    }
+                    for (int i = 0; i < 11; ++i) dy[i] = 0.0f;
+                    continue;
                 }
+                const int64_t g = anc * a.k + off;
+                const Decoded d = decode_one(a, &ys[wave][al][off * 11], g);
+                float ds[3], dq[4], dc[3], dop;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    stg[e * 6 + i] = dm[i];
-                    stg[e * 6 + 3 + i] = dl[i];
+                    ds[i] = dGv.scale ? dGv.scale[i * n + g] : 0.0f;
+                    dc[i] = dGv.color ? dGv.color[i * n + g] : 0.0f;
                 }
-            }
-            wsync();
-            if (lane < 16 && a0 + lane < a.na) {
-                const int64_t anc = a0 + lane;
-                float dx[3] = {0.0f, 0.0f, 0.0f}, dls[3] = {0.0f, 0.0f, 0.0f};
-                for (int off = 0; off < a.k; ++off) {
-                    const float* q = stg + (lane * a.k + off) * 6;
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        dx[i] += q[i];
-                        dls[i] += q[3 + i];
+                for (int i = 0; i < 4; ++i) dq[i] = dGv.quat ? dGv.quat[i * n + g] : 0.0f;
+                dop = dGv.opacity ? dGv.opacity[g] : 0.0f;
+                if (a.mask_logit) {
+                    const float m = a.mask_logit[g];
+                    float gm = 0.0f;
+                    if (d.keep) {
+                        const float sg = sigm(m);
+                        gm = sg * (1.0f - sg) * (ds[0] * d.s_raw[0] + ds[1] * d.s_raw[1] + ds[2] * d.s_raw[2] + dop * d.o_raw);
+                    } else {
+                        ds[0] = ds[1] = ds[2] = 0.0f;
+                        dop = 0.0f;
                     }
+                    if (out.mask_logit) put(out.mask_logit + g, first, gm);
                 }
+                dy[0] = dop * d.o_raw * (1.0f - d.o_raw);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    if (out.scaling) out.scaling[i * a.na + anc] = dls[i];
-                    if (out.xa) out.xa[i * a.na + anc] = dx[i];
-                }
-            }
-            wsync();
-        }
-        v4f d1[2];
-        float vin;
-        layer1_lds(w1s, a, an, avalid, lane, d1, vin);
-        if (view) vs[wave][lane & 15][lane >> 4] = vin;
-        float pre[2][4], h[2][4];
+                for (int i = 0; i < 3; ++i) dy[1 + i] = dc[i] * d.c[i] * (1.0f - d.c[i]);
+                float dv[7];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+                for (int i = 0; i < 3; ++i) dv[i] = ds[i] * d.s_raw[i];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                pre[mt][i] = d1[mt][i] + b1s[mt * 16 + 4 * (lane >> 4) + i];
-                h[mt][i] = avalid ? fmaxf(pre[mt][i], 0.0f) : 0.0f;
-            }
-        wsync();
+                for (int i = 0; i < 4; ++i) dv[3 + i] = dq[i];
+                if (a.books) {
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+                    for (int i = 0; i < 7; ++i) dy[4 + i] = 0.0f;
+                    if (out.books) {
+                        for (int s = 0; s < a.stages; ++s) {
+                            float* row = out.books + ((int64_t)s * a.cb_size + code_index(a, s, n, g)) * 7;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) hs[wave][lane & 15][mt * 16 + 4 * (lane >> 4) + i] = h[mt][i];
-#pragma unroll
-        for (int t = 0; t < OT; ++t) {
-            v4f d2 = {0.f, 0.f, 0.f, 0.f};
-            const float* wr = w2s + (t * 16 + (lane & 15)) * kW2S + 4 * (lane >> 4);
-#pragma unroll
-            for (int st = 0; st < 8; ++st) d2 = mfma4(wr[(st >> 2) * 16 + (st & 3)], h[st >> 2][st & 3], d2);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int m = t * 16 + 4 * (lane >> 4) + i;
-                if (m < O) ys[wave][lane & 15][m] = d2[i] + b2s[m];
-            }
-        }
-        wsync();
-        // dL/dy per (anchor, offset); codebook and mask gradients
-        for (int e = lane; e < 16 * a.k; e += 64) {
-            const int al = e / a.k, off = e - al * a.k;
-            const int64_t anc = a0 + al;
-            float* dy = &dys[wave][al][off * 11];
-            if (anc >= a.na) {
-#pragma unroll
-                for (int i = 0; i < 11; ++i) dy[i] = 0.0f;
-                continue;
-            }
-            const int64_t g = anc * a.k + off;
-            const Decoded d = decode_one(a, &ys[wave][al][off * 11], g);
-            float ds[3], dq[4], dc[3], dop;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                ds[i] = dG.scale ? dG.scale[i * n + g] : 0.0f;
-                dc[i] = dG.color ? dG.color[i * n + g] : 0.0f;
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) dq[i] = dG.quat ? dG.quat[i * n + g] : 0.0f;
-            dop = dG.opacity ? dG.opacity[g] : 0.0f;
-            if (a.mask_logit) {
-                const float m = a.mask_logit[g];
-                float gm = 0.0f;
-                if (d.keep) {
-                    const float sg = sigm(m);
-                    gm = sg * (1.0f - sg) * (ds[0] * d.s_raw[0] + ds[1] * d.s_raw[1] + ds[2] * d.s_raw[2] + dop * d.o_raw);
+                            for (int i = 0; i < 7; ++i) atomicAdd(row + i, dv[i]);
+                        }
+                    }
                 } else {
-                    ds[0] = ds[1] = ds[2] = 0.0f;
-                    dop = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 7; ++i) dy[4 + i] = dv[i];
                 }
-                if (out.mask_logit) out.mask_logit[g] = gm;
             }
-            dy[0] = dop * d.o_raw * (1.0f - d.o_raw);
+            wsync();
+            // db2 and dW2 += dy h^T  (K = the 16 anchors)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) dy[1 + i] = dc[i] * d.c[i] * (1.0f - d.c[i]);
-            float dv[7];
+            for (int j = 0; j < (kMaxO + 63) / 64; ++j) {
+                const int m = lane + 64 * j;
+                if (m < O) {
+                    float sacc = 0.0f;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) dv[i] = ds[i] * d.s_raw[i];
+                    for (int al = 0; al < 16; ++al) sacc += dys[wave][al][m];
+                    accB2[j] += sacc;
+                }
+            }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) dv[3 + i] = dq[i];
-            if (a.books) {
+            for (int ks = 0; ks < 4; ++ks) {
+                const int al = ks * 4 + (lane >> 4);
+                const float hb0 = hs[wave][al][lane & 15];
+                const float hb1 = hs[wave][al][16 + (lane & 15)];
 #pragma unroll
-                for (int i = 0; i < 7; ++i) dy[4 + i] = 0.0f;
-                if (out.books) {
-                    for (int s = 0; s < a.stages; ++s) {
-                        float* row = out.books + ((int64_t)s * a.cb_size + code_index(a, s, n, g)) * 7;
+                for (int t = 0; t < OT; ++t) {
+                    const int m = t * 16 + (lane & 15);
+                    const float av = m < O ? dys[wave][al][m] : 0.0f;
+                    accW2[t][0] = mfma4(av, hb0, accW2[t][0]);
+                    accW2[t][1] = mfma4(av, hb1, accW2[t][1]);
+                }
+            }
+            // dh = W2^T dy  (K = m)
+            v4f dh[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-                        for (int i = 0; i < 7; ++i) atomicAdd(row + i, dv[i]);
+            for (int ks = 0; ks < OT * 4; ++ks) {
+                const int m = ks * 4 + (lane >> 4);
+                const float bv = m < O ? dys[wave][lane & 15][m] : 0.0f;
+                const float* wr = w2s + (ks * 4 + (lane >> 4)) * kW2S + (lane & 15);
+                dh[0] = mfma4(wr[0], bv, dh[0]);
+                dh[1] = mfma4(wr[16], bv, dh[1]);
+            }
+            float dpre[2][4];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dpre[mt][i] = (avalid && pre[mt][i] > 0.0f) ? dh[mt][i] : 0.0f;
+            // df = W1^T dpre (tile 2: the view inputs)
+            v4f df[3] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int st = 0; st < 8; ++st) {
+                const float* wr = w1s + ((st >> 2) * 16 + 4 * (lane >> 4) + (st & 3)) * kW1S + (lane & 15);
+                df[0] = mfma4(wr[0], dpre[st >> 2][st & 3], df[0]);
+                df[1] = mfma4(wr[16], dpre[st >> 2][st & 3], df[1]);
+                if (view) df[2] = mfma4(wr[32], dpre[st >> 2][st & 3], df[2]);
+            }
+            if (view) {  // uniform
+                float dc[3] = {0.0f, 0.0f, 0.0f};  // this anchor's share of dL/d camera centre
+                if (lane < 16 && avalid) {
+                    // lanes 0-15 hold rows 32..35 (dL/d distance, dL/d direction) of anchor `lane`:
+                    // dL/dv = dL/ddelta d + (dL/dd - (dL/dd . d) d) / delta,  v = x_a - x_c
+                    const float dist = vs[wave][lane][0];
+                    const float d0 = vs[wave][lane][1], d1v = vs[wave][lane][2], d2 = vs[wave][lane][3];
+                    const float gd = df[2][1] * d0 + df[2][2] * d1v + df[2][3] * d2;
+                    const float dv[3] = {df[2][0] * d0 + (df[2][1] - gd * d0) / dist,
+                                         df[2][0] * d1v + (df[2][2] - gd * d1v) / dist,
+                                         df[2][0] * d2 + (df[2][3] - gd * d2) / dist};
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        if (out.xa) out.xa[i * a.na + an] += dv[i];
+                        dc[i] = -dv[i];
                     }
                 }
-            } else {
+                // the 16 anchors' sum (lanes 0-15), added to this wave's view-v total
 #pragma unroll
-                for (int i = 0; i < 7; ++i) dy[4 + i] = dv[i];
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int o = 8; o > 0; o >>= 1) dc[i] += __shfl_xor(dc[i], o, 16);
+                if (lane == 0) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) camw[wave][v * 3 + i] += dc[i];
+                }
             }
-        }
-        wsync();
-        // db2 and dW2 += dy h^T  (K = the 16 anchors)
+            if (out.feat && avalid) {
 #pragma unroll
-        for (int j = 0; j < (kMaxO + 63) / 64; ++j) {
-            const int m = lane + 64 * j;
-            if (m < O) {
+                for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) put(out.feat + an * kF + ft * 16 + 4 * (lane >> 4) + i, first, df[ft][i]);
+            }
+            // dW1 += dpre f^T, db1 += sum dpre (K = the 16 anchors)
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ps[wave][lane & 15][mt * 16 + 4 * (lane >> 4) + i] = dpre[mt][i];
+            wsync();
+            if (lane < kF) {
                 float sacc = 0.0f;
 #pragma unroll
-                for (int al = 0; al < 16; ++al) sacc += dys[wave][al][m];
-                accB2[j] += sacc;
+                for (int al = 0; al < 16; ++al) sacc += ps[wave][al][lane];
+                accB1 += sacc;
             }
-        }
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int al = ks * 4 + (lane >> 4);
-            const float hb0 = hs[wave][al][lane & 15];
-            const float hb1 = hs[wave][al][16 + (lane & 15)];
+            for (int ks = 0; ks < 4; ++ks) {
+                const int al = ks * 4 + (lane >> 4);
+                const int64_t anc = a0 + al;
+                const float f0 = anc < a.na ? a.feat[anc * kF + (lane & 15)] : 0.0f;
+                const float f1 = anc < a.na ? a.feat[anc * kF + 16 + (lane & 15)] : 0.0f;
+                const float f2 = (view && (lane & 15) < 4) ? vs[wave][al][lane & 15] : 0.0f;
 #pragma unroll
-            for (int t = 0; t < OT; ++t) {
-                const int m = t * 16 + (lane & 15);
-                const float av = m < O ? dys[wave][al][m] : 0.0f;
-                accW2[t][0] = mfma4(av, hb0, accW2[t][0]);
-                accW2[t][1] = mfma4(av, hb1, accW2[t][1]);
+                for (int nt = 0; nt < 2; ++nt) {
+                    const float av = ps[wave][al][nt * 16 + (lane & 15)];
+                    accW1[nt][0] = mfma4(av, f0, accW1[nt][0]);
+                    accW1[nt][1] = mfma4(av, f1, accW1[nt][1]);
+                    if (view) accW1[nt][2] = mfma4(av, f2, accW1[nt][2]);
+                }
             }
+            wsync();
         }
-        // dh = W2^T dy  (K = m)
-        v4f dh[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-        for (int ks = 0; ks < OT * 4; ++ks) {
-            const int m = ks * 4 + (lane >> 4);
-            const float bv = m < O ? dys[wave][lane & 15][m] : 0.0f;
-            const float* wr = w2s + (ks * 4 + (lane >> 4)) * kW2S + (lane & 15);
-            dh[0] = mfma4(wr[0], bv, dh[0]);
-            dh[1] = mfma4(wr[16], bv, dh[1]);
-        }
-        float dpre[2][4];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) dpre[mt][i] = (avalid && pre[mt][i] > 0.0f) ? dh[mt][i] : 0.0f;
-        // df = W1^T dpre (tile 2: the view inputs)
-        v4f df[3] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            const float* wr = w1s + ((st >> 2) * 16 + 4 * (lane >> 4) + (st & 3)) * kW1S + (lane & 15);
-            df[0] = mfma4(wr[0], dpre[st >> 2][st & 3], df[0]);
-            df[1] = mfma4(wr[16], dpre[st >> 2][st & 3], df[1]);
-            if (view) df[2] = mfma4(wr[32], dpre[st >> 2][st & 3], df[2]);
-        }
-        if (view && lane < 16 && avalid) {
-            // lanes 0-15 hold rows 32..35 (dL/d distance, dL/d direction) of anchor `lane`:
-            // dL/dv = dL/ddelta d + (dL/dd - (dL/dd . d) d) / delta,  v = x_a - x_c
-            const float dist = vs[wave][lane][0];
-            const float d0 = vs[wave][lane][1], d1v = vs[wave][lane][2], d2 = vs[wave][lane][3];
-            const float gd = df[2][1] * d0 + df[2][2] * d1v + df[2][3] * d2;
-            const float dv[3] = {df[2][0] * d0 + (df[2][1] - gd * d0) / dist,
-                                 df[2][0] * d1v + (df[2][2] - gd * d1v) / dist,
-                                 df[2][0] * d2 + (df[2][3] - gd * d2) / dist};
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                if (out.xa) out.xa[i * a.na + an] += dv[i];
-                accCam[i] -= dv[i];
-            }
-        }
-        if (out.feat && avalid) {
-#pragma unroll
-            for (int ft = 0; ft < 2; ++ft)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) out.feat[an * kF + ft * 16 + 4 * (lane >> 4) + i] = df[ft][i];
-        }
-        // dW1 += dpre f^T, db1 += sum dpre (K = the 16 anchors)
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ps[wave][lane & 15][mt * 16 + 4 * (lane >> 4) + i] = dpre[mt][i];
-        wsync();
-        if (lane < kF) {
-            float sacc = 0.0f;
-#pragma unroll
-            for (int al = 0; al < 16; ++al) sacc += ps[wave][al][lane];
-            accB1 += sacc;
-        }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int al = ks * 4 + (lane >> 4);
-            const int64_t anc = a0 + al;
-            const float f0 = anc < a.na ? a.feat[anc * kF + (lane & 15)] : 0.0f;
-            const float f1 = anc < a.na ? a.feat[anc * kF + 16 + (lane & 15)] : 0.0f;
-            const float f2 = (view && (lane & 15) < 4) ? vs[wave][al][lane & 15] : 0.0f;
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                const float av = ps[wave][al][nt * 16 + (lane & 15)];
-                accW1[nt][0] = mfma4(av, f0, accW1[nt][0]);
-                accW1[nt][1] = mfma4(av, f1, accW1[nt][1]);
-                if (view) accW1[nt][2] = mfma4(av, f2, accW1[nt][2]);
-            }
-        }
-        wsync();
     }
     // block reduction in wave order, then one partial row per block
     __syncthreads();
     float* red = smem;  // bwd_smem_floats(OT) >= bwd_red_floats(OT)
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) accCam[i] += __shfl_xor(accCam[i], o, 64);
-    float cam = lane == 0 ? accCam[0] : (lane == 1 ? accCam[1] : (lane == 2 ? accCam[2] : 0.0f));
     // Wave w adds the sum of waves 0..w-1 into its accumulators, then stores
     // them: all its loads are issued before any store.
     for (int w = 0; w < kBwdWaves; ++w) {
@@ -603,7 +602,6 @@ __global__ void __launch_bounds__(64 * kBwdWaves, 2) k_decode_bwd(DecodeArgs a, 
                             accW1[nt][ft][i] +=
                                 red[red_w1(OT) + (nt * 16 + 4 * (lane >> 4) + i) * kRedW1Cols + ft * 16 + (lane & 15)];
                 accB1 += red[red_b1(OT) + lane];
-                cam += red[red_cam(OT) + lane];
             }
 #pragma unroll
             for (int t = 0; t < OT; ++t)
@@ -623,12 +621,17 @@ __global__ void __launch_bounds__(64 * kBwdWaves, 2) k_decode_bwd(DecodeArgs a, 
                         red[red_w1(OT) + (nt * 16 + 4 * (lane >> 4) + i) * kRedW1Cols + ft * 16 + (lane & 15)] =
                             accW1[nt][ft][i];
             red[red_b1(OT) + lane] = accB1;
-            red[red_cam(OT) + lane] = cam;
         }
         __syncthreads();
     }
-    // compact partial row: dW2 [O][32] | db2 [O] | dW1 [32][in_dim] | db1 [32] | dcam [3]
-    const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim);
+    if (threadIdx.x < 3 * a.views) {  // camera-centre sums in wave order
+        float c = camw[0][threadIdx.x];
+        for (int w = 1; w < kBwdWaves; ++w) c += camw[w][threadIdx.x];
+        red[red_cam(OT) + threadIdx.x] = c;
+    }
+    __syncthreads();
+    // compact partial row: dW2 [O][32] | db2 [O] | dW1 [32][in_dim] | db1 [32] | dcam [views][3]
+    const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim, a.views);
     const int oB2 = O * kF, oW1 = oB2 + O, oB1 = oW1 + kF * a.in_dim, oCam = oB1 + kF;
     for (int i = threadIdx.x; i < PF; i += blockDim.x) {
         int src;
@@ -688,7 +691,7 @@ void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, con
         default: break;
     }
 #undef VCGS_DEC_BWD
-    const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim);
+    const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim, a.views);
     k_decode_bwd_reduce<<<(unsigned)((PF + 63) / 64), 64 * kRedWaves, 0, s>>>(partial, nblocks, PF, a.k * 11, a.in_dim, out.W2,
                                                                    out.b2, out.W1, out.b1, out.cam);
 }

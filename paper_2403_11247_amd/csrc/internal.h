@@ -224,6 +224,8 @@ struct Options {
 Options& options();
 
 // decode.hip
+constexpr int kDecodeMaxViews = 16;  // camera centres per decode launch
+
 struct DecodeArgs {
     int64_t na;
     int k;
@@ -234,12 +236,13 @@ struct DecodeArgs {
     const int32_t* idx;
     const float* mask_logit;
     float mask_thr;  // keep iff logit > mask_thr
-    int in_dim;      // 32: feature input; 36: [feature, distance, direction] from the camera centre cam
-    float cam[3];
+    int in_dim;      // 32: feature input; 36: [feature, distance, direction] from the camera centres cam
+    int views;       // number of camera centres (1 without the view input); outputs and dG are stacked per view
+    float cam[kDecodeMaxViews][3];
 };
 void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hipStream_t s);
 int decode_bwd_blocks(int64_t na, int k);
-__host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim);
+__host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim, int views);
 void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, const vcgs_anchor_grads& out,
                        float* partial, int nblocks, hipStream_t s);
 

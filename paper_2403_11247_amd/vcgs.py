@@ -105,7 +105,8 @@ def lib():
                      "vcgs_server_submit", "vcgs_server_progress", "vcgs_server_stats_read",
                      "vcgs_decode_anchors_view", "vcgs_decode_anchors_view_backward", "vcgs_render_forward_hits",
                      "vcgs_mask_loss", "vcgs_mask_prune", "vcgs_rvq_assign", "vcgs_track_loss",
-                     "vcgs_icp_loss", "vcgs_ssim_loss", "vcgs_render_batch_hits", "vcgs_set_allocator"):
+                     "vcgs_icp_loss", "vcgs_ssim_loss", "vcgs_render_batch_hits", "vcgs_set_allocator",
+                     "vcgs_decode_anchors_views", "vcgs_decode_anchors_views_backward"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -452,6 +453,67 @@ def decode_anchors_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG, books
                                                        _stream()))
     del keep
     return out
+
+
+def _centres(cam_centres):
+    c = np.asarray(cam_centres, np.float64).reshape(-1, 3)
+    return len(c), (c_f * c.size)(*[float(x) for x in c.reshape(-1)])
+
+
+def decode_anchors_views(xa, feat, scaling, offset, W1, b1, W2, b2, cam_centres, books=None, idx=None,
+                         mask_logit=None, mask_eps=0.01, ctx: Context | None = None, out=None):
+    """View-dependent decode for V camera centres ((V, 3)) in one launch.
+    Returns the stacked per-view set: mean/scale/color (V, 3, n), quat (V, 4, n),
+    opacity (V, n); out: optional dict of such contiguous device tensors."""
+    ctx = ctx or default_context()
+    a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx, 36)
+    V, cc = _centres(cam_centres)
+    n = na * k
+    shapes = {"mean": (V, 3, n), "scale": (V, 3, n), "quat": (V, 4, n), "opacity": (V, n), "color": (V, 3, n)}
+    if out is None:
+        out = {f: torch.empty(sh, device=feat.device) for f, sh in shapes.items()}
+    elif not all(tuple(out[f].shape) == sh and out[f].is_contiguous() and out[f].is_cuda
+                 and out[f].dtype == torch.float32 for f, sh in shapes.items()):
+        raise VcgsError("decode_anchors_views: out tensors must be contiguous float32 device tensors (V, ., n)")
+    ob = CGaussianBuffers(*[_ptr(out[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
+    ml = None if mask_logit is None else _dev(mask_logit)
+    _check(lib().vcgs_decode_anchors_views(ctx.h, ctypes.byref(a), ctypes.byref(m), ctypes.byref(cb) if cb else None,
+                                           _ptr(ml), c_f(mask_eps), ctypes.c_int(V), cc, ctypes.byref(ob), _stream()))
+    del keep
+    return out
+
+
+def decode_anchors_views_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG, cam_centres, books=None, idx=None,
+                                  mask_logit=None, mask_eps=0.01, ctx: Context | None = None):
+    """Gradients of decode_anchors_views: dG maps each field to its stacked
+    (V, ., n) gradient.  Anchor, MLP, codebook and mask gradients are summed
+    over the views; "cam" is dL/d(camera centre) per view, (V, 3)."""
+    ctx = ctx or default_context()
+    a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx, 36)
+    V, cc = _centres(cam_centres)
+    dg = {f: None if dG.get(f) is None else _dev(dG[f]) for f in ("mean", "scale", "quat", "opacity", "color")}
+    gb = CGaussianBuffers(*[_ptr(dg[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
+    out = {"feat": torch.empty_like(keep[1]), "offset": torch.empty_like(keep[3]),
+           "scaling": torch.empty_like(keep[2]), "xa": torch.empty_like(keep[0]), "W1": torch.empty_like(keep[4]),
+           "b1": torch.empty_like(keep[5]), "W2": torch.empty_like(keep[6]), "b2": torch.empty_like(keep[7])}
+    out["books"] = torch.empty_like(keep[8]) if books is not None else None
+    ml = None if mask_logit is None else _dev(mask_logit)
+    out["mask_logit"] = torch.empty_like(ml) if ml is not None else None
+    out["cam"] = torch.empty((V, 3), device=keep[0].device)
+    ag = CAnchorGrads(*[_ptr(out[f]) for f in ("feat", "offset", "scaling", "xa", "W1", "b1", "W2", "b2", "books",
+                                                "mask_logit", "cam")])
+    _check(lib().vcgs_decode_anchors_views_backward(ctx.h, ctypes.byref(a), ctypes.byref(m),
+                                                    ctypes.byref(cb) if cb else None, _ptr(ml), c_f(mask_eps),
+                                                    ctypes.c_int(V), cc, ctypes.byref(gb), ctypes.byref(ag),
+                                                    _stream()))
+    del keep
+    return out
+
+
+def poses_grad_from_centres(poses, dcam):
+    """pose_grad_from_centre for V poses at once: dcam (V, 3) -> (V, 6)."""
+    R = torch.as_tensor(np.stack([np.asarray(p.R, np.float32) for p in poses]), device=dcam.device)
+    return torch.cat([-(R @ dcam.unsqueeze(-1)).squeeze(-1), torch.zeros_like(dcam)], dim=1)
 
 
 def mask_loss(mask_logit, in_frustum_count=None, weight=1.0, dl_dm=None, ctx: Context | None = None):

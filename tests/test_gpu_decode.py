@@ -168,3 +168,69 @@ def test_view_decode_pose_gradient_helper(V):
     d = np.array([0.3, -0.2, 0.9])
     g = pose_grad_from_centre(pose, dev(d)).cpu().numpy()
     np.testing.assert_allclose(g, odec.pose_grad_from_centre(pose.R, d), rtol=1e-5, atol=1e-6)
+
+
+def _centres(V_, seed):
+    rng = np.random.default_rng(seed)
+    return (CAM_C + rng.uniform(-0.6, 0.6, (V_, 3))).astype(np.float32)
+
+
+@pytest.mark.parametrize("na,k,nv,extras", [(300, 10, 3, False), (37, 10, 1, False), (45, 7, 16, False),
+                                            (200, 10, 4, True)])
+def test_decode_views_forward_and_backward(V, na, k, nv, extras):
+    """One launch for nv camera centres (a keyframe window): every view's block
+    equals the single-centre decode bit for bit and matches the oracle; the
+    backward's anchor, MLP, codebook and mask gradients match the oracle's sums
+    over the views, and its centre gradients match the oracle per view."""
+    a = scenes.room_anchors(na, k=k, seed=na + 11)
+    m = scenes.room_mlp_view(k=k, seed=7, view_gain=4.0)
+    n = a.n * a.k
+    books = idx = mask = None
+    if extras:
+        mask, books, idx = scenes.mask_and_codebook(n, size=64, mask_mu=0.0, mask_sigma=3.0)
+        thr = np.log(0.01 / 0.99)
+        mask[np.abs(mask - thr) < 1e-4] += 1e-3
+    cs = _centres(nv, na)
+    A = [dev(x) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    kw = dict(books=None if books is None else dev(books), idx=None if idx is None else dev(idx, torch.int32),
+              mask_logit=None if mask is None else dev(mask))
+    say("decode views na", na, "k", k, "views", nv, "codebook+mask", extras)
+    got = V.decode_anchors_views(*A, cs, **kw)
+    rng = np.random.default_rng(na)
+    dG = {"mean": rng.normal(size=(nv, 3, n)), "scale": rng.normal(size=(nv, 3, n)) * 10,
+          "quat": rng.normal(size=(nv, 4, n)), "opacity": rng.normal(size=(nv, n)),
+          "color": rng.normal(size=(nv, 3, n))}
+    dG = {kk: v.astype(np.float32) for kk, v in dG.items()}
+    gb = V.decode_anchors_views_backward(*A, {kk: dev(v) for kk, v in dG.items()}, cs, **kw)
+    torch.cuda.synchronize()
+    keys = ["feat", "W1", "b1", "W2", "b2", "offset", "scaling", "xa"] + (["books", "mask_logit"] if extras else [])
+    sums = None
+    for v in range(nv):
+        one = V.decode_anchors(*A, cam_centre=cs[v], **kw)
+        torch.cuda.synchronize()
+        for f in FIELDS:
+            assert torch.equal(got[f][v], one[f]), (v, f)
+        c64 = cs[v].astype(np.float64)
+        fwd = odec.decode(a, m, books, idx, mask, cam=c64)
+        check_decode({f: got[f][v] for f in FIELDS}, fwd)
+        ref = odec.decode_backward(a, m, fwd, {kk: x[v] for kk, x in dG.items()}, books, idx, mask, cam=c64)
+        if extras:
+            ref["books"] = np.stack(ref["books"])
+        e = rel_err(gb["cam"][v].cpu().numpy(), ref["cam"])
+        assert e <= DEC_GRAD_TOL, ("cam", v, e)
+        sums = {kk: np.asarray(ref[kk], np.float64) for kk in keys} if sums is None else \
+            {kk: sums[kk] + np.asarray(ref[kk], np.float64) for kk in keys}
+    for kk in keys:
+        e = rel_err(gb[kk].cpu().numpy().reshape(np.shape(sums[kk])), sums[kk])
+        say("decode views backward", kk, "rel err %.2e" % e)
+        assert e <= DEC_GRAD_TOL, (kk, e)
+
+
+def test_decode_views_limits(V):
+    a = scenes.room_anchors(40, k=10, seed=2)
+    m = scenes.room_mlp_view(k=10, seed=2)
+    A = [dev(x) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    with pytest.raises(V.VcgsError):
+        V.decode_anchors_views(*A, _centres(17, 1))
+    with pytest.raises(V.VcgsError):
+        V.decode_anchors_views(*A, np.zeros((0, 3), np.float32))
