@@ -499,6 +499,20 @@ int vcgs_decode_anchors_views_backward(vcgs_ctx* ctx, const vcgs_anchors* a, con
                                        int n_views, const float* cam_centres, const vcgs_gaussian_buffers* dG,
                                        vcgs_anchor_grads* out, void* stream);
 
+/* A novel-view server (vcgs_server_create) over the view-dependent decode of
+ * anchors (paper eqs. (8)-(9)):
+ * every pass decodes its requests' camera centres in one launch (as
+ * vcgs_decode_anchors_views; x_c = -R^T t computed in binary64 from the
+ * pose's values and rounded to binary32) into the slot's per-view sets, then
+ * renders each request from its own set.  A request's images equal
+ * vcgs_render_forward of vcgs_decode_anchors_view at that centre, bit for bit.
+ * a, mlp (W1 [32][36]), cb and mask_logit are kept (not copied) and must stay
+ * valid and unchanged while the server lives.  Per slot it adds 56 bytes per
+ * Gaussian per view of max_views for the decoded sets. */
+int vcgs_server_create_anchors(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
+                               const float* mask_logit, float mask_eps, const vcgs_server_config* cfg,
+                               vcgs_server** out);
+
 /* ---- kernel configuration ---------------------------------------------- */
 
 /* Process-wide settings read by every later launch (all contexts):

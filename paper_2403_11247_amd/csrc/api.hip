@@ -78,10 +78,11 @@ int vcgs_l1_loss(vcgs_ctx* ctx, const vcgs_images* img, const float* target_colo
     return VCGS_OK;
 }
 
-// cam: NULL, or views camera centres (host, [views][3]) for the view-dependent decode.
-static int make_decode_args(const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
-                            const float* mask_logit, float mask_eps, DecodeArgs* d, const float* cam = nullptr,
-                            int views = 1)
+}  // extern "C"
+
+namespace vcgs {
+int make_decode_args(const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb, const float* mask_logit,
+                     float mask_eps, DecodeArgs* d, const float* cam, int views)
 {
     if (views < 1 || views > kDecodeMaxViews || (!cam && views != 1))
         return fail(VCGS_E_INVALID, "views must be in [1, 16] (and 1 without camera centres)");
@@ -116,6 +117,9 @@ static int make_decode_args(const vcgs_anchors* a, const vcgs_mlp* mlp, const vc
     }
     return VCGS_OK;
 }
+}  // namespace vcgs
+
+extern "C" {
 
 static int decode_fwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
                       const float* mask_logit, float mask_eps, const float* cam, int views,

@@ -240,6 +240,10 @@ struct DecodeArgs {
     int views;       // number of camera centres (1 without the view input); outputs and dG are stacked per view
     float cam[kDecodeMaxViews][3];
 };
+// Validates the decode inputs and fills d.  cam: NULL, or `views` camera centres
+// (host, [views][3]) for the view-dependent decode.
+int make_decode_args(const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb, const float* mask_logit,
+                     float mask_eps, DecodeArgs* d, const float* cam = nullptr, int views = 1);
 void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hipStream_t s);
 int decode_bwd_blocks(int64_t na, int k);
 __host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim, int views);

@@ -6,6 +6,11 @@
 // projection / depth sort / tile sort / compositing as every other render
 // call, over the views of its requests (entry e = view e / n, Gaussian e % n),
 // so each request's images do not depend on what it was batched with.
+//
+// A server created from anchors serves the view-dependent decode (eqs.
+// (8)-(9)): a pass first decodes its requests' camera centres in one launch
+// into the slot's stacked per-view sets, then renders each request from its
+// own set (the per-view form of the same pass).
 #include <chrono>
 #include <cmath>
 #include <deque>
@@ -38,6 +43,7 @@ struct Slot {
     std::vector<Req> reqs;
     bool busy = false;
     std::vector<void*> blocks_e, blocks_p, blocks_r;
+    vcgs_gaussian_buffers set{};  // decoded per-view sets (servers created from anchors)
 };
 
 Prof& quiet_prof()
@@ -51,7 +57,9 @@ Prof& quiet_prof()
 struct vcgs_server {
     vcgs_ctx* ctx = nullptr;
     bool counted = false;  // included in ctx->servers
-    vcgs_gaussians map{};
+    vcgs_gaussians map{};  // the resident map; for a decoding server only n (Gaussians per view) is set
+    bool decode = false;   // created from anchors: each pass decodes its requests' camera centres
+    DecodeArgs dec{};
     vcgs_server_config cfg{};
     std::deque<Req> queue;
     std::vector<Slot> slots;
@@ -171,6 +179,23 @@ struct vcgs_server {
         }
         Frame& f = sl.f;
         build_tables(V, map.n, cams, poses, cfg.bg, f);
+        vcgs_gaussians g = map;
+        if (decode) {
+            // x_c = -R^T t in binary64 from the pose's values, rounded to binary32
+            dec.views = V;
+            for (int v = 0; v < V; ++v)
+                for (int i = 0; i < 3; ++i) {
+                    const float* R = poses[v].R;
+                    const float* t = poses[v].t;
+                    dec.cam[v][i] = (float)-((double)R[i] * t[0] + (double)R[3 + i] * t[1] + (double)R[6 + i] * t[2]);
+                }
+            g.mean = sl.set.mean;
+            g.scale = sl.set.scale;
+            g.quat = sl.set.quat;
+            g.opacity = sl.set.opacity;
+            g.color = sl.set.color;
+            f.pt.per_view = 1;
+        }
         for (int v = 0; v < V; ++v) {
             f.vt.color[v] = sl.reqs[v].out.color;
             f.vt.depth[v] = sl.reqs[v].out.depth;
@@ -185,7 +210,8 @@ struct vcgs_server {
         std::memcpy(sl.pt_host, &f.pt, sizeof(ProjTab));
         HIP_TRY(hipMemcpyAsync(f.pt_dev, sl.pt_host, sizeof(ProjTab), hipMemcpyHostToDevice, sl.s));
         if (f.E > 0) {
-            const uint32_t* ord = phase_a(quiet_prof(), map, f, sl.w, sl.s);
+            if (decode) launch_decode_fwd(dec, sl.set, sl.s);
+            const uint32_t* ord = phase_a(quiet_prof(), g, f, sl.w, sl.s);
             phase_b(quiet_prof(), f, sl.w, ord, sl.s);
             HIP_TRY(hipMemcpyAsync(sl.flags_host, sl.w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, sl.s));
             HIP_TRY(hipMemcpyAsync(sl.flags_host + 1, sl.w.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, sl.s));
@@ -256,23 +282,25 @@ struct vcgs_server {
 
 extern "C" {
 
-int vcgs_server_create(vcgs_ctx* ctx, const vcgs_gaussians* map, const vcgs_server_config* cfg, vcgs_server** out)
+}  // extern "C"
+
+namespace {
+
+// Shared by both constructors: dec is NULL for a resident map, else the
+// decode of the anchors behind map (only map->n is used then).
+int create_server(vcgs_ctx* ctx, const vcgs_gaussians* map, const DecodeArgs* dec, const vcgs_server_config* cfg,
+                  vcgs_server** out)
 {
-    if (!ctx || !cfg || !out) return fail(VCGS_E_INVALID, "ctx, cfg or out is NULL");
-    *out = nullptr;
-    int rc;
-    if (cfg->max_views < 1 || cfg->max_views > kMaxViews) return fail(VCGS_E_INVALID, "max_views must be in [1, 16]");
-    if (cfg->slots < 1 || cfg->slots > 8) return fail(VCGS_E_INVALID, "slots must be in [1, 8]");
-    if (cfg->pair_budget <= 0 || !(cfg->pairs_per_pixel > 0.0f))
-        return fail(VCGS_E_INVALID, "pair_budget and pairs_per_pixel must be positive");
-    if (cfg->pair_budget > kMaxSortItems) return fail(VCGS_E_UNSUPPORTED, "pair_budget above 2^30-1");
-    if ((rc = check_gaussians(map, cfg->max_views)) != VCGS_OK) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     vcgs_server* srv = new vcgs_server();
     srv->ctx = ctx;
     ++ctx->servers;
     srv->counted = true;
     srv->map = *map;
+    if (dec) {
+        srv->decode = true;
+        srv->dec = *dec;
+    }
     srv->cfg = *cfg;
     srv->ppp = cfg->pairs_per_pixel;
     srv->slots.resize(cfg->slots);
@@ -294,6 +322,13 @@ int vcgs_server_create(vcgs_ctx* ctx, const vcgs_gaussians* map, const vcgs_serv
         f.rect = static_cast<uint2*>(srv->dalloc((size_t)Emax * 8, sl.blocks_e));
         f.count = static_cast<uint32_t*>(srv->dalloc((size_t)Emax * 4, sl.blocks_e));
         alloc_work_e(sl.w, Emax, [&](int64_t c) { return static_cast<uint32_t*>(srv->dalloc((size_t)c * 4, sl.blocks_e)); });
+        if (dec) {  // stacked per-view sets: mean/scale/color [V][3][n], quat [V][4][n], opacity [V][n]
+            sl.set.mean = static_cast<float*>(srv->dalloc((size_t)Emax * 3 * 4, sl.blocks_e));
+            sl.set.scale = static_cast<float*>(srv->dalloc((size_t)Emax * 3 * 4, sl.blocks_e));
+            sl.set.quat = static_cast<float*>(srv->dalloc((size_t)Emax * 4 * 4, sl.blocks_e));
+            sl.set.opacity = static_cast<float*>(srv->dalloc((size_t)Emax * 4, sl.blocks_e));
+            sl.set.color = static_cast<float*>(srv->dalloc((size_t)Emax * 3 * 4, sl.blocks_e));
+        }
         if (srv->oom || srv->alloc_pairs(sl, cfg->pair_budget) != VCGS_OK || srv->alloc_ranges(sl, 4096) != VCGS_OK) {
             srv->release();
             delete srv;
@@ -302,6 +337,48 @@ int vcgs_server_create(vcgs_ctx* ctx, const vcgs_gaussians* map, const vcgs_serv
     }
     *out = srv;
     return VCGS_OK;
+}
+
+int check_config(const vcgs_server_config* cfg)
+{
+    if (cfg->max_views < 1 || cfg->max_views > kMaxViews) return fail(VCGS_E_INVALID, "max_views must be in [1, 16]");
+    if (cfg->slots < 1 || cfg->slots > 8) return fail(VCGS_E_INVALID, "slots must be in [1, 8]");
+    if (cfg->pair_budget <= 0 || !(cfg->pairs_per_pixel > 0.0f))
+        return fail(VCGS_E_INVALID, "pair_budget and pairs_per_pixel must be positive");
+    if (cfg->pair_budget > kMaxSortItems) return fail(VCGS_E_UNSUPPORTED, "pair_budget above 2^30-1");
+    return VCGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vcgs_server_create(vcgs_ctx* ctx, const vcgs_gaussians* map, const vcgs_server_config* cfg, vcgs_server** out)
+{
+    if (!ctx || !cfg || !out) return fail(VCGS_E_INVALID, "ctx, cfg or out is NULL");
+    *out = nullptr;
+    int rc;
+    if ((rc = check_config(cfg)) != VCGS_OK) return rc;
+    if ((rc = check_gaussians(map, cfg->max_views)) != VCGS_OK) return rc;
+    return create_server(ctx, map, nullptr, cfg, out);
+}
+
+int vcgs_server_create_anchors(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_codebook* cb,
+                               const float* mask_logit, float mask_eps, const vcgs_server_config* cfg,
+                               vcgs_server** out)
+{
+    if (!ctx || !cfg || !out) return fail(VCGS_E_INVALID, "ctx, cfg or out is NULL");
+    *out = nullptr;
+    int rc;
+    if ((rc = check_config(cfg)) != VCGS_OK) return rc;
+    DecodeArgs d;
+    const float origin[3] = {0.0f, 0.0f, 0.0f};  // placeholder centre: each pass sets its own
+    if ((rc = make_decode_args(a, mlp, cb, mask_logit, mask_eps, &d, origin, 1)) != VCGS_OK) return rc;
+    if (d.na * d.k * (int64_t)cfg->max_views > kMaxSortItems)
+        return fail(VCGS_E_UNSUPPORTED, "server: max_views x Gaussians above 2^30-1");
+    vcgs_gaussians map{};
+    map.n = d.na * d.k;
+    return create_server(ctx, &map, &d, cfg, out);
 }
 
 void vcgs_server_destroy(vcgs_server* srv)

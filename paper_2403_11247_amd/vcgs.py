@@ -106,7 +106,8 @@ def lib():
                      "vcgs_decode_anchors_view", "vcgs_decode_anchors_view_backward", "vcgs_render_forward_hits",
                      "vcgs_mask_loss", "vcgs_mask_prune", "vcgs_rvq_assign", "vcgs_track_loss",
                      "vcgs_icp_loss", "vcgs_ssim_loss", "vcgs_render_batch_hits", "vcgs_set_allocator",
-                     "vcgs_decode_anchors_views", "vcgs_decode_anchors_views_backward"):
+                     "vcgs_decode_anchors_views", "vcgs_decode_anchors_views_backward",
+                     "vcgs_server_create_anchors"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -775,17 +776,35 @@ class Server:
     tickets that completed."""
 
     def __init__(self, means, scales, quats, opacities, colors, max_views=16, slots=2, pair_budget=1 << 25,
-                 pairs_per_pixel=4.0, bg=(0.0, 0.0, 0.0), ctx=None):
+                 pairs_per_pixel=4.0, bg=(0.0, 0.0, 0.0), ctx=None, _anchors=None):
         self.ctx = ctx or default_context()
-        self._g, self._keep = _gauss(means, scales, quats, opacities, colors)
-        self.dev = self._keep[0].device
         cfg = CServerConfig(int(max_views), int(slots), int(pair_budget), float(pairs_per_pixel),
                             (c_f * 3)(*[float(b) for b in bg]))
         h = c_p()
-        _check(lib().vcgs_server_create(self.ctx.h, ctypes.byref(self._g), ctypes.byref(cfg), ctypes.byref(h)))
+        if _anchors is None:
+            self._g, self._keep = _gauss(means, scales, quats, opacities, colors)
+            _check(lib().vcgs_server_create(self.ctx.h, ctypes.byref(self._g), ctypes.byref(cfg), ctypes.byref(h)))
+        else:
+            a, m, cb, self._keep, ml, eps = _anchors
+            self._structs = (a, m, cb)
+            _check(lib().vcgs_server_create_anchors(self.ctx.h, ctypes.byref(a), ctypes.byref(m),
+                                                    ctypes.byref(cb) if cb else None, _ptr(ml), c_f(eps),
+                                                    ctypes.byref(cfg), ctypes.byref(h)))
+        self.dev = self._keep[0].device
         self.h = h
         self._outs = {}
         self._done = (c_i64 * 64)()
+
+    @classmethod
+    def from_anchors(cls, xa, feat, scaling, offset, W1, b1, W2, b2, books=None, idx=None, mask_logit=None,
+                     mask_eps=0.01, **kw):
+        """A server over the view-dependent decode (W1 (32, 36)): each request
+        is rendered from the anchors decoded at its own camera centre."""
+        a, m, cb, keep, _, _ = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx, 36)
+        ml = None if mask_logit is None else _dev(mask_logit)
+        if ml is not None:
+            keep.append(ml)
+        return cls(None, None, None, None, None, _anchors=(a, m, cb, keep, ml, mask_eps), **kw)
 
     def submit(self, camera, pose, out=None):
         H, W = int(camera.height), int(camera.width)

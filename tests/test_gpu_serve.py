@@ -107,3 +107,38 @@ def test_empty_map_gives_background(V):
     for ch, b in enumerate((0.25, 0.5, 1.0)):
         assert torch.all(C[ch] == b)
     assert torch.all(D == 0) and torch.all(A == 0)
+
+
+def test_view_dependent_server(V):
+    """A server over the view-dependent decode (eqs. (8)-(9)): each request is
+    the plain render of the anchors decoded at its own camera centre, bit for
+    bit, alone or batched with others, through admission limits and overflow
+    reruns; one request is checked against the render oracle on the decoded set."""
+    from tests.gpu_common import dev
+    a = scenes.room_anchors(3000, k=10, seed=4)
+    m = scenes.room_mlp_view(seed=4)
+    A = [dev(x) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    trace = scenes.serve_trace(12, qps=100.0, seed=24, sizes=SIZES)
+    ref, sets = [], []
+    for _, cam, pose in trace:
+        G = V.decode_anchors(*A, cam_centre=V.camera_centre(pose))
+        C, D, Al, _ = V.render_forward(*[G[f] for f in FIELDS], cam, pose, keep_state=False)
+        ref.append((C, D, Al))
+        sets.append(G)
+    torch.cuda.synchronize()
+    for cfg in (dict(max_views=16, slots=1, pair_budget=1 << 22, pairs_per_pixel=4.0),
+                dict(max_views=5, slots=2, pair_budget=1 << 22, pairs_per_pixel=4.0),
+                dict(max_views=8, slots=2, pair_budget=5000, pairs_per_pixel=0.01)):
+        srv = V.Server.from_anchors(*A, **cfg)
+        tickets = [srv.submit(cam, pose) for _, cam, pose in trace]
+        done = srv.drain(timeout_us=200)
+        st = srv.stats()
+        srv.close()
+        say("view-dependent serve", cfg, st)
+        assert sorted(done) == [t for t, _ in tickets]
+        assert_same([o for _, o in tickets], ref, cfg)
+    _, cam, pose = trace[0]
+    g = scenes.Gaussians(*[sets[0][f].cpu().numpy() for f in FIELDS])
+    r = compare_images(*ref[0], raster.render(g, cam, pose))
+    say("view-dependent served vs oracle colour %.2e depth %.2e flagged %d" % (r["color"], r["depth"], r["flagged"]))
+    assert r["pass_"], r
