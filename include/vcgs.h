@@ -552,6 +552,10 @@ enum {
 
 /* Turn per-stage event timing on (1) or off (0); turning it on clears the totals. */
 int vcgs_profile_enable(vcgs_ctx* ctx, int on);
+/* Stages that event timing covers while on: bit s = VCGS_STAGE s (default all).
+ * Each timed stage records two events per launch on the stream, which shows in
+ * the time between kernels; timing one stage keeps that cost to two events. */
+int vcgs_profile_stages(vcgs_ctx* ctx, uint32_t mask);
 /* Synchronises the recorded events and returns the summed duration (ms) and
  * the number of timed launches of `stage` since profiling was enabled. */
 int vcgs_profile_read(vcgs_ctx* ctx, int stage, double* total_ms, int64_t* launches);

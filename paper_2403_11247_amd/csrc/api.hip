@@ -298,6 +298,13 @@ int vcgs_profile_enable(vcgs_ctx* ctx, int on)
     return VCGS_OK;
 }
 
+int vcgs_profile_stages(vcgs_ctx* ctx, uint32_t mask)
+{
+    if (!ctx) return fail(VCGS_E_INVALID, "ctx is NULL");
+    ctx->prof.mask = mask;
+    return VCGS_OK;
+}
+
 int vcgs_profile_read(vcgs_ctx* ctx, int stage, double* total_ms, int64_t* launches)
 {
     if (!ctx || stage < 0 || stage >= VCGS_STAGE_COUNT) return fail(VCGS_E_INVALID, "bad ctx or stage");

@@ -146,6 +146,7 @@ struct Scratch {
 // Per-stage HIP-event timing on the caller's stream.
 struct Prof {
     bool on = false;
+    uint32_t mask = 0xFFFFu;  // stages timed while on (bit = stage)
     bool count = false;
     bool capturing = false;  // a graph is being captured: record nothing
     struct Rec {
@@ -171,7 +172,7 @@ struct Prof {
     }
     void begin(int stage, hipStream_t s)
     {
-        if (!on || capturing) return;
+        if (!on || capturing || !((mask >> stage) & 1u)) return;
         if (pending.size() > 8192) fold();
         Rec r{stage, event(), event()};
         if (r.a) (void)hipEventRecord(r.a, s);
@@ -179,7 +180,7 @@ struct Prof {
     }
     void end(int stage, hipStream_t s)
     {
-        if (!on || capturing) return;
+        if (!on || capturing || !((mask >> stage) & 1u)) return;
         for (auto it = pending.rbegin(); it != pending.rend(); ++it)
             if (it->stage == stage) {
                 if (it->b) (void)hipEventRecord(it->b, s);

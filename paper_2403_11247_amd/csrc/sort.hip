@@ -4,16 +4,15 @@
 // Sort: one launch per 8-bit digit pass (single sweep), after one histogram
 // launch for all passes:
 //   1. histogram: every digit of every pass counted over the whole input;
-//   2. per pass, each block takes the next 4096-item partition (the partition
+//   2. per pass, each block takes the next partition (2048 or 4096 items; the partition
 //      number comes from an atomic counter, so every lower partition is already
-//      running), ranks its items stably (each wave walks its 1024 items in
-//      order, 64 at a time, grouping equal digits with 8 ballots), publishes its
+//      running), ranks its items stably (each wave walks its quarter of the
+//      partition in order, 64 at a time, grouping equal digits with 8 ballots), publishes its
 //      digit counts, and looks back over the published counts of the lower
 //      partitions for its global offsets (decoupled look-back: a partition
 //      publishes its own counts before it waits on anyone, so the wait always
-//      ends; sixteen predecessors are read at a time); items are then staged in LDS in digit order and written out so
+//      ends; eight predecessors are read at a time); items are then staged in LDS in digit order and written out so
 //      that consecutive threads write consecutive addresses of a digit's run.
-#include "internal.h"
 #include "internal.h"
 
 namespace vcgs {
@@ -43,7 +42,16 @@ __device__ __forceinline__ uint64_t match8(uint32_t d, uint64_t active)
     return m;
 }
 
-int radix_blocks(int64_t n) { return (int)((n + kBlockItems - 1) / kBlockItems) > 0 ? (int)((n + kBlockItems - 1) / kBlockItems) : 1; }
+// Items per thread of a sort pass: small sorts (e.g. the depth sort over the
+// Gaussians) use 2048-item partitions, so that more partitions run at once;
+// large ones (the tile sort over the pairs) 4096.
+constexpr int64_t kSmallSort = 1 << 20;
+int sort_items(int64_t cap) { return cap <= kSmallSort ? 8 : 16; }
+int radix_blocks(int64_t cap)
+{
+    const int64_t part = (int64_t)kThreads * sort_items(cap);
+    return (int)std::max<int64_t>(1, (cap + part - 1) / part);
+}
 
 __device__ __forceinline__ int64_t dev_count(int64_t cap, const uint32_t* dev)
 {
@@ -188,7 +196,7 @@ __global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restri
                                                         const uint32_t* __restrict__ ndev, int passes,
                                                         uint32_t* __restrict__ ghist, int drop,
                                                         uint32_t* __restrict__ kept, uint32_t* __restrict__ state,
-                                                        int64_t state_stride)
+                                                        int64_t state_stride, int64_t part_items)
 {
     __shared__ uint32_t h[4][kMaxPasses][kBins];
     __shared__ uint32_t s_kept;
@@ -201,7 +209,7 @@ __global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restri
     // zero the passes' look-back words of the partitions they will use
     // (state_stride words per pass; the passes run after this kernel)
     {
-        const int64_t words = ((n + kBlockItems - 1) / kBlockItems) * kBins;
+        const int64_t words = ((n + part_items - 1) / part_items) * kBins;
         const int64_t gt = (int64_t)blockIdx.x * kThreads + threadIdx.x, gs = (int64_t)gridDim.x * kThreads;
         for (int p = 0; p < passes; ++p)
             for (int64_t i = gt; i < words; i += gs) state[(int64_t)p * state_stride + i] = 0u;
@@ -250,6 +258,7 @@ __global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restri
 // One digit pass.  ghist: this pass's 256 global counts in histogram copy 0
 // (the other copies follow at a stride of kMaxPasses * 256); state: this
 // pass's [partition][256] look-back words (zero on entry); counter: zero on entry.
+template <int ITEMS>
 __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restrict__ keys_in,
                                                         const uint32_t* __restrict__ vals_in,
                                                         uint32_t* __restrict__ keys_out,
@@ -258,8 +267,10 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
                                                         const uint32_t* __restrict__ ghist, uint32_t* state,
                                                         uint32_t* counter, int drop)
 {
-    __shared__ uint32_t s_key[kBlockItems];
-    __shared__ uint32_t s_val[kBlockItems];
+    constexpr int BI = kThreads * ITEMS;  // partition
+    constexpr int WI = BI / 4;            // per wave
+    __shared__ uint32_t s_key[BI];
+    __shared__ uint32_t s_val[BI];
     __shared__ uint32_t cnt[4][kBins];
     __shared__ uint32_t s_start[kBins];  // block-local first slot of each digit
     __shared__ uint32_t s_out[kBins];    // global position of that slot
@@ -273,7 +284,7 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
     for (int i = threadIdx.x; i < 4 * kBins; i += kThreads) (&cnt[0][0])[i] = 0u;
     __syncthreads();
     const uint32_t part = s_part;
-    const int64_t base = (int64_t)part * kBlockItems;
+    const int64_t base = (int64_t)part * BI;
     if (base >= n) return;  // every partition above this one is empty too
     // this digit's global count (thread t = digit t), loaded early so its latency overlaps the ranking
     uint32_t gcount = 0u;
@@ -281,11 +292,11 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
     for (int r = 0; r < kHistRep; ++r) gcount += ghist[(int64_t)r * kMaxPasses * kBins + threadIdx.x];
     const int w = threadIdx.x >> 6;
     const unsigned lane = __lane_id();
-    const int64_t wbase = base + (int64_t)w * kWaveItems;
+    const int64_t wbase = base + (int64_t)w * WI;
     const uint64_t lt = lanemask_lt();
-    uint32_t key[kItems], val[kItems], rank[kItems];
+    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
         const bool valid = idx < n;
         key[r] = valid ? keys_in[idx] : 0u;
@@ -293,7 +304,7 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
     }
     // stable rank of every item among the wave's items of its digit
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const bool valid = wbase + r * 64 + lane < n && !(drop && key[r] == kDropKey);
         const uint64_t active = __ballot(valid);
         rank[r] = 0u;
@@ -317,10 +328,10 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
     uint32_t tot;
     const uint32_t start = block_excl_scan(bc, &tot);
     // look back: sum this digit's counts over all lower partitions, reading
-    // sixteen predecessors at a time (their loads are in flight together)
+    // eight predecessors at a time (their loads are in flight together)
     uint32_t excl = 0u;
     if (part > 0) {
-        constexpr int kWin = 16;
+        constexpr int kWin = 8;
         int64_t q = (int64_t)part - 1;
         while (q >= 0) {  // partition 0 publishes an inclusive count, so this ends there at the latest
             uint32_t v[kWin];
@@ -350,7 +361,7 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
     __syncthreads();
     // stage in digit order, then write runs out with consecutive addresses
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         if (wbase + r * 64 + lane < n && !(drop && key[r] == kDropKey)) {
             const uint32_t dd = (key[r] >> shift) & 0xFFu;
             const uint32_t li = s_start[dd] + cnt[w][dd] + rank[r];
@@ -377,6 +388,7 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, 
     if (n.cap <= 0) return 0;
     if (n.cap > (int64_t)kCountMask) return -1;  // counts share a word with the look-back flags
     const int nb = radix_blocks(n.cap);
+    const int items = sort_items(n.cap);
     const int passes = std::min(kMaxPasses, (end_bit + 7) / 8);
     uint32_t* ghist = t.hist;
     uint32_t* counters = t.hist + kHistWords;
@@ -388,17 +400,17 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, 
     const int pb = std::min(nb, 2048);
     const uint32_t* first = keys_src ? keys_src : keys;
     k_sort_hist<<<hb, kThreads, 0, s>>>(first, n.cap, n.dev, passes, ghist, drop, kept_dev, state,
-                                        (int64_t)nb * kBins);
+                                        (int64_t)nb * kBins, (int64_t)kThreads * items);
     uint32_t* kb[2] = {keys, t.keys_alt};
     uint32_t* vb[2] = {vals, t.vals_alt};
     int cur = 0;
     for (int p = 0; p < passes; ++p) {
         // after a dropping first pass the later ones see only the kept items
         const uint32_t* nd = (p > 0 && drop) ? kept_dev : n.dev;
-        k_sort_pass<<<pb, kThreads, 0, s>>>(p == 0 ? first : kb[cur], identity_vals ? nullptr : vb[cur],
-                                            kb[cur ^ 1], vb[cur ^ 1],
-                                            n.cap, nd, 8 * p, ghist + p * kBins,
-                                            state + (int64_t)p * nb * kBins, counters + p, p == 0 ? drop : 0);
+        auto pass = items == 8 ? k_sort_pass<8> : k_sort_pass<16>;
+        pass<<<pb, kThreads, 0, s>>>(p == 0 ? first : kb[cur], identity_vals ? nullptr : vb[cur], kb[cur ^ 1],
+                                     vb[cur ^ 1], n.cap, nd, 8 * p, ghist + p * kBins,
+                                     state + (int64_t)p * nb * kBins, counters + p, p == 0 ? drop : 0);
         identity_vals = false;
         cur ^= 1;
     }

@@ -61,10 +61,12 @@ def replay(server: "vcgs.Server", trace, poll_us=200):
     return out
 
 
-def replay_plain(gauss, trace):
+def replay_plain(gauss, trace, anchors=None):
     """FIFO baseline: one request at a time with the plain forward render
     (which sizes its pair buffers with one synchronisation) and a wait for its
-    completion before the next starts."""
+    completion before the next starts.  With anchors (the decode inputs, W1
+    (32, 36)) each request first decodes the map at its own camera centre and
+    gauss is ignored."""
     n = len(trace)
     lat = [0.0] * n
     pixels = sum(int(c.width) * int(c.height) for _, c, _ in trace)
@@ -73,6 +75,9 @@ def replay_plain(gauss, trace):
     for j, (arr, cam, pose) in enumerate(trace):
         while time.perf_counter() - t0 < arr:
             pass
+        if anchors is not None:
+            G = vcgs.decode_anchors(*anchors, cam_centre=vcgs.camera_centre(pose))
+            gauss = [G[f] for f in ("mean", "scale", "quat", "opacity", "color")]
         vcgs.render_forward(*gauss, cam, pose, keep_state=False)
         torch.cuda.synchronize()
         t_last = time.perf_counter() - t0

@@ -107,7 +107,7 @@ def lib():
                      "vcgs_mask_loss", "vcgs_mask_prune", "vcgs_rvq_assign", "vcgs_track_loss",
                      "vcgs_icp_loss", "vcgs_ssim_loss", "vcgs_render_batch_hits", "vcgs_set_allocator",
                      "vcgs_decode_anchors_views", "vcgs_decode_anchors_views_backward",
-                     "vcgs_server_create_anchors"):
+                     "vcgs_server_create_anchors", "vcgs_profile_stages"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -631,6 +631,13 @@ def profile_enable(on=True, ctx: Context | None = None):
     """Per-stage HIP-event timing on the current stream (clears the totals)."""
     ctx = ctx or default_context()
     _check(lib().vcgs_profile_enable(ctx.h, c_i32(1 if on else 0)))
+
+
+def profile_stages(stages=None, ctx: Context | None = None):
+    """Restricts event timing to the named stages (None: all)."""
+    ctx = ctx or default_context()
+    mask = 0xFFFF if stages is None else sum(1 << STAGES.index(s) for s in stages)
+    _check(lib().vcgs_profile_stages(ctx.h, ctypes.c_uint32(mask)))
 
 
 def profile_read(ctx: Context | None = None) -> dict:
