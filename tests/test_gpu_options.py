@@ -1,7 +1,8 @@
 """Every launch configuration the autotuner may pick (pixels per lane of the
 forward and backward compositing, culling, block order) gives the same
 images bit for bit and the same gradients up to summation order (1e-5
-relative), on a ragged image whose tiles have long lists."""
+relative), on a ragged image whose tiles have long lists; the stage-timing
+mask times only the selected stages."""
 import numpy as np
 import pytest
 import torch
@@ -52,3 +53,36 @@ def test_all_launch_configurations_agree(V):
         say("launch configurations checked:", n)
     finally:
         autotune.apply(saved)
+
+
+def test_stage_timing_mask(V):
+    """vcgs_profile_stages: with one stage selected only that stage records
+    launches; the default times every stage of a forward + backward."""
+    g = scenes.random_scene(3000, seed=5)
+    gd = gauss_dev(g)
+    cam = scenes.Camera(128, 96, 100.0, 100.0, 64.0, 48.0)
+    pose = scenes.identity_pose()
+    up = [dev(x) for x in scenes.upstream_grads(cam.width, cam.height, seed=2)]
+
+    def step():
+        _, _, _, st = V.render_forward(*gd, cam, pose)
+        V.render_backward(st, *gd, cam, pose, *up)
+        st.free()
+
+    try:
+        V.profile_stages(["composite_bwd"])
+        V.profile_enable(True)
+        step()
+        step()
+        prof = V.profile_read()
+        assert prof["composite_bwd"][1] == 2 and prof["composite_bwd"][0] > 0
+        assert all(n == 0 for k, (_, n) in prof.items() if k != "composite_bwd")
+        V.profile_stages(None)
+        V.profile_enable(True)
+        step()
+        prof = V.profile_read()
+        for k in ("preprocess", "depth_sort", "tile_sort", "composite", "composite_bwd", "preprocess_bwd"):
+            assert prof[k][1] >= 1, k
+    finally:
+        V.profile_enable(False)
+        V.profile_stages(None)
