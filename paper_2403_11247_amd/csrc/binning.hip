@@ -64,7 +64,8 @@ void launch_gather_counts(int64_t n, const uint32_t* order, const uint32_t* coun
 // Pair emission, balanced over the output: block c writes pairs
 // [c * kChunk, (c + 1) * kChunk).  k_chunk_starts records, for every chunk, the
 // depth-ordered entry that owns its first pair; the block then stages the
-// entries from there (offsets, Gaussian ids, rectangles) in LDS, and its
+// entries from there up to the owner of the next chunk's first pair (offsets,
+// Gaussian ids, rectangles) in LDS, and its
 // threads stride over the chunk's pairs (coalesced stores), locating each
 // pair's owner by binary search over the staged offsets.  Entry e belongs to
 // view e / n, and its pairs carry that view's global tile ids, row-major
@@ -106,9 +107,11 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
     const int64_t p0 = c * kChunk;
     const int64_t p1 = min(p0 + kChunk, P);
     int64_t kbase = chunk_start[c];
+    // the chunk's pairs belong to entries up to the one owning the next chunk's first pair
+    const int64_t kend = p1 < P ? min((int64_t)chunk_start[c + 1] + 1, n) : n;
     int64_t pcur = p0;
-    while (pcur < p1 && kbase < n) {  // uniform; every round consumes kSpan entries or ends the chunk
-        const int S = (int)min((int64_t)kSpan, n - kbase);
+    while (pcur < p1 && kbase < kend) {  // uniform; every round consumes kSpan entries or ends the chunk
+        const int S = (int)min((int64_t)kSpan, kend - kbase);
         for (int i = threadIdx.x; i < S; i += kEmitG) {
             const uint32_t g = order[kbase + i];
             s_gid[i] = g;
