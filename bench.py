@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving replay")
     ap.add_argument("--serve-requests", type=int, default=400, help="requests per arrival rate")
     ap.add_argument("--serve-qps", type=str, default="50,100,200,400")
-    ap.add_argument("--only", choices=("main", "ba", "ba_view", "serve", "view", "mask", "rvq", "track"), default=None,
+    ap.add_argument("--only", choices=("main", "ba", "ba_view", "serve", "view", "mask", "codebook", "rvq", "track"),
+                    default=None,
                     help="run one section only (for profiling)")
     return ap.parse_args()
 
@@ -375,6 +376,54 @@ def mask_step_section(args, dev, steps=20, warmup=5, lam=5e-4):
             "prune_ms": round(ms_prune, 4), "kept": int(idx.numel()), "n": n}
 
 
+def codebook_section(args, dev, steps=20, warmup=5):
+    """The compacted room (mask + residual codebooks, Sec. 3.3-3.4): 2-stage
+    residual k-means codebooks of 4096 x 7 fit to the room's decoded
+    (log-scale, quaternion), mask logits N(2, 1); the render against the
+    unquantized one (PSNR), and the room step with codebook and mask gradients."""
+    import torch
+    from paper_2403_11247_amd import codebook_fit, scenes, vcgs
+    a = scenes.room_anchors(40000, k=10)
+    m = scenes.room_mlp(seed=0)
+    n = a.xa.shape[1] * 10
+    cam, pose = scenes.room_camera()
+    tpose = scenes.perturb_pose(pose, 2)
+    A = [_up(x, dev) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    G0 = vcgs.decode_anchors(*A)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    books, idx = codebook_fit.residual_kmeans(codebook_fit.shape_vectors(G0), stages=2, size=4096, iters=10)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    mask, _, _ = scenes.mask_and_codebook(n)
+    ml = _up(mask, dev)
+    kw = dict(books=books, idx=idx, mask_logit=ml)
+    Gq = vcgs.decode_anchors(*A, **kw)
+    C0, D0, _, _ = vcgs.render_forward(*[G0[f] for f in F], cam, pose, keep_state=False)
+    Cq, Dq, _, _ = vcgs.render_forward(*[Gq[f] for f in F], cam, pose, keep_state=False)
+    tC, tD, _, _ = vcgs.render_forward(*[Gq[f] for f in F], cam, tpose, keep_state=False)
+    torch.cuda.synchronize()
+    psnr = codebook_fit.psnr(Cq.clamp(0, 1), C0.clamp(0, 1))
+    depth_mae = float((Dq - D0).abs().mean())
+
+    def step():
+        G = vcgs.decode_anchors(*A, **kw)
+        C, D, _, st = vcgs.render_forward(*[G[f] for f in F], cam, pose)
+        _, dlc, dld = vcgs.l1_loss(C, D, tC, tD, 0.5)
+        grads, dpose = vcgs.render_backward(st, *[G[f] for f in F], cam, pose, dlc, dld, None)
+        ag = vcgs.decode_anchors_backward(*A, grads, **kw)
+        st.free()
+        return dpose, ag
+
+    ms = _timed(step, steps, warmup)
+    return {"workload": "room 40k anchors x 10 with mask logits N(2,1) and 2-stage residual k-means codebooks "
+                        "4096 x 7 (10 Lloyd iterations) for log-scale and rotation; fwd + L1 + bwd incl. codebook "
+                        "(straight-through) and mask gradients, 1200x680",
+            "ms_per_step": round(ms, 4), "mpix_s": round(cam.width * cam.height / (ms * 1e-3) / 1e6, 2),
+            "psnr_vs_unquantized_db": round(psnr, 2), "depth_mae_m": round(depth_mae, 5),
+            "codebook_fit_s": round(fit_s, 2), "gaussians": n}
+
+
 def rvq_section(args, dev, steps=50, warmup=5):
     """Residual vector quantization (eqs. (14)-(15)) of the room map's
     attributes: assignment, reconstruction, loss and code gradient in one call.
@@ -530,10 +579,10 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    if args.only in ("ba", "ba_view", "serve", "view", "mask", "rvq", "track"):
+    if args.only in ("ba", "ba_view", "serve", "view", "mask", "codebook", "rvq", "track"):
         res = {"ba": ba_section, "serve": serve_section, "view": view_decode_section,
                "mask": mask_step_section, "rvq": rvq_section, "track": track_section,
-               "ba_view": ba_view_section}[args.only](args, dev)
+               "ba_view": ba_view_section, "codebook": codebook_section}[args.only](args, dev)
         print(json.dumps({args.only: res}), flush=True)
         return
     if args.only == "main":
@@ -672,6 +721,7 @@ def main():
     if args.only != "main":
         out["view_decode_step"] = view_decode_section(args, dev)
         out["mask_step"] = mask_step_section(args, dev)
+        out["codebook_step"] = codebook_section(args, dev)
         out["rvq"] = rvq_section(args, dev)
         out["tracking"] = track_section(args, dev)
     if not args.no_ba:

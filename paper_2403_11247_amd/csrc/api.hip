@@ -158,9 +158,15 @@ static int decode_bwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
     Scratch sc(&ctx->pool);
     const int nb = decode_bwd_blocks(d.na, d.k);
     float* partial = sc.get<float>((int64_t)nb * decode_bwd_partial_floats(d.k, d.in_dim, d.views));
+    float *dvbuf = nullptr, *book_partial = nullptr;
+    if (o.books && (size_t)d.cb_size * 7 * sizeof(float) <= kBookLdsMax) {
+        const int64_t ng = d.na * d.k;
+        dvbuf = sc.get<float>(ng * 8);
+        book_partial = sc.get<float>((int64_t)books_grad_blocks(ng) * d.stages * d.cb_size * 7);
+    }
     if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (decode backward)");
     ctx->prof.begin(VCGS_STAGE_DECODE_BWD, s);
-    launch_decode_bwd(d, *dG, o, partial, nb, s);
+    launch_decode_bwd(d, *dG, o, partial, nb, dvbuf, book_partial, s);
     ctx->prof.end(VCGS_STAGE_DECODE_BWD, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));

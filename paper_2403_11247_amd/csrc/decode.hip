@@ -298,7 +298,8 @@ int decode_bwd_blocks(int64_t na, int k)
 
 template <int OT>
 __global__ void __launch_bounds__(64 * kBwdWaves, 2) k_decode_bwd(DecodeArgs a, vcgs_gaussian_buffers dG,
-                                                               vcgs_anchor_grads out, float* __restrict__ partial)
+                                                               vcgs_anchor_grads out, float* __restrict__ partial,
+                                                               float* __restrict__ dvbuf)
 {
     // Each wave's [16 anchors][k * 11] outputs y are overwritten in place by
     // dL/dy (every slot is read before it is written, by the same lane); the
@@ -452,7 +453,10 @@ __global__ void __launch_bounds__(64 * kBwdWaves, 2) k_decode_bwd(DecodeArgs a, 
                 if (a.books) {
 #pragma unroll
                     for (int i = 0; i < 7; ++i) dy[4 + i] = 0.0f;
-                    if (out.books) {
+                    if (out.books && dvbuf) {  // per-Gaussian rows, summed per code by k_books_partial
+#pragma unroll
+                        for (int i = 0; i < 7; ++i) put(dvbuf + g * 8 + i, first, dv[i]);
+                    } else if (out.books) {
                         for (int s = 0; s < a.stages; ++s) {
                             float* row = out.books + ((int64_t)s * a.cb_size + code_index(a, s, n, g)) * 7;
 #pragma unroll
@@ -676,14 +680,83 @@ __global__ void __launch_bounds__(64 * kRedWaves) k_decode_bwd_reduce(const floa
     else { if (dcam && in_dim > kF) dcam[i - oB1] = s; }
 }
 
+// ---------------------------------------------------------------------------
+// Codebook gradient (straight-through sums of eq. (14)'s gathered rows)
+// ---------------------------------------------------------------------------
+// Each of 8192 rows of a 2 x 4096 codebook is shared by ~100 Gaussians of the
+// room, so adding every Gaussian's 7 values to its rows with device atomics
+// contends (0.32 ms of the room's decode backward).  Instead the backward
+// stores each Gaussian's 7 values; every block then adds its share of the
+// Gaussians into a stage's whole table in LDS (low contention: the rows are
+// spread) and writes that table as its partial, and the partials are summed
+// in block order.
+constexpr int kBookThreads = 1024;
+constexpr int kBookMaxBlocks = 256;
+
+int books_grad_blocks(int64_t n)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, kBookMaxBlocks));
+}
+
+__global__ void __launch_bounds__(kBookThreads) k_books_partial(DecodeArgs a, const float* __restrict__ dv,
+                                                                float* __restrict__ partial)
+{
+    extern __shared__ float tab[];  // cb_size * 7
+    const int64_t n = a.na * a.k;
+    const int rows7 = a.cb_size * 7;
+    for (int s = 0; s < a.stages; ++s) {
+        for (int i = threadIdx.x; i < rows7; i += blockDim.x) tab[i] = 0.0f;
+        __syncthreads();
+        for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+            float* row = tab + code_index(a, s, n, g) * 7;
+            const float4 v0 = *reinterpret_cast<const float4*>(dv + g * 8);
+            const float4 v1 = *reinterpret_cast<const float4*>(dv + g * 8 + 4);
+            atomicAdd(row + 0, v0.x); atomicAdd(row + 1, v0.y); atomicAdd(row + 2, v0.z); atomicAdd(row + 3, v0.w);
+            atomicAdd(row + 4, v1.x); atomicAdd(row + 5, v1.y); atomicAdd(row + 6, v1.z);
+        }
+        __syncthreads();
+        float* out = partial + ((int64_t)blockIdx.x * a.stages + s) * rows7;
+        for (int i = threadIdx.x; i < rows7; i += blockDim.x) out[i] = tab[i];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_books_reduce(const float* __restrict__ partial, int nblocks, int64_t per,
+                                                      float* __restrict__ books_grad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= per) return;
+    float sacc = 0.0f;
+    for (int b = 0; b < nblocks; ++b) sacc += partial[(int64_t)b * per + i];
+    books_grad[i] = sacc;
+}
+
+// LDS bytes of k_books_partial's table; 0 when a codebook stage does not fit
+// (the backward then adds to the rows with device atomics).
+size_t books_lds_bytes(int cb_size)
+{
+    static int state[64] = {};  // per device: 0 unknown, 1 allowed, -1 refused
+    const size_t bytes = (size_t)cb_size * 7 * sizeof(float);
+    if (bytes > kBookLdsMax) return 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (state[dev] == 0)
+        state[dev] = hipFuncSetAttribute((const void*)k_books_partial, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)kBookLdsMax) == hipSuccess ? 1 : -1;
+    return state[dev] > 0 ? bytes : 0;
+}
+
 void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, const vcgs_anchor_grads& out,
-                       float* partial, int nblocks, hipStream_t s)
+                       float* partial, int nblocks, float* dvbuf, float* book_partial, hipStream_t s)
 {
     if (a.na <= 0) return;
-    if (out.books && a.books) launch_fill_f32(out.books, 0.0f, (int64_t)a.stages * a.cb_size * 7, s);
+    const bool books = out.books && a.books;
+    const size_t lds = books && dvbuf && book_partial ? books_lds_bytes(a.cb_size) : 0;
+    if (!lds) dvbuf = nullptr;
+    if (books && !lds) launch_fill_f32(out.books, 0.0f, (int64_t)a.stages * a.cb_size * 7, s);
 #define VCGS_DEC_BWD(OT)                                                                           \
     case OT:                                                                                       \
-        k_decode_bwd<OT><<<nblocks, 64 * kBwdWaves, 0, s>>>(a, dG, out, partial);                  \
+        k_decode_bwd<OT><<<nblocks, 64 * kBwdWaves, 0, s>>>(a, dG, out, partial, dvbuf);           \
         break;
     switch (out_tiles(a.k)) {
         VCGS_DEC_BWD(1) VCGS_DEC_BWD(2) VCGS_DEC_BWD(3) VCGS_DEC_BWD(4) VCGS_DEC_BWD(5) VCGS_DEC_BWD(6)
@@ -694,6 +767,12 @@ void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, con
     const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim, a.views);
     k_decode_bwd_reduce<<<(unsigned)((PF + 63) / 64), 64 * kRedWaves, 0, s>>>(partial, nblocks, PF, a.k * 11, a.in_dim, out.W2,
                                                                    out.b2, out.W1, out.b1, out.cam);
+    if (lds) {
+        const int nbk = books_grad_blocks(a.na * a.k);
+        const int64_t per = (int64_t)a.stages * a.cb_size * 7;
+        k_books_partial<<<nbk, kBookThreads, lds, s>>>(a, dvbuf, book_partial);
+        k_books_reduce<<<(unsigned)((per + 255) / 256), 256, 0, s>>>(book_partial, nbk, per, out.books);
+    }
 }
 
 }  // namespace vcgs

@@ -247,7 +247,11 @@ int make_decode_args(const vcgs_anchors* a, const vcgs_mlp* mlp, const vcgs_code
 void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hipStream_t s);
 int decode_bwd_blocks(int64_t na, int k);
 __host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim, int views);
+// dvbuf: na*k*8 floats and book_partial: books_grad_blocks(na*k) * stages * cb_size * 7
+// floats of scratch for the codebook gradient (NULL: device atomics on the rows).
 void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, const vcgs_anchor_grads& out,
-                       float* partial, int nblocks, hipStream_t s);
+                       float* partial, int nblocks, float* dvbuf, float* book_partial, hipStream_t s);
+int books_grad_blocks(int64_t n);
+constexpr size_t kBookLdsMax = 150 * 1024;  // largest codebook stage table summed in LDS
 
 }  // namespace vcgs
