@@ -154,7 +154,18 @@ static int decode_bwd(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_mlp* mlp,
     if (!cb) o.books = nullptr;
     if (!mask_logit) o.mask_logit = nullptr;
     if (!cam) o.cam = nullptr;
-    if (d.na == 0) return VCGS_OK;
+    if (d.na == 0) {  // no anchors: the weight, codebook and centre gradients are zero
+        const int O = d.k * 11;
+        if (o.W1) launch_fill_f32(o.W1, 0.0f, 32 * d.in_dim, s);
+        if (o.b1) launch_fill_f32(o.b1, 0.0f, 32, s);
+        if (o.W2) launch_fill_f32(o.W2, 0.0f, (int64_t)O * 32, s);
+        if (o.b2) launch_fill_f32(o.b2, 0.0f, O, s);
+        if (o.books) launch_fill_f32(o.books, 0.0f, (int64_t)d.stages * d.cb_size * 7, s);
+        if (o.cam) launch_fill_f32(o.cam, 0.0f, 3 * d.views, s);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+        return VCGS_OK;
+    }
     Scratch sc(&ctx->pool);
     const int nb = decode_bwd_blocks(d.na, d.k);
     float* partial = sc.get<float>((int64_t)nb * decode_bwd_partial_floats(d.k, d.in_dim, d.views));

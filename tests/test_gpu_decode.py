@@ -234,3 +234,27 @@ def test_decode_views_limits(V):
         V.decode_anchors_views(*A, _centres(17, 1))
     with pytest.raises(V.VcgsError):
         V.decode_anchors_views(*A, np.zeros((0, 3), np.float32))
+
+
+def test_decode_with_no_anchors(V):
+    """An empty anchor set decodes to empty sets, and every backward form
+    returns zero weight and camera-centre gradients (not uninitialised memory)."""
+    m = scenes.room_mlp(seed=1)
+    mv = scenes.room_mlp_view(seed=1)
+    empty = [torch.zeros((3, 0), device="cuda"), torch.zeros((0, 32), device="cuda"),
+             torch.zeros((3, 0), device="cuda"), torch.zeros((0, 10, 3), device="cuda")]
+    for mm, kw in ((m, {}), (mv, {"cam_centre": CAM_C})):
+        A = empty + [dev(x) for x in (mm.W1, mm.b1, mm.W2, mm.b2)]
+        G = V.decode_anchors(*A, **kw)
+        assert all(G[f].numel() == 0 for f in FIELDS)
+        ag = V.decode_anchors_backward(*A, G, **kw)
+        torch.cuda.synchronize()
+        for k in ("W1", "b1", "W2", "b2") + (("cam",) if kw else ()):
+            assert bool((ag[k] == 0).all()), k
+    A = empty + [dev(x) for x in (mv.W1, mv.b1, mv.W2, mv.b2)]
+    cs = _centres(3, 5)
+    Gs = V.decode_anchors_views(*A, cs)
+    ag = V.decode_anchors_views_backward(*A, Gs, cs)
+    torch.cuda.synchronize()
+    for k in ("W1", "b1", "W2", "b2", "cam"):
+        assert bool((ag[k] == 0).all()), k
