@@ -72,10 +72,19 @@ def test_empty_and_all_culled(V):
     g0 = scenes.random_scene(0, seed=0)
     gd, C, D, A, st = run_fwd(V, g0, cam, scenes.identity_pose(), (0.2, 0.4, 0.6))
     assert torch.all(C[1] == np.float32(0.4)) and torch.all(A == 0) and torch.all(D == 0)
+    up0 = [dev(x) for x in scenes.upstream_grads(cam.width, cam.height, seed=4)]
+    _, dpose0 = V.render_backward(st, *gd, cam, scenes.identity_pose(), *up0)
+    torch.cuda.synchronize()
+    assert bool((dpose0 == 0).all())
     g = scenes.random_scene(100, seed=0)
     g.mean[2] = -1.0  # all behind the camera
     gd, C, D, A, st = run_fwd(V, g, cam, scenes.identity_pose(), (0.2, 0.4, 0.6))
     assert st.view()["n_pairs"] == 0 and torch.all(A == 0)
+    # the backward of a map nothing of which is drawn: zero gradients, zero pose gradient
+    up = [dev(x) for x in scenes.upstream_grads(cam.width, cam.height, seed=3)]
+    grads, dpose = V.render_backward(st, *gd, cam, scenes.identity_pose(), *up)
+    torch.cuda.synchronize()
+    assert all(bool((grads[k] == 0).all()) for k in FIELDS) and bool((dpose == 0).all())
 
 
 def test_depth_ties_keep_index_order(V):
