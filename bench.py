@@ -269,7 +269,7 @@ def ba_view_section(args, dev):
         vcgs.decode_anchors_views(*A, centres, out=stacked)
         win.run(*[stacked[f] for f in F], poses, targets)
         ag = vcgs.decode_anchors_views_backward(*A, win.grads, centres)
-        got["dpose"] = win.dpose + vcgs.poses_grad_from_centres(poses, ag["cam"])
+        got["dpose"] = vcgs.add_centre_pose_grad(poses, ag["cam"], win.dpose)
         got["W1"] = ag["W1"]
 
     ref = {"dpose": torch.empty((V, 6), device=dev)}
@@ -283,7 +283,8 @@ def ba_view_section(args, dev):
             _, dlc, dld = vcgs.l1_loss(C, D, tg[0], tg[1], 0.5)
             gr, dp = vcgs.render_backward(st, *gs, c, p, dlc, dld, None)
             ag = vcgs.decode_anchors_backward(*A, gr, cam_centre=centres[v])
-            ref["dpose"][v].copy_(dp + vcgs.pose_grad_from_centre(p, ag["cam"]))
+            vcgs.add_centre_pose_grad([p], ag["cam"].reshape(1, 3), dp.reshape(1, 6))
+            ref["dpose"][v].copy_(dp)
             dW1 = ag["W1"] if dW1 is None else dW1 + ag["W1"]
             st.free()
         ref["W1"] = dW1
@@ -330,7 +331,7 @@ def view_decode_section(args, dev, steps=20, warmup=5):
         grads, dpose = vcgs.render_backward(st, *[G[f] for f in F], cam, pose, dlc, dld, None)
         ag = vcgs.decode_anchors_backward(*A, grads, cam_centre=c_now)
         st.free()
-        return dpose + vcgs.pose_grad_from_centre(pose, ag["cam"])
+        return vcgs.add_centre_pose_grad([pose], ag["cam"].reshape(1, 3), dpose.reshape(1, 6))
 
     ms = _timed(step, steps, warmup)
     return {"workload": "room step with the view-dependent decode (36-d MLP input), pose gradient through "

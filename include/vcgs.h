@@ -499,6 +499,16 @@ int vcgs_decode_anchors_views_backward(vcgs_ctx* ctx, const vcgs_anchors* a, con
                                        int n_views, const float* cam_centres, const vcgs_gaussian_buffers* dG,
                                        vcgs_anchor_grads* out, void* stream);
 
+/* The pose's share of the camera-centre input of the view-dependent decode
+ * (paper eq. (9)): for a world-to-camera pose {R|t} the centre -R^T t moves by
+ * -R^T rho under the left perturbation, so dpose[v] (device, 6 floats per
+ * view: rho, phi) gets -R_v dcam[v] ADDED to its rho part (phi unchanged).
+ * poses: host, n_views of them (R is passed with the launch, no copy);
+ * dcam: device [n_views][3], e.g. out->cam of the decode backward.
+ * 0 <= n_views <= VCGS_DECODE_MAX_VIEWS. */
+int vcgs_centre_pose_grad(vcgs_ctx* ctx, int n_views, const vcgs_pose* poses, const float* dcam, float* dpose,
+                          void* stream);
+
 /* A novel-view server (vcgs_server_create) over the view-dependent decode of
  * anchors (paper eqs. (8)-(9)):
  * every pass decodes its requests' camera centres in one launch (as

@@ -231,6 +231,23 @@ int vcgs_decode_anchors_views_backward(vcgs_ctx* ctx, const vcgs_anchors* a, con
     return decode_bwd(ctx, a, mlp, cb, mask_logit, mask_eps, cam_centres, n_views, dG, out, stream);
 }
 
+int vcgs_centre_pose_grad(vcgs_ctx* ctx, int n_views, const vcgs_pose* poses, const float* dcam, float* dpose,
+                          void* stream)
+{
+    if (!ctx || !poses || (n_views > 0 && (!dcam || !dpose)))
+        return fail(VCGS_E_INVALID, "ctx, poses, dcam or dpose is NULL");
+    if (n_views < 0 || n_views > kDecodeMaxViews) return fail(VCGS_E_INVALID, "n_views must be in [0, 16]");
+    CentreTab t;
+    t.views = n_views;
+    for (int v = 0; v < n_views; ++v)
+        for (int k = 0; k < 9; ++k) t.R[v][k] = poses[v].R[k];
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_centre_pose_grad(t, dcam, dpose, (hipStream_t)stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return VCGS_OK;
+}
+
 int vcgs_mask_loss(vcgs_ctx* ctx, int64_t n, const float* mask_logit, const uint32_t* in_frustum_count,
                    float weight, float* dl_dm, float* loss, void* stream)
 {

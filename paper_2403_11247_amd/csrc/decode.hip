@@ -681,6 +681,26 @@ __global__ void __launch_bounds__(64 * kRedWaves) k_decode_bwd_reduce(const floa
 }
 
 // ---------------------------------------------------------------------------
+// Pose share of the camera-centre input (eq. (9)): the centre x_c = -R^T t of
+// a world-to-camera pose moves by -R^T rho under the left perturbation
+// exp(xi^) {R|t}, so dL/drho gains -R dL/dx_c and dL/dphi nothing.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_centre_pose_grad(CentreTab t, const float* __restrict__ dcam,
+                                                         float* __restrict__ dpose)
+{
+    const int v = threadIdx.x / 3, i = threadIdx.x % 3;
+    if (v >= t.views) return;
+    const float* R = t.R[v];
+    const float* g = dcam + 3 * v;
+    dpose[6 * v + i] -= R[3 * i] * g[0] + R[3 * i + 1] * g[1] + R[3 * i + 2] * g[2];
+}
+
+void launch_centre_pose_grad(const CentreTab& t, const float* dcam, float* dpose, hipStream_t s)
+{
+    if (t.views > 0) k_centre_pose_grad<<<1, 64, 0, s>>>(t, dcam, dpose);
+}
+
+// ---------------------------------------------------------------------------
 // Codebook gradient (straight-through sums of eq. (14)'s gathered rows)
 // ---------------------------------------------------------------------------
 // Each of 8192 rows of a 2 x 4096 codebook is shared by ~100 Gaussians of the

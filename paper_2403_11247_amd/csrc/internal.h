@@ -252,6 +252,12 @@ __host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim, int vie
 void launch_decode_bwd(const DecodeArgs& a, const vcgs_gaussian_buffers& dG, const vcgs_anchor_grads& out,
                        float* partial, int nblocks, float* dvbuf, float* book_partial, hipStream_t s);
 int books_grad_blocks(int64_t n);
+struct CentreTab {
+    int views;
+    float R[kDecodeMaxViews][9];  // world-to-camera rotations, row-major
+};
+// dpose [views][6] += (-R dL/dx_c, 0) for dcam [views][3] (device).
+void launch_centre_pose_grad(const CentreTab& t, const float* dcam, float* dpose, hipStream_t s);
 constexpr size_t kBookLdsMax = 150 * 1024;  // largest codebook stage table summed in LDS
 
 }  // namespace vcgs

@@ -107,7 +107,7 @@ def lib():
                      "vcgs_mask_loss", "vcgs_mask_prune", "vcgs_rvq_assign", "vcgs_track_loss",
                      "vcgs_icp_loss", "vcgs_ssim_loss", "vcgs_render_batch_hits", "vcgs_set_allocator",
                      "vcgs_decode_anchors_views", "vcgs_decode_anchors_views_backward",
-                     "vcgs_server_create_anchors", "vcgs_profile_stages"):
+                     "vcgs_server_create_anchors", "vcgs_profile_stages", "vcgs_centre_pose_grad"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
@@ -389,10 +389,22 @@ def camera_centre(pose):
     return -R.T @ np.asarray(pose.t, np.float64)
 
 
+def add_centre_pose_grad(poses, dcam, dpose, ctx: Context | None = None):
+    """dpose (V, 6) += (-R_v dL/dcam_v, 0) on the device for V poses (the
+    camera-centre input's share of the pose gradient); returns dpose."""
+    ctx = ctx or default_context()
+    poses = list(poses)
+    d = _dev(dcam)
+    assert d.shape == (len(poses), 3) and dpose.shape == (len(poses), 6) and dpose.is_contiguous()
+    arr = (CPose * len(poses))(*[pose_struct(p) for p in poses])
+    _check(lib().vcgs_centre_pose_grad(ctx.h, c_i32(len(poses)), arr, _ptr(d), _ptr(dpose), _stream()))
+    return dpose
+
+
 def pose_grad_from_centre(pose, dcam):
     """Share of dL/dxi (rho, phi) of the camera-centre input: (-R dL/dcam, 0)."""
-    R = torch.as_tensor(np.asarray(pose.R, np.float32), device=dcam.device)
-    return torch.cat([-(R @ dcam), torch.zeros(3, device=dcam.device)])
+    out = torch.zeros((1, 6), device=dcam.device)
+    return add_centre_pose_grad([pose], dcam.reshape(1, 3), out)[0]
 
 
 def decode_anchors(xa, feat, scaling, offset, W1, b1, W2, b2, books=None, idx=None, mask_logit=None, mask_eps=0.01,
@@ -513,8 +525,7 @@ def decode_anchors_views_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG,
 
 def poses_grad_from_centres(poses, dcam):
     """pose_grad_from_centre for V poses at once: dcam (V, 3) -> (V, 6)."""
-    R = torch.as_tensor(np.stack([np.asarray(p.R, np.float32) for p in poses]), device=dcam.device)
-    return torch.cat([-(R @ dcam.unsqueeze(-1)).squeeze(-1), torch.zeros_like(dcam)], dim=1)
+    return add_centre_pose_grad(poses, dcam, torch.zeros((len(poses), 6), device=dcam.device))
 
 
 def mask_loss(mask_logit, in_frustum_count=None, weight=1.0, dl_dm=None, ctx: Context | None = None):

@@ -168,6 +168,14 @@ def test_view_decode_pose_gradient_helper(V):
     d = np.array([0.3, -0.2, 0.9])
     g = pose_grad_from_centre(pose, dev(d)).cpu().numpy()
     np.testing.assert_allclose(g, odec.pose_grad_from_centre(pose.R, d), rtol=1e-5, atol=1e-6)
+    # several poses at once, added to what the pose gradients already hold
+    rng = np.random.default_rng(4)
+    poses = [scenes.perturb_pose(pose, 30 + i, trans=0.3, rot_deg=40.0) for i in range(5)]
+    dc = rng.normal(size=(5, 3))
+    base = rng.normal(size=(5, 6))
+    got = V.add_centre_pose_grad(poses, dev(dc), dev(base).contiguous()).cpu().numpy()
+    want = base + np.stack([odec.pose_grad_from_centre(p.R, dc[i]) for i, p in enumerate(poses)])
+    np.testing.assert_allclose(got, want, rtol=1e-5, atol=1e-6)
 
 
 def _centres(V_, seed):
