@@ -61,8 +61,8 @@ inline void alloc_work_e(Work& w, int64_t E, Get get)
     w.scanE = get(scan_temp_words(E) + 8);
     w.cnt = get(E);
     w.offs = get(E);
-    w.total = get(4);
-    w.overflow = get(4);
+    w.total = get(8);
+    w.overflow = w.total + 1;  // adjacent: one 8-byte copy reads both
 }
 
 template <class Get>

@@ -602,8 +602,8 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
     } else {
         enqueue_plan(ctx, *plan, *g, outs, target_color, target_depth, gb, dl_dpose, loss, s);
     }
-    HIP_TRY(hipMemcpyAsync(plan->host_flags, plan->w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(plan->host_flags + 1, plan->w.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    // pair total and overflow flag are adjacent words
+    HIP_TRY(hipMemcpyAsync(plan->host_flags, plan->w.total, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     ctx->last_plan = plan;
     ctx->last_stream = s;
     const hipError_t e = hipGetLastError();

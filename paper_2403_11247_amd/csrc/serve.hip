@@ -213,8 +213,8 @@ struct vcgs_server {
             if (decode) launch_decode_fwd(dec, sl.set, sl.s);
             const uint32_t* ord = phase_a(quiet_prof(), g, f, sl.w, sl.s);
             phase_b(quiet_prof(), f, sl.w, ord, sl.s);
-            HIP_TRY(hipMemcpyAsync(sl.flags_host, sl.w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, sl.s));
-            HIP_TRY(hipMemcpyAsync(sl.flags_host + 1, sl.w.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, sl.s));
+            // pair total and overflow flag are adjacent words
+            HIP_TRY(hipMemcpyAsync(sl.flags_host, sl.w.total, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, sl.s));
         } else {
             f.cap = 0;
             phase_b(quiet_prof(), f, sl.w, nullptr, sl.s);  // background images
