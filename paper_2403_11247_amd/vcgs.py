@@ -264,6 +264,20 @@ class _DevArray:
                                          "version": 2}
 
 
+def _arg(t, shape, name, dtype=torch.float32):
+    """A caller's tensor that a kernel reads or writes in place: it must be a
+    contiguous device tensor of exactly this shape and dtype (a mismatch would
+    make a kernel access memory outside it, so it is refused here)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise VcgsError(f"{name} must be a device tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(int(x) for x in shape) or not t.is_contiguous():
+        raise VcgsError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)}, "
+                        f"got {t.dtype} {tuple(t.shape)}")
+    return t
+
+
 def _wrap(ptr, count, dtype, device):
     """Zero-copy torch view of library-owned device memory (valid while the owner lives)."""
     return torch.as_tensor(_DevArray(ptr, count, dtype), device=device)
@@ -297,7 +311,7 @@ def render_forward(means, scales, quats, opacities, colors, camera, pose, bg=(0.
         _check(lib().vcgs_render_forward(ctx.h, ctypes.byref(g), ctypes.byref(cam), ctypes.byref(ps), bgv,
                                          ctypes.byref(imgs), ctypes.byref(h) if keep_state else None, _stream()))
     else:
-        assert hits.is_cuda and hits.dtype == torch.int32 and hits.numel() == g.n and hits.is_contiguous()
+        _arg(hits, (g.n,), "hits", torch.int32)
         _check(lib().vcgs_render_forward_hits(ctx.h, ctypes.byref(g), ctypes.byref(cam), ctypes.byref(ps), bgv,
                                               ctypes.byref(imgs), ctypes.byref(h) if keep_state else None,
                                               _ptr(hits), _stream()))
@@ -315,7 +329,10 @@ def render_backward(state: State, means, scales, quats, opacities, colors, camer
     grads = {k: torch.empty_like(t) for k, t in zip(("mean", "scale", "quat", "opacity", "color"), keep)}
     gb = CGaussianBuffers(*[_ptr(grads[k]) for k in ("mean", "scale", "quat", "opacity", "color")])
     dpose = torch.empty(6, dtype=torch.float32, device=dev)
-    ups = [None if u is None else _dev(u) for u in (dl_dcolor, dl_ddepth, dl_dalpha)]
+    H, W = int(camera.height), int(camera.width)
+    ups = [None if u is None else _arg(_dev(u), sh, nm)
+           for u, sh, nm in ((dl_dcolor, (3, H, W), "dl_dcolor"), (dl_ddepth, (H, W), "dl_ddepth"),
+                             (dl_dalpha, (H, W), "dl_dalpha"))]
     cam, ps = camera_struct(camera), pose_struct(pose)
     _check(lib().vcgs_render_backward(ctx.h, state.h, ctypes.byref(g), ctypes.byref(cam), ctypes.byref(ps),
                                       *[_ptr(u) for u in ups], ctypes.byref(gb), _ptr(dpose), _stream()))
@@ -326,11 +343,14 @@ def l1_loss(color, depth, target_color, target_depth, w_depth=0.5, ctx: Context 
     """L = mean_p(sum_c |C - C*| + w_depth |D - D*|); returns (loss (1,), dL/dC, dL/dD)."""
     ctx = ctx or default_context()
     H, W = depth.shape
+    color, depth = _arg(_dev(color), (3, H, W), "color"), _dev(depth)
+    target_color = _arg(_dev(target_color), (3, H, W), "target_color")
+    target_depth = _arg(_dev(target_depth), (H, W), "target_depth")
     dlc = torch.empty_like(color)
     dld = torch.empty_like(depth)
     loss = torch.empty(1, dtype=torch.float32, device=color.device)
-    imgs = CImages(_ptr(_dev(color)), _ptr(_dev(depth)), None)
-    _check(lib().vcgs_l1_loss(ctx.h, ctypes.byref(imgs), _ptr(_dev(target_color)), _ptr(_dev(target_depth)),
+    imgs = CImages(_ptr(color), _ptr(depth), None)
+    _check(lib().vcgs_l1_loss(ctx.h, ctypes.byref(imgs), _ptr(target_color), _ptr(target_depth),
                               c_i32(W), c_i32(H), c_f(w_depth), _ptr(dlc), _ptr(dld), _ptr(loss), _stream()))
     return loss, dlc, dld
 
@@ -394,8 +414,8 @@ def add_centre_pose_grad(poses, dcam, dpose, ctx: Context | None = None):
     camera-centre input's share of the pose gradient); returns dpose."""
     ctx = ctx or default_context()
     poses = list(poses)
-    d = _dev(dcam)
-    assert d.shape == (len(poses), 3) and dpose.shape == (len(poses), 6) and dpose.is_contiguous()
+    d = _arg(_dev(dcam), (len(poses), 3), "dcam")
+    _arg(dpose, (len(poses), 6), "dpose")
     arr = (CPose * len(poses))(*[pose_struct(p) for p in poses])
     _check(lib().vcgs_centre_pose_grad(ctx.h, c_i32(len(poses)), arr, _ptr(d), _ptr(dpose), _stream()))
     return dpose
@@ -536,8 +556,12 @@ def mask_loss(mask_logit, in_frustum_count=None, weight=1.0, dl_dm=None, ctx: Co
     n = int(m.numel())
     if dl_dm is None:
         dl_dm = torch.zeros_like(m)
+    _arg(dl_dm, (n,), "dl_dm")
     loss = torch.empty(1, device=m.device)
-    cnt = None if in_frustum_count is None else in_frustum_count.contiguous()
+    cnt = None if in_frustum_count is None else _arg(in_frustum_count.contiguous(), (n,), "in_frustum_count",
+                                                     in_frustum_count.dtype)
+    if cnt is not None and cnt.dtype not in (torch.int32, torch.uint32):
+        raise VcgsError("in_frustum_count must be int32 or uint32")
     _check(lib().vcgs_mask_loss(ctx.h, c_i64(n), _ptr(m), _ptr(cnt), c_f(weight), _ptr(dl_dm), _ptr(loss),
                                 _stream()))
     return loss, dl_dm
@@ -551,7 +575,9 @@ def mask_prune(mask_logit, hits=None, mask_eps=0.01, min_hits=1, ctx: Context | 
     keep = torch.empty(n, dtype=torch.uint8, device=m.device)
     idx = torch.empty(max(n, 1), dtype=torch.int32, device=m.device)
     nk = c_i64()
-    h = None if hits is None else hits.contiguous()
+    h = None if hits is None else _arg(hits.contiguous(), (n,), "hits", hits.dtype)
+    if h is not None and h.dtype not in (torch.int32, torch.uint32):
+        raise VcgsError("hits must be int32 or uint32")
     _check(lib().vcgs_mask_prune(ctx.h, c_i64(n), _ptr(m), c_f(mask_eps), _ptr(h), ctypes.c_uint32(int(min_hits)),
                                  _ptr(keep), _ptr(idx), ctypes.byref(nk), _stream()))
     return keep, idx[:nk.value]
@@ -563,11 +589,15 @@ def track_loss(color, depth, alpha, target_color, target_depth, lam_d=1.0, norm=
     (loss (1,), dL/dC (3, H, W), dL/dD (H, W))."""
     ctx = ctx or default_context()
     H, W = depth.shape
+    color, depth = _arg(_dev(color), (3, H, W), "color"), _dev(depth)
+    alpha = _arg(_dev(alpha), (H, W), "alpha")
+    target_color = _arg(_dev(target_color), (3, H, W), "target_color")
+    target_depth = _arg(_dev(target_depth), (H, W), "target_depth")
     dlc = torch.empty_like(color)
     dld = torch.empty_like(depth)
     loss = torch.empty(1, dtype=torch.float32, device=color.device)
-    imgs = CImages(_ptr(_dev(color)), _ptr(_dev(depth)), _ptr(_dev(alpha)))
-    _check(lib().vcgs_track_loss(ctx.h, ctypes.byref(imgs), _ptr(_dev(target_color)), _ptr(_dev(target_depth)),
+    imgs = CImages(_ptr(color), _ptr(depth), _ptr(alpha))
+    _check(lib().vcgs_track_loss(ctx.h, ctypes.byref(imgs), _ptr(target_color), _ptr(target_depth),
                                  c_i32(W), c_i32(H), c_f(lam_d), c_i32(norm), c_f(sil_thresh), _ptr(dlc), _ptr(dld),
                                  _ptr(loss), _stream()))
     return loss, dlc, dld
@@ -581,12 +611,17 @@ def icp_loss(means, camera, pose, depth, tau=0.05, stride=1, weight=1.0, dmeans=
     ctx = ctx or default_context()
     m = _dev(means)
     n = int(m.shape[1]) if m.dim() == 2 else 0
+    if n > 0:
+        _arg(m, (3, n), "means")
     if dpose is None:
         dpose = torch.zeros(6, device=m.device)
+    _arg(dpose, (6,), "dpose")
+    _arg(dmeans, (3, n), "dmeans")
+    depth = _arg(_dev(depth), (int(camera.height), int(camera.width)), "depth")
     loss = torch.empty(1, device=m.device)
     matched = torch.empty(1, dtype=torch.int32, device=m.device)
     cam, ps = camera_struct(camera), pose_struct(pose)
-    _check(lib().vcgs_icp_loss(ctx.h, c_i64(n), _ptr(m), ctypes.byref(cam), ctypes.byref(ps), _ptr(_dev(depth)),
+    _check(lib().vcgs_icp_loss(ctx.h, c_i64(n), _ptr(m), ctypes.byref(cam), ctypes.byref(ps), _ptr(depth),
                                c_f(tau), c_i32(stride), c_f(weight), _ptr(dmeans), _ptr(dpose), _ptr(loss),
                                _ptr(matched), _stream()))
     return loss, dmeans, dpose, matched
@@ -600,8 +635,11 @@ def ssim_loss(color, target_color, weight=1.0, dl_dcolor=None, ctx: Context | No
     _, H, W = c.shape
     if dl_dcolor is None:
         dl_dcolor = torch.zeros_like(c)
+    _arg(c, (3, H, W), "color")
+    _arg(dl_dcolor, (3, H, W), "dl_dcolor")
+    tcol = _arg(_dev(target_color), (3, H, W), "target_color")
     loss = torch.empty(1, device=c.device)
-    _check(lib().vcgs_ssim_loss(ctx.h, _ptr(c), _ptr(_dev(target_color)), c_i32(W), c_i32(H), c_f(weight),
+    _check(lib().vcgs_ssim_loss(ctx.h, _ptr(c), _ptr(tcol), c_i32(W), c_i32(H), c_f(weight),
                                 _ptr(dl_dcolor), _ptr(loss), _stream()))
     return loss, dl_dcolor
 
@@ -626,7 +664,7 @@ def rvq_assign(books, x, idx_bytes=1, idx=True, recon=True, loss=True, dbooks=No
     if loss:
         out["loss"] = torch.empty(1, device=b.device)
     if grad:
-        out["dbooks"] = torch.zeros_like(b) if dbooks is None else dbooks
+        out["dbooks"] = torch.zeros_like(b) if dbooks is None else _arg(dbooks, (L, P, D), "dbooks")
     q = CRvqBooks(D, L, P, _ptr(b))
     _check(lib().vcgs_rvq_assign(ctx.h, ctypes.byref(q), c_i64(n), _ptr(xx), _ptr(out["idx"]),
                                  ctypes.c_int32(idx_bytes), _ptr(out["recon"]), _ptr(out["loss"]),
@@ -758,11 +796,13 @@ class BatchWindow:
         tc = td = None
         if self.backward:
             assert targets is not None and len(targets) == self.V
-            self._tkeep = [(_dev(t[0]), _dev(t[1])) for t in targets]
+            self._tkeep = [(_arg(_dev(t[0]), (3, int(c.height), int(c.width)), "target colour"),
+                            _arg(_dev(t[1]), (int(c.height), int(c.width)), "target depth"))
+                           for t, c in zip(targets, self.cameras)]
             tc = (c_p * self.V)(*[_ptr(t[0]) for t in self._tkeep])
             td = (c_p * self.V)(*[_ptr(t[1]) for t in self._tkeep])
         if hits is not None:
-            assert hits.is_cuda and hits.dtype == torch.int32 and hits.numel() == self.n and hits.is_contiguous()
+            _arg(hits, (self.n,), "hits", torch.int32)
             saved = hits.clone()
         args = (self.ctx.h, ctypes.byref(g), ctypes.byref(views), self.bg, tc, td, c_f(self.w_depth), self.c_outs,
                 ctypes.byref(self.c_grads) if self.backward else None,
