@@ -393,7 +393,9 @@ def _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx, in_di
     cb = None
     if books is not None:
         bk = _dev(books)
-        ix = _dev(idx, torch.int32)
+        if bk.dim() != 3 or bk.shape[2] != 7:
+            raise VcgsError("books must be (stages, size, 7)")
+        ix = _arg(_dev(idx, torch.int32), (int(bk.shape[0]), na * k), "idx", torch.int32)
         cb = CCodebook(int(bk.shape[0]), int(bk.shape[1]), _ptr(bk), _ptr(ix))
         ts += [bk, ix]
     return a, m, cb, ts, na, k
@@ -445,7 +447,7 @@ def decode_anchors(xa, feat, scaling, offset, W1, b1, W2, b2, books=None, idx=No
                  and out[f].dtype == torch.float32 for f, sh in shapes.items()):
         raise VcgsError("decode_anchors: out tensors must be contiguous float32 device tensors of the decoded shapes")
     ob = CGaussianBuffers(*[_ptr(out[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
-    ml = None if mask_logit is None else _dev(mask_logit)
+    ml = None if mask_logit is None else _arg(_dev(mask_logit), (na * k,), "mask_logit")
     if cam_centre is None:
         _check(lib().vcgs_decode_anchors(ctx.h, ctypes.byref(a), ctypes.byref(m), ctypes.byref(cb) if cb else None,
                                          _ptr(ml), c_f(mask_eps), ctypes.byref(ob), _stream()))
@@ -470,7 +472,7 @@ def decode_anchors_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG, books
            "scaling": torch.empty_like(keep[2]), "xa": torch.empty_like(keep[0]), "W1": torch.empty_like(keep[4]),
            "b1": torch.empty_like(keep[5]), "W2": torch.empty_like(keep[6]), "b2": torch.empty_like(keep[7])}
     out["books"] = torch.empty_like(keep[8]) if books is not None else None
-    ml = None if mask_logit is None else _dev(mask_logit)
+    ml = None if mask_logit is None else _arg(_dev(mask_logit), (na * k,), "mask_logit")
     out["mask_logit"] = torch.empty_like(ml) if ml is not None else None
     out["cam"] = torch.empty(3, device=keep[0].device) if cam_centre is not None else None
     ag = CAnchorGrads(*[_ptr(out[f]) for f in ("feat", "offset", "scaling", "xa", "W1", "b1", "W2", "b2", "books",
@@ -509,7 +511,7 @@ def decode_anchors_views(xa, feat, scaling, offset, W1, b1, W2, b2, cam_centres,
                  and out[f].dtype == torch.float32 for f, sh in shapes.items()):
         raise VcgsError("decode_anchors_views: out tensors must be contiguous float32 device tensors (V, ., n)")
     ob = CGaussianBuffers(*[_ptr(out[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
-    ml = None if mask_logit is None else _dev(mask_logit)
+    ml = None if mask_logit is None else _arg(_dev(mask_logit), (na * k,), "mask_logit")
     _check(lib().vcgs_decode_anchors_views(ctx.h, ctypes.byref(a), ctypes.byref(m), ctypes.byref(cb) if cb else None,
                                            _ptr(ml), c_f(mask_eps), ctypes.c_int(V), cc, ctypes.byref(ob), _stream()))
     del keep
@@ -530,7 +532,7 @@ def decode_anchors_views_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG,
            "scaling": torch.empty_like(keep[2]), "xa": torch.empty_like(keep[0]), "W1": torch.empty_like(keep[4]),
            "b1": torch.empty_like(keep[5]), "W2": torch.empty_like(keep[6]), "b2": torch.empty_like(keep[7])}
     out["books"] = torch.empty_like(keep[8]) if books is not None else None
-    ml = None if mask_logit is None else _dev(mask_logit)
+    ml = None if mask_logit is None else _arg(_dev(mask_logit), (na * k,), "mask_logit")
     out["mask_logit"] = torch.empty_like(ml) if ml is not None else None
     out["cam"] = torch.empty((V, 3), device=keep[0].device)
     ag = CAnchorGrads(*[_ptr(out[f]) for f in ("feat", "offset", "scaling", "xa", "W1", "b1", "W2", "b2", "books",
@@ -858,8 +860,8 @@ class Server:
                      mask_eps=0.01, **kw):
         """A server over the view-dependent decode (W1 (32, 36)): each request
         is rendered from the anchors decoded at its own camera centre."""
-        a, m, cb, keep, _, _ = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx, 36)
-        ml = None if mask_logit is None else _dev(mask_logit)
+        a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx, 36)
+        ml = None if mask_logit is None else _arg(_dev(mask_logit), (na * k,), "mask_logit")
         if ml is not None:
             keep.append(ml)
         return cls(None, None, None, None, None, _anchors=(a, m, cb, keep, ml, mask_eps), **kw)

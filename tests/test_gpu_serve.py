@@ -142,3 +142,29 @@ def test_view_dependent_server(V):
     r = compare_images(*ref[0], raster.render(g, cam, pose))
     say("view-dependent served vs oracle colour %.2e depth %.2e flagged %d" % (r["color"], r["depth"], r["flagged"]))
     assert r["pass_"], r
+
+
+def test_view_dependent_server_with_mask_and_codebook(V):
+    """The anchors server with a mask that prunes part of the map and a
+    residual codebook: each request equals the plain decode + render at its
+    centre, bit for bit."""
+    from tests.gpu_common import dev
+    a = scenes.room_anchors(2000, k=10, seed=8)
+    m = scenes.room_mlp_view(seed=8)
+    n = a.n * a.k
+    mask, books, idx = scenes.mask_and_codebook(n, size=256, mask_mu=0.0, mask_sigma=3.0)
+    A = [dev(x) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    kw = dict(books=dev(books), idx=dev(idx, torch.int32), mask_logit=dev(mask))
+    trace = scenes.serve_trace(6, qps=100.0, seed=25, sizes=SIZES)
+    ref = []
+    for _, cam, pose in trace:
+        G = V.decode_anchors(*A, cam_centre=V.camera_centre(pose), **kw)
+        ref.append(V.render_forward(*[G[f] for f in FIELDS], cam, pose, keep_state=False)[:3])
+    torch.cuda.synchronize()
+    srv = V.Server.from_anchors(*A, **kw, max_views=4, slots=2, pair_budget=1 << 22, pairs_per_pixel=4.0)
+    tickets = [srv.submit(cam, pose) for _, cam, pose in trace]
+    srv.drain(timeout_us=200)
+    srv.close()
+    assert_same([o for _, o in tickets], ref, "mask+codebook")
+    say("view-dependent server with mask and codebook: %d requests bit-exact, %d of %d Gaussians pruned"
+        % (len(trace), int((torch.sigmoid(kw["mask_logit"]) <= 0.01).sum()), n))
