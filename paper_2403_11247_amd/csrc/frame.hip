@@ -65,11 +65,18 @@ const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hi
     return ord;
 }
 
-// Pairs, stable tile sort, tile ranges, forward compositing.
-void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s)
+// Zeroing of the tile ranges and the overflow flag, which phase_b needs first
+// (issued early by a caller that synchronises in between).
+void phase_b_prefill(Frame& f, Work& w, hipStream_t s)
 {
     launch_fill_u32(f.ranges, 0u, 2 * (int64_t)f.total_tiles, s);
     launch_fill_u32(w.overflow, 0u, 1, s);
+}
+
+// Pairs, stable tile sort, tile ranges, forward compositing.
+void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s, bool prefilled)
+{
+    if (!prefilled) phase_b_prefill(f, w, s);
     if (f.cap > 0) {
         const Count P{f.cap, w.total};
         pf.begin(VCGS_STAGE_EMIT, s);
@@ -370,6 +377,8 @@ static int render_forward_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
         if (hipMemcpyAsync(f.pt_dev, ctx->host_tab, sizeof(ProjTab), hipMemcpyHostToDevice, s) != hipSuccess)
             return drop(VCGS_E_HIP, "table upload failed");
         const uint32_t* ord = f.E > 0 ? phase_a(ctx->prof, *g, f, w, s) : nullptr;
+        // what does not depend on the pair count runs while the host waits for it
+        phase_b_prefill(f, w, s);
         if (f.E > 0) {
             if (hipMemcpyAsync(ctx->host_u32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
@@ -382,7 +391,7 @@ static int render_forward_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
         f.gids = st->get<uint32_t>(f.cap);
         if (f.cap > 0) alloc_work_p(w, f.cap, [&](int64_t c) { return sc.get<uint32_t>(c); });
         if (!st->ok() || sc.oom) return drop(VCGS_E_NOMEM, "device allocation failed (pairs)");
-        phase_b(ctx->prof, f, w, ord, s);
+        phase_b(ctx->prof, f, w, ord, s, true);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return drop(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     }
