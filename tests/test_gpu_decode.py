@@ -266,3 +266,17 @@ def test_decode_with_no_anchors(V):
     torch.cuda.synchronize()
     for k in ("W1", "b1", "W2", "b2", "cam"):
         assert bool((ag[k] == 0).all()), k
+
+
+def test_decode_views_full_window_size(V):
+    """The BA window's map size (50k anchors x 10) at three camera centres in
+    one launch: every view's 500k decoded Gaussians against the oracle."""
+    a = scenes.room_anchors(50000, k=10, spacing=0.05, seed=1)
+    m = scenes.room_mlp_view(seed=1)
+    A = [dev(x) for x in (a.xa, a.feat, a.scaling, a.offset, m.W1, m.b1, m.W2, m.b2)]
+    _, poses = scenes.ba_window(3)
+    cs = np.stack([V.camera_centre(p) for p in poses]).astype(np.float32)
+    got = V.decode_anchors_views(*A, cs)
+    torch.cuda.synchronize()
+    for v in range(3):
+        check_decode({f: got[f][v] for f in FIELDS}, odec.decode(a, m, cam=cs[v].astype(np.float64)))
