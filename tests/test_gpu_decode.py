@@ -280,3 +280,19 @@ def test_decode_views_full_window_size(V):
     torch.cuda.synchronize()
     for v in range(3):
         check_decode({f: got[f][v] for f in FIELDS}, odec.decode(a, m, cam=cs[v].astype(np.float64)))
+
+
+def test_decode_full_room_codebook_and_mask(V):
+    """The compacted room's decode at full size (40k anchors x 10, mask logits
+    N(2, 1), 2 x 4096 x 7 codebooks) against the oracle."""
+    a = scenes.room_anchors(40000, k=10)
+    m = scenes.room_mlp(seed=0)
+    n = a.n * a.k
+    logits, books, idx = scenes.mask_and_codebook(n)
+    thr = np.log(0.01 / 0.99)
+    logits[np.abs(logits - thr) < 1e-4] += 1e-3
+    out = run_decode(V, a, m, books, idx, logits)
+    torch.cuda.synchronize()
+    ref = odec.decode(a, m, books, idx, logits)
+    check_decode(out, ref)
+    assert np.array_equal(out["opacity"].cpu().numpy() == 0, ref["opacity"] == 0)
