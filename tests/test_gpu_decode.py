@@ -296,3 +296,16 @@ def test_decode_full_room_codebook_and_mask(V):
     ref = odec.decode(a, m, books, idx, logits)
     check_decode(out, ref)
     assert np.array_equal(out["opacity"].cpu().numpy() == 0, ref["opacity"] == 0)
+
+
+def test_decode_backward_full_room_codebook_and_mask(V):
+    """The compacted room's decode adjoint at full size: the codebook rows'
+    straight-through sums come from ~100 per-block LDS tables, checked with
+    every other gradient against the oracle."""
+    a = scenes.room_anchors(40000, k=10, seed=4)
+    m = scenes.room_mlp(seed=4)
+    n = a.n * a.k
+    logits, books, idx = scenes.mask_and_codebook(n, mask_mu=0.0, mask_sigma=3.0)
+    thr = np.log(0.01 / 0.99)
+    logits[np.abs(logits - thr) < 1e-4] += 1e-3
+    check_decode_backward(V, a, m, books, idx, logits, seed=9)
