@@ -85,11 +85,14 @@ def tile_ranges(keys_sorted, cam):
     return rng
 
 
+SPLAT = 12
+
+
 def project(g, cam, pose):
-    """FP64 splat parameters (n, 8): u, v, conic A, B, C, camera depth,
-    condition number of Sigma' + 0.3 I, 0."""
+    """FP64 splat parameters (n, 12): u, v, conic A, B, C, camera depth,
+    condition number of Sigma' + 0.3 I, and five zeros (no decision form)."""
     n = g.n
-    out = np.empty((n, 8), np.float64)
+    out = np.empty((n, SPLAT), np.float64)
     m, s, q = (_c(x, np.float64) for x in (g.mean, g.scale, g.quat))
     R, t = _c(pose.R, np.float64), _c(pose.t, np.float64)
     c = _cam(cam)
@@ -97,14 +100,33 @@ def project(g, cam, pose):
     return out
 
 
-def render(g, cam, pose, bg=(0.0, 0.0, 0.0)):
+def decision_form(g, cam, pose, splat):
+    """Fills slots 7-11 of ``splat`` in place with the decision form: the
+    eigen form of the binary32 footprint covariance of the key path, on which
+    the threshold decisions (1/255, 0.99, the stop) are taken."""
+    m, s, q, o = (_c(x, np.float32) for x in (g.mean, g.scale, g.quat, g.opacity))
+    R, t = _c(pose.R, np.float32), _c(pose.t, np.float32)
+    c = _cam(cam)
+    assert splat.flags.c_contiguous and splat.dtype == np.float64 and splat.shape == (g.n, SPLAT)
+    lib().orc_decision_form(ctypes.c_int64(g.n), _p(m), _p(s), _p(q), _p(o), ctypes.byref(c), _p(R), _p(t),
+                            _p(splat))
+    return splat
+
+
+def render(g, cam, pose, bg=(0.0, 0.0, 0.0), decisions="fp32"):
     """Forward render.  Returns a dict with the FP32 keys, the sorted pairs,
     the tile ranges, and FP64 colour (3,H,W), depth, alpha, final
-    transmittance, contributor count and ambiguity flags (H, W)."""
+    transmittance, contributor count and ambiguity flags (H, W).
+    decisions="fp32" takes the threshold decisions on the binary32 footprint
+    covariance (``decision_form``); "fp64" on the FP64 footprint."""
     db, rect, cnt = keys(g, cam, pose)
     ks, gids = sorted_pairs(db, rect, cnt, cam)
     rng = tile_ranges(ks, cam)
     splat = project(g, cam, pose)
+    if decisions == "fp32":
+        decision_form(g, cam, pose, splat)
+    else:
+        assert decisions == "fp64", decisions
     W, H = cam.width, cam.height
     C = np.empty((3, H, W)); D = np.empty((H, W)); A = np.empty((H, W)); T = np.empty((H, W))
     nc = np.empty((H, W), np.int32); fl = np.empty((H, W), np.uint8)
@@ -115,6 +137,40 @@ def render(g, cam, pose, bg=(0.0, 0.0, 0.0)):
                          _p(rng), _p(gids), _p(C), _p(D), _p(A), _p(T), _p(nc), _p(fl))
     return dict(depth_bits=db, rect=rect, count=cnt, keys=ks, gids=gids, ranges=rng, splat=splat,
                 color=C, depth=D, alpha=A, T_final=T, n_contrib=nc, flags=fl, bg=bgv)
+
+
+def variants(g, cam, fwd, pixels, maxv=64):
+    """Every outcome an FP32 renderer may legitimately produce at the given
+    flat pixel indices of a forward result ``fwd``: one per combination of the
+    pixel's ambiguous threshold decisions (alpha >= 1/255, or the stop at
+    T < 1e-4, within FP32 noise) taken either way.  Returns (vals, nvar):
+    vals (npx, maxv, 7) = (C0, C1, C2, D, A, T_final, n_contrib) per variant,
+    variant 0 the FP64 decisions; nvar (npx,) = number of variants, -1 when a
+    pixel has more than maxv."""
+    pix = _c(pixels, np.int64)
+    npx = pix.shape[0]
+    vals = np.full((max(npx, 1), maxv, 7), np.nan)
+    nvar = np.zeros(max(npx, 1), np.int32)
+    o, col = _c(g.opacity, np.float64), _c(g.color, np.float64)
+    c = _cam(cam)
+    lib().orc_variants(ctypes.c_int64(g.n), _p(fwd["splat"]), _p(o), _p(col), ctypes.byref(c), _p(fwd["bg"]),
+                       _p(fwd["ranges"]), _p(fwd["gids"]), ctypes.c_int64(npx), _p(pix), ctypes.c_int32(maxv),
+                       _p(vals), _p(nvar))
+    return vals[:npx], nvar[:npx]
+
+
+def decision_hash(g, cam, fwd, splat=None, opacity=None):
+    """Per-pixel hash (H, W) uint64 of which tile-list entries contribute and
+    where the pixel stops, over the tile lists of ``fwd``; ``splat`` and
+    ``opacity`` replace the footprints of ``fwd`` when given (same lists)."""
+    sp = fwd["splat"] if splat is None else _c(splat, np.float64)
+    o = _c(g.opacity if opacity is None else opacity, np.float64)
+    col = _c(g.color, np.float64)
+    out = np.empty((cam.height, cam.width), np.uint64)
+    c = _cam(cam)
+    lib().orc_decision_hash(ctypes.c_int64(g.n), _p(sp), _p(o), _p(col), ctypes.byref(c), _p(fwd["ranges"]),
+                            _p(fwd["gids"]), _p(out))
+    return out
 
 
 def hit_counts(g, cam, fwd):
@@ -130,17 +186,21 @@ def hit_counts(g, cam, fwd):
     return hits, amb
 
 
-def render_backward(g, cam, pose, fwd, dl_dc, dl_dd, dl_da):
+def render_backward(g, cam, pose, fwd, dl_dc, dl_dd, dl_da, variant=None):
     """Exact FP64 gradients of sum(dl_dc*C + dl_dd*D + dl_da*A) with respect
     to mean, scale, quat, opacity, colour (same shapes as the inputs) and the
-    pose tangent xi = (rho, phi) under left perturbation."""
+    pose tangent xi = (rho, phi) under left perturbation.  ``variant`` (H, W)
+    int32, optional: per pixel, which of its ``variants`` the derivative
+    follows (0 = every decision as in FP64)."""
     n = g.n
     g2 = np.empty((n, 10))
     o, col = _c(g.opacity, np.float64), _c(g.color, np.float64)
     dc, dd, da = _c(dl_dc, np.float64), _c(dl_dd, np.float64), _c(dl_da, np.float64)
     c = _cam(cam)
+    var = None if variant is None else _c(variant, np.int32)
     lib().orc_render_bwd_2d(ctypes.c_int64(n), _p(fwd["splat"]), _p(o), _p(col), ctypes.byref(c),
-                            _p(fwd["bg"]), _p(fwd["ranges"]), _p(fwd["gids"]), _p(dc), _p(dd), _p(da), _p(g2))
+                            _p(fwd["bg"]), _p(fwd["ranges"]), _p(fwd["gids"]), _p(dc), _p(dd), _p(da),
+                            None if var is None else _p(var), _p(g2))
     vis = (fwd["count"] > 0).astype(np.int32)
     m, s, q = (_c(x, np.float64) for x in (g.mean, g.scale, g.quat))
     R, t = _c(pose.R, np.float64), _c(pose.t, np.float64)

@@ -233,6 +233,22 @@ class State:
             return torch.empty(0, dtype=torch.int32, device=dev)
         return _wrap(v.count, v.n, torch.int32, dev)
 
+    def pixel_state(self, width: int, height: int):
+        """Copies of the saved per-pixel final transmittance (H, W) float32 and
+        last-contributor count (H, W) int32 of a single-view state."""
+        v = CStateView()
+        _check(lib().vcgs_state_query(self.h, ctypes.byref(v)))
+        dev = torch.device("cuda", self.ctx.device)
+        if not v.t_final or not v.n_contrib:
+            raise VcgsError("state holds no per-pixel transmittance")
+        npx = int(width) * int(height)
+        tiles = ((int(width) + 15) // 16) * ((int(height) + 15) // 16)
+        if tiles != v.tiles_x * v.tiles_y:
+            raise VcgsError(f"image {width}x{height} does not match the state's {v.tiles_x}x{v.tiles_y} tiles")
+        T = _wrap(v.t_final, npx, torch.float32, dev).clone().view(int(height), int(width))
+        nc = _wrap(v.n_contrib, npx, torch.int32, dev).clone().view(int(height), int(width))
+        return T, nc
+
     def view(self) -> dict:
         """Copies of the saved binning/sort results as torch tensors."""
         v = CStateView()

@@ -64,7 +64,7 @@ def test_batch_forward_equals_plain_and_oracle(V):
     for i, (c, p) in enumerate(zip(cams, poses)):
         C, D, A = win.outs[i]
         assert torch.equal(C, ref[i]["C"]) and torch.equal(D, ref[i]["D"]) and torch.equal(A, ref[i]["A"]), i
-        r = compare_images(C, D, A, raster.render(g, c, p))
+        r = compare_images(C, D, A, raster.render(g, c, p), g=g, cam=c)
         assert r["pass_"], (i, r)
     say("batch forward", len(cams), "views, pairs", win.pairs)
 
@@ -147,6 +147,6 @@ def test_ba_window_full_size(V):
     check_backward(win, plain_views(V, gd, cams, poses, tg))
     # one full-size view against the oracle
     i = 8
-    r = compare_images(*win.outs[i], raster.render(g, cams[i], poses[i]))
+    r = compare_images(*win.outs[i], raster.render(g, cams[i], poses[i]), g=g, cam=cams[i])
     say("BA view", i, "max err colour %.2e depth %.2e flagged %d" % (r["color"], r["depth"], r["flagged"]))
     assert r["pass_"], r

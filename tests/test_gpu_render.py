@@ -1,9 +1,12 @@
 """GPU parity of the plain render path against the oracle, through the C ABI.
 
 Bars: tile keys, sort order and tile ranges bit-exact; colour/depth/alpha
-within 1e-4 absolute on pixels whose threshold decisions are not within FP32
-noise (the oracle flags those, and their count is reported); gradients within
-1e-3 relative (per tensor, L2), with zero upstream gradient at flagged pixels.
+within 1e-4 absolute of the oracle on every pixel -- where a threshold decision
+lies within FP32 noise (a flagged pixel), of one of the outcomes the oracle
+enumerates for that pixel; A + T_final = 1 to the rounding of the sums;
+gradients within 1e-3 relative per tensor (L2) and element by element
+(|d| <= 1e-3 |g| + 1e-6 max|g|), the oracle following at each flagged pixel the
+outcome the GPU took (zero upstream gradient only where two outcomes match).
 """
 import numpy as np
 import pytest
@@ -12,7 +15,9 @@ import torch
 from oracle import raster
 from paper_2403_11247_amd import scenes
 from tests.gpu_common import (GRAD_REL_TOL, IMG_TOL, FIELDS, compare_images, compare_keys, dev, gauss_dev,
-                              rel_err, say)
+                              grad_check, rel_err, say, zero_at)
+
+U32 = 2.0 ** -24
 
 pytestmark = pytest.mark.gpu
 
@@ -32,18 +37,30 @@ def run_fwd(V, g, cam, pose, bg=(0.0, 0.0, 0.0)):
     return gd, C, D, A, st
 
 
+def check_invariant(A, T, nc):
+    """A + T_final = 1 per pixel, up to four roundings (of quantities <= 1) per
+    contributor: the weight, the alpha sum, and the transmittance update."""
+    A = A.cpu().numpy().astype(np.float64)
+    T = T.cpu().numpy().astype(np.float64)
+    nc = nc.cpu().numpy().astype(np.float64)
+    dev_ = np.abs(A + T - 1.0)
+    bound = 4.0 * U32 * (nc + 1.0)
+    say("A + T_final - 1: max %.2e (bound at that pixel %.2e), %d pixels above 2e-6" %
+        (dev_.max(initial=0.0), bound.ravel()[np.argmax(dev_)] if dev_.size else 0.0, int((dev_ > 2e-6).sum())))
+    assert (dev_ <= bound).all()
+
+
 def check_forward(V, g, cam, pose, bg=(0.0, 0.0, 0.0), name=""):
     say("forward", name, "n =", g.n, "image", cam.width, "x", cam.height)
     gd, C, D, A, st = run_fwd(V, g, cam, pose, bg)
     ref = raster.render(g, cam, pose, bg)
     compare_keys(st.view(), ref, g.n, cam)
-    r = compare_images(C, D, A, ref)
-    say(name, "max err colour %.2e depth %.2e alpha %.2e flagged %d (flagged colour err %.2e)" %
-        (r["color"], r["depth"], r["alpha"], r["flagged"], r["flagged_color"]))
+    T, nc = st.pixel_state(cam.width, cam.height)
+    r = compare_images(C, D, A, ref, g=g, cam=cam, pix_state=(T, nc))
+    say(name, "max err colour %.2e depth %.2e alpha %.2e flagged %d (unmatched %d, ambiguous %d)" %
+        (r["color"], r["depth"], r["alpha"], r["flagged"], r["flagged_unmatched"], r["flagged_ambiguous"]))
     assert r["pass_"], r
-    assert r["flagged"] <= max(2, 0.01 * cam.width * cam.height)
-    # invariant: A + T_final = 1 per pixel
-    view = st.view()
+    check_invariant(A, T, nc)
     return gd, C, D, A, st, ref
 
 
@@ -105,22 +122,21 @@ def test_forward_is_deterministic(V):
 def check_backward(V, g, cam, pose, up, bg=(0.0, 0.0, 0.0), name="", tol=GRAD_REL_TOL):
     gd, C, D, A, st = run_fwd(V, g, cam, pose, bg)
     ref = raster.render(g, cam, pose, bg)
-    flagged = ref["flags"] != 0
-    up = [u.copy() for u in up]
-    up[0][:, flagged] = 0.0
-    up[1][flagged] = 0.0
-    up[2][flagged] = 0.0
-    say("backward", name, "flagged", int(flagged.sum()))
+    r = compare_images(C, D, A, ref, g=g, cam=cam, pix_state=st.pixel_state(cam.width, cam.height))
+    assert r["pass_"], r
+    # the oracle follows the outcome the GPU took at each flagged pixel; where
+    # that is not unique, or the 0.99 clamp is ambiguous, the pixel gets no gradient
+    skip = (r["variant"] < 0) | ((ref["flags"] & 4) != 0)
+    up = zero_at(up, skip)
+    say("backward", name, "flagged", r["flagged"], "without gradient", int(skip.sum()))
     grads, dpose = V.render_backward(st, *gd, cam, pose, dev(up[0]), dev(up[1]), dev(up[2]))
     torch.cuda.synchronize()
-    gref = raster.render_backward(g, cam, pose, ref, *up)
+    gref = raster.render_backward(g, cam, pose, ref, *up, variant=np.maximum(r["variant"], 0))
     errs = {}
     for k in FIELDS:
-        errs[k] = rel_err(grads[k].cpu().numpy(), gref[k])
-    errs["pose"] = rel_err(dpose.cpu().numpy(), gref["pose"])
+        errs[k] = grad_check(k, grads[k].cpu().numpy(), gref[k], tol)
+    errs["pose"] = grad_check("pose", dpose.cpu().numpy(), gref["pose"], tol)
     say(name, "grad rel err", {k: "%.2e" % v for k, v in errs.items()})
-    for k, e in errs.items():
-        assert e <= tol, (k, e)
     return grads, dpose, gref
 
 

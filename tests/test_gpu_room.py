@@ -4,7 +4,8 @@ against a target rendered at a pose perturbed by 2 cm / 1 degree.
 
 The render-only checks feed both sides the same FP32 Gaussians (the oracle's
 decode rounded to FP32), so tile keys and sort order must agree bit for bit;
-the end-to-end check runs the GPU decode as well and compares images.
+the end-to-end check runs the GPU decode as well, checks it against the
+oracle's decode, and the images against the oracle rendering the GPU's decode.
 """
 import numpy as np
 import pytest
@@ -12,7 +13,12 @@ import torch
 
 from oracle import decode as odec, raster
 from paper_2403_11247_amd import scenes
-from tests.gpu_common import FIELDS, GRAD_REL_TOL, compare_images, compare_keys, dev, gauss_dev, rel_err, say
+from tests.gpu_common import (FIELDS, GRAD_REL_TOL, compare_images, compare_keys, dev, gauss_dev, grad_check, say,
+                              zero_at)
+
+# Flagged pixels (a threshold decision within FP32 noise; each is checked
+# against the oracle's enumerated outcomes): at most 0.05% of the image.
+FLAG_BUDGET = 5e-4
 
 pytestmark = pytest.mark.gpu
 
@@ -45,12 +51,16 @@ def test_room_forward(V, room):
     C, D, A, st = V.render_forward(*gd, cam, pose)
     torch.cuda.synchronize()
     compare_keys(st.view(), ref, g.n, cam)
-    r = compare_images(C, D, A, ref)
-    say("room max err colour %.2e depth %.2e alpha %.2e flagged %d (%.3f%%) flagged-colour %.2e" %
+    T, nc = st.pixel_state(cam.width, cam.height)
+    r = compare_images(C, D, A, ref, g=g, cam=cam, pix_state=(T, nc))
+    say("room max err colour %.2e depth %.2e alpha %.2e flagged %d (%.3f%%; unmatched %d, ambiguous %d)" %
         (r["color"], r["depth"], r["alpha"], r["flagged"], 100.0 * r["flagged"] / (cam.width * cam.height),
-         r["flagged_color"]))
+         r["flagged_unmatched"], r["flagged_ambiguous"]))
     assert r["pass_"], r
-    assert r["flagged"] <= 0.01 * cam.width * cam.height
+    assert r["flagged"] <= FLAG_BUDGET * cam.width * cam.height
+    # A + T_final = 1 up to four roundings per contributor
+    dev_ = np.abs(A.cpu().numpy().astype(np.float64) + T.cpu().numpy() - 1.0)
+    assert (dev_ <= 4.0 * 2.0 ** -24 * (nc.cpu().numpy() + 1.0)).all(), dev_.max()
 
 
 def l1_upstream(ref, tgt, w_depth=0.5):
@@ -58,9 +68,6 @@ def l1_upstream(ref, tgt, w_depth=0.5):
     dc = (np.sign(ref["color"] - tgt["color"]) / npix).astype(np.float32)
     dd = (w_depth * np.sign(ref["depth"] - tgt["depth"]) / npix).astype(np.float32)
     da = np.zeros_like(dd)
-    bad = ref["flags"] != 0
-    dc[:, bad] = 0.0
-    dd[bad] = 0.0
     return dc, dd, da
 
 
@@ -68,25 +75,36 @@ def test_room_backward(V, room):
     g, cam, pose, ref, tgt = room["g"], room["cam"], room["pose"], room["ref"], room["tgt"]
     gd = gauss_dev(g)
     C, D, A, st = V.render_forward(*gd, cam, pose)
-    up = l1_upstream(ref, tgt)
-    say("room backward")
+    r = compare_images(C, D, A, ref, g=g, cam=cam, pix_state=st.pixel_state(cam.width, cam.height))
+    assert r["pass_"], r
+    skip = (r["variant"] < 0) | ((ref["flags"] & 4) != 0)
+    up = zero_at(l1_upstream(ref, tgt), skip)
+    say("room backward: flagged", r["flagged"], "without gradient", int(skip.sum()))
     grads, dpose = V.render_backward(st, *gd, cam, pose, *[dev(u) for u in up])
     torch.cuda.synchronize()
-    gref = raster.render_backward(g, cam, pose, ref, *up)
-    errs = {k: rel_err(grads[k].cpu().numpy(), gref[k]) for k in FIELDS}
-    errs["pose"] = rel_err(dpose.cpu().numpy(), gref["pose"])
+    gref = raster.render_backward(g, cam, pose, ref, *up, variant=np.maximum(r["variant"], 0))
+    errs = {k: grad_check(k, grads[k].cpu().numpy(), gref[k], GRAD_REL_TOL) for k in FIELDS}
+    errs["pose"] = grad_check("pose", dpose.cpu().numpy(), gref["pose"], GRAD_REL_TOL)
     say("room grad rel err", {k: "%.2e" % v for k, v in errs.items()})
-    for k, e in errs.items():
-        assert e <= GRAD_REL_TOL, (k, e)
 
 
 def test_room_end_to_end_decode_and_render(V, room):
-    """GPU decode -> GPU render versus oracle decode -> oracle render."""
-    a, m, cam, pose, ref = room["a"], room["m"], room["cam"], room["pose"], room["ref"]
+    """GPU decode -> GPU render.  The decode is checked against the oracle's
+    (1e-5 relative per field); the render against the oracle rendering the
+    GPU's decoded FP32 Gaussians, so that keys and decisions see the same
+    inputs (MFMA accumulation order moves the decode by a few ulps)."""
+    a, m, cam, pose, g0 = room["a"], room["m"], room["cam"], room["pose"], room["g"]
     out = V.decode_anchors(dev(a.xa), dev(a.feat), dev(a.scaling), dev(a.offset), dev(m.W1), dev(m.b1),
                            dev(m.W2), dev(m.b2))
     C, D, A, st = V.render_forward(*[out[f] for f in FIELDS], cam, pose)
     torch.cuda.synchronize()
-    r = compare_images(C, D, A, ref)
-    say("room end-to-end max err colour %.2e depth %.2e alpha %.2e" % (r["color"], r["depth"], r["alpha"]))
+    gg = scenes.Gaussians(*[out[f].cpu().numpy() for f in FIELDS])
+    for f in FIELDS:
+        e = np.abs(getattr(gg, f).astype(np.float64) - getattr(g0, f)).max() / np.abs(getattr(g0, f)).max()
+        assert e <= 1e-5, (f, e)
+    ref = raster.render(gg, cam, pose)
+    compare_keys(st.view(), ref, gg.n, cam)
+    r = compare_images(C, D, A, ref, g=gg, cam=cam, pix_state=st.pixel_state(cam.width, cam.height))
+    say("room end-to-end max err colour %.2e depth %.2e alpha %.2e flagged %d" %
+        (r["color"], r["depth"], r["alpha"], r["flagged"]))
     assert r["pass_"], r

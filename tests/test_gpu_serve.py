@@ -91,7 +91,7 @@ def test_served_view_matches_oracle(V, room_map):
     trace = scenes.serve_trace(4, qps=100.0, seed=23, sizes=[(160, 120)])
     got, _ = serve_all(V, gd, trace, max_views=4, slots=1, pair_budget=1 << 22)
     for (_, cam, pose), (C, D, A) in zip(trace[:2], got[:2]):
-        r = compare_images(C, D, A, raster.render(room_map, cam, pose))
+        r = compare_images(C, D, A, raster.render(room_map, cam, pose), g=room_map, cam=cam)
         say("served vs oracle colour %.2e depth %.2e flagged %d" % (r["color"], r["depth"], r["flagged"]))
         assert r["pass_"], r
 
@@ -139,7 +139,7 @@ def test_view_dependent_server(V):
         assert_same([o for _, o in tickets], ref, cfg)
     _, cam, pose = trace[0]
     g = scenes.Gaussians(*[sets[0][f].cpu().numpy() for f in FIELDS])
-    r = compare_images(*ref[0], raster.render(g, cam, pose))
+    r = compare_images(*ref[0], raster.render(g, cam, pose), g=g, cam=cam)
     say("view-dependent served vs oracle colour %.2e depth %.2e flagged %d" % (r["color"], r["depth"], r["flagged"]))
     assert r["pass_"], r
 
