@@ -201,6 +201,8 @@ enum { VCGS_BATCH_GRAPH = 1, VCGS_BATCH_PER_VIEW = 2 };
 /* Render n_views views of the same Gaussians in one pass (the keyframes of a
  * local bundle-adjustment window, paper Sec. 3.5, or the requests of one
  * serving step), and optionally run the loss and the backward for all of them.
+ * This is the convenience form with the workload's L1 loss built in; the loss
+ * stays outside the library with vcgs_render_batch_forward / _backward below.
  *   outs: HOST array of n_views device image sets (sizes of each camera).
  *   Forward only: target_color = target_depth = grads = dl_dpose = loss = NULL.
  *   Forward + backward: target_color / target_depth are HOST arrays of
@@ -215,14 +217,43 @@ enum { VCGS_BATCH_GRAPH = 1, VCGS_BATCH_PER_VIEW = 2 };
  * pointer argument) prepares a plan: it allocates the pass's buffers and
  * synchronises `stream` once to size the pair buffers with headroom.  Later
  * calls with the same signature (poses and Gaussian values may change) reuse
- * it without synchronising.  With VCGS_BATCH_GRAPH the whole pass is captured
- * once into a hipGraph (on a library-owned stream ordered after `stream`) and
- * replayed as one launch.  If the pairs outgrow the buffers, vcgs_batch_check
- * reports VCGS_E_CAPACITY; the next call resizes and the pass must be rerun. */
+ * it without synchronising or reading anything back.  With VCGS_BATCH_GRAPH
+ * the whole pass is captured once into a hipGraph (on a library-owned stream
+ * ordered after `stream`) and replayed as one launch.  If the pairs of a pass
+ * outgrow the buffers, the pass writes only what fits and the plan keeps, on
+ * the device, the largest pair count any pass needed; vcgs_batch_check
+ * reports it (VCGS_E_CAPACITY), the next call resizes, and the passes since
+ * the previous check must be rerun. */
 int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
                       const float* const* target_color, const float* const* target_depth, float w_depth,
                       const vcgs_images* outs, vcgs_gaussian_buffers* grads, float* dl_dpose, float* loss,
                       int flags, void* stream);
+
+/* Batched pass with the loss outside the library (paper Sec. 3.5: the
+ * bundle-adjustment loss is the tracking-like colour/depth term plus SSIM,
+ * summed over the window's keyframes).  vcgs_render_batch_forward renders the
+ * views as vcgs_render_batch does (same plans, capacity handling and graph
+ * replay) and keeps the pass for one vcgs_render_batch_backward; the caller
+ * computes the per-view upstream gradients from outs in between (e.g. with
+ * vcgs_l1_loss, vcgs_track_loss, vcgs_ssim_loss). */
+int vcgs_render_batch_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
+                              const vcgs_images* outs, int flags, void* stream);
+
+/* Backward of the last vcgs_render_batch_forward of ctx.  g, views (cameras
+ * and poses) and flags must be those of that forward (VCGS_E_INVALID
+ * otherwise).  dl_dcolor, dl_ddepth, dl_dalpha: HOST arrays of n_views device
+ * pointers to each view's upstream gradient ([3][H][W], [H][W], [H][W]); an
+ * array or an entry may be NULL (zero).  grads (device, Gaussian shapes, any
+ * field NULL) are OVERWRITTEN with dL/d(mean, scale, quat, opacity, color)
+ * summed over the views (per view with VCGS_BATCH_PER_VIEW), dl_dpose (device
+ * float [n_views][6] or NULL) with each view's pose gradient, as in
+ * vcgs_render_backward.  With VCGS_BATCH_GRAPH the backward is captured into
+ * its own hipGraph the first time (and again when a pointer argument
+ * changes) and replayed. */
+int vcgs_render_batch_backward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views,
+                               const float* const* dl_dcolor, const float* const* dl_ddepth,
+                               const float* const* dl_dalpha, vcgs_gaussian_buffers* grads, float* dl_dpose,
+                               int flags, void* stream);
 
 /* vcgs_render_batch that also adds, for every Gaussian, the number of pixels
  * of all the window's views whose composite blends it to hits [n] (device
@@ -234,10 +265,22 @@ int vcgs_render_batch_hits(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_vi
                            const vcgs_images* outs, vcgs_gaussian_buffers* grads, float* dl_dpose, float* loss,
                            int flags, uint32_t* hits, void* stream);
 
-/* Waits for the last vcgs_render_batch of ctx to finish.  Returns VCGS_OK, or
- * VCGS_E_CAPACITY if its pair buffers overflowed (its results are then
- * incomplete).  pairs (optional) receives the pass's pair count. */
+/* Waits for the last batched pass of ctx to finish.  Returns VCGS_OK, or
+ * VCGS_E_CAPACITY if the pair buffers of that plan overflowed in any pass
+ * since the previous check (those passes' results are incomplete; the
+ * required pair count is then also readable with vcgs_last_required_pairs,
+ * and the flag is cleared).  pairs (optional) receives the last pass's pair
+ * count. */
 int vcgs_batch_check(vcgs_ctx* ctx, int64_t* pairs);
+
+/* After VCGS_E_CAPACITY: the pair count the overflowing pass needed (0 before
+ * any overflow).  The next pass with that plan sizes its buffers for it. */
+int64_t vcgs_last_required_pairs(const vcgs_ctx* ctx);
+
+/* Camera centres x_c = -R^T t of n_views world-to-camera poses (HOST arrays;
+ * centres [n_views][3]), the camera input of the view-dependent decode (paper
+ * eq. (9)); evaluated in binary64 and rounded to binary32. */
+void vcgs_camera_centres(int n_views, const vcgs_pose* poses, float* centres);
 
 /* ---- serving: continuous batching of novel-view requests --------------- */
 

@@ -101,7 +101,8 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
     __shared__ uint2 s_rect[kSpan];
     const int64_t n = nvis ? min((int64_t)*nvis, n_all) : n_all;
     const int64_t P = min((int64_t)*total, cap);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && overflow && (int64_t)*total > cap) *overflow = 1u;
+    // sticky: the largest pair count of any pass that outgrew the buffers since the flag was cleared
+    if (blockIdx.x == 0 && threadIdx.x == 0 && overflow && (int64_t)*total > cap) *overflow = max(*overflow, *total);
     // chunks strided by the grid, so a generous capacity does not launch blocks that only exit
     for (int64_t c = blockIdx.x; c * kChunk < P; c += gridDim.x) {  // uniform
     const int64_t p0 = c * kChunk;

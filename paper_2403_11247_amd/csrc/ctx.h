@@ -230,6 +230,8 @@ struct vcgs_ctx {
     std::vector<vcgs::BatchPlan*> plans;  // prepared batched windows, most recent last
     vcgs::BatchPlan* last_plan = nullptr;
     hipStream_t last_stream = nullptr;
+    vcgs::BatchPlan* fwd_plan = nullptr;  // last forward kept for vcgs_render_batch_backward
+    int64_t last_required_pairs = 0;      // pair count of the last pass that outgrew its buffers
     int servers = 0;  // live servers (their slot buffers come from dalloc)
 };
 

@@ -39,8 +39,10 @@ void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* po
 const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s);
 // Pairs (at most f.cap, overflow flagged in w.overflow), stable tile sort,
 // tile ranges, forward compositing.
-void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s, bool prefilled = false);
-void phase_b_prefill(Frame& f, Work& w, hipStream_t s);
+void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s, bool prefilled = false,
+             bool keep_overflow = false);
+// Zeroes the tile ranges and (unless keep_overflow) the overflow flag.
+void phase_b_prefill(Frame& f, Work& w, hipStream_t s, bool keep_overflow = false);
 
 // Significant bits of v (at least 1).
 inline int bits_for(uint32_t v)

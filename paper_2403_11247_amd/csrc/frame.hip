@@ -66,17 +66,18 @@ const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hi
 }
 
 // Zeroing of the tile ranges and the overflow flag, which phase_b needs first
-// (issued early by a caller that synchronises in between).
-void phase_b_prefill(Frame& f, Work& w, hipStream_t s)
+// (issued early by a caller that synchronises in between).  A batched plan
+// keeps its overflow flag across passes until vcgs_batch_check reads it.
+void phase_b_prefill(Frame& f, Work& w, hipStream_t s, bool keep_overflow)
 {
     launch_fill_u32(f.ranges, 0u, 2 * (int64_t)f.total_tiles, s);
-    launch_fill_u32(w.overflow, 0u, 1, s);
+    if (!keep_overflow) launch_fill_u32(w.overflow, 0u, 1, s);
 }
 
 // Pairs, stable tile sort, tile ranges, forward compositing.
-void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s, bool prefilled)
+void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s, bool prefilled, bool keep_overflow)
 {
-    if (!prefilled) phase_b_prefill(f, w, s);
+    if (!prefilled) phase_b_prefill(f, w, s, keep_overflow);
     if (f.cap > 0) {
         const Count P{f.cap, w.total};
         pf.begin(VCGS_STAGE_EMIT, s);
@@ -174,6 +175,13 @@ struct BatchPlan {
     bool tab_pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // a forward kept for the caller's backward (vcgs_render_batch_forward):
+    // the backward's own captured graph and the pointers it was captured with
+    bool split = false;
+    hipGraph_t graph_bwd = nullptr;
+    hipGraphExec_t exec_bwd = nullptr;
+    std::vector<const void*> bwd_ptrs;
+    hipEvent_t bwd_ready = nullptr;
     std::vector<void*> blocks_e, blocks_p;
     int64_t need = 0;
     vcgs_ctx* ctx = nullptr;
@@ -204,8 +212,13 @@ struct BatchPlan {
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (exec_bwd) (void)hipGraphExecDestroy(exec_bwd);
+        if (graph_bwd) (void)hipGraphDestroy(graph_bwd);
         exec = nullptr;
         graph = nullptr;
+        exec_bwd = nullptr;
+        graph_bwd = nullptr;
+        bwd_ptrs.clear();
     }
     void release_p()
     {
@@ -221,9 +234,11 @@ struct BatchPlan {
         if (pt_host) (void)hipHostFree(pt_host);
         if (host_flags) (void)hipHostFree(host_flags);
         if (tab_copied) (void)hipEventDestroy(tab_copied);
+        if (bwd_ready) (void)hipEventDestroy(bwd_ready);
         pt_host = nullptr;
         host_flags = nullptr;
         tab_copied = nullptr;
+        bwd_ready = nullptr;
     }
 };
 
@@ -236,6 +251,7 @@ void destroy_plans(vcgs_ctx* ctx)
     }
     ctx->plans.clear();
     ctx->last_plan = nullptr;
+    ctx->fwd_plan = nullptr;
     if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
     ctx->graph_stream = nullptr;
 }
@@ -246,7 +262,7 @@ static void enqueue_plan(vcgs_ctx* ctx, BatchPlan& p, const vcgs_gaussians& g, c
                          float* dl_dpose, float* loss, hipStream_t s)
 {
     const uint32_t* ord = phase_a(ctx->prof, g, p.f, p.w, s);
-    phase_b(ctx->prof, p.f, p.w, ord, s);
+    phase_b(ctx->prof, p.f, p.w, ord, s, false, true);
     if (!p.backward) return;
     ctx->prof.begin(VCGS_STAGE_LOSS, s);
     LossTab lt;
@@ -449,10 +465,11 @@ int vcgs_render_backward(vcgs_ctx* ctx, const vcgs_state* st_, const vcgs_gaussi
     return VCGS_OK;
 }
 
+// split: a forward only, kept for a later vcgs_render_batch_backward.
 static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
                              const float* const* target_color, const float* const* target_depth, float w_depth,
                              const vcgs_images* outs, vcgs_gaussian_buffers* grads, float* dl_dpose, float* loss,
-                             int flags, uint32_t* hits, void* stream)
+                             int flags, uint32_t* hits, bool split, void* stream)
 {
     if (!ctx || !views || !outs || !bg) return fail(VCGS_E_INVALID, "ctx, views, outs or bg is NULL");
     const int V = views->n_views;
@@ -487,8 +504,9 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
     }
     BatchPlan* plan = nullptr;
     for (BatchPlan* p : ctx->plans) {
-        bool same = p->n == g->n && p->V == V && p->flags == flags && p->backward == backward && p->ptrs == ptrs &&
-                    p->w_depth == w_depth && std::memcmp(p->bg, bg, sizeof(p->bg)) == 0;
+        bool same = p->n == g->n && p->V == V && p->flags == flags && p->backward == backward &&
+                    p->split == split && p->ptrs == ptrs && p->w_depth == w_depth &&
+                    std::memcmp(p->bg, bg, sizeof(p->bg)) == 0;
         for (int v = 0; same && v < V; ++v) same = std::memcmp(&p->cams[v], &views->cams[v], sizeof(vcgs_camera)) == 0;
         if (same) {
             plan = p;
@@ -500,6 +518,7 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
             BatchPlan* old = ctx->plans.front();
             (void)hipDeviceSynchronize();  // its last pass may have run on another stream
             if (ctx->last_plan == old) ctx->last_plan = nullptr;
+            if (ctx->fwd_plan == old) ctx->fwd_plan = nullptr;
             old->release();
             delete old;
             ctx->plans.erase(ctx->plans.begin());
@@ -510,6 +529,7 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
         plan->V = V;
         plan->flags = flags;
         plan->backward = backward;
+        plan->split = split;
         plan->ptrs = ptrs;
         plan->w_depth = w_depth;
         for (int i = 0; i < 3; ++i) plan->bg[i] = bg[i];
@@ -556,6 +576,7 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
             delete plan;
             return fail(VCGS_E_NOMEM, "allocation failed (batch plan)");
         }
+        launch_fill_u32(plan->w.overflow, 0u, 1, s);  // cleared again by each vcgs_batch_check
         ctx->plans.push_back(plan);
     }
     Frame& f = plan->f;
@@ -611,10 +632,9 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
     } else {
         enqueue_plan(ctx, *plan, *g, outs, target_color, target_depth, gb, dl_dpose, loss, s);
     }
-    // pair total and overflow flag are adjacent words
-    HIP_TRY(hipMemcpyAsync(plan->host_flags, plan->w.total, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     ctx->last_plan = plan;
     ctx->last_stream = s;
+    if (split) ctx->fwd_plan = plan;
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return VCGS_OK;
@@ -626,7 +646,7 @@ int vcgs_render_batch(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* 
                       int flags, void* stream)
 {
     return render_batch_impl(ctx, g, views, bg, target_color, target_depth, w_depth, outs, grads, dl_dpose, loss,
-                             flags, nullptr, stream);
+                             flags, nullptr, false, stream);
 }
 
 int vcgs_render_batch_hits(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
@@ -636,7 +656,101 @@ int vcgs_render_batch_hits(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_vi
 {
     if (!hits) return fail(VCGS_E_INVALID, "hits is NULL");
     return render_batch_impl(ctx, g, views, bg, target_color, target_depth, w_depth, outs, grads, dl_dpose, loss,
-                             flags, hits, stream);
+                             flags, hits, false, stream);
+}
+
+int vcgs_render_batch_forward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views, const float bg[3],
+                              const vcgs_images* outs, int flags, void* stream)
+{
+    return render_batch_impl(ctx, g, views, bg, nullptr, nullptr, 0.0f, outs, nullptr, nullptr, nullptr, flags,
+                             nullptr, true, stream);
+}
+
+int vcgs_render_batch_backward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_views* views,
+                               const float* const* dl_dcolor, const float* const* dl_ddepth,
+                               const float* const* dl_dalpha, vcgs_gaussian_buffers* grads, float* dl_dpose,
+                               int flags, void* stream)
+{
+    if (!ctx || !views) return fail(VCGS_E_INVALID, "ctx or views is NULL");
+    BatchPlan* p = ctx->fwd_plan;
+    if (!p) return fail(VCGS_E_INVALID, "no batched forward (vcgs_render_batch_forward) to differentiate");
+    const int V = views->n_views;
+    int rc;
+    if ((rc = check_gaussians(g, std::max(V, 1))) != VCGS_OK) return rc;
+    if (V != p->V || g->n != p->n || flags != p->flags || !views->cams || !views->poses)
+        return fail(VCGS_E_INVALID, "views, Gaussian count or flags differ from the last batched forward");
+    const void* gp[5] = {g->mean, g->scale, g->quat, g->opacity, g->color};
+    for (int i = 0; i < 5; ++i)
+        if (p->ptrs[i] != gp[i]) return fail(VCGS_E_INVALID, "Gaussians differ from the last batched forward");
+    for (int v = 0; v < V; ++v) {
+        if (std::memcmp(&p->cams[v], &views->cams[v], sizeof(vcgs_camera)) != 0)
+            return fail(VCGS_E_INVALID, "cameras differ from the last batched forward");
+        const PoseK pk = make_posek(views->poses[v]);
+        if (std::memcmp(&pk, &p->f.pt.pose[v], sizeof(PoseK)) != 0)
+            return fail(VCGS_E_INVALID, "poses differ from the last batched forward");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!p->g2) {
+        p->pb = std::max(1, preprocess_bwd_blocks(p->f.n));
+        p->g2 = p->get_e<float>((int64_t)kG2 * p->f.E);
+        p->partial = p->get_e<float>(6 * (int64_t)p->pb * V);
+        if (!p->ok()) {
+            // the failed blocks stay listed (null) until the plan is released; later calls refuse
+            return fail(VCGS_E_NOMEM, "allocation failed (batch backward)");
+        }
+    }
+    if (!p->ok()) return fail(VCGS_E_NOMEM, "allocation failed (batch backward)");
+    const vcgs_gaussian_buffers gb =
+        grads ? *grads : vcgs_gaussian_buffers{nullptr, nullptr, nullptr, nullptr, nullptr};
+    Frame fb = p->f;  // the forward's tables with this call's upstream gradients
+    std::vector<const void*> key = {gb.mean, gb.scale, gb.quat, gb.opacity, gb.color, dl_dpose};
+    for (int v = 0; v < V; ++v) {
+        fb.vt.dl_dc[v] = dl_dcolor ? dl_dcolor[v] : nullptr;
+        fb.vt.dl_dd[v] = dl_ddepth ? dl_ddepth[v] : nullptr;
+        fb.vt.dl_da[v] = dl_dalpha ? dl_dalpha[v] : nullptr;
+        key.push_back(fb.vt.dl_dc[v]);
+        key.push_back(fb.vt.dl_dd[v]);
+        key.push_back(fb.vt.dl_da[v]);
+    }
+    if (flags & VCGS_BATCH_GRAPH) {
+        if (!ctx->graph_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking));
+        hipStream_t gs = ctx->graph_stream;
+        if (!p->bwd_ready) HIP_TRY(hipEventCreateWithFlags(&p->bwd_ready, hipEventDisableTiming));
+        if (!p->exec_bwd || p->bwd_ptrs != key) {
+            if (p->exec_bwd) (void)hipGraphExecDestroy(p->exec_bwd);
+            if (p->graph_bwd) (void)hipGraphDestroy(p->graph_bwd);
+            p->exec_bwd = nullptr;
+            p->graph_bwd = nullptr;
+            HIP_TRY(hipStreamSynchronize(s));
+            ctx->prof.capturing = true;
+            hipError_t e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                backward_core(ctx, fb, *g, gb, dl_dpose, p->g2, p->partial, p->pb, gs);
+                e = hipStreamEndCapture(gs, &p->graph_bwd);
+            }
+            ctx->prof.capturing = false;
+            if (e == hipSuccess) e = hipGraphInstantiate(&p->exec_bwd, p->graph_bwd, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                if (p->graph_bwd) (void)hipGraphDestroy(p->graph_bwd);
+                p->graph_bwd = nullptr;
+                p->exec_bwd = nullptr;
+                return fail(VCGS_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+            }
+            p->bwd_ptrs = key;
+        }
+        HIP_TRY(hipEventRecord(p->bwd_ready, s));
+        HIP_TRY(hipStreamWaitEvent(gs, p->bwd_ready, 0));
+        HIP_TRY(hipGraphLaunch(p->exec_bwd, gs));
+        HIP_TRY(hipEventRecord(ctx->graph_done, gs));
+        HIP_TRY(hipStreamWaitEvent(s, ctx->graph_done, 0));
+    } else {
+        backward_core(ctx, fb, *g, gb, dl_dpose, p->g2, p->partial, p->pb, s);
+    }
+    ctx->last_stream = s;
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return VCGS_OK;
 }
 
 int vcgs_batch_check(vcgs_ctx* ctx, int64_t* pairs)
@@ -647,14 +761,36 @@ int vcgs_batch_check(vcgs_ctx* ctx, int64_t* pairs)
     if (!p) return VCGS_OK;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(hipStreamSynchronize(ctx->last_stream));
+    // pair total of the last pass and the sticky overflow word are adjacent
+    HIP_TRY(hipMemcpy(p->host_flags, p->w.total, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost));
     const int64_t total = p->host_flags[0];
+    const int64_t over = p->host_flags[1];
     if (pairs) *pairs = total;
-    if (p->host_flags[1] != 0u) {
-        p->need = total;
-        return fail(VCGS_E_CAPACITY, "pair buffer of the batched pass was too small (" + std::to_string(total) +
-                                         " pairs); the next call resizes it, rerun the pass");
+    if (over != 0) {
+        p->need = over;
+        ctx->last_required_pairs = over;
+        launch_fill_u32(p->w.overflow, 0u, 1, ctx->last_stream);
+        HIP_TRY(hipStreamSynchronize(ctx->last_stream));
+        return fail(VCGS_E_CAPACITY, "pair buffer of a batched pass was too small (" + std::to_string(over) +
+                                         " pairs needed); the next call resizes it, rerun the pass");
     }
     return VCGS_OK;
+}
+
+int64_t vcgs_last_required_pairs(const vcgs_ctx* ctx)
+{
+    return ctx ? ctx->last_required_pairs : 0;
+}
+
+void vcgs_camera_centres(int n_views, const vcgs_pose* poses, float* centres)
+{
+    // paper eq. (9): the camera centre of a world-to-camera pose {R|t} is -R^T t
+    for (int v = 0; poses && centres && v < n_views; ++v) {
+        const float* R = poses[v].R;
+        const float* t = poses[v].t;
+        for (int i = 0; i < 3; ++i)
+            centres[3 * v + i] = (float)(-((double)R[i] * t[0] + (double)R[3 + i] * t[1] + (double)R[6 + i] * t[2]));
+    }
 }
 
 }  // extern "C"

@@ -122,7 +122,7 @@ constexpr uint32_t kDropKey = 0xFFFFFFFFu;
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
                    hipStream_t s, const uint32_t** kept = nullptr, const uint32_t* keys_src = nullptr);
 // Exclusive scan of n uint32 values (out may equal in); if total != nullptr
-// the sum is written there.
+// the sum is written there.  Sums saturate at 2^31 instead of wrapping.
 void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
                         hipStream_t s);
 
@@ -138,7 +138,8 @@ void launch_gather_counts(int64_t n, const uint32_t* order, const uint32_t* coun
                           uint32_t* out, hipStream_t s);
 // Entries k < min(n_entries, *nvis) of the depth order (offsets offs and
 // counts cnt in that order) emit their pairs; writes pairs p < cap only; if the
-// total exceeds cap sets *overflow = 1 (when non-null).  chunk_start: scratch
+// total exceeds cap raises *overflow to the total (when non-null; the flag
+// keeps the largest such total until the host clears it).  chunk_start: scratch
 // of emit_chunk_words(cap) words.
 void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis, const uint32_t* order,
                        const uint32_t* offs, const uint32_t* cnt, const uint2* rect, uint32_t* chunk_start,

@@ -419,18 +419,31 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
             const float rz = slab_z[wave][k];
             const float i1 = -2.0f * kLn2 * rb.z, i2 = -2.0f * kLn2 * rb.w;  // eigenvalues of Q
             const float dx = (pxf - ra.x) - ra.z;
+            // footprints first: a wave-entry that blends into none of the wave's
+            // pixels changes no state and adds nothing, so it skips the adjoint
+            Fp fj[PPL];
+            bool cj[PPL];
+            float dyv[PPL];
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                dyv[j] = (pyf[j] - ra.y) - ra.w;
+                fj[j] = footprint(dx, dyv[j], rb.x, rb.y, rb.z, rb.w, rc.x);
+                const bool in = local < last[j];
+                cj[j] = in && fj[j].alpha >= kAlphaMin;
+                if (COUNT) { n_eval += in ? 1u : 0u; n_blend += cj[j] ? 1u : 0u; }
+                any = any || cj[j];
+            }
+            if (__ballot(any) == 0ull) continue;
             float p[10];
 #pragma unroll
             for (int i = 0; i < 10; ++i) p[i] = 0.0f;
-            bool contrib = false;
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 // branch-free: every lane evaluates, only contributing pixels change state
-                const float dyj = (pyf[j] - ra.y) - ra.w;
-                const Fp f = footprint(dx, dyj, rb.x, rb.y, rb.z, rb.w, rc.x);
-                const bool in = local < last[j];
-                const bool c = in && f.alpha >= kAlphaMin;
-                if (COUNT) { n_eval += in ? 1u : 0u; n_blend += c ? 1u : 0u; }
+                const float dyj = dyv[j];
+                const Fp& f = fj[j];
+                const bool c = cj[j];
                 const float a = f.alpha;
                 const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
                 const float x[5] = {rc.y, rc.z, rc.w, rz, 1.0f};
@@ -460,9 +473,7 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
                 p[4] += dp * (-0.5f * dyj * dyj);
                 p[5] += dg * f.G;
                 T[j] = c ? Ti : T[j];
-                contrib = contrib || c;
             }
-            if (__ballot(contrib) == 0ull) continue;
             const float rsum = reduce_scatter10(p, lane);
             if (rsv) pend[wave][npend][lane >> 4][rsi] = rsum;
             if (lane == 0) pend_gid[wave][npend] = slab_gid[wave][k];

@@ -62,13 +62,23 @@ __device__ __forceinline__ int64_t dev_count(int64_t cap, const uint32_t* dev)
 // Exclusive scan
 // ---------------------------------------------------------------------------
 
+// Sums in the scan saturate at kScanSat: a pair count of 2^31 or more reads as
+// 2^31 instead of wrapping, so the callers' limit of 2^30 - 1 pairs refuses it.
+// min(a + b, kScanSat) is associative, so every prefix below the bound is exact.
+constexpr uint32_t kScanSat = 0x80000000u;
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b)
+{
+    const uint32_t s = a + b;
+    return (s < a || s > kScanSat) ? kScanSat : s;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
     const unsigned lane = __lane_id();
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t t = __shfl_up(v, o, 64);
-        if (lane >= (unsigned)o) v += t;
+        if (lane >= (unsigned)o) v = sat_add(v, t);
     }
     return v;
 }
@@ -81,16 +91,17 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
     const int w = threadIdx.x >> 6;
     const uint32_t inc = wave_incl_scan(v);
     if (__lane_id() == 63) ws[w] = inc;
+    const uint32_t prev = __shfl_up(inc, 1, 64);
     __syncthreads();
     uint32_t off = 0, tot = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        if (i < w) off += ws[i];
-        tot += ws[i];
+        if (i < w) off = sat_add(off, ws[i]);
+        tot = sat_add(tot, ws[i]);
     }
     __syncthreads();
     *total = tot;
-    return off + inc - v;
+    return sat_add(off, __lane_id() == 0 ? 0u : prev);
 }
 
 __global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
@@ -101,7 +112,7 @@ __global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __rest
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
         const int64_t idx = base + i * kThreads + threadIdx.x;
-        if (idx < n) s += in[idx];
+        if (idx < n) s = sat_add(s, in[idx]);
     }
     uint32_t tot;
     (void)block_excl_scan(s, &tot);
@@ -120,15 +131,15 @@ __global__ void __launch_bounds__(kThreads) k_scan_down(const uint32_t* __restri
     for (int i = 0; i < kItems; ++i) {
         const int64_t idx = base + i;
         v[i] = idx < n ? in[idx] : 0u;
-        s += v[i];
+        s = sat_add(s, v[i]);
     }
     uint32_t tot;
-    uint32_t run = block_excl_scan(s, &tot) + (bases ? bases[blockIdx.x] : 0u);
+    uint32_t run = sat_add(block_excl_scan(s, &tot), bases ? bases[blockIdx.x] : 0u);
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
         const int64_t idx = base + i;
         if (idx < n) out[idx] = run;
-        run += v[i];
+        run = sat_add(run, v[i]);
     }
     if (total && threadIdx.x == kThreads - 1 && blockIdx.x == gridDim.x - 1) *total = run;
 }

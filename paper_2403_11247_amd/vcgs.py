@@ -4,8 +4,10 @@ device memory and the current stream.
 
 The functions mirror the C ABI in include/vcgs.h:
     render_forward, render_backward, l1_loss, decode_anchors,
-    decode_anchors_backward, render_batch_* (batched views)
-and ``RenderFn`` / ``DecodeFn`` wrap them as ``torch.autograd.Function``s.
+    decode_anchors_backward, BatchWindow (vcgs_render_batch*: batched views),
+    Server (continuous batching), the mask, R-VQ and tracking losses;
+and ``RenderFn`` (``render``) / ``DecodeFn`` (``decode``) wrap the render and the
+decode as ``torch.autograd.Function``s.
 """
 from __future__ import annotations
 
@@ -107,8 +109,11 @@ def lib():
                      "vcgs_mask_loss", "vcgs_mask_prune", "vcgs_rvq_assign", "vcgs_track_loss",
                      "vcgs_icp_loss", "vcgs_ssim_loss", "vcgs_render_batch_hits", "vcgs_set_allocator",
                      "vcgs_decode_anchors_views", "vcgs_decode_anchors_views_backward",
-                     "vcgs_server_create_anchors", "vcgs_profile_stages", "vcgs_centre_pose_grad"):
+                     "vcgs_server_create_anchors", "vcgs_profile_stages", "vcgs_centre_pose_grad",
+                     "vcgs_render_batch_forward", "vcgs_render_batch_backward"):
             getattr(L, name).restype = ctypes.c_int
+        L.vcgs_last_required_pairs.restype = ctypes.c_int64
+        L.vcgs_camera_centres.restype = None
         L.vcgs_destroy.restype = None
         L.vcgs_state_free.restype = None
         L.vcgs_server_destroy.restype = None
@@ -302,8 +307,9 @@ def _wrap(ptr, count, dtype, device):
 def _gauss(means, scales, quats, opacities, colors):
     n = int(opacities.shape[0])
     ts = [_dev(x) for x in (means, scales, quats, opacities, colors)]
-    assert ts[0].shape == (3, n) and ts[1].shape == (3, n) and ts[2].shape == (4, n) and ts[4].shape == (3, n), \
-        "Gaussian attributes must be SoA: mean/scale/color (3, n), quat (4, n), opacity (n,)"
+    if not (ts[0].shape == (3, n) and ts[1].shape == (3, n) and ts[2].shape == (4, n) and ts[3].shape == (n,)
+            and ts[4].shape == (3, n)):
+        raise VcgsError("Gaussian attributes must be SoA: mean/scale/color (3, n), quat (4, n), opacity (n,)")
     return CGaussians(n, *[_ptr(t) for t in ts]), ts
 
 
@@ -339,6 +345,8 @@ def render_forward(means, scales, quats, opacities, colors, camera, pose, bg=(0.
 def render_backward(state: State, means, scales, quats, opacities, colors, camera, pose, dl_dcolor=None,
                     dl_ddepth=None, dl_dalpha=None):
     """Backward render.  Returns (dict of attribute gradients, dL/dxi (6,))."""
+    if state is None or state.h is None:
+        raise VcgsError("render_backward: the forward's state was freed (or the forward kept none)")
     ctx = state.ctx
     g, keep = _gauss(means, scales, quats, opacities, colors)
     dev = means.device
@@ -385,25 +393,62 @@ class RenderFn(torch.autograd.Function):
 
     @staticmethod
     def backward(fctx, dl_dcolor, dl_ddepth, dl_dalpha):
+        # the saved state lives as long as the autograd graph (State frees it
+        # when collected), so a graph kept with retain_graph=True replays again
         means, scales, quats, opacities, colors = fctx.saved_tensors
         grads, dpose = render_backward(fctx.state, means, scales, quats, opacities, colors, fctx.camera, fctx.pose,
                                        dl_dcolor, dl_ddepth, dl_dalpha)
-        fctx.state.free()
         return (grads["mean"], grads["scale"], grads["quat"], grads["opacity"], grads["color"], dpose,
                 None, None, None)
 
 
 def render(means, scales, quats, opacities, colors, camera, pose, pose_tangent=None, bg=(0.0, 0.0, 0.0)):
+    """Differentiable render (RenderFn): (colour, depth, alpha); gradients reach
+    the Gaussian attributes and, through ``pose_tangent``, the pose."""
     if pose_tangent is None:
         pose_tangent = torch.zeros(6, dtype=torch.float32, device=means.device)
     return RenderFn.apply(means, scales, quats, opacities, colors, pose_tangent, camera, pose, bg)
 
 
+class DecodeFn(torch.autograd.Function):
+    """Differentiable anchor decode (eqs. (7)-(9)): anchors and MLP weights to
+    the Gaussian attributes.  ``cam_centre`` (a (3,) tensor, or None for the
+    feature-only decode with a (32, 32) W1) makes it view-dependent (W1
+    (32, 36)); its gradient is dL/d(camera centre)."""
+
+    @staticmethod
+    def forward(fctx, xa, feat, scaling, offset, W1, b1, W2, b2, cam_centre=None):
+        cc = None if cam_centre is None else cam_centre.detach().cpu().numpy()
+        out = decode_anchors(xa, feat, scaling, offset, W1, b1, W2, b2, cam_centre=cc)
+        fctx.cc = cc
+        fctx.save_for_backward(xa, feat, scaling, offset, W1, b1, W2, b2)
+        return out["mean"], out["scale"], out["quat"], out["opacity"], out["color"]
+
+    @staticmethod
+    def backward(fctx, dmean, dscale, dquat, dopac, dcolor):
+        xa, feat, scaling, offset, W1, b1, W2, b2 = fctx.saved_tensors
+        dG = {"mean": dmean, "scale": dscale, "quat": dquat, "opacity": dopac, "color": dcolor}
+        dG = {k: None if v is None else v.contiguous() for k, v in dG.items()}
+        g = decode_anchors_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG, cam_centre=fctx.cc)
+        return (g["xa"], g["feat"], g["scaling"], g["offset"], g["W1"], g["b1"], g["W2"], g["b2"],
+                g["cam"] if fctx.cc is not None else None)
+
+
+def decode(xa, feat, scaling, offset, W1, b1, W2, b2, cam_centre=None):
+    """Differentiable decode (DecodeFn): (mean, scale, quat, opacity, colour)."""
+    return DecodeFn.apply(xa, feat, scaling, offset, W1, b1, W2, b2, cam_centre)
+
+
 def _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx, in_dim=32):
     na, k = int(feat.shape[0]), int(offset.shape[1])
     ts = [_dev(t) for t in (xa, feat, scaling, offset, W1, b1, W2, b2)]
-    assert ts[0].shape == (3, na) and ts[1].shape == (na, 32) and ts[2].shape == (3, na) and ts[3].shape == (na, k, 3)
-    assert ts[4].shape == (32, in_dim) and ts[6].shape == (k * 11, 32), "W1 must be (32, 32), or (32, 36) with a camera"
+    if not (ts[0].shape == (3, na) and ts[1].shape == (na, 32) and ts[2].shape == (3, na)
+            and ts[3].shape == (na, k, 3)):
+        raise VcgsError("anchors must be xa (3, na), feat (na, 32), scaling (3, na), offset (na, k, 3)")
+    if not (ts[4].shape == (32, in_dim) and ts[5].shape == (32,) and ts[6].shape == (k * 11, 32)
+            and ts[7].shape == (k * 11,)):
+        raise VcgsError(f"MLP must be W1 (32, {in_dim}), b1 (32,), W2 (k*11, 32), b2 (k*11,)"
+                        + (" (W1 (32, 36) with a camera centre)" if in_dim == 32 else ""))
     a = CAnchors(na, k, 32, *[_ptr(t) for t in ts[:4]])
     m = CMLP(*[_ptr(t) for t in ts[4:]])
     cb = None
@@ -417,14 +462,23 @@ def _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx, in_di
     return a, m, cb, ts, na, k
 
 
+def _dG(dG, lead, n):
+    """Validated upstream gradients of decoded Gaussians (None = zero)."""
+    shapes = {"mean": (3, n), "scale": (3, n), "quat": (4, n), "opacity": (n,), "color": (3, n)}
+    return {f: None if dG.get(f) is None else _arg(_dev(dG[f]), lead + sh, "dG " + f) for f, sh in shapes.items()}
+
+
 def _centre(cam_centre):
     return None if cam_centre is None else (c_f * 3)(*[float(x) for x in np.asarray(cam_centre).reshape(3)])
 
 
 def camera_centre(pose):
-    """Camera centre -R^T t of a world-to-camera pose."""
-    R = np.asarray(pose.R, np.float64)
-    return -R.T @ np.asarray(pose.t, np.float64)
+    """Camera centre -R^T t of a world-to-camera pose (eq. (9)'s x_c), computed
+    by the library (vcgs_camera_centres); float32 (3,)."""
+    out = (c_f * 3)()
+    ps = pose_struct(pose)
+    lib().vcgs_camera_centres(c_i32(1), ctypes.byref(ps), out)
+    return np.array(out[:], np.float32)
 
 
 def add_centre_pose_grad(poses, dcam, dpose, ctx: Context | None = None):
@@ -482,7 +536,7 @@ def decode_anchors_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG, books
     ctx = ctx or default_context()
     a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx,
                                             32 if cam_centre is None else 36)
-    dg = {f: None if dG.get(f) is None else _dev(dG[f]) for f in ("mean", "scale", "quat", "opacity", "color")}
+    dg = _dG(dG, (), na * k)
     gb = CGaussianBuffers(*[_ptr(dg[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
     out = {"feat": torch.empty_like(keep[1]), "offset": torch.empty_like(keep[3]),
            "scaling": torch.empty_like(keep[2]), "xa": torch.empty_like(keep[0]), "W1": torch.empty_like(keep[4]),
@@ -542,7 +596,7 @@ def decode_anchors_views_backward(xa, feat, scaling, offset, W1, b1, W2, b2, dG,
     ctx = ctx or default_context()
     a, m, cb, keep, na, k = _anchor_structs(xa, feat, scaling, offset, W1, b1, W2, b2, books, idx, 36)
     V, cc = _centres(cam_centres)
-    dg = {f: None if dG.get(f) is None else _dev(dG[f]) for f in ("mean", "scale", "quat", "opacity", "color")}
+    dg = _dG(dG, (V,), na * k)
     gb = CGaussianBuffers(*[_ptr(dg[f]) for f in ("mean", "scale", "quat", "opacity", "color")])
     out = {"feat": torch.empty_like(keep[1]), "offset": torch.empty_like(keep[3]),
            "scaling": torch.empty_like(keep[2]), "xa": torch.empty_like(keep[0]), "W1": torch.empty_like(keep[4]),
@@ -673,7 +727,8 @@ def rvq_assign(books, x, idx_bytes=1, idx=True, recon=True, loss=True, dbooks=No
     xx = _dev(x)
     L, P, D = (int(v) for v in b.shape)
     n = int(xx.shape[0])
-    assert xx.shape == (n, D), "x must be (n, D) with the codebooks' D"
+    if tuple(xx.shape) != (n, D):
+        raise VcgsError("x must be (n, D) with the codebooks' D")
     out = {"idx": None, "recon": None, "loss": None, "dbooks": None}
     if idx:
         out["idx"] = torch.empty((L, n), dtype=torch.uint8 if idx_bytes == 1 else torch.int32, device=b.device)
@@ -768,7 +823,8 @@ class BatchWindow:
         self.dev = torch.device("cuda", self.ctx.device if device is None else device)
         self.cameras = list(cameras)
         self.V = len(self.cameras)
-        assert 1 <= self.V <= 16
+        if not 1 <= self.V <= 16:
+            raise VcgsError("a batched pass takes 1 to 16 views")
         self.n = int(n)
         self.backward = backward
         self.flags = (VCGS_BATCH_GRAPH if graph else 0) | (VCGS_BATCH_PER_VIEW if per_view else 0)
@@ -803,17 +859,20 @@ class BatchWindow:
             ts = [_dev(x) for x in (means, scales, quats, opacities, colors)]
             shapes = [(self.V, 3, self.n), (self.V, 3, self.n), (self.V, 4, self.n), (self.V, self.n),
                       (self.V, 3, self.n)]
-            assert all(tuple(t.shape) == sh for t, sh in zip(ts, shapes)), "per-view sets are stacked (V, ., n)"
+            if not all(tuple(t.shape) == sh for t, sh in zip(ts, shapes)):
+                raise VcgsError("per-view sets are stacked (V, ., n)")
             g, keep = CGaussians(self.n, *[_ptr(t) for t in ts]), ts
         else:
             g, keep = _gauss(means, scales, quats, opacities, colors)
-        assert g.n == self.n and len(poses) == self.V
+        if g.n != self.n or len(poses) != self.V:
+            raise VcgsError(f"the window was made for {self.n} Gaussians and {self.V} poses")
         views = CViews(self.V, ctypes.cast(self.c_cams, c_p),
                        ctypes.cast((CPose * self.V)(*[pose_struct(p) for p in poses]), c_p))
         self._views_keep = views
         tc = td = None
         if self.backward:
-            assert targets is not None and len(targets) == self.V
+            if targets is None or len(targets) != self.V:
+                raise VcgsError("the backward needs one (colour, depth) target per view")
             self._tkeep = [(_arg(_dev(t[0]), (3, int(c.height), int(c.width)), "target colour"),
                             _arg(_dev(t[1]), (int(c.height), int(c.width)), "target depth"))
                            for t, c in zip(targets, self.cameras)]
@@ -887,6 +946,9 @@ class Server:
         if out is None:
             out = (torch.empty((3, H, W), device=self.dev), torch.empty((H, W), device=self.dev),
                    torch.empty((H, W), device=self.dev))
+        else:
+            out = (_arg(out[0], (3, H, W), "out colour"), _arg(out[1], (H, W), "out depth"),
+                   _arg(out[2], (H, W), "out alpha"))
         imgs = CImages(_ptr(out[0]), _ptr(out[1]), _ptr(out[2]))
         t = c_i64()
         _check(lib().vcgs_server_submit(self.h, ctypes.byref(camera_struct(camera)), ctypes.byref(pose_struct(pose)),
