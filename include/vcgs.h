@@ -145,6 +145,28 @@ int vcgs_render_backward(vcgs_ctx* ctx, const vcgs_state* state, const vcgs_gaus
 
 void vcgs_state_free(vcgs_ctx* ctx, vcgs_state* state);
 
+/* Allocation-free forward render, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and images as vcgs_render_forward with
+ * state = NULL, from the same kernels, but every buffer of the pass comes
+ * from one fixed device array of VCGS_NOALLOC_SCRATCH_BYTES (128 MiB) per
+ * GPU, held from the first vcgs_create on that GPU until the process ends;
+ * the call makes no hipMalloc, hipFree or other allocating call.
+ *   Sizes: the pass needs about 104 bytes per Gaussian, 8 per pixel and 16 per
+ *   (tile, Gaussian) pair (one 1200x680 view of 400k Gaussians with 2.3M pairs
+ *   takes about 85 MB).  A pass that does not fit returns VCGS_E_CAPACITY
+ *   before any launch (Gaussians and pixels) or after the pair count is known
+ *   (pairs; vcgs_last_required_pairs then holds the count); the output images
+ *   are left unwritten.
+ *   Like vcgs_render_forward it synchronises `stream` once, after binning.
+ *   Every call on one GPU, from any context or thread, uses that GPU's one
+ *   array and leaves its contents behind: calls that overlap in time on one
+ *   GPU (other streams, other threads) race and must be serialised by the
+ *   caller.  The kernels clear what they need before use. */
+#define VCGS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int vcgs_render_forward_noalloc(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_camera* cam,
+                                const vcgs_pose* pose, const float bg[3], vcgs_images* out, void* stream);
+
 /* Read-only view of a saved state, for inspection and tests.  Device pointers
  * stay valid until vcgs_state_free.
  *   depth_bits[n]  uint32 bits of the float camera depth (0xFFFFFFFF = culled)

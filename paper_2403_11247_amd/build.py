@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvcgs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["api.hip", "frame.hip", "preprocess.hip", "sort.hip", "binning.hip", "render.hip", "decode.hip", "serve.hip", "mask.hip", "rvq.hip", "track.hip"]
+SOURCES = ["api.hip", "frame.hip", "preprocess.hip", "sort.hip", "binning.hip", "render.hip", "decode.hip", "serve.hip", "mask.hip", "rvq.hip", "track.hip", "noalloc.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function",
          "-Wno-unused-variable", "-Wno-unknown-pragmas"]

@@ -28,6 +28,8 @@ int vcgs_create(int device, vcgs_ctx** out)
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(VCGS_E_UNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", not gfx950");
     HIP_TRY(hipSetDevice(device));
+    int rc = noalloc_init(device);
+    if (rc != VCGS_OK) return rc;
     vcgs_ctx* c = new vcgs_ctx();
     c->device = device;
     c->pool.dev = &c->dalloc;

@@ -237,4 +237,7 @@ struct vcgs_ctx {
 
 namespace vcgs {
 void destroy_plans(vcgs_ctx* ctx);
+// Device address of the allocation-free forward's scratch array on `device`
+// (which must be current); looked up once per device.
+int noalloc_init(int device);
 }  // namespace vcgs

@@ -110,7 +110,7 @@ def lib():
                      "vcgs_icp_loss", "vcgs_ssim_loss", "vcgs_render_batch_hits", "vcgs_set_allocator",
                      "vcgs_decode_anchors_views", "vcgs_decode_anchors_views_backward",
                      "vcgs_server_create_anchors", "vcgs_profile_stages", "vcgs_centre_pose_grad",
-                     "vcgs_render_batch_forward", "vcgs_render_batch_backward"):
+                     "vcgs_render_batch_forward", "vcgs_render_batch_backward", "vcgs_render_forward_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         L.vcgs_last_required_pairs.restype = ctypes.c_int64
         L.vcgs_camera_centres.restype = None
@@ -340,6 +340,41 @@ def render_forward(means, scales, quats, opacities, colors, camera, pose, bg=(0.
     st = State(ctx, h) if keep_state else None
     del keep
     return color, depth, alpha, st
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def render_forward_noalloc(means, scales, quats, opacities, colors, camera, pose, out, bg=(0.0, 0.0, 0.0),
+                           ctx: Context | None = None):
+    """Forward render without device allocation (vcgs_render_forward_noalloc):
+    the library takes every buffer of the pass from its fixed per-GPU scratch
+    array, and the images go into the caller's ``out`` = (color (3,H,W),
+    depth (H,W), alpha (H,W)).  No state is kept.  Raises VcgsError (code -3)
+    when the pass does not fit the array.  Calls that overlap in time on one
+    GPU race on the array."""
+    ctx = ctx or default_context()
+    g, keep = _gauss(means, scales, quats, opacities, colors)
+    H, W = int(camera.height), int(camera.width)
+    if out is None or len(out) != 3:
+        raise VcgsError("out must be (color, depth, alpha) device tensors")
+    color = _arg(out[0], (3, H, W), "out color")
+    depth = _arg(out[1], (H, W), "out depth")
+    alpha = _arg(out[2], (H, W), "out alpha")
+    imgs = CImages(_ptr(color), _ptr(depth), _ptr(alpha))
+    cam, ps = camera_struct(camera), pose_struct(pose)
+    bgv = (c_f * 3)(*[float(b) for b in bg])
+    _check(lib().vcgs_render_forward_noalloc(ctx.h, ctypes.byref(g), ctypes.byref(cam), ctypes.byref(ps), bgv,
+                                             ctypes.byref(imgs), _stream()))
+    del keep
+    return color, depth, alpha
+
+
+def last_required_pairs(ctx: Context | None = None) -> int:
+    """(tile, Gaussian) pair count of the last pass of this context that
+    outgrew its pair buffers (vcgs_last_required_pairs)."""
+    ctx = ctx or default_context()
+    return int(lib().vcgs_last_required_pairs(ctx.h))
 
 
 def render_backward(state: State, means, scales, quats, opacities, colors, camera, pose, dl_dcolor=None,
