@@ -3,11 +3,14 @@ the render and decode runs in the library's HIP kernels; PyTorch provides the
 device memory and the current stream.
 
 The functions mirror the C ABI in include/vcgs.h:
-    render_forward, render_backward, l1_loss, decode_anchors,
-    decode_anchors_backward, BatchWindow (vcgs_render_batch*: batched views),
+    render_forward, render_backward, render_forward_noalloc, l1_loss,
+    decode_anchors, decode_anchors_backward, BatchWindow (vcgs_render_batch:
+    batched views with the L1 loss built in), BatchRender
+    (vcgs_render_batch_forward / _backward: batched views, loss outside),
     Server (continuous batching), the mask, R-VQ and tracking losses;
-and ``RenderFn`` (``render``) / ``DecodeFn`` (``decode``) wrap the render and the
-decode as ``torch.autograd.Function``s.
+and ``RenderFn`` (``render``), ``BatchRenderFn`` (``render_views``) and
+``DecodeFn`` (``decode``) wrap the render, the batched render and the decode
+as ``torch.autograd.Function``s.
 """
 from __future__ import annotations
 
@@ -26,6 +29,9 @@ c_f = ctypes.c_float
 c_i32 = ctypes.c_int32
 c_i64 = ctypes.c_int64
 c_p = ctypes.c_void_p
+
+
+FIELD_NAMES = ("mean", "scale", "quat", "opacity", "color")
 
 
 class CCamera(ctypes.Structure):
@@ -936,6 +942,140 @@ class BatchWindow:
             break
         del keep
         return self
+
+
+class BatchRender:
+    """A batched pass with the loss outside the library
+    (vcgs_render_batch_forward / vcgs_render_batch_backward): ``forward``
+    renders up to 16 views of one map into persistent images (``outs``), the
+    caller computes each view's upstream gradients from them (L1, SSIM, a
+    tracking loss, ...), and ``backward`` returns the Gaussian gradients summed
+    over the views (per view with ``per_view``) and each view's pose gradient.
+    Only the most recent forward of the context can be differentiated."""
+
+    def __init__(self, n, cameras, graph=False, per_view=False, bg=(0.0, 0.0, 0.0), ctx=None, device=None):
+        self.ctx = ctx or default_context()
+        self.dev = torch.device("cuda", self.ctx.device if device is None else device)
+        self.cameras = list(cameras)
+        self.V = len(self.cameras)
+        if not 1 <= self.V <= 16:
+            raise VcgsError("a batched pass takes 1 to 16 views")
+        self.n = int(n)
+        self.per_view = per_view
+        self.flags = (VCGS_BATCH_GRAPH if graph else 0) | (VCGS_BATCH_PER_VIEW if per_view else 0)
+        self.bg = (c_f * 3)(*[float(b) for b in bg])
+        self.outs = [(torch.empty((3, int(c.height), int(c.width)), device=self.dev),
+                      torch.empty((int(c.height), int(c.width)), device=self.dev),
+                      torch.empty((int(c.height), int(c.width)), device=self.dev)) for c in self.cameras]
+        self.c_outs = (CImages * self.V)(*[CImages(_ptr(o[0]), _ptr(o[1]), _ptr(o[2])) for o in self.outs])
+        self.c_cams = (CCamera * self.V)(*[camera_struct(c) for c in self.cameras])
+        lead = (self.V,) if per_view else ()
+        self.grads = {"mean": torch.empty(lead + (3, self.n), device=self.dev),
+                      "scale": torch.empty(lead + (3, self.n), device=self.dev),
+                      "quat": torch.empty(lead + (4, self.n), device=self.dev),
+                      "opacity": torch.empty(lead + (self.n,), device=self.dev),
+                      "color": torch.empty(lead + (3, self.n), device=self.dev)}
+        self.dpose = torch.empty((self.V, 6), device=self.dev)
+        self.c_grads = CGaussianBuffers(*[_ptr(self.grads[k]) for k in FIELD_NAMES])
+        self.pairs = None
+        self.generation = 0
+        self._g = self._views = None
+
+    def _gaussians(self, means, scales, quats, opacities, colors):
+        if self.per_view:
+            ts = [_dev(x) for x in (means, scales, quats, opacities, colors)]
+            shapes = [(self.V, 3, self.n), (self.V, 3, self.n), (self.V, 4, self.n), (self.V, self.n),
+                      (self.V, 3, self.n)]
+            if not all(tuple(t.shape) == sh for t, sh in zip(ts, shapes)):
+                raise VcgsError("per-view sets are stacked (V, ., n)")
+            return CGaussians(self.n, *[_ptr(t) for t in ts]), ts
+        g, keep = _gauss(means, scales, quats, opacities, colors)
+        if g.n != self.n:
+            raise VcgsError(f"the pass was made for {self.n} Gaussians")
+        return g, keep
+
+    def forward(self, means, scales, quats, opacities, colors, poses, check=True):
+        """Renders the views at ``poses``; returns ``outs`` (overwritten by the
+        next forward).  ``check`` waits for the pass and reruns it once if its
+        pairs outgrew the buffers (the library has then resized them)."""
+        if len(poses) != self.V:
+            raise VcgsError(f"the pass was made for {self.V} poses")
+        g, keep = self._gaussians(means, scales, quats, opacities, colors)
+        views = CViews(self.V, ctypes.cast(self.c_cams, c_p),
+                       ctypes.cast((CPose * self.V)(*[pose_struct(p) for p in poses]), c_p))
+        for attempt in range(2):
+            _check(lib().vcgs_render_batch_forward(self.ctx.h, ctypes.byref(g), ctypes.byref(views), self.bg,
+                                                   self.c_outs, c_i32(self.flags), _stream()))
+            if not check:
+                break
+            pairs = c_i64()
+            rc = lib().vcgs_batch_check(self.ctx.h, ctypes.byref(pairs))
+            self.pairs = pairs.value
+            if rc == VCGS_E_CAPACITY and attempt == 0:
+                continue
+            _check(rc)
+            break
+        self._g, self._views, self._keep = g, views, keep
+        self.generation += 1
+        self.ctx._last_batch = (self, self.generation)
+        return self.outs
+
+    def backward(self, dl_dcolor=None, dl_ddepth=None, dl_dalpha=None):
+        """Per-view upstream gradients (lists of V device tensors or None, each
+        entry may be None = zero).  Returns (grads dict, dpose (V, 6)), both
+        overwritten by the next backward."""
+        if self._g is None or getattr(self.ctx, "_last_batch", None) != (self, self.generation):
+            raise VcgsError("only the context's most recent batched forward can be differentiated")
+        arrs = []
+        self._ukeep = []
+        for lst, shape, name in ((dl_dcolor, lambda c: (3, int(c.height), int(c.width)), "dl_dcolor"),
+                                 (dl_ddepth, lambda c: (int(c.height), int(c.width)), "dl_ddepth"),
+                                 (dl_dalpha, lambda c: (int(c.height), int(c.width)), "dl_dalpha")):
+            if lst is None:
+                arrs.append(None)
+                continue
+            if len(lst) != self.V:
+                raise VcgsError(f"{name}: one entry per view")
+            ts = [None if u is None else _arg(_dev(u), shape(c), name) for u, c in zip(lst, self.cameras)]
+            self._ukeep += [t for t in ts if t is not None]
+            arrs.append((c_p * self.V)(*[_ptr(t) for t in ts]))
+        _check(lib().vcgs_render_batch_backward(self.ctx.h, ctypes.byref(self._g), ctypes.byref(self._views),
+                                                arrs[0], arrs[1], arrs[2], ctypes.byref(self.c_grads),
+                                                _ptr(self.dpose), c_i32(self.flags), _stream()))
+        return self.grads, self.dpose
+
+
+class BatchRenderFn(torch.autograd.Function):
+    """Differentiable batched render of a window of views (BatchRender):
+    returns (colour, depth, alpha) of every view, flattened; ``pose_tangents``
+    (V, 6) must be zero, its gradient is each view's dL/dxi."""
+
+    @staticmethod
+    def forward(fctx, means, scales, quats, opacities, colors, pose_tangents, batch, poses):
+        outs = batch.forward(means, scales, quats, opacities, colors, poses)
+        fctx.batch, fctx.gen = batch, batch.generation
+        flat = []
+        for C, D, A in outs:
+            flat += [C.clone(), D.clone(), A.clone()]
+        return tuple(flat)
+
+    @staticmethod
+    def backward(fctx, *ups):
+        b = fctx.batch
+        if b.generation != fctx.gen:
+            raise VcgsError("the batched pass was run again before this backward")
+        grads, dpose = b.backward(list(ups[0::3]), list(ups[1::3]), list(ups[2::3]))
+        return tuple(grads[k].clone() for k in FIELD_NAMES) + (dpose.clone(), None, None)
+
+
+def render_views(means, scales, quats, opacities, colors, batch: BatchRender, poses, pose_tangents=None):
+    """Differentiable batched render (BatchRenderFn): a list of (colour, depth,
+    alpha) per view; gradients reach the Gaussians and, through
+    ``pose_tangents`` (V, 6), every view's pose."""
+    if pose_tangents is None:
+        pose_tangents = torch.zeros((batch.V, 6), dtype=torch.float32, device=means.device)
+    flat = BatchRenderFn.apply(means, scales, quats, opacities, colors, pose_tangents, batch, poses)
+    return [tuple(flat[3 * i:3 * i + 3]) for i in range(batch.V)]
 
 
 class Server:
