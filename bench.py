@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--stages", action="store_true", help="also print a per-stage table to stderr")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -112,9 +113,10 @@ def measured_traffic(stage):
     return int(rec["bytes_per_launch"])
 
 
-def cpu_baseline(budget_s):
+def cpu_baseline_run(budget_s):
     """The oracle, as it stands, on the same workload: full fwd+bwd steps until
-    the time budget is used (at least one)."""
+    the time budget is used (at least one, at most three).  The oracle's
+    OpenMP loops use OMP_NUM_THREADS threads; its adjoint is single-threaded."""
     from oracle import decode as odec, raster
     from paper_2403_11247_amd import scenes
     a, m, cam, pose, tpose = room_inputs()
@@ -138,10 +140,29 @@ def cpu_baseline(budget_s):
     dt = (time.perf_counter() - t0) / steps
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(cam.width * cam.height / dt / 1e6, 4), "unit": "Mpix/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "step_s": round(dt, 3),
             "sample": f"{steps} full fwd+bwd step(s) of the room workload (1200x680, 400k Gaussians), "
-                      f"{dt:.2f} s each; projection/compositing forward on {threads} OpenMP threads, "
+                      f"{dt:.2f} s each; projection/compositing forward on {threads} OpenMP thread(s), "
                       f"adjoint single-threaded"}
+
+
+def cpu_baseline(budget_s):
+    """The oracle timed twice, each in a child process of its own (the thread
+    count of its OpenMP loops is fixed when a process starts): on all the host
+    threads this process may use, and on one thread."""
+    import subprocess
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    runs = {}
+    for n in (cores, 1):
+        env = dict(os.environ, OMP_NUM_THREADS=str(n))
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                            "--cpu-budget-s", str(budget_s)], env=env, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("CPU baseline run failed:\n" + r.stderr[-2000:])
+        runs[n] = json.loads(r.stdout.strip().splitlines()[-1])
+    out = dict(runs[cores])
+    out["single_thread"] = {k: runs[1][k] for k in ("value", "unit", "cores", "step_s")}
+    return out
 
 
 F = ("mean", "scale", "quat", "opacity", "color")
@@ -569,6 +590,9 @@ def serve_section(args, dev):
 
 def main():
     args = parse()
+    if args.cpu_baseline_child:  # the oracle only; no GPU in this process
+        print(json.dumps(cpu_baseline_run(args.cpu_budget_s)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only",
                           "n_gpus": args.gpus}))
