@@ -169,10 +169,13 @@ struct BatchPlan {
     float* g2 = nullptr;
     float* partial = nullptr;
     int pb = 0;
-    ProjTab* pt_host = nullptr;   // pinned
+    // pinned staging of the per-view table, two slots used in turn: a pass
+    // only waits for the upload of the pass before the previous one
+    ProjTab* pt_host[2] = {};
     uint32_t* host_flags = nullptr;  // pinned: pair count, overflow
-    hipEvent_t tab_copied = nullptr;
-    bool tab_pending = false;
+    hipEvent_t tab_copied[2] = {};
+    bool tab_pending[2] = {};
+    int tab_slot = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     // a forward kept for the caller's backward (vcgs_render_batch_forward):
@@ -181,7 +184,6 @@ struct BatchPlan {
     hipGraph_t graph_bwd = nullptr;
     hipGraphExec_t exec_bwd = nullptr;
     std::vector<const void*> bwd_ptrs;
-    hipEvent_t bwd_ready = nullptr;
     std::vector<void*> blocks_e, blocks_p;
     int64_t need = 0;
     vcgs_ctx* ctx = nullptr;
@@ -231,14 +233,15 @@ struct BatchPlan {
         release_p();
         for (void* b : blocks_e) ctx->pool.free(b);
         blocks_e.clear();
-        if (pt_host) (void)hipHostFree(pt_host);
+        for (int i = 0; i < 2; ++i) {
+            if (pt_host[i]) (void)hipHostFree(pt_host[i]);
+            if (tab_copied[i]) (void)hipEventDestroy(tab_copied[i]);
+            pt_host[i] = nullptr;
+            tab_copied[i] = nullptr;
+            tab_pending[i] = false;
+        }
         if (host_flags) (void)hipHostFree(host_flags);
-        if (tab_copied) (void)hipEventDestroy(tab_copied);
-        if (bwd_ready) (void)hipEventDestroy(bwd_ready);
-        pt_host = nullptr;
         host_flags = nullptr;
-        tab_copied = nullptr;
-        bwd_ready = nullptr;
     }
 };
 
@@ -514,7 +517,7 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
         }
     }
     if (!plan) {
-        if (ctx->plans.size() >= 8) {  // keep a few plans; drop the oldest
+        if (ctx->plans.size() >= 32) {  // keep a few plans; drop the oldest
             BatchPlan* old = ctx->plans.front();
             (void)hipDeviceSynchronize();  // its last pass may have run on another stream
             if (ctx->last_plan == old) ctx->last_plan = nullptr;
@@ -568,9 +571,10 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
             plan->g2 = plan->get_e<float>((int64_t)kG2 * f.E);
             plan->partial = plan->get_e<float>(6 * (int64_t)plan->pb * V);
         }
-        bool ok = plan->ok() && hipHostMalloc((void**)&plan->pt_host, sizeof(ProjTab), hipHostMallocDefault) == hipSuccess &&
-                  hipHostMalloc((void**)&plan->host_flags, 16, hipHostMallocDefault) == hipSuccess &&
-                  hipEventCreateWithFlags(&plan->tab_copied, hipEventDisableTiming) == hipSuccess;
+        bool ok = plan->ok() && hipHostMalloc((void**)&plan->host_flags, 16, hipHostMallocDefault) == hipSuccess;
+        for (int i = 0; ok && i < 2; ++i)
+            ok = hipHostMalloc((void**)&plan->pt_host[i], sizeof(ProjTab), hipHostMallocDefault) == hipSuccess &&
+                 hipEventCreateWithFlags(&plan->tab_copied[i], hipEventDisableTiming) == hipSuccess;
         if (!ok) {
             plan->release();
             delete plan;
@@ -581,12 +585,14 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
     }
     Frame& f = plan->f;
     // poses of this call, staged through pinned memory into the device table
-    if (plan->tab_pending) HIP_TRY(hipEventSynchronize(plan->tab_copied));
+    const int slot = plan->tab_slot;
+    plan->tab_slot ^= 1;
+    if (plan->tab_pending[slot]) HIP_TRY(hipEventSynchronize(plan->tab_copied[slot]));
     for (int v = 0; v < V; ++v) f.pt.pose[v] = make_posek(views->poses[v]);
-    std::memcpy(plan->pt_host, &f.pt, sizeof(ProjTab));
-    HIP_TRY(hipMemcpyAsync(f.pt_dev, plan->pt_host, sizeof(ProjTab), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(plan->tab_copied, s));
-    plan->tab_pending = true;
+    std::memcpy(plan->pt_host[slot], &f.pt, sizeof(ProjTab));
+    HIP_TRY(hipMemcpyAsync(f.pt_dev, plan->pt_host[slot], sizeof(ProjTab), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(plan->tab_copied[slot], s));
+    plan->tab_pending[slot] = true;
 
     // size the pair buffers once (and again after an overflow was reported)
     if (f.cap == 0 || plan->need > f.cap) {
@@ -623,12 +629,8 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
             }
             HIP_TRY(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
         }
-        // order the replay after the caller's stream and the caller's stream after the replay
-        hipEvent_t ev = plan->tab_copied;
-        HIP_TRY(hipStreamWaitEvent(gs, ev, 0));
-        HIP_TRY(hipGraphLaunch(plan->exec, gs));
-        HIP_TRY(hipEventRecord(ctx->graph_done, gs));
-        HIP_TRY(hipStreamWaitEvent(s, ctx->graph_done, 0));
+        // captured on the library's stream, replayed in order on the caller's
+        HIP_TRY(hipGraphLaunch(plan->exec, s));
     } else {
         enqueue_plan(ctx, *plan, *g, outs, target_color, target_depth, gb, dl_dpose, loss, s);
     }
@@ -716,7 +718,6 @@ int vcgs_render_batch_backward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
     if (flags & VCGS_BATCH_GRAPH) {
         if (!ctx->graph_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking));
         hipStream_t gs = ctx->graph_stream;
-        if (!p->bwd_ready) HIP_TRY(hipEventCreateWithFlags(&p->bwd_ready, hipEventDisableTiming));
         if (!p->exec_bwd || p->bwd_ptrs != key) {
             if (p->exec_bwd) (void)hipGraphExecDestroy(p->exec_bwd);
             if (p->graph_bwd) (void)hipGraphDestroy(p->graph_bwd);
@@ -739,11 +740,7 @@ int vcgs_render_batch_backward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
             }
             p->bwd_ptrs = key;
         }
-        HIP_TRY(hipEventRecord(p->bwd_ready, s));
-        HIP_TRY(hipStreamWaitEvent(gs, p->bwd_ready, 0));
-        HIP_TRY(hipGraphLaunch(p->exec_bwd, gs));
-        HIP_TRY(hipEventRecord(ctx->graph_done, gs));
-        HIP_TRY(hipStreamWaitEvent(s, ctx->graph_done, 0));
+        HIP_TRY(hipGraphLaunch(p->exec_bwd, s));
     } else {
         backward_core(ctx, fb, *g, gb, dl_dpose, p->g2, p->partial, p->pb, s);
     }

@@ -892,10 +892,14 @@ class BatchWindow:
                                                                              "color")])
         self.pairs = None
 
-    def run(self, means, scales, quats, opacities, colors, poses, targets=None, hits=None):
+    def run(self, means, scales, quats, opacities, colors, poses, targets=None, hits=None, check=True):
         """targets: list of (colour (3,H,W), depth (H,W)) per view when backward.
         hits: optional int32 (n,) device tensor to which every Gaussian's number
-        of blended pixels over the window's views is added (mask step)."""
+        of blended pixels over the window's views is added (mask step).
+        check: wait for the pass, read its pair count and rerun it once if the
+        pairs outgrew the buffers.  With check=False the call returns at once;
+        the caller calls ``check()`` later (e.g. once per optimisation window)
+        and reruns the passes since the previous check if it returns False."""
         if self.per_view:
             ts = [_dev(x) for x in (means, scales, quats, opacities, colors)]
             shapes = [(self.V, 3, self.n), (self.V, 3, self.n), (self.V, 4, self.n), (self.V, self.n),
@@ -931,6 +935,8 @@ class BatchWindow:
                 _check(lib().vcgs_render_batch(*args, _stream()))
             else:
                 _check(lib().vcgs_render_batch_hits(*args, _ptr(hits), _stream()))
+            if not check:
+                break
             pairs = c_i64()
             rc = lib().vcgs_batch_check(self.ctx.h, ctypes.byref(pairs))
             self.pairs = pairs.value
@@ -942,6 +948,18 @@ class BatchWindow:
             break
         del keep
         return self
+
+    def check(self):
+        """Waits for the context's last batched pass.  True if every pass since
+        the previous check fitted its pair buffers; False if one outgrew them
+        (the library has resized them: rerun those passes)."""
+        pairs = c_i64()
+        rc = lib().vcgs_batch_check(self.ctx.h, ctypes.byref(pairs))
+        self.pairs = pairs.value
+        if rc == VCGS_E_CAPACITY:
+            return False
+        _check(rc)
+        return True
 
 
 class BatchRender:

@@ -150,3 +150,33 @@ def test_ba_window_full_size(V):
     r = compare_images(*win.outs[i], raster.render(g, cams[i], poses[i]), g=g, cam=cams[i])
     say("BA view", i, "max err colour %.2e depth %.2e flagged %d" % (r["color"], r["depth"], r["flagged"]))
     assert r["pass_"], r
+
+
+def test_unchecked_passes_then_one_check(V):
+    """Passes enqueued back to back without a host synchronisation (eager and
+    graph windows, the graph launched on the caller's stream), then one check:
+    the last pass's results equal the plain calls, and a window whose pairs
+    outgrow its buffers while unchecked is reported by the later check."""
+    g = scenes.random_scene(3000, seed=9, xy=1.2)
+    gd = gauss_dev(g)
+    cams, _ = small_window(seed=40)
+    tg = random_targets(cams, seed=10)
+    for graph in (False, True):
+        win = V.BatchWindow(g.n, cams, backward=True, graph=graph)
+        for it in range(3):
+            _, poses = small_window(seed=41 + it)
+            win.run(*gd, poses, tg, check=False)
+        assert win.check()
+        check_backward(win, plain_views(V, gd, cams, poses, tg))
+    g2 = scenes.random_scene(3000, seed=7, xy=1.0, log_scale=(0.05, 0.2))
+    gd2 = gauss_dev(g2)
+    cams2 = [scenes.Camera(w, h, 0.8 * w, 0.8 * w, w / 2.0, h / 2.0) for (w, h) in [(200, 150), (160, 120)]]
+    far = [scenes.Pose(np.eye(3, dtype=np.float32), np.array([0, 0, 20.0], np.float32))] * 2
+    near = [scenes.Pose(np.eye(3, dtype=np.float32), np.array([0, 0, -1.2], np.float32))] * 2
+    tg2 = random_targets(cams2, seed=11)
+    win = V.BatchWindow(g2.n, cams2, backward=True, graph=True)
+    win.run(*gd2, far, tg2)
+    win.run(*gd2, near, tg2, check=False)
+    assert not win.check()
+    win.run(*gd2, near, tg2)  # resized: the rerun fits
+    check_backward(win, plain_views(V, gd2, cams2, near, tg2))
