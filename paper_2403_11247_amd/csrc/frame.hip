@@ -120,7 +120,7 @@ static void backward_core(vcgs_ctx* ctx, Frame& f, const vcgs_gaussians& g, cons
     if (f.cap > 0) launch_composite_bwd(f.vt, f.total_tiles, f.rec, f.gids, f.ranges, g2, cnts, s);
     pf.end(VCGS_STAGE_COMPOSITE_BWD, s);
     pf.begin(VCGS_STAGE_PREPROCESS_BWD, s);
-    if (f.n > 0) launch_preprocess_bwd(f.pt, f.pt_dev, g, f.count, g2, gb, partial, pb, s);
+    if (f.n > 0) launch_preprocess_bwd(f.pt, f.pt_dev, g, f.count, f.rec, g2, gb, partial, pb, s);
     else launch_fill_f32(partial, 0.0f, 6 * (int64_t)f.V, s);
     if (dl_dpose) launch_pose_reduce(partial, f.V, f.n > 0 ? pb : 1, dl_dpose, s);
     pf.end(VCGS_STAGE_PREPROCESS_BWD, s);

@@ -70,8 +70,10 @@ struct Splat {
     float4 a, b, c, d;
 };
 
-// Per-entry gradient of the 2D quantities, 12 floats:
-// du, dv, dA, dB, dC, dopacity, dr, dg, db, ddepth, -, -.
+// Per-entry gradient sums of the compositing adjoint, 12 floats: five sums of
+// dL/dpower against the pixel offset (p1, p2) in the footprint's eigen frame
+// (p1, p2, p1^2, p1 p2, p2^2; the projection adjoint rotates them into
+// dL/d(u, v) and dL/d(conic)), dopacity, dr, dg, db, ddepth, -, -.
 constexpr int kG2 = 12;
 
 CamK make_camk(const vcgs_camera& c, uint32_t tile_base = 0);
@@ -91,10 +93,10 @@ struct Count {
 void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
                        uint32_t* depth_key, uint2* rect, uint32_t* count, hipStream_t s);
 int preprocess_bwd_blocks(int64_t n);
-// g2 and count have n_views * n entries; pose_partial holds n_views * blocks * 6 floats.
+// g2, count and rec have n_views * n entries; pose_partial holds n_views * blocks * 6 floats.
 void launch_preprocess_bwd(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, const uint32_t* count,
-                           const float* g2, const vcgs_gaussian_buffers& out, float* pose_partial, int blocks,
-                           hipStream_t s);
+                           const Splat* rec, const float* g2, const vcgs_gaussian_buffers& out, float* pose_partial,
+                           int blocks, hipStream_t s);
 // dl_dpose: n_views * 6 floats
 void launch_pose_reduce(const float* partial, int n_views, int nblocks, float* dl_dpose, hipStream_t s);
 

@@ -205,8 +205,8 @@ constexpr int kBwdThreads = 256;
 
 __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
     const ProjTab* __restrict__ tabp, const float* __restrict__ mean, const float* __restrict__ scale,
-    const float* __restrict__ quat, const uint32_t* __restrict__ count, const float* __restrict__ g2,
-    float* __restrict__ d_mean, float* __restrict__ d_scale, float* __restrict__ d_quat,
+    const float* __restrict__ quat, const uint32_t* __restrict__ count, const Splat* __restrict__ rec,
+    const float* __restrict__ g2, float* __restrict__ d_mean, float* __restrict__ d_scale, float* __restrict__ d_quat,
     float* __restrict__ d_opac, float* __restrict__ d_color, float* __restrict__ pose_partial)
 {
     __shared__ float red[6][kBwdThreads];
@@ -228,7 +228,23 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
             const float4 a = *reinterpret_cast<const float4*>(g2 + kG2 * e);
             const float4 b = *reinterpret_cast<const float4*>(g2 + kG2 * e + 4);
             const float4 c = *reinterpret_cast<const float4*>(g2 + kG2 * e + 8);
-            gg[0] = a.x; gg[1] = a.y; gg[2] = a.z; gg[3] = a.w; gg[4] = b.x;
+            // The compositing adjoint sums dL/dpower against the pixel offset in
+            // the footprint's eigen frame: a = (sum dP p1, sum dP p2, sum dP p1^2,
+            // sum dP p1 p2), b.x = sum dP p2^2, with p1 = d . e, p2 = d . e_perp,
+            // e = (ex, ey).  Since d = p1 e + p2 e_perp and power = -1/2 d^T Q d
+            // with Q = i1 e e^T + i2 e_perp e_perp^T: dL/du = sum dP (Q d)_x,
+            // dL/dv = sum dP (Q d)_y, and the conic terms -1/2 dx^2, -dx dy,
+            // -1/2 dy^2 follow from the second moments rotated back.
+            const float4 eb = rec[e].b;  // ex, ey, j1, j2 (j = -1 / (2 ln2 lambda))
+            const float ex = eb.x, ey = eb.y;
+            const float i1 = -2.0f * kLn2 * eb.z, i2 = -2.0f * kLn2 * eb.w;  // 1 / lambda
+            const float s1 = i1 * a.x, s2 = i2 * a.y;
+            gg[0] = ex * s1 - ey * s2;
+            gg[1] = ey * s1 + ex * s2;
+            const float exx = ex * ex, eyy = ey * ey, exy = ex * ey;
+            gg[2] = -0.5f * ((exx * a.z - 2.0f * exy * a.w) + eyy * b.x);
+            gg[3] = -(exy * (a.z - b.x) + (exx - eyy) * a.w);
+            gg[4] = -0.5f * ((eyy * a.z + 2.0f * exy * a.w) + exx * b.x);
             gg[5] = b.y; gg[6] = b.z; gg[7] = b.w; gg[8] = c.x; gg[9] = c.y;
         } else {
 #pragma unroll
@@ -435,12 +451,12 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
 int preprocess_bwd_blocks(int64_t n) { return (int)((n + kBwdThreads - 1) / kBwdThreads); }
 
 void launch_preprocess_bwd(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, const uint32_t* count,
-                           const float* g2, const vcgs_gaussian_buffers& out, float* pose_partial, int blocks,
-                           hipStream_t s)
+                           const Splat* rec, const float* g2, const vcgs_gaussian_buffers& out, float* pose_partial,
+                           int blocks, hipStream_t s)
 {
     if (t.n <= 0) return;
-    k_preprocess_bwd<<<blocks, kBwdThreads, 0, s>>>(t_dev, g.mean, g.scale, g.quat, count, g2, out.mean, out.scale,
-                                                    out.quat, out.opacity, out.color, pose_partial);
+    k_preprocess_bwd<<<blocks, kBwdThreads, 0, s>>>(t_dev, g.mean, g.scale, g.quat, count, rec, g2, out.mean,
+                                                    out.scale, out.quat, out.opacity, out.color, pose_partial);
 }
 
 // Sum of the per-block pose partials in block order, one block per view (deterministic).

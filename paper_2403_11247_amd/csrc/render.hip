@@ -22,10 +22,10 @@
 //
 // Backward: the same walk in reverse, from each pixel's final transmittance and
 // last contributor (saved by the forward), recovering T_i = T_{i+1} / (1 - alpha_i)
-// and the normalised colour behind i by acc <- alpha c + (1 - alpha) acc.  The ten
-// per-Gaussian partial derivatives are reduce-scattered over each 16-lane row
-// with DPP, parked in LDS for six Gaussians, and then summed over the four rows
-// and added to the Gaussian's gradient slot with one atomic per value.
+// and, instead of the normalised colour behind i, its product U with the
+// pixel's upstream gradient.  The ten per-Gaussian sums are reduce-scattered
+// over the wave (lane swaps across rows, DPP inside rows), parked in LDS for six
+// Gaussians and added to the Gaussian's gradient slot with one atomic per value.
 #include "internal.h"
 
 namespace vcgs {
@@ -296,37 +296,52 @@ __device__ __forceinline__ float dpp_add(float keep, float send)
     return keep + __builtin_amdgcn_update_dpp(0.0f, send, CTRL, 0xF, 0xF, true);
 }
 
-// Reduce-scatter of ten per-lane values over each 16-lane row.  Every step
-// pairs lanes that differ in one bit of the column c (c^8 by row_ror:8, then the
-// half-row mirror, then c^2, c^1); each lane keeps half of the values still
-// held, adds its partner's copy of that half and passes on the other half.
-// Afterwards the row sum of value rs_index(c) is in column c, for the ten
-// columns 0,1,2,4,5 (values 0-4) and 8,9,10,12,13 (values 5-9): 33 lane
-// operations instead of 40 for ten separate row sums, and no select chain.
-__device__ __forceinline__ float reduce_scatter10(const float p[10], int lane)
+// Reduce-scatter of ten per-lane values over the whole wave.  The two
+// cross-row steps use the gfx950 lane swaps: v_permlane32_swap exchanges the
+// upper 32 lanes of one register with the lower 32 lanes of another, so after
+// one swap and one add lanes 0-31 hold value k summed over (l, l + 32) and
+// lanes 32-63 value k + 5; v_permlane16_swap does the same for odd and even
+// 16-lane rows.  The last four steps pair lanes inside each row with DPP
+// (c^8 by row_ror:8, then the half-row mirror, then c^2 and c^1); at the c^8
+// and mirror steps each lane keeps one of two values and passes the other.
+// Afterwards the total of value q is in lane wr_lane(q) (and a few others):
+// 26 lane operations for ten totals, no LDS.
+__device__ __forceinline__ float swap_add32(float x, float y)
 {
-    const bool h3 = lane & 8, h2 = lane & 4, h1 = lane & 2, h0 = lane & 1;
-    float r[5];
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_add16(float x, float y)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float wave_reduce10(const float p[10], int lane)
+{
+    float a[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) r[k] = dpp_add<0x128>(h3 ? p[k + 5] : p[k], h3 ? p[k] : p[k + 5]);
-    const float s0 = dpp_add<0x141>(h2 ? r[3] : r[0], h2 ? r[0] : r[3]);
-    const float s1 = dpp_add<0x141>(h2 ? r[4] : r[1], h2 ? r[1] : r[4]);
-    const float s2 = dpp_add<0x141>(h2 ? 0.0f : r[2], h2 ? r[2] : 0.0f);
-    const float t0 = dpp_add<0x4E>(h1 ? s2 : s0, h1 ? s0 : s2);
-    const float t1 = dpp_add<0x4E>(h1 ? 0.0f : s1, h1 ? s1 : 0.0f);
-    return dpp_add<0xB1>(h0 ? t1 : t0, h0 ? t0 : t1);
+    for (int k = 0; k < 5; ++k) a[k] = swap_add32(p[k], p[k + 5]);  // value k + 5 (lane & 32)
+    const float b0 = swap_add16(a[0], a[1]);  // value 0 + (lane & 16 ? 1 : 0)
+    const float b1 = swap_add16(a[2], a[3]);  // value 2 + (lane & 16 ? 1 : 0)
+    const float b2 = swap_add16(a[4], a[4]);  // value 4, in every row
+    const bool h3 = lane & 8, h2 = lane & 4;
+    const float c0 = dpp_add<0x128>(h3 ? b1 : b0, h3 ? b0 : b1);
+    const float c1 = dpp_add<0x128>(b2, b2);
+    const float d0 = dpp_add<0x141>(h2 ? c1 : c0, h2 ? c0 : c1);
+    const float e0 = dpp_add<0x4E>(d0, d0);
+    return dpp_add<0xB1>(e0, e0);
 }
-__device__ __forceinline__ bool rs_valid(int lane)
+// Which total lane `lane` holds after wave_reduce10, or -1 if it is not the
+// lane that passes it on (one lane per value).
+__device__ __forceinline__ int wr_value(int lane)
 {
-    const bool h2 = lane & 4, h1 = lane & 2, h0 = lane & 1;
-    return !((h2 && h1) || (!h2 && h1 && h0));
-}
-__device__ __forceinline__ int rs_index(int lane)
-{
-    return 5 * ((lane >> 3) & 1) + 3 * ((lane >> 2) & 1) + 2 * ((lane >> 1) & 1) + (lane & 1);
+    if (lane & 3) return -1;
+    const int h5 = (lane >> 5) & 1, h4 = (lane >> 4) & 1, h3 = (lane >> 3) & 1, h2 = (lane >> 2) & 1;
+    if (h2) return (h3 || h4) ? -1 : 4 + 5 * h5;
+    return 2 * h3 + h4 + 5 * h5;
 }
 
-constexpr int kPend = 6;  // Gaussians whose row sums are gathered before one atomic flush
+constexpr int kPend = 6;  // Gaussians whose totals are gathered before one atomic flush
 
 template <int PPL, bool COUNT>
 __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t total_tiles,
@@ -343,8 +358,8 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
     __shared__ float4 slab[4][3][64];
     __shared__ float slab_z[4][64];
     __shared__ uint32_t slab_gid[4][64];
-    // per-Gaussian row sums (4 rows x 10 values) waiting to be added to g2
-    __shared__ float pend[4][kPend][4][10];
+    // per-Gaussian totals (10 values) waiting to be added to g2
+    __shared__ float pend[4][kPend][10];
     __shared__ uint32_t pend_gid[4][kPend];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gw = (sched ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + wave;
@@ -362,8 +377,7 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
     const float bg0 = tab.bg[0], bg1 = tab.bg[1], bg2 = tab.bg[2];
     uint32_t n_eval = 0, n_blend = 0, n_flush = 0;
     int npend = 0;  // uniform
-    const bool rsv = rs_valid(threadIdx.x & 63);
-    const int rsi = rs_index(threadIdx.x & 63);
+    const int wrv = wr_value(lane);
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int qx = PPL == 1 ? (sub & 1) : 0, qy = PPL == 1 ? (sub >> 1) : sub;
     const int px = tx * kTile + qx * SW + lane % SW;
@@ -371,7 +385,13 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
     const float rx0 = (float)(tx * kTile + qx * SW) + 0.5f, rx1 = rx0 + (float)(SW - 1);
     const float ry0 = (float)row0 + 0.5f, ry1 = ry0 + (float)(SH - 1);
     const int HW = cam.W * cam.H;
-    float T[PPL], up[PPL][5], acc[PPL][5];
+    // Per pixel: T = transmittance in front of the current entry, up = upstream
+    // gradient of (r, g, b, depth, alpha), U = up . acc where acc is the
+    // normalised composite behind the current entry ((bg, 0, 0) behind the
+    // last one).  acc itself is never needed: dL/dalpha_i = T_i (up . x_i - U)
+    // with x_i = (c_i, z_i, 1), and acc <- acc + alpha (x - acc) gives
+    // U <- U + alpha (up . x - U).
+    float T[PPL], up[PPL][5], U[PPL];
     uint32_t last[PPL];
     float pyf[PPL];
     uint32_t wl = 0;
@@ -388,13 +408,21 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
         up[j][2] = (in && dl_dc) ? dl_dc[2 * HW + p] : 0.0f;
         up[j][3] = (in && dl_dd) ? dl_dd[p] : 0.0f;
         up[j][4] = (in && dl_da) ? dl_da[p] : 0.0f;
-        acc[j][0] = bg0; acc[j][1] = bg1; acc[j][2] = bg2; acc[j][3] = 0.0f; acc[j][4] = 0.0f;
+        U[j] = fmaf(up[j][0], bg0, fmaf(up[j][1], bg1, up[j][2] * bg2));
         wl = max(wl, last[j]);
     }
     const float pxf = (float)px + 0.5f;
     wl = wave_max_u32(wl);
     if (wl == 0u) return;  // uniform across the wave
     const uint32_t start = ranges[2 * gt];
+    auto flush = [&](int count) {
+        wave_lds_sync();
+        if (lane < 10 * count) {
+            const int sl = lane / 10, v = lane - 10 * sl;
+            atomicAdd(g2 + (size_t)kG2 * pend_gid[wave][sl] + v, pend[wave][sl][v]);
+        }
+        wave_lds_sync();
+    };
     for (int bs = (int)((wl - 1u) & ~63u); bs >= 0; bs -= 64) {
         wave_lds_sync();
         const uint32_t li = (uint32_t)bs + lane;
@@ -415,90 +443,70 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
             const int k = 63 - __builtin_clzll(hits);
             hits &= ~(1ull << k);
             const uint32_t local = (uint32_t)(bs + k);
-            const float4 ra = slab[wave][0][k], rb = slab[wave][1][k], rc = slab[wave][2][k];
-            const float rz = slab_z[wave][k];
-            const float i1 = -2.0f * kLn2 * rb.z, i2 = -2.0f * kLn2 * rb.w;  // eigenvalues of Q
+            const float4 ra = slab[wave][0][k], rb = slab[wave][1][k];
             const float dx = (pxf - ra.x) - ra.z;
             // footprints first: a wave-entry that blends into none of the wave's
             // pixels changes no state and adds nothing, so it skips the adjoint
             Fp fj[PPL];
             bool cj[PPL];
-            float dyv[PPL];
             bool any = false;
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
-                dyv[j] = (pyf[j] - ra.y) - ra.w;
-                fj[j] = footprint(dx, dyv[j], rb.x, rb.y, rb.z, rb.w, rc.x);
+                fj[j] = footprint(dx, (pyf[j] - ra.y) - ra.w, rb.x, rb.y, rb.z, rb.w, slab[wave][2][k].x);
                 const bool in = local < last[j];
                 cj[j] = in && fj[j].alpha >= kAlphaMin;
                 if (COUNT) { n_eval += in ? 1u : 0u; n_blend += cj[j] ? 1u : 0u; }
                 any = any || cj[j];
             }
             if (__ballot(any) == 0ull) continue;
+            const float4 rc = slab[wave][2][k];
+            const float rz = slab_z[wave][k];
+            // Per-lane sums: p0 = sum dP p1, p1 = sum dP p2, p2 = sum dP p1^2,
+            // p3 = sum dP p1 p2, p4 = sum dP p2^2 (dP = dL/dpower, (p1, p2) the
+            // pixel offset in the footprint's eigen frame; the projection adjoint
+            // turns them into dL/d(u, v) and dL/d(conic)), p5 = dL/dopacity,
+            // p6-p9 = dL/d(r, g, b, depth).
             float p[10];
 #pragma unroll
             for (int i = 0; i < 10; ++i) p[i] = 0.0f;
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 // branch-free: every lane evaluates, only contributing pixels change state
-                const float dyj = dyv[j];
                 const Fp& f = fj[j];
                 const bool c = cj[j];
                 const float a = f.alpha;
                 const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
-                const float x[5] = {rc.y, rc.z, rc.w, rz, 1.0f};
-                // a masked to 0 leaves acc unchanged exactly (acc + 0 d), one select for five channels
-                const float am = c ? a : 0.0f;
-                float dla = 0.0f;
-#pragma unroll
-                for (int ch = 0; ch < 5; ++ch) {
-                    const float d = x[ch] - acc[j][ch];
-                    dla += up[j][ch] * d;
-                    acc[j][ch] = fmaf(am, d, acc[j][ch]);
-                }
-                dla *= Ti;
+                const float X = fmaf(up[j][0], rc.y, fmaf(up[j][1], rc.z, fmaf(up[j][2], rc.w, fmaf(up[j][3], rz, up[j][4]))));
+                const float d = X - U[j];
+                U[j] = fmaf(c ? a : 0.0f, d, U[j]);
                 const float w = c ? a * Ti : 0.0f;
-                p[6] += w * up[j][0];
-                p[7] += w * up[j][1];
-                p[8] += w * up[j][2];
-                p[9] += w * up[j][3];
-                const bool g = c && !f.clamped;
-                const float dg = g ? dla : 0.0f;
-                const float dp = dg * a;  // dL/dpower, power = -1/2 d^T Q d
-                const float q1 = i1 * f.p1, q2 = i2 * f.p2;
-                p[0] += dp * (q1 * rb.x - q2 * rb.y);   // d power / d u = (Q d)_x
-                p[1] += dp * (q1 * rb.y + q2 * rb.x);   // d power / d v = (Q d)_y
-                p[2] += dp * (-0.5f * dx * dx);
-                p[3] += dp * (-dx * dyj);
-                p[4] += dp * (-0.5f * dyj * dyj);
-                p[5] += dg * f.G;
+                p[6] = fmaf(w, up[j][0], p[6]);
+                p[7] = fmaf(w, up[j][1], p[7]);
+                p[8] = fmaf(w, up[j][2], p[8]);
+                p[9] = fmaf(w, up[j][3], p[9]);
+                const float dg = (c && !f.clamped) ? d * Ti : 0.0f;  // dL/d(o G)
+                const float dP = dg * a;                             // dL/dpower
+                const float t1 = dP * f.p1, t2 = dP * f.p2;
+                p[0] += t1;
+                p[1] += t2;
+                p[2] = fmaf(t1, f.p1, p[2]);
+                p[3] = fmaf(t1, f.p2, p[3]);
+                p[4] = fmaf(t2, f.p2, p[4]);
+                p[5] = fmaf(dg, f.G, p[5]);
                 T[j] = c ? Ti : T[j];
             }
-            const float rsum = reduce_scatter10(p, lane);
-            if (rsv) pend[wave][npend][lane >> 4][rsi] = rsum;
+            const float tot = wave_reduce10(p, lane);
+            if (wrv >= 0) pend[wave][npend][wrv] = tot;
             if (lane == 0) pend_gid[wave][npend] = slab_gid[wave][k];
             ++npend;
             if (COUNT && lane == 0) ++n_flush;
             if (npend == kPend) {
-                wave_lds_sync();
-                if (lane < 10 * kPend) {
-                    const int sl = lane / 10, v = lane - 10 * sl;
-                    const float t = (pend[wave][sl][0][v] + pend[wave][sl][1][v]) + (pend[wave][sl][2][v] + pend[wave][sl][3][v]);
-                    atomicAdd(g2 + (size_t)kG2 * pend_gid[wave][sl] + v, t);
-                }
-                wave_lds_sync();
+                flush(kPend);
                 npend = 0;
             }
         }
     }
-    if (npend > 0) {
-        wave_lds_sync();
-        if (lane < 10 * npend) {
-            const int sl = lane / 10, v = lane - 10 * sl;
-            const float t = (pend[wave][sl][0][v] + pend[wave][sl][1][v]) + (pend[wave][sl][2][v] + pend[wave][sl][3][v]);
-            atomicAdd(g2 + (size_t)kG2 * pend_gid[wave][sl] + v, t);
-        }
-    }
+    if (npend > 0) flush(npend);
     if (COUNT) {
         if (n_eval) atomicAdd(counters + 2, (unsigned long long)n_eval);
         if (n_blend) atomicAdd(counters + 3, (unsigned long long)n_blend);
