@@ -31,10 +31,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
-# Algorithmic work per unit (see the design notes for the derivation).
-FLOP_FOOTPRINT = 16     # one (pixel, Gaussian) footprint evaluation incl. the exponential
-FLOP_BLEND_FWD = 13     # transmittance update and colour/depth/alpha accumulation
-FLOP_BLEND_BWD = 47     # one contributing (pixel, Gaussian) in the adjoint
+# Algorithmic work per evaluated (pixel, list entry), the exponential and the
+# division counted as one flop each: the forward about 25 flops plus the
+# exponential, the adjoint about 70 flops plus the exponential and the division.
+FLOP_EVAL_FWD = 26
+FLOP_EVAL_BWD = 72
 
 
 def parse():
@@ -51,8 +52,8 @@ def parse():
     ap.add_argument("--no-ba", action="store_true", help="skip the 12-keyframe bundle-adjustment window")
     ap.add_argument("--ba-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving replay")
-    ap.add_argument("--serve-requests", type=int, default=400, help="requests per arrival rate")
-    ap.add_argument("--serve-qps", type=str, default="50,100,200,400")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
+    ap.add_argument("--serve-qps", type=str, default="50,100,200,400,1000,2000,4000")
     ap.add_argument("--only", choices=("main", "ba", "ba_view", "serve", "view", "mask", "codebook", "rvq", "track"),
                     default=None,
                     help="run one section only (for profiling)")
@@ -594,7 +595,7 @@ def serve_section(args, dev):
     vsrv = vcgs.Server.from_anchors(*A, **cfg)
     serve.replay(vsrv, warm)
     serve.replay_plain(None, warm[:8], anchors=A)
-    vq = float(args.serve_qps.split(",")[len(args.serve_qps.split(",")) // 2])
+    vq = 200.0
     trq = scenes.serve_trace(args.serve_requests, qps=vq, seed=11)
     v_rate = {"qps": vq, "batched": serve.replay(vsrv, trq), "plain": serve.replay_plain(None, trq, anchors=A)}
     v_b = serve.replay(vsrv, tr)
@@ -726,13 +727,12 @@ def main():
     avg_ms = prof_dom[0] / launches
     na = a.n
     if dom in ("composite", "composite_bwd"):
-        if dom == "composite":
-            flop = counts["fwd_evals"] * FLOP_FOOTPRINT + counts["fwd_blends"] * FLOP_BLEND_FWD
-        else:
-            flop = counts["bwd_evals"] * FLOP_FOOTPRINT + counts["bwd_blends"] * FLOP_BLEND_BWD
-        ach = flop / (avg_ms * 1e-3) / 1e12
+        units = counts["fwd_evals"] if dom == "composite" else counts["bwd_evals"]
+        per_unit = FLOP_EVAL_FWD if dom == "composite" else FLOP_EVAL_BWD
+        ach = units * per_unit / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None}
+                "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "flop_per_eval": per_unit, "evals_per_launch": int(units)}
     else:
         b = stage_bytes(dom, n, nvis, P, na, cam.width, cam.height,
                         ((cam.width + 15) // 16) * ((cam.height + 15) // 16))

@@ -204,8 +204,10 @@ struct vcgs_server {
         // grids of the pair stages are sized from the capacity: use the pass's own
         // estimate (with a margin) rather than the whole slot
         f.cap = std::min<int64_t>(sl.cap, est + est / 4 + 4096);
-        // order the pass after whatever each request's submitting stream had enqueued
-        for (const Req& r : sl.reqs) HIP_TRY(hipStreamWaitEvent(sl.s, r.submitted, 0));
+        // order the pass after whatever each request's submitting stream had
+        // enqueued; an event that has already completed needs no wait
+        for (const Req& r : sl.reqs)
+            if (hipEventQuery(r.submitted) != hipSuccess) HIP_TRY(hipStreamWaitEvent(sl.s, r.submitted, 0));
         // the slot is idle, so its previous table upload has completed
         std::memcpy(sl.pt_host, &f.pt, sizeof(ProjTab));
         HIP_TRY(hipMemcpyAsync(f.pt_dev, sl.pt_host, sizeof(ProjTab), hipMemcpyHostToDevice, sl.s));

