@@ -110,6 +110,22 @@ def test_depth_ties_keep_index_order(V):
     check_forward(V, g, scenes.random_camera(), scenes.identity_pose(), name="ties")
 
 
+@pytest.mark.parametrize("n", [6000, 20000])
+def test_long_tile_lists_keep_the_oracle_order(V, n):
+    """Every one of the 12 tiles of a 64x48 view holds about n entries (6000,
+    20000): long per-tile lists, each in (depth, index) order.  Depths are
+    rounded to 1 cm so that many entries tie."""
+    rng = np.random.default_rng(n)
+    mean = np.stack([rng.uniform(-0.1, 0.1, n), rng.uniform(-0.08, 0.08, n), np.round(rng.uniform(2.0, 3.0, n), 2)])
+    g = scenes.Gaussians(mean.astype(np.float32), np.full((3, n), 0.45, np.float32),
+                         rng.normal(size=(4, n)).astype(np.float32), rng.uniform(0.05, 0.6, n).astype(np.float32),
+                         rng.uniform(0, 1, (3, n)).astype(np.float32))
+    cam = scenes.Camera(64, 48, 40.0, 40.0, 32.0, 24.0)
+    gd, C, D, A, st, ref = check_forward(V, g, cam, scenes.identity_pose(), name=f"long-{n}")
+    rng_ = ref["ranges"]
+    assert int((rng_[:, 1] - rng_[:, 0]).min()) > 0.9 * n, rng_
+
+
 def test_forward_is_deterministic(V):
     g = scenes.random_scene(2000, seed=3)
     cam = scenes.random_camera()
