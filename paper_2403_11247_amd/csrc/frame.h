@@ -21,6 +21,9 @@ struct Frame {
     uint32_t* ranges = nullptr;
     uint32_t* gids = nullptr;
     int64_t cap = 0;  // pair capacity (exact pair count in the synchronising path)
+    // per-entry gradient sums of the backward: the projection zeroes the
+    // slots of the visible entries when this is set (no separate fill)
+    float* g2 = nullptr;
 };
 
 struct Work {

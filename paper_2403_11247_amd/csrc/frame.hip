@@ -50,7 +50,7 @@ void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* po
 const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s)
 {
     pf.begin(VCGS_STAGE_PREPROCESS, s);
-    launch_preprocess(f.pt, f.pt_dev, g, f.rec, f.depth_key, f.rect, f.count, s);
+    launch_preprocess(f.pt, f.pt_dev, g, f.rec, f.depth_key, f.rect, f.count, f.g2, s);
     pf.end(VCGS_STAGE_PREPROCESS, s);
     pf.begin(VCGS_STAGE_DEPTH_SORT, s);
     // culled entries carry the drop key and leave the depth order in its first pass
@@ -105,9 +105,11 @@ void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s, bo
 }
 
 // Replayed compositing adjoint and projection adjoint; g2 holds 12 floats per
-// entry, partial 6 floats per (view, block).
+// entry (zero on entry for every visible one: the forward's projection zeroes
+// them when the frame's g2 is set, else fill_g2 does), partial 6 floats per
+// (view, block).
 static void backward_core(vcgs_ctx* ctx, Frame& f, const vcgs_gaussians& g, const vcgs_gaussian_buffers& gb,
-                          float* dl_dpose, float* g2, float* partial, int pb, hipStream_t s)
+                          float* dl_dpose, float* g2, float* partial, int pb, hipStream_t s, bool fill_g2)
 {
     Prof& pf = ctx->prof;
     unsigned long long* cnts = nullptr;
@@ -115,7 +117,7 @@ static void backward_core(vcgs_ctx* ctx, Frame& f, const vcgs_gaussians& g, cons
         cnts = pf.d_counters;
         launch_fill_u32(reinterpret_cast<uint32_t*>(cnts) + 4, 0u, 6, s);
     }
-    launch_fill_f32(g2, 0.0f, (int64_t)kG2 * f.E, s);
+    if (fill_g2) launch_fill_f32(g2, 0.0f, (int64_t)kG2 * f.E, s);
     pf.begin(VCGS_STAGE_COMPOSITE_BWD, s);
     if (f.cap > 0) launch_composite_bwd(f.vt, f.total_tiles, f.rec, f.gids, f.ranges, g2, cnts, s);
     pf.end(VCGS_STAGE_COMPOSITE_BWD, s);
@@ -169,6 +171,8 @@ struct BatchPlan {
     float* g2 = nullptr;
     float* partial = nullptr;
     int pb = 0;
+    bool graph_g2 = false;   // the captured forward zeroes g2 (f.g2 was set at capture)
+    bool g2_zeroed = false;  // the last forward zeroed g2 and no backward has used it since
     // pinned staging of the per-view table, two slots used in turn: a pass
     // only waits for the upload of the pass before the previous one
     ProjTab* pt_host[2] = {};
@@ -284,7 +288,8 @@ static void enqueue_plan(vcgs_ctx* ctx, BatchPlan& p, const vcgs_gaussians& g, c
     }
     launch_l1_loss_views(lt, loss, p.loss_partial, s);
     ctx->prof.end(VCGS_STAGE_LOSS, s);
-    backward_core(ctx, p.f, g, gb, dl_dpose, p.g2, p.partial, p.pb, s);
+    // the pass's projection zeroed the gradient slots (the plan's frame carries g2)
+    backward_core(ctx, p.f, g, gb, dl_dpose, p.g2, p.partial, p.pb, s, false);
 }
 
 }  // namespace vcgs
@@ -296,6 +301,7 @@ struct vcgs_state {
     int64_t P = 0;
     float* t_final = nullptr;
     uint32_t* n_contrib = nullptr;
+    bool g2_clean = false;  // f.g2 zeroed by the forward and not used by a backward since
     std::vector<void*> blocks;
 
     template <class T>
@@ -373,6 +379,8 @@ static int render_forward_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
     f.ranges = st->get<uint32_t>(2 * (int64_t)f.total_tiles);
     st->t_final = st->get<float>(HW);
     st->n_contrib = st->get<uint32_t>(HW);
+    // a kept state carries the backward's gradient slots, zeroed by the projection
+    if (state_out) f.g2 = st->get<float>((int64_t)kG2 * f.E);
     f.vt.color[0] = out->color;
     f.vt.depth[0] = out->depth;
     f.vt.alpha[0] = out->alpha;
@@ -415,6 +423,7 @@ static int render_forward_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
         if (e != hipSuccess) return drop(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     }
     if (state_out) {
+        st->g2_clean = f.g2 != nullptr;
         *state_out = st;
     } else {
         st->release();
@@ -459,10 +468,11 @@ int vcgs_render_backward(vcgs_ctx* ctx, const vcgs_state* st_, const vcgs_gaussi
     f.vt.dl_da[0] = dl_dalpha;
     Scratch sc(&ctx->pool);
     const int pb = std::max(1, preprocess_bwd_blocks(f.n));
-    float* g2 = sc.get<float>((int64_t)kG2 * f.E);
     float* partial = sc.get<float>(6 * (int64_t)pb * f.V);
-    if (sc.oom) return fail(VCGS_E_NOMEM, "device allocation failed (backward)");
-    backward_core(ctx, f, *g, gb, dl_dpose, g2, partial, pb, s);
+    if (sc.oom || !st->f.g2) return fail(VCGS_E_NOMEM, "device allocation failed (backward)");
+    // a second backward of the same state starts from zero again
+    backward_core(ctx, f, *g, gb, dl_dpose, st->f.g2, partial, pb, s, !st->g2_clean);
+    st->g2_clean = false;
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return VCGS_OK;
@@ -569,6 +579,7 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
             plan->loss_partial = plan->get_e<float>((int64_t)V * plan->loss_blocks);
             plan->pb = std::max(1, preprocess_bwd_blocks(f.n));
             plan->g2 = plan->get_e<float>((int64_t)kG2 * f.E);
+            f.g2 = plan->g2;  // every pass's projection zeroes the gradient slots
             plan->partial = plan->get_e<float>(6 * (int64_t)plan->pb * V);
         }
         bool ok = plan->ok() && hipHostMalloc((void**)&plan->host_flags, 16, hipHostMallocDefault) == hipSuccess;
@@ -628,6 +639,7 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
                 return fail(VCGS_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
             }
             HIP_TRY(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+            plan->graph_g2 = f.g2 != nullptr;
         }
         // captured on the library's stream, replayed in order on the caller's
         HIP_TRY(hipGraphLaunch(plan->exec, s));
@@ -636,6 +648,7 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
     }
     ctx->last_plan = plan;
     ctx->last_stream = s;
+    plan->g2_zeroed = (flags & VCGS_BATCH_GRAPH) ? plan->graph_g2 : f.g2 != nullptr;
     if (split) ctx->fwd_plan = plan;
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -701,6 +714,13 @@ int vcgs_render_batch_backward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
             // the failed blocks stay listed (null) until the plan is released; later calls refuse
             return fail(VCGS_E_NOMEM, "allocation failed (batch backward)");
         }
+        // later forwards zero the gradient slots in their projection (a
+        // captured forward without them is captured again)
+        p->f.g2 = p->g2;
+        if (p->exec) {
+            HIP_TRY(hipStreamSynchronize(s));
+            p->drop_graph();
+        }
     }
     if (!p->ok()) return fail(VCGS_E_NOMEM, "allocation failed (batch backward)");
     const vcgs_gaussian_buffers gb =
@@ -715,6 +735,10 @@ int vcgs_render_batch_backward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
         key.push_back(fb.vt.dl_dd[v]);
         key.push_back(fb.vt.dl_da[v]);
     }
+    // the gradient slots start at zero: zeroed by the forward's projection, or
+    // here (first backward after a forward without them, or a second backward)
+    if (!p->g2_zeroed) launch_fill_f32(p->g2, 0.0f, (int64_t)kG2 * p->f.E, s);
+    p->g2_zeroed = false;
     if (flags & VCGS_BATCH_GRAPH) {
         if (!ctx->graph_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking));
         hipStream_t gs = ctx->graph_stream;
@@ -727,7 +751,7 @@ int vcgs_render_batch_backward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
             ctx->prof.capturing = true;
             hipError_t e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                backward_core(ctx, fb, *g, gb, dl_dpose, p->g2, p->partial, p->pb, gs);
+                backward_core(ctx, fb, *g, gb, dl_dpose, p->g2, p->partial, p->pb, gs, false);
                 e = hipStreamEndCapture(gs, &p->graph_bwd);
             }
             ctx->prof.capturing = false;
@@ -742,7 +766,7 @@ int vcgs_render_batch_backward(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
         }
         HIP_TRY(hipGraphLaunch(p->exec_bwd, s));
     } else {
-        backward_core(ctx, fb, *g, gb, dl_dpose, p->g2, p->partial, p->pb, s);
+        backward_core(ctx, fb, *g, gb, dl_dpose, p->g2, p->partial, p->pb, s, false);
     }
     ctx->last_stream = s;
     const hipError_t e = hipGetLastError();

@@ -90,8 +90,9 @@ struct Count {
 // preprocess.hip
 // The kernels read the table from device memory (t_dev, a copy of t) so that a
 // captured graph can be replayed with new poses.
+// g2_zero (optional): kG2 floats per entry, zeroed for every visible entry.
 void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
-                       uint32_t* depth_key, uint2* rect, uint32_t* count, hipStream_t s);
+                       uint32_t* depth_key, uint2* rect, uint32_t* count, float* g2_zero, hipStream_t s);
 int preprocess_bwd_blocks(int64_t n);
 // g2, count and rec have n_views * n entries; pose_partial holds n_views * blocks * 6 floats.
 void launch_preprocess_bwd(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, const uint32_t* count,

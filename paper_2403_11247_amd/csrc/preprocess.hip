@@ -141,7 +141,8 @@ __global__ void __launch_bounds__(256) k_preprocess(const ProjTab* __restrict__ 
                                                     const float* __restrict__ scale, const float* __restrict__ quat,
                                                     const float* __restrict__ opac, const float* __restrict__ color,
                                                     Splat* __restrict__ rec, uint32_t* __restrict__ depth_key,
-                                                    uint2* __restrict__ rect, uint32_t* __restrict__ count)
+                                                    uint2* __restrict__ rect, uint32_t* __restrict__ count,
+                                                    float* __restrict__ g2_zero)
 {
     const ProjTab& tab = *tabp;
     const int64_t n = tab.n;
@@ -183,15 +184,19 @@ __global__ void __launch_bounds__(256) k_preprocess(const ProjTab* __restrict__ 
     depth_key[e] = __float_as_uint(k.Z);
     count[e] = (uint32_t)((k.tx1 - k.tx0 + 1) * (k.ty1 - k.ty0 + 1));
     rect[e] = make_uint2((uint32_t)k.tx0 | ((uint32_t)k.ty0 << 16), (uint32_t)k.tx1 | ((uint32_t)k.ty1 << 16));
+    if (g2_zero) {  // the backward's gradient slots of this entry start at zero
+        float4* z = reinterpret_cast<float4*>(g2_zero + (int64_t)kG2 * e);
+        z[0] = z[1] = z[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
 }
 
 void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
-                       uint32_t* depth_key, uint2* rect, uint32_t* count, hipStream_t s)
+                       uint32_t* depth_key, uint2* rect, uint32_t* count, float* g2_zero, hipStream_t s)
 {
     const int64_t total = t.n * t.n_views;
     if (total <= 0) return;
     k_preprocess<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(t_dev, g.mean, g.scale, g.quat, g.opacity, g.color, rec,
-                                                                 depth_key, rect, count);
+                                                                 depth_key, rect, count, g2_zero);
 }
 
 // ---------------------------------------------------------------------------

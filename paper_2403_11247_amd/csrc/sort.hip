@@ -120,28 +120,43 @@ __global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __rest
 }
 
 // Block-local exclusive scan of a 4096-chunk plus an optional per-block base.
+// Loads and stores are coalesced (consecutive threads, consecutive words) and
+// transposed through LDS, so that each thread scans 16 consecutive items.
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 4); }  // one spare word per 16: no bank conflicts
+
 __global__ void __launch_bounds__(kThreads) k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                         int64_t n, const uint32_t* __restrict__ bases,
                                                         uint32_t* __restrict__ total)
 {
-    const int64_t base = (int64_t)blockIdx.x * kBlockItems + (int64_t)threadIdx.x * kItems;
+    __shared__ uint32_t tile[kBlockItems + kBlockItems / 16];
+    const int64_t base = (int64_t)blockIdx.x * kBlockItems;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const int k = i * kThreads + threadIdx.x;
+        tile[scan_pad(k)] = base + k < n ? in[base + k] : 0u;
+    }
+    __syncthreads();
     uint32_t v[kItems];
     uint32_t s = 0;
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
-        const int64_t idx = base + i;
-        v[i] = idx < n ? in[idx] : 0u;
+        v[i] = tile[scan_pad(threadIdx.x * kItems + i)];
         s = sat_add(s, v[i]);
     }
     uint32_t tot;
     uint32_t run = sat_add(block_excl_scan(s, &tot), bases ? bases[blockIdx.x] : 0u);
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
-        const int64_t idx = base + i;
-        if (idx < n) out[idx] = run;
+        tile[scan_pad(threadIdx.x * kItems + i)] = run;
         run = sat_add(run, v[i]);
     }
     if (total && threadIdx.x == kThreads - 1 && blockIdx.x == gridDim.x - 1) *total = run;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const int k = i * kThreads + threadIdx.x;
+        if (base + k < n) out[base + k] = tile[scan_pad(k)];
+    }
 }
 
 int64_t scan_temp_words(int64_t n)

@@ -278,3 +278,27 @@ def test_decode_fn_autograd_matches_direct_and_oracle(V):
         assert rel_err(got[k].cpu().numpy(), direct[k].cpu().numpy()) <= 1e-6, k
         e = rel_err(got[k].cpu().numpy().reshape(np.shape(ref[k])), ref[k])
         assert e <= 1e-4, (k, e)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_repeated_batch_backward_after_one_forward(V, graph):
+    """Two backwards of one batched forward give the same gradients (the
+    gradient slots start from zero again), also when the backward is a
+    replayed graph; a later forward and backward agree with the first pass."""
+    g = scenes.random_scene(2000, seed=15, xy=1.2)
+    gd = gauss_dev(g)
+    cams, poses = small_window(3, seed=95)
+    br = V.BatchRender(g.n, cams, graph=graph)
+    ups = [[dev(u) for u in scenes.upstream_grads(c.width, c.height, seed=30 + i)] for i, c in enumerate(cams)]
+    first = None
+    for it in range(2):
+        br.forward(*gd, poses)
+        for rep in range(2):
+            grads, dpose = br.backward([u[0] for u in ups], [u[1] for u in ups], [u[2] for u in ups])
+            torch.cuda.synchronize()
+            got = {k: grads[k].cpu().numpy().copy() for k in FIELDS}
+            got["pose"] = dpose.cpu().numpy().copy()
+            if first is None:
+                first = got
+            for k in got:
+                assert rel_err(got[k], first[k]) <= 1e-6, (it, rep, k)
