@@ -598,11 +598,16 @@ int vcgs_server_create_anchors(vcgs_ctx* ctx, const vcgs_anchors* a, const vcgs_
  *   VCGS_OPT_SCHED: order in which compositing blocks take tiles, 0 = linear
  *     (default), 1 = XCD-aware (each of the 8 XCDs gets a contiguous run of
  *     tiles, so that neighbouring tiles share its L2); results are identical
- *     either way.
- * Defaults: 1 pixel per lane both ways, culling on, linear order.
+ *     either way;
+ *   VCGS_OPT_BWD_MERGE: with 1 pixel per lane in the backward, 1 = the four
+ *     waves of a tile step through its list together and merge their
+ *     per-Gaussian sums in LDS before adding them to the gradient (one atomic
+ *     per value per tile instead of per quarter tile), 0 = independent waves
+ *     (default); equal up to the order of floating-point sums.
+ * Defaults: 1 pixel per lane both ways, culling on, linear order, no merging.
  * A captured batch graph keeps the settings it was captured with.
  * Invalid keys or values return VCGS_E_INVALID and change nothing. */
-enum { VCGS_OPT_PPL_FWD = 1, VCGS_OPT_PPL_BWD = 2, VCGS_OPT_CULL = 3, VCGS_OPT_SCHED = 4 };
+enum { VCGS_OPT_PPL_FWD = 1, VCGS_OPT_PPL_BWD = 2, VCGS_OPT_CULL = 3, VCGS_OPT_SCHED = 4, VCGS_OPT_BWD_MERGE = 5 };
 int vcgs_set_option(int key, int value);
 int vcgs_get_option(int key, int* value);
 

@@ -3,8 +3,9 @@
 The tunable settings are the library's kernel options (vcgs_set_option):
 pixels per lane of the forward and backward compositing (1, 2, 4: a 16x16 tile
 walked by 4, 2 or 1 waves, i.e. the block's tile shape), per-wave culling of
-tile-list entries, and the block schedule (linear or XCD-aware).  None changes
-a result.  ``tune`` times every candidate on the window as given (eager
+tile-list entries, the block schedule (linear or XCD-aware), and, at one pixel
+per lane, whether a tile's waves merge their gradient sums before the atomics.
+None changes a result beyond the order of floating-point sums.  ``tune`` times every candidate on the window as given (eager
 passes, median of ``reps``) and leaves the fastest set; a graph captured
 afterwards keeps it.  Results are cached per window signature (image sizes,
 map size, backward or not).
@@ -20,8 +21,8 @@ import torch
 
 from . import vcgs
 
-KEYS = ("ppl_fwd", "ppl_bwd", "cull", "sched")
-SPACE = {"ppl_fwd": (1, 2, 4), "ppl_bwd": (1, 2, 4), "cull": (1, 0), "sched": (1, 0)}
+KEYS = ("ppl_fwd", "ppl_bwd", "cull", "sched", "bwd_merge")
+SPACE = {"ppl_fwd": (1, 2, 4), "ppl_bwd": (1, 2, 4), "cull": (1, 0), "sched": (1, 0), "bwd_merge": (0, 1)}
 
 _cache: dict = {}
 
@@ -44,7 +45,10 @@ def apply(cfg: dict):
 def candidates(backward=True):
     keys = KEYS if backward else ("ppl_fwd", "cull", "sched")
     for vals in itertools.product(*[SPACE[k] for k in keys]):
-        yield dict(zip(keys, vals))
+        cfg = dict(zip(keys, vals))
+        if cfg.get("bwd_merge") and cfg["ppl_bwd"] != 1:
+            continue  # merging applies to the one-pixel-per-lane backward only
+        yield cfg
 
 
 def _time(fn, reps):

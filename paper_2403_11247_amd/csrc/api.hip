@@ -303,6 +303,10 @@ int vcgs_set_option(int key, int value)
         if (value != 0 && value != 1) return fail(VCGS_E_INVALID, "cull must be 0 or 1");
         o.cull = value;
         return VCGS_OK;
+    case VCGS_OPT_BWD_MERGE:
+        if (value != 0 && value != 1) return fail(VCGS_E_INVALID, "bwd_merge must be 0 or 1");
+        o.bwd_merge = value;
+        return VCGS_OK;
     case VCGS_OPT_SCHED:
         if (value != 0 && value != 1) return fail(VCGS_E_INVALID, "sched must be 0 or 1");
         o.sched = value;
@@ -321,6 +325,7 @@ int vcgs_get_option(int key, int* value)
     case VCGS_OPT_PPL_BWD: *value = o.ppl_bwd; return VCGS_OK;
     case VCGS_OPT_CULL: *value = o.cull; return VCGS_OK;
     case VCGS_OPT_SCHED: *value = o.sched; return VCGS_OK;
+    case VCGS_OPT_BWD_MERGE: *value = o.bwd_merge; return VCGS_OK;
     default: return fail(VCGS_E_INVALID, "unknown option");
     }
 }

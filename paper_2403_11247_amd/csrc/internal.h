@@ -224,6 +224,7 @@ struct Options {
     int ppl_bwd = 1;  // pixels per lane of the backward compositing (1, 2, 4)
     int cull = 1;     // per-wave ellipse culling of tile-list entries
     int sched = 0;    // compositing block order: 0 linear, 1 XCD-aware (consecutive tiles on one XCD)
+    int bwd_merge = 0;  // backward at 1 pixel per lane: a tile's 4 waves merge their totals before the atomics
 };
 Options& options();
 

@@ -341,6 +341,68 @@ __device__ __forceinline__ int wr_value(int lane)
     return 2 * h3 + h4 + 5 * h5;
 }
 
+// One list entry k of a staged slab for the wave's pixels (local = its index
+// in the tile's list): footprints, then, if it blends into any of the wave's
+// pixels, the adjoint of each pixel's blend, returned as the ten per-lane sums
+// p (p0-p4: dL/dpower against the eigen-frame offset (p1, p2, p1^2, p1 p2,
+// p2^2), p5: dL/dopacity, p6-p9: dL/d(r, g, b, depth)), stepping T and U back
+// over the entry.  Returns false (and changes nothing) when no lane blends it.
+template <int PPL, bool COUNT>
+__device__ __forceinline__ bool adjoint_entry(const float4* s0, const float4* s1, const float4* s2, const float* sz,
+                                              int k, uint32_t local, float pxf, const float pyf[PPL],
+                                              const uint32_t last[PPL], float T[PPL], float U[PPL],
+                                              const float up[PPL][5], float p[10], uint32_t& n_eval,
+                                              uint32_t& n_blend)
+{
+    const float4 ra = s0[k], rb = s1[k];
+    const float dx = (pxf - ra.x) - ra.z;
+    // footprints first: a wave-entry that blends into none of the wave's
+    // pixels changes no state and adds nothing, so it skips the adjoint
+    Fp fj[PPL];
+    bool cj[PPL];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        fj[j] = footprint(dx, (pyf[j] - ra.y) - ra.w, rb.x, rb.y, rb.z, rb.w, s2[k].x);
+        const bool in = local < last[j];
+        cj[j] = in && fj[j].alpha >= kAlphaMin;
+        if (COUNT) { n_eval += in ? 1u : 0u; n_blend += cj[j] ? 1u : 0u; }
+        any = any || cj[j];
+    }
+    if (__ballot(any) == 0ull) return false;
+    const float4 rc = s2[k];
+    const float rz = sz[k];
+#pragma unroll
+    for (int i = 0; i < 10; ++i) p[i] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        // branch-free: every lane evaluates, only contributing pixels change state
+        const Fp& f = fj[j];
+        const bool c = cj[j];
+        const float a = f.alpha;
+        const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
+        const float X = fmaf(up[j][0], rc.y, fmaf(up[j][1], rc.z, fmaf(up[j][2], rc.w, fmaf(up[j][3], rz, up[j][4]))));
+        const float d = X - U[j];
+        U[j] = fmaf(c ? a : 0.0f, d, U[j]);
+        const float w = c ? a * Ti : 0.0f;
+        p[6] = fmaf(w, up[j][0], p[6]);
+        p[7] = fmaf(w, up[j][1], p[7]);
+        p[8] = fmaf(w, up[j][2], p[8]);
+        p[9] = fmaf(w, up[j][3], p[9]);
+        const float dg = (c && !f.clamped) ? d * Ti : 0.0f;  // dL/d(o G)
+        const float dP = dg * a;                             // dL/dpower
+        const float t1 = dP * f.p1, t2 = dP * f.p2;
+        p[0] += t1;
+        p[1] += t2;
+        p[2] = fmaf(t1, f.p1, p[2]);
+        p[3] = fmaf(t1, f.p2, p[3]);
+        p[4] = fmaf(t2, f.p2, p[4]);
+        p[5] = fmaf(dg, f.G, p[5]);
+        T[j] = c ? Ti : T[j];
+    }
+    return true;
+}
+
 constexpr int kPend = 6;  // Gaussians whose totals are gathered before one atomic flush
 
 template <int PPL, bool COUNT>
@@ -442,59 +504,10 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
         while (hits) {
             const int k = 63 - __builtin_clzll(hits);
             hits &= ~(1ull << k);
-            const uint32_t local = (uint32_t)(bs + k);
-            const float4 ra = slab[wave][0][k], rb = slab[wave][1][k];
-            const float dx = (pxf - ra.x) - ra.z;
-            // footprints first: a wave-entry that blends into none of the wave's
-            // pixels changes no state and adds nothing, so it skips the adjoint
-            Fp fj[PPL];
-            bool cj[PPL];
-            bool any = false;
-#pragma unroll
-            for (int j = 0; j < PPL; ++j) {
-                fj[j] = footprint(dx, (pyf[j] - ra.y) - ra.w, rb.x, rb.y, rb.z, rb.w, slab[wave][2][k].x);
-                const bool in = local < last[j];
-                cj[j] = in && fj[j].alpha >= kAlphaMin;
-                if (COUNT) { n_eval += in ? 1u : 0u; n_blend += cj[j] ? 1u : 0u; }
-                any = any || cj[j];
-            }
-            if (__ballot(any) == 0ull) continue;
-            const float4 rc = slab[wave][2][k];
-            const float rz = slab_z[wave][k];
-            // Per-lane sums: p0 = sum dP p1, p1 = sum dP p2, p2 = sum dP p1^2,
-            // p3 = sum dP p1 p2, p4 = sum dP p2^2 (dP = dL/dpower, (p1, p2) the
-            // pixel offset in the footprint's eigen frame; the projection adjoint
-            // turns them into dL/d(u, v) and dL/d(conic)), p5 = dL/dopacity,
-            // p6-p9 = dL/d(r, g, b, depth).
             float p[10];
-#pragma unroll
-            for (int i = 0; i < 10; ++i) p[i] = 0.0f;
-#pragma unroll
-            for (int j = 0; j < PPL; ++j) {
-                // branch-free: every lane evaluates, only contributing pixels change state
-                const Fp& f = fj[j];
-                const bool c = cj[j];
-                const float a = f.alpha;
-                const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
-                const float X = fmaf(up[j][0], rc.y, fmaf(up[j][1], rc.z, fmaf(up[j][2], rc.w, fmaf(up[j][3], rz, up[j][4]))));
-                const float d = X - U[j];
-                U[j] = fmaf(c ? a : 0.0f, d, U[j]);
-                const float w = c ? a * Ti : 0.0f;
-                p[6] = fmaf(w, up[j][0], p[6]);
-                p[7] = fmaf(w, up[j][1], p[7]);
-                p[8] = fmaf(w, up[j][2], p[8]);
-                p[9] = fmaf(w, up[j][3], p[9]);
-                const float dg = (c && !f.clamped) ? d * Ti : 0.0f;  // dL/d(o G)
-                const float dP = dg * a;                             // dL/dpower
-                const float t1 = dP * f.p1, t2 = dP * f.p2;
-                p[0] += t1;
-                p[1] += t2;
-                p[2] = fmaf(t1, f.p1, p[2]);
-                p[3] = fmaf(t1, f.p2, p[3]);
-                p[4] = fmaf(t2, f.p2, p[4]);
-                p[5] = fmaf(dg, f.G, p[5]);
-                T[j] = c ? Ti : T[j];
-            }
+            if (!adjoint_entry<PPL, COUNT>(slab[wave][0], slab[wave][1], slab[wave][2], slab_z[wave], k,
+                                           (uint32_t)(bs + k), pxf, pyf, last, T, U, up, p, n_eval, n_blend))
+                continue;
             const float tot = wave_reduce10(p, lane);
             if (wrv >= 0) pend[wave][npend][wrv] = tot;
             if (lane == 0) pend_gid[wave][npend] = slab_gid[wave][k];
@@ -507,6 +520,119 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
         }
     }
     if (npend > 0) flush(npend);
+    if (COUNT) {
+        if (n_eval) atomicAdd(counters + 2, (unsigned long long)n_eval);
+        if (n_blend) atomicAdd(counters + 3, (unsigned long long)n_blend);
+        if (n_flush) atomicAdd(counters + 4, (unsigned long long)n_flush);
+    }
+}
+
+// The backward with the four waves of a tile (one pixel per lane: 8x8
+// quadrants) in step, one slab of 64 list entries at a time: the slab's
+// records are staged once for the block, every wave adds its per-Gaussian
+// totals (after its own reduce-scatter) into the slab's LDS accumulator, and
+// after the slab the block adds the nonzero totals to g2, one atomic per value:
+// one flush per (tile, Gaussian) instead of one per (quadrant, Gaussian).
+template <bool COUNT>
+__global__ void __launch_bounds__(256) k_composite_bwd_tile(ViewTab tab, uint32_t total_tiles,
+                                                            const Splat* __restrict__ rec,
+                                                            const uint32_t* __restrict__ gids,
+                                                            const uint32_t* __restrict__ ranges,
+                                                            float* __restrict__ g2,
+                                                            unsigned long long* __restrict__ counters, int cull,
+                                                            int sched)
+{
+    __shared__ float4 slab[3][64];
+    __shared__ float slab_z[64];
+    __shared__ uint32_t slab_gid[64];
+    __shared__ float acc[64][11];  // 10 totals per entry (one spare word against bank conflicts)
+    __shared__ uint32_t s_wl[4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t gt = (uint32_t)(sched ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x);
+    if (gt >= total_tiles) return;  // uniform across the block
+    const int vw = view_of(tab, gt);
+    const CamK& cam = tab.cam[vw];
+    const int tile = (int)(gt - cam.tile_base);
+    const float* __restrict__ t_final = tab.t_final[vw];
+    const uint32_t* __restrict__ n_contrib = tab.n_contrib[vw];
+    const float* __restrict__ dl_dc = tab.dl_dc[vw];
+    const float* __restrict__ dl_dd = tab.dl_dd[vw];
+    const float* __restrict__ dl_da = tab.dl_da[vw];
+    uint32_t n_eval = 0, n_blend = 0, n_flush = 0;
+    const int wrv = wr_value(lane);
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
+    const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+    const float rx0 = (float)(tx * kTile + (wave & 1) * 8) + 0.5f, rx1 = rx0 + 7.0f;
+    const float ry0 = (float)(ty * kTile + (wave >> 1) * 8) + 0.5f, ry1 = ry0 + 7.0f;
+    const int HW = cam.W * cam.H;
+    const bool in = px < cam.W && py < cam.H;
+    const int pix = py * cam.W + px;
+    float T[1], up[1][5], U[1];
+    uint32_t last[1];
+    const float pyf[1] = {(float)py + 0.5f};
+    T[0] = in ? t_final[pix] : 1.0f;
+    last[0] = in ? n_contrib[pix] : 0u;
+    up[0][0] = (in && dl_dc) ? dl_dc[pix] : 0.0f;
+    up[0][1] = (in && dl_dc) ? dl_dc[HW + pix] : 0.0f;
+    up[0][2] = (in && dl_dc) ? dl_dc[2 * HW + pix] : 0.0f;
+    up[0][3] = (in && dl_dd) ? dl_dd[pix] : 0.0f;
+    up[0][4] = (in && dl_da) ? dl_da[pix] : 0.0f;
+    U[0] = fmaf(up[0][0], tab.bg[0], fmaf(up[0][1], tab.bg[1], up[0][2] * tab.bg[2]));
+    const float pxf = (float)px + 0.5f;
+    const uint32_t wl = wave_max_u32(last[0]);
+    if (lane == 0) s_wl[wave] = wl;
+    for (int i = threadIdx.x; i < 64 * 11; i += 256) (&acc[0][0])[i] = 0.0f;
+    __syncthreads();
+    const uint32_t bwl = max(max(s_wl[0], s_wl[1]), max(s_wl[2], s_wl[3]));
+    const uint32_t start = ranges[2 * gt];
+    for (int bs = bwl ? (int)((bwl - 1u) & ~63u) : -1; bs >= 0; bs -= 64) {  // uniform across the block
+        {
+            // stage: thread t loads quarter t / 64 of record t % 64
+            const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+            const uint32_t li = (uint32_t)bs + r;
+            if (li < bwl) {
+                const uint32_t g = gids[start + li];
+                const float4 v = reinterpret_cast<const float4*>(rec + g)[q];
+                if (q < 3) slab[q][r] = v; else slab_z[r] = v.x;
+                if (q == 0) slab_gid[r] = g;
+            }
+        }
+        __syncthreads();
+        // this wave's entries of the slab: below its own last contributor and
+        // (with culling) reaching its quadrant
+        bool keep = false;
+        if ((uint32_t)bs + lane < wl) {
+            Splat sp;
+            sp.a = slab[0][lane];
+            sp.b = slab[1][lane];
+            sp.c = slab[2][lane];
+            keep = !cull || reaches_rect(sp, rx0, rx1, ry0, ry1);
+        }
+        uint64_t hits = __ballot(keep);
+        while (hits) {
+            const int k = 63 - __builtin_clzll(hits);
+            hits &= ~(1ull << k);
+            float p[10];
+            if (!adjoint_entry<1, COUNT>(slab[0], slab[1], slab[2], slab_z, k, (uint32_t)(bs + k), pxf, pyf, last, T,
+                                         U, up, p, n_eval, n_blend))
+                continue;
+            const float tot = wave_reduce10(p, lane);
+            if (wrv >= 0) atomicAdd(&acc[k][wrv], tot);
+        }
+        __syncthreads();
+        // flush: the block's nonzero totals of the slab, one atomic per value
+        for (int i = threadIdx.x; i < 64 * 10; i += 256) {
+            const int k = i / 10, v = i - 10 * k;
+            const float t = acc[k][v];
+            if (t != 0.0f) {
+                atomicAdd(g2 + (size_t)kG2 * slab_gid[k] + v, t);
+                acc[k][v] = 0.0f;
+                if (COUNT && v == 0) ++n_flush;
+            }
+        }
+        __syncthreads();
+    }
     if (COUNT) {
         if (n_eval) atomicAdd(counters + 2, (unsigned long long)n_eval);
         if (n_blend) atomicAdd(counters + 3, (unsigned long long)n_blend);
@@ -560,6 +686,15 @@ void launch_composite_bwd(const ViewTab& v, uint32_t total_tiles, const Splat* r
 {
     if (total_tiles == 0) return;
     const int ppl = options().ppl_bwd, cull = options().cull, sched = options().sched;
+    if (ppl == 1 && options().bwd_merge) {  // one block per tile, the waves' totals merged per slab
+        if (counters)
+            k_composite_bwd_tile<true><<<total_tiles, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, g2, counters,
+                                                                    cull, sched);
+        else
+            k_composite_bwd_tile<false><<<total_tiles, 256, 0, s>>>(v, total_tiles, rec, gids, ranges, g2, nullptr,
+                                                                     cull, sched);
+        return;
+    }
     const int blocks = (int)(((int64_t)total_tiles * (4 / ppl) + 3) / 4);
     if (ppl == 4) bwd_launch<4>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull, sched);
     else if (ppl == 2) bwd_launch<2>(blocks, s, v, total_tiles, rec, gids, ranges, g2, counters, cull, sched);

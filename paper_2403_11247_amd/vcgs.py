@@ -827,7 +827,7 @@ def count_read(ctx: Context | None = None) -> dict:
     return dict(zip(("fwd_evals", "fwd_blends", "bwd_evals", "bwd_blends", "bwd_flushes"), list(arr)))
 
 
-OPTIONS = {"ppl_fwd": 1, "ppl_bwd": 2, "cull": 3, "sched": 4}
+OPTIONS = {"ppl_fwd": 1, "ppl_bwd": 2, "cull": 3, "sched": 4, "bwd_merge": 5}
 
 
 def set_option(name: str, value: int):
