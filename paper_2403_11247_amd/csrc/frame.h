@@ -27,8 +27,9 @@ struct Frame {
 };
 
 struct Work {
-    uint32_t *dk, *order, *kaltE, *valtE, *histE, *scanE, *cnt, *offs, *total, *overflow;
-    uint32_t *tile_ids, *kaltP, *valtP, *histP, *scanP;  // scanP: emission chunk starts
+    uint32_t *dk, *order, *kaltE, *valtE, *headE, *stateE, *scanE, *cnt, *offs, *total, *overflow;
+    uint32_t *headP;  // the pair sort's counters (entry-sized work, so that one launch can zero it early)
+    uint32_t *tile_ids, *kaltP, *valtP, *stateP, *scanP;  // scanP: emission chunk starts
     const uint32_t* nvis;  // device count of entries in the depth order (culled ones are dropped)
 };
 
@@ -37,15 +38,17 @@ int check_gaussians(const vcgs_gaussians* g, int V);
 // Fills the projection, emission and compositing tables of V views (outputs,
 // final transmittance and upstream-gradient pointers of vt are left null).
 void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* poses, const float bg[3], Frame& f);
-// Projection, depth order of all entries, pair offsets; the pair count ends
-// up in w.total on the device.  Returns the depth order.
-const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s);
+// Zeroes, in one launch, what a pass needs at zero: both sorts' counters, the
+// tile ranges and (unless keep_overflow) the overflow flag.
+void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow = false);
+// zero_pass, projection, depth order of all entries, pair offsets; the pair
+// count ends up in w.total on the device.  Returns the depth order.
+const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s,
+                        bool keep_overflow = false);
 // Pairs (at most f.cap, overflow flagged in w.overflow), stable tile sort,
-// tile ranges, forward compositing.
-void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s, bool prefilled = false,
-             bool keep_overflow = false);
-// Zeroes the tile ranges and (unless keep_overflow) the overflow flag.
-void phase_b_prefill(Frame& f, Work& w, hipStream_t s, bool keep_overflow = false);
+// tile ranges, forward compositing (after phase_a, or zero_pass when there
+// are no entries).
+void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s);
 
 // Significant bits of v (at least 1).
 inline int bits_for(uint32_t v)
@@ -63,7 +66,9 @@ inline void alloc_work_e(Work& w, int64_t E, Get get)
     w.order = get(E);
     w.kaltE = get(E);
     w.valtE = get(E);
-    w.histE = get(sort_temp_words(E));
+    w.headE = get(sort_head_words());
+    w.stateE = get(sort_state_words(E));
+    w.headP = get(sort_head_words());
     w.scanE = get(scan_temp_words(E) + 8);
     w.cnt = get(E);
     w.offs = get(E);
@@ -77,7 +82,7 @@ inline void alloc_work_p(Work& w, int64_t cap, Get get)
     w.tile_ids = get(cap);
     w.kaltP = get(cap);
     w.valtP = get(cap);
-    w.histP = get(sort_temp_words(cap));
+    w.stateP = get(sort_state_words(cap));
     w.scanP = get(emit_chunk_words(cap));
 }
 

@@ -47,14 +47,29 @@ void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* po
 
 // Projection, depth order of all entries, pair offsets; the pair count ends
 // up in w.total on the device.  Returns the depth order.
-const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s)
+void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow)
 {
+    ZeroSegs z;
+    z.p[0] = w.headE;
+    z.n[0] = sort_head_words();
+    z.p[1] = w.headP;
+    z.n[1] = sort_head_words();
+    z.p[2] = f.ranges;
+    z.n[2] = 2 * (int64_t)f.total_tiles;
+    z.p[3] = keep_overflow ? nullptr : w.overflow;
+    z.n[3] = 1;
+    launch_zero_u32(z, s);
+}
+
+const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s, bool keep_overflow)
+{
+    zero_pass(f, w, s, keep_overflow);
     pf.begin(VCGS_STAGE_PREPROCESS, s);
     launch_preprocess(f.pt, f.pt_dev, g, f.rec, f.depth_key, f.rect, f.count, f.g2, s);
     pf.end(VCGS_STAGE_PREPROCESS, s);
     pf.begin(VCGS_STAGE_DEPTH_SORT, s);
     // culled entries carry the drop key and leave the depth order in its first pass
-    const SortTemp t{w.kaltE, w.valtE, w.histE, w.scanE};
+    const SortTemp t{w.kaltE, w.valtE, w.headE, w.stateE};
     const int which = radix_sort_u32(w.dk, w.order, true, Count{f.E, nullptr}, 32, t, s, &w.nvis, f.depth_key);
     pf.end(VCGS_STAGE_DEPTH_SORT, s);
     const uint32_t* ord = which ? w.valtE : w.order;
@@ -65,19 +80,9 @@ const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hi
     return ord;
 }
 
-// Zeroing of the tile ranges and the overflow flag, which phase_b needs first
-// (issued early by a caller that synchronises in between).  A batched plan
-// keeps its overflow flag across passes until vcgs_batch_check reads it.
-void phase_b_prefill(Frame& f, Work& w, hipStream_t s, bool keep_overflow)
-{
-    launch_fill_u32(f.ranges, 0u, 2 * (int64_t)f.total_tiles, s);
-    if (!keep_overflow) launch_fill_u32(w.overflow, 0u, 1, s);
-}
-
 // Pairs, stable tile sort, tile ranges, forward compositing.
-void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s, bool prefilled, bool keep_overflow)
+void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s)
 {
-    if (!prefilled) phase_b_prefill(f, w, s, keep_overflow);
     if (f.cap > 0) {
         const Count P{f.cap, w.total};
         pf.begin(VCGS_STAGE_EMIT, s);
@@ -85,7 +90,7 @@ void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s, bo
                           w.total, w.overflow, s);
         pf.end(VCGS_STAGE_EMIT, s);
         pf.begin(VCGS_STAGE_TILE_SORT, s);
-        const SortTemp tp{w.kaltP, w.valtP, w.histP, w.scanP};
+        const SortTemp tp{w.kaltP, w.valtP, w.headP, w.stateP};
         const int ws = radix_sort_u32(w.tile_ids, f.gids, false, P, bits_for(f.total_tiles - 1), tp, s);
         const uint32_t* tsorted = ws ? w.kaltP : w.tile_ids;
         if (ws) launch_copy_u32(f.gids, w.valtP, P, s);
@@ -268,8 +273,8 @@ static void enqueue_plan(vcgs_ctx* ctx, BatchPlan& p, const vcgs_gaussians& g, c
                          const float* const* tc, const float* const* td, const vcgs_gaussian_buffers& gb,
                          float* dl_dpose, float* loss, hipStream_t s)
 {
-    const uint32_t* ord = phase_a(ctx->prof, g, p.f, p.w, s);
-    phase_b(ctx->prof, p.f, p.w, ord, s, false, true);
+    const uint32_t* ord = phase_a(ctx->prof, g, p.f, p.w, s, true);
+    phase_b(ctx->prof, p.f, p.w, ord, s);
     if (!p.backward) return;
     ctx->prof.begin(VCGS_STAGE_LOSS, s);
     LossTab lt;
@@ -403,9 +408,9 @@ static int render_forward_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
         std::memcpy(ctx->host_tab, &f.pt, sizeof(ProjTab));
         if (hipMemcpyAsync(f.pt_dev, ctx->host_tab, sizeof(ProjTab), hipMemcpyHostToDevice, s) != hipSuccess)
             return drop(VCGS_E_HIP, "table upload failed");
-        const uint32_t* ord = f.E > 0 ? phase_a(ctx->prof, *g, f, w, s) : nullptr;
-        // what does not depend on the pair count runs while the host waits for it
-        phase_b_prefill(f, w, s);
+        const uint32_t* ord = nullptr;
+        if (f.E > 0) ord = phase_a(ctx->prof, *g, f, w, s);
+        else zero_pass(f, w, s);
         if (f.E > 0) {
             if (hipMemcpyAsync(ctx->host_u32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
@@ -418,7 +423,7 @@ static int render_forward_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
         f.gids = st->get<uint32_t>(f.cap);
         if (f.cap > 0) alloc_work_p(w, f.cap, [&](int64_t c) { return sc.get<uint32_t>(c); });
         if (!st->ok() || sc.oom) return drop(VCGS_E_NOMEM, "device allocation failed (pairs)");
-        phase_b(ctx->prof, f, w, ord, s, true);
+        phase_b(ctx->prof, f, w, ord, s);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return drop(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     }
@@ -608,7 +613,7 @@ static int render_batch_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcgs_
     // size the pair buffers once (and again after an overflow was reported)
     if (f.cap == 0 || plan->need > f.cap) {
         plan->drop_graph();
-        const uint32_t* ord = phase_a(ctx->prof, *g, f, plan->w, s);
+        const uint32_t* ord = phase_a(ctx->prof, *g, f, plan->w, s, true);
         (void)ord;
         HIP_TRY(hipMemcpyAsync(plan->host_flags, plan->w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));

@@ -105,16 +105,18 @@ void launch_pose_reduce(const float* partial, int n_views, int nblocks, float* d
 struct SortTemp {
     uint32_t* keys_alt;
     uint32_t* vals_alt;
-    uint32_t* hist;     // >= sort_temp_words(cap): digit counts, partition counters, look-back state
-    uint32_t* scan_tmp; // unused by the sort
+    uint32_t* head;     // sort_head_words(): digit counts and partition counters, zero on entry
+    uint32_t* state;    // sort_state_words(cap): look-back state (the sort zeroes what it uses)
 };
 constexpr int64_t kMaxSortItems = (1ll << 30) - 1;
 int radix_blocks(int64_t n);
-int64_t sort_temp_words(int64_t cap);
+int64_t sort_head_words();
+int64_t sort_state_words(int64_t cap);
 int64_t scan_temp_words(int64_t n);
-// Stable LSD radix sort of (keys, vals) on bits [0, end_bit), end_bit <= 32.  With
-// identity_vals the input values are 0..n-1 and `vals` is not read (it must
-// still hold cap entries).  Returns 0 if the result is in (keys, vals), 1 if
+// Stable LSD radix sort of (keys, vals) on bits [0, end_bit), end_bit <= 32.
+// t.head must be zero on entry (launch_zero_u32 clears it with other buffers
+// in one launch).  With identity_vals the input values are 0..n-1 and `vals`
+// is not read (it must still hold cap entries).  Returns 0 if the result is in (keys, vals), 1 if
 // it is in (t.keys_alt, t.vals_alt).  At most kMaxSortItems items (returns -1
 // and does nothing above that).
 // With kept != nullptr, items whose key is kDropKey are dropped (the others
@@ -151,6 +153,12 @@ void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis
 int64_t emit_chunk_words(int64_t cap);
 void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+// Zeroes up to four buffers (null or empty ones are skipped) in one launch.
+struct ZeroSegs {
+    uint32_t* p[4];
+    int64_t n[4];
+};
+void launch_zero_u32(const ZeroSegs& z, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 void launch_copy_u32(uint32_t* dst, const uint32_t* src, Count n, hipStream_t s);
 

@@ -109,8 +109,9 @@ int vcgs_render_forward_noalloc(vcgs_ctx* ctx, const vcgs_gaussians* g, const vc
     // the pinned staging copy is free again after the synchronisation below
     std::memcpy(ctx->host_tab, &f.pt, sizeof(ProjTab));
     HIP_TRY(hipMemcpyAsync(f.pt_dev, ctx->host_tab, sizeof(ProjTab), hipMemcpyHostToDevice, s));
-    const uint32_t* ord = f.E > 0 ? phase_a(ctx->prof, *g, f, w, s) : nullptr;
-    phase_b_prefill(f, w, s);
+    const uint32_t* ord = nullptr;
+    if (f.E > 0) ord = phase_a(ctx->prof, *g, f, w, s);
+    else zero_pass(f, w, s);
     int64_t P = 0;
     if (f.E > 0) {
         HIP_TRY(hipMemcpyAsync(ctx->host_u32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -127,7 +128,7 @@ int vcgs_render_forward_noalloc(vcgs_ctx* ctx, const vcgs_gaussians* g, const vc
                                          std::to_string(cv.used) + " bytes of scratch; the array holds " +
                                          std::to_string(kNoAllocBytes));
     }
-    phase_b(ctx->prof, f, w, ord, s, true);
+    phase_b(ctx->prof, f, w, ord, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(VCGS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return VCGS_OK;

@@ -156,14 +156,15 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     // then its final transmittance.  Keeping the state in the sign lets the
     // blend below run without any per-lane branch or mask bookkeeping.
     float dy[PPL];
-    float T[PPL], c0[PPL], c1[PPL], c2[PPL], dd[PPL], aa[PPL];
+    // the silhouette sum_i alpha_i T_i telescopes to 1 - T_final: no channel of its own
+    float T[PPL], c0[PPL], c1[PPL], c2[PPL], dd[PPL];
     uint32_t last[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
         const int py = row0 + lane / SW + LR * j;
         dy[j] = (float)py + 0.5f;
         T[j] = (px < cam.W && py < cam.H) ? 1.0f : -1.0f;
-        c0[j] = c1[j] = c2[j] = dd[j] = aa[j] = 0.0f;
+        c0[j] = c1[j] = c2[j] = dd[j] = 0.0f;
         last[j] = 0u;
     }
     const float pxf = (float)px + 0.5f;
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
         const float w = stop ? 0.0f : a * T[j];
         if (COUNT) { n_eval += (en && T[j] > 0.0f) ? 1u : 0u; n_blend += w > 0.0f ? 1u : 0u; }
         c0[j] += w * rc.y; c1[j] += w * rc.z; c2[j] += w * rc.w;
-        dd[j] += w * rz; aa[j] += w;
+        dd[j] += w * rz;
         last[j] = w > 0.0f ? idx : last[j];
         T[j] = stop ? -fabsf(T[j]) : Tn;
         return w > 0.0f;
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
             color[HW + p] = c1[j] + T[j] * bg1;
             color[2 * HW + p] = c2[j] + T[j] * bg2;
             depth[p] = dd[j];
-            alpha_out[p] = aa[j];
+            alpha_out[p] = 1.0f - T[j];
             if (t_final) {  // null for forward-only callers
                 t_final[p] = T[j];
                 n_contrib[p] = last[j];
@@ -504,10 +505,59 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
         while (hits) {
             const int k = 63 - __builtin_clzll(hits);
             hits &= ~(1ull << k);
+            const uint32_t local = (uint32_t)(bs + k);
+            const float4 ra = slab[wave][0][k], rb = slab[wave][1][k];
+            const float dx = (pxf - ra.x) - ra.z;
+            // footprints first: a wave-entry that blends into none of the wave's
+            // pixels changes no state and adds nothing, so it skips the adjoint
+            Fp fj[PPL];
+            bool cj[PPL];
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                fj[j] = footprint(dx, (pyf[j] - ra.y) - ra.w, rb.x, rb.y, rb.z, rb.w, slab[wave][2][k].x);
+                const bool in = local < last[j];
+                cj[j] = in && fj[j].alpha >= kAlphaMin;
+                if (COUNT) { n_eval += in ? 1u : 0u; n_blend += cj[j] ? 1u : 0u; }
+                any = any || cj[j];
+            }
+            if (__ballot(any) == 0ull) continue;
+            const float4 rc = slab[wave][2][k];
+            const float rz = slab_z[wave][k];
+            // Per-lane sums: p0 = sum dP p1, p1 = sum dP p2, p2 = sum dP p1^2,
+            // p3 = sum dP p1 p2, p4 = sum dP p2^2 (dP = dL/dpower, (p1, p2) the
+            // pixel offset in the footprint's eigen frame; the projection adjoint
+            // turns them into dL/d(u, v) and dL/d(conic)), p5 = dL/dopacity,
+            // p6-p9 = dL/d(r, g, b, depth).
             float p[10];
-            if (!adjoint_entry<PPL, COUNT>(slab[wave][0], slab[wave][1], slab[wave][2], slab_z[wave], k,
-                                           (uint32_t)(bs + k), pxf, pyf, last, T, U, up, p, n_eval, n_blend))
-                continue;
+#pragma unroll
+            for (int i = 0; i < 10; ++i) p[i] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                // branch-free: every lane evaluates, only contributing pixels change state
+                const Fp& f = fj[j];
+                const bool c = cj[j];
+                const float a = f.alpha;
+                const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
+                const float X = fmaf(up[j][0], rc.y, fmaf(up[j][1], rc.z, fmaf(up[j][2], rc.w, fmaf(up[j][3], rz, up[j][4]))));
+                const float d = X - U[j];
+                U[j] = fmaf(c ? a : 0.0f, d, U[j]);
+                const float w = c ? a * Ti : 0.0f;
+                p[6] = fmaf(w, up[j][0], p[6]);
+                p[7] = fmaf(w, up[j][1], p[7]);
+                p[8] = fmaf(w, up[j][2], p[8]);
+                p[9] = fmaf(w, up[j][3], p[9]);
+                const float dg = (c && !f.clamped) ? d * Ti : 0.0f;  // dL/d(o G)
+                const float dP = dg * a;                             // dL/dpower
+                const float t1 = dP * f.p1, t2 = dP * f.p2;
+                p[0] += t1;
+                p[1] += t2;
+                p[2] = fmaf(t1, f.p1, p[2]);
+                p[3] = fmaf(t1, f.p2, p[3]);
+                p[4] = fmaf(t2, f.p2, p[4]);
+                p[5] = fmaf(dg, f.G, p[5]);
+                T[j] = c ? Ti : T[j];
+            }
             const float tot = wave_reduce10(p, lane);
             if (wrv >= 0) pend[wave][npend][wrv] = tot;
             if (lane == 0) pend_gid[wave][npend] = slab_gid[wave][k];

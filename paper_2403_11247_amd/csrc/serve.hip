@@ -219,6 +219,7 @@ struct vcgs_server {
             HIP_TRY(hipMemcpyAsync(sl.flags_host, sl.w.total, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, sl.s));
         } else {
             f.cap = 0;
+            zero_pass(f, sl.w, sl.s);
             phase_b(quiet_prof(), f, sl.w, nullptr, sl.s);  // background images
             sl.flags_host[0] = sl.flags_host[1] = 0u;
         }

@@ -201,10 +201,8 @@ constexpr int64_t kStateBase = kHistWords + 64;  // words: histograms, counters,
 // Temp layout (uint32 words): [copy][pass][256] global digit counts, [pass]
 // partition counters (at kHistWords), the kept count, then
 // [pass][partition][256] look-back state.
-int64_t sort_temp_words(int64_t cap)
-{
-    return kStateBase + (int64_t)kMaxPasses * radix_blocks(cap) * kBins;
-}
+int64_t sort_head_words() { return kStateBase; }
+int64_t sort_state_words(int64_t cap) { return (int64_t)kMaxPasses * radix_blocks(cap) * kBins; }
 
 __device__ __forceinline__ uint32_t load_agent(const uint32_t* p)
 {
@@ -416,12 +414,11 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, 
     const int nb = radix_blocks(n.cap);
     const int items = sort_items(n.cap);
     const int passes = std::min(kMaxPasses, (end_bit + 7) / 8);
-    uint32_t* ghist = t.hist;
-    uint32_t* counters = t.hist + kHistWords;
+    uint32_t* ghist = t.head;  // histograms and counters: zero on entry
+    uint32_t* counters = t.head + kHistWords;
     uint32_t* kept_dev = counters + kMaxPasses;
-    uint32_t* state = t.hist + kStateBase;
+    uint32_t* state = t.state;  // the look-back words: zeroed by k_sort_hist
     const int drop = kept != nullptr;
-    launch_fill_u32(t.hist, 0u, kStateBase, s);  // histograms, counters (the look-back words: k_sort_hist)
     const int hb = std::min(nb, 1024);
     const int pb = std::min(nb, 2048);
     const uint32_t* first = keys_src ? keys_src : keys;
