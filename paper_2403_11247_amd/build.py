@@ -1,10 +1,12 @@
 """Build libvcgs.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2403_11247_amd.build [-v]
+    python -m paper_2403_11247_amd.build [-v] [--sort-bench]
 
 Every HIP source is compiled with the packed-FP32 instructions disabled and
 hardware float atomics enabled, then linked into one shared library next to
-this file.  The build always recompiles.
+this file.  The build always recompiles.  With --sort-bench it also builds
+bench_sort, a stand-alone timing of the library's radix sort against hipCUB's
+(linked against libvcgs.so; not part of the render path).
 """
 from __future__ import annotations
 
@@ -57,5 +59,19 @@ def build(verbose=False):
     return LIB
 
 
+def build_sort_bench(verbose=False):
+    exe = os.path.join(HERE, "bench_sort")
+    cmd = [HIPCC, *[f for f in FLAGS if f != "-fPIC"], os.path.join(CSRC, "bench_sort.hip"), f"-L{HERE}",
+           "-lvcgs", "-Wl,-rpath,$ORIGIN", "-o", exe]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("bench_sort build failed:\n" + r.stderr)
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    if "--sort-bench" in sys.argv:
+        print(build_sort_bench(verbose="-v" in sys.argv))
