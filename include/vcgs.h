@@ -175,9 +175,11 @@ int vcgs_render_forward_noalloc(vcgs_ctx* ctx, const vcgs_gaussians* g, const vc
  *   gids[P]        Gaussian index of every (tile, depth)-sorted pair
  *   ranges[T][2]   [start, end) of each tile's pairs in gids
  *   t_final[H][W], n_contrib[H][W] (uint32: list entries up to the last contributor)
- *   splats[n][16]  float: u, v, u_lo, v_lo, ex, ey, j1, j2, opacity, r, g, b, depth, 0, 0, 0
- *                  (visible Gaussians only): screen position u + u_lo, v + v_lo; unit major axis
- *                  (ex, ey); j1, j2 = -1 / (2 ln2 lambda) for the eigenvalues of Sigma' + 0.3 I
+ *   splats[n][16]  float: u, v, u_lo, v_lo, s1 ex, s1 ey, s2 ex, s2 ey, opacity, r, g, b, depth,
+ *                  s1, s2, 0 (visible Gaussians only): screen position u + u_lo, v + v_lo; unit
+ *                  major axis (ex, ey); s = sqrt(1 / (2 ln2 lambda)) for the eigenvalues lambda1 >=
+ *                  lambda2 of Sigma' + 0.3 I (the footprint is 2^-(q1^2 + q2^2) with
+ *                  q1 = s1 d . (ex, ey), q2 = s2 d . (-ey, ex))
  */
 typedef struct {
     int64_t n, n_pairs;

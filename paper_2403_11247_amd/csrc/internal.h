@@ -16,7 +16,7 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 constexpr float kLowPass = 0.3f;
 constexpr float kLowPass2 = 0.09f;
-constexpr float kNegHalfLog2e = -0.72134752f;  // -1 / (2 ln 2)
+constexpr float kHalfLog2e = 0.72134752f;      // 1 / (2 ln 2)
 constexpr float kLn2 = 0.69314718f;
 constexpr float kClampFov = 1.3f;
 constexpr float kTwoLn2 = 1.3862944f;
@@ -62,18 +62,19 @@ struct ViewTab {
     uint32_t* hits;  // optional: per-Gaussian count of blended pixels, accumulated (Gaussian = entry % n)
 };
 
-// Projected splat record, 64 bytes: (u, v, u_lo, v_lo) (ex, ey, j1, j2) (o, r, g, b) (depth, -, -, -).
-// The screen position is u + u_lo (a binary32 pair).  The footprint exponent in base 2
-// is j1 p1^2 + j2 p2^2 with p1 = d . (ex, ey), p2 = d . (-ey, ex), d = pixel centre -
-// (u, v), j = -1 / (2 ln2 lambda) for the two eigenvalues of Sigma' + 0.3 I.
+// Projected splat record, 64 bytes: (u, v, u_lo, v_lo) (s1 ex, s1 ey, s2 ex, s2 ey)
+// (o, r, g, b) (depth, s1, s2, -).  The screen position is u + u_lo (a binary32 pair),
+// (ex, ey) the unit eigenvector of the larger eigenvalue lambda1 of Sigma' + 0.3 I and
+// s = sqrt(1 / (2 ln2 lambda)) for each eigenvalue.  The footprint exponent in base 2 is
+// -(q1^2 + q2^2) with q1 = s1 d . (ex, ey), q2 = s2 d . (-ey, ex), d = pixel centre - (u, v).
 struct Splat {
     float4 a, b, c, d;
 };
 
 // Per-entry gradient sums of the compositing adjoint, 12 floats: five sums of
-// dL/dpower against the pixel offset (p1, p2) in the footprint's eigen frame
-// (p1, p2, p1^2, p1 p2, p2^2; the projection adjoint rotates them into
-// dL/d(u, v) and dL/d(conic)), dopacity, dr, dg, db, ddepth, -, -.
+// dL/dpower against the scaled pixel offset (q1, q2) in the footprint's eigen
+// frame (q1, q2, q1^2, q1 q2, q2^2; the projection adjoint unscales and rotates
+// them into dL/d(u, v) and dL/d(conic)), dopacity, dr, dg, db, ddepth, -, -.
 constexpr int kG2 = 12;
 
 CamK make_camk(const vcgs_camera& c, uint32_t tile_base = 0);

@@ -168,18 +168,22 @@ __global__ void __launch_bounds__(256) k_preprocess(const ProjTab* __restrict__ 
     // Eigen form of the inverse 2D covariance: d^T Sigma''^-1 d = p1^2 / lam + p2^2 / lmin with
     // p1 = d . e, p2 = d . e_perp, e the unit eigenvector of the larger eigenvalue lam; lmin = det / lam.
     // Both terms are non-negative, so evaluating it loses no precision for thin footprints.
+    // The record holds the eigenvector scaled by s1 = sqrt(log2(e) / (2 lam)) and by
+    // s2 = sqrt(log2(e) / (2 lmin)), so that the base-2 exponent of the footprint is
+    // -(q1^2 + q2^2) with q1 = s1 p1 = d . (s1 e), q2 = s2 p2 = d . (s2 e_perp).
     const float lmin = k.det / k.lam;
     const float da = k.lam - k.ca, dc = k.lam - k.cc;
     float ex, ey;
     if (fabsf(da) >= fabsf(dc)) { ex = k.cb; ey = da; } else { ex = dc; ey = k.cb; }
     const float nrm = sqrtf(ex * ex + ey * ey);
     if (nrm > 0.0f) { ex /= nrm; ey /= nrm; } else { ex = 1.0f; ey = 0.0f; }
+    const float s1 = sqrtf(kHalfLog2e / k.lam), s2 = sqrtf(kHalfLog2e / lmin);
     Splat sp;
     sp.a = make_float4(k.u, k.v, (float)(k.ud - (double)k.u), (float)(k.vd - (double)k.v));
-    sp.b = make_float4(ex, ey, kNegHalfLog2e / k.lam, kNegHalfLog2e / lmin);
+    sp.b = make_float4(s1 * ex, s1 * ey, s2 * ex, s2 * ey);
     const float* vc = color + 3 * vb;
     sp.c = make_float4(o, vc[g], vc[n + g], vc[2 * n + g]);
-    sp.d = make_float4(k.Z, 0.0f, 0.0f, 0.0f);
+    sp.d = make_float4(k.Z, s1, s2, 0.0f);
     rec[e] = sp;
     depth_key[e] = __float_as_uint(k.Z);
     count[e] = (uint32_t)((k.tx1 - k.tx0 + 1) * (k.ty1 - k.ty0 + 1));
@@ -233,23 +237,26 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
             const float4 a = *reinterpret_cast<const float4*>(g2 + kG2 * e);
             const float4 b = *reinterpret_cast<const float4*>(g2 + kG2 * e + 4);
             const float4 c = *reinterpret_cast<const float4*>(g2 + kG2 * e + 8);
-            // The compositing adjoint sums dL/dpower against the pixel offset in
-            // the footprint's eigen frame: a = (sum dP p1, sum dP p2, sum dP p1^2,
-            // sum dP p1 p2), b.x = sum dP p2^2, with p1 = d . e, p2 = d . e_perp,
-            // e = (ex, ey).  Since d = p1 e + p2 e_perp and power = -1/2 d^T Q d
-            // with Q = i1 e e^T + i2 e_perp e_perp^T: dL/du = sum dP (Q d)_x,
-            // dL/dv = sum dP (Q d)_y, and the conic terms -1/2 dx^2, -dx dy,
-            // -1/2 dy^2 follow from the second moments rotated back.
-            const float4 eb = rec[e].b;  // ex, ey, j1, j2 (j = -1 / (2 ln2 lambda))
-            const float ex = eb.x, ey = eb.y;
-            const float i1 = -2.0f * kLn2 * eb.z, i2 = -2.0f * kLn2 * eb.w;  // 1 / lambda
-            const float s1 = i1 * a.x, s2 = i2 * a.y;
-            gg[0] = ex * s1 - ey * s2;
-            gg[1] = ey * s1 + ex * s2;
+            // The compositing adjoint sums dL/dpower against the scaled pixel
+            // offset in the footprint's eigen frame: a = (sum dP q1, sum dP q2,
+            // sum dP q1^2, sum dP q1 q2), b.x = sum dP q2^2, with q1 = s1 p1,
+            // q2 = s2 p2, p1 = d . e, p2 = d . e_perp, e = (ex, ey) and
+            // s^2 = 1 / (2 ln2 lambda).  Since d = p1 e + p2 e_perp and power =
+            // -1/2 d^T Q d with Q = i1 e e^T + i2 e_perp e_perp^T (i = 1 / lambda
+            // = 2 ln2 s^2): dL/du = sum dP (Q d)_x, dL/dv = sum dP (Q d)_y, where
+            // i1 p1 e = 2 ln2 q1 (s1 e); the conic terms -1/2 dx^2, -dx dy,
+            // -1/2 dy^2 follow from the second moments of (p1, p2) rotated back.
+            const float4 eb = rec[e].b;  // s1 ex, s1 ey, s2 ex, s2 ey
+            const float4 ed = rec[e].d;  // depth, s1, s2
+            const float r1 = 1.0f / ed.y, r2 = 1.0f / ed.z;
+            const float ex = eb.x * r1, ey = eb.y * r1;
+            gg[0] = 2.0f * kLn2 * (eb.x * a.x - eb.w * a.y);
+            gg[1] = 2.0f * kLn2 * (eb.y * a.x + eb.z * a.y);
+            const float m11 = a.z * (r1 * r1), m12 = a.w * (r1 * r2), m22 = b.x * (r2 * r2);
             const float exx = ex * ex, eyy = ey * ey, exy = ex * ey;
-            gg[2] = -0.5f * ((exx * a.z - 2.0f * exy * a.w) + eyy * b.x);
-            gg[3] = -(exy * (a.z - b.x) + (exx - eyy) * a.w);
-            gg[4] = -0.5f * ((eyy * a.z + 2.0f * exy * a.w) + exx * b.x);
+            gg[2] = -0.5f * ((exx * m11 - 2.0f * exy * m12) + eyy * m22);
+            gg[3] = -(exy * (m11 - m22) + (exx - eyy) * m12);
+            gg[4] = -0.5f * ((eyy * m11 + 2.0f * exy * m12) + exx * m22);
             gg[5] = b.y; gg[6] = b.z; gg[7] = b.w; gg[8] = c.x; gg[9] = c.y;
         } else {
 #pragma unroll

@@ -37,30 +37,35 @@ struct Fp {
 };
 
 // Shared by forward and backward so both take identical skip decisions.
-__device__ __forceinline__ Fp footprint(float dx, float dy, float ex, float ey, float j1, float j2, float o)
+// (ax, ay) = s1 e and (bx, by) = s2 e (see Splat): p1, p2 here are the scaled
+// eigen-frame offsets q1 = s1 d . e and q2 = s2 d . e_perp, and the base-2
+// exponent is -(q1^2 + q2^2).
+__device__ __forceinline__ Fp footprint(float dx, float dy, float ax, float ay, float bx, float by, float o)
 {
 #pragma clang fp contract(off)
     Fp f;
-    f.p1 = __builtin_fmaf(dy, ey, dx * ex);
-    f.p2 = __builtin_fmaf(dy, ex, -(dx * ey));
-    const float pw = __builtin_fmaf(f.p1, f.p1 * j1, f.p2 * (f.p2 * j2));
+    f.p1 = __builtin_fmaf(dy, ay, dx * ax);
+    f.p2 = __builtin_fmaf(dy, bx, -(dx * by));
+    const float pw = __builtin_fmaf(-f.p1, f.p1, -(f.p2 * f.p2));
     f.G = __builtin_amdgcn_exp2f(pw);
     const float raw = o * f.G;
     f.clamped = raw > kAlphaMax;
-    f.alpha = f.clamped ? kAlphaMax : raw;
+    f.alpha = fminf(raw, kAlphaMax);
     return f;
 }
 
 // Can the Gaussian reach alpha >= 1/255 at some point of [x0, x1] x [y0, y1]?
-// Exact minimum of q(d) = -(j1 p1^2 + j2 p2^2) (base-2 units) over the
-// rectangle, compared with log2(255 o) plus a margin far above FP32 error.
+// Exact minimum of q(d) = q1^2 + q2^2 (base-2 units) over the rectangle,
+// compared with log2(255 o) plus a margin far above FP32 error.  With the
+// scaled rows (ax, ay) = s1 e and (bx, by) = s2 e, q(d) = A dx^2 + 2 B dx dy
+// + C dy^2 with A = ax^2 + by^2, B = ax ay - bx by, C = ay^2 + bx^2.
 __device__ __forceinline__ bool reaches_rect(const Splat& s, float x0, float x1, float y0, float y1)
 {
-    const float u = s.a.x + s.a.z, v = s.a.y + s.a.w, ex = s.b.x, ey = s.b.y;
-    const float k1 = -s.b.z, k2 = -s.b.w, o = s.c.x;  // k > 0
-    const float A = ex * ex * k1 + ey * ey * k2;
-    const float B = ex * ey * (k1 - k2);
-    const float C = ey * ey * k1 + ex * ex * k2;
+    const float u = s.a.x + s.a.z, v = s.a.y + s.a.w, o = s.c.x;
+    const float ax = s.b.x, ay = s.b.y, bx = s.b.z, by = s.b.w;
+    const float A = ax * ax + by * by;
+    const float B = ax * ay - bx * by;
+    const float C = ay * ay + bx * bx;
     const float thr = __log2f(255.0f * o) * 1.001f + 1e-3f;
     if (u >= x0 && u <= x1 && v >= y0 && v <= y1) return true;
     // the edge minimisers need not be exact: any point of an edge bounds the
@@ -345,8 +350,8 @@ __device__ __forceinline__ int wr_value(int lane)
 // One list entry k of a staged slab for the wave's pixels (local = its index
 // in the tile's list): footprints, then, if it blends into any of the wave's
 // pixels, the adjoint of each pixel's blend, returned as the ten per-lane sums
-// p (p0-p4: dL/dpower against the eigen-frame offset (p1, p2, p1^2, p1 p2,
-// p2^2), p5: dL/dopacity, p6-p9: dL/d(r, g, b, depth)), stepping T and U back
+// p (p0-p4: dL/dpower against the scaled eigen-frame offset (q1, q2, q1^2,
+// q1 q2, q2^2), p5: dL/dopacity, p6-p9: dL/d(r, g, b, depth)), stepping T and U back
 // over the entry.  Returns false (and changes nothing) when no lane blends it.
 template <int PPL, bool COUNT>
 __device__ __forceinline__ bool adjoint_entry(const float4* s0, const float4* s1, const float4* s2, const float* sz,
@@ -524,10 +529,10 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
             if (__ballot(any) == 0ull) continue;
             const float4 rc = slab[wave][2][k];
             const float rz = slab_z[wave][k];
-            // Per-lane sums: p0 = sum dP p1, p1 = sum dP p2, p2 = sum dP p1^2,
-            // p3 = sum dP p1 p2, p4 = sum dP p2^2 (dP = dL/dpower, (p1, p2) the
-            // pixel offset in the footprint's eigen frame; the projection adjoint
-            // turns them into dL/d(u, v) and dL/d(conic)), p5 = dL/dopacity,
+            // Per-lane sums: p0 = sum dP q1, p1 = sum dP q2, p2 = sum dP q1^2,
+            // p3 = sum dP q1 q2, p4 = sum dP q2^2 (dP = dL/dpower, (q1, q2) the
+            // scaled pixel offset in the footprint's eigen frame; the projection
+            // adjoint turns them into dL/d(u, v) and dL/d(conic)), p5 = dL/dopacity,
             // p6-p9 = dL/d(r, g, b, depth).
             float p[10];
 #pragma unroll
