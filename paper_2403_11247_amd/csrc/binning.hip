@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(256) k_zero_u32(ZeroSegs z, int64_t total)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t k = i;
         int seg = 0;
-        while (seg < 3 && k >= z.n[seg]) {
+        while (seg < kZeroSegs - 1 && k >= z.n[seg]) {
             k -= z.n[seg];
             ++seg;
         }
@@ -42,7 +42,7 @@ void launch_zero_u32(const ZeroSegs& zin, hipStream_t s)
 {
     ZeroSegs z = zin;
     int64_t total = 0;
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kZeroSegs; ++i) {
         if (!z.p[i] || z.n[i] < 0) z.n[i] = 0;
         total += z.n[i];
     }
@@ -69,22 +69,6 @@ void launch_copy_u32(uint32_t* dst, const uint32_t* src, Count n, hipStream_t s)
 {
     if (n.cap <= 0) return;
     k_copy_u32<<<(unsigned)((n.cap + 255) / 256), 256, 0, s>>>(dst, src, n.cap, n.dev);
-}
-
-__global__ void __launch_bounds__(256) k_gather_counts(int64_t n, const uint32_t* __restrict__ order,
-                                                       const uint32_t* __restrict__ count,
-                                                       const uint32_t* __restrict__ nvis, uint32_t* __restrict__ out)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t m = nvis ? min((int64_t)*nvis, n) : n;
-    if (k < n) out[k] = k < m ? count[order[k]] : 0u;
-}
-
-void launch_gather_counts(int64_t n, const uint32_t* order, const uint32_t* count, const uint32_t* nvis,
-                          uint32_t* out, hipStream_t s)
-{
-    if (n <= 0) return;
-    k_gather_counts<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, order, count, nvis, out);
 }
 
 // Pair emission, balanced over the output: block c writes pairs

@@ -39,7 +39,8 @@ int check_gaussians(const vcgs_gaussians* g, int V);
 // final transmittance and upstream-gradient pointers of vt are left null).
 void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* poses, const float bg[3], Frame& f);
 // Zeroes, in one launch, what a pass needs at zero: both sorts' counters, the
-// tile ranges and (unless keep_overflow) the overflow flag.
+// pair scan's look-back words, the tile ranges and (unless keep_overflow) the
+// overflow flag.
 void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow = false);
 // zero_pass, projection, depth order of all entries, pair offsets; the pair
 // count ends up in w.total on the device.  Returns the depth order.
@@ -69,7 +70,7 @@ inline void alloc_work_e(Work& w, int64_t E, Get get)
     w.headE = get(sort_head_words());
     w.stateE = get(sort_state_words(E));
     w.headP = get(sort_head_words());
-    w.scanE = get(scan_temp_words(E) + 8);
+    w.scanE = get(pair_scan_words(E));
     w.cnt = get(E);
     w.offs = get(E);
     w.total = get(8);

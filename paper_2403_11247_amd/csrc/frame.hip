@@ -49,7 +49,7 @@ void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* po
 // up in w.total on the device.  Returns the depth order.
 void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow)
 {
-    ZeroSegs z;
+    ZeroSegs z{};
     z.p[0] = w.headE;
     z.n[0] = sort_head_words();
     z.p[1] = w.headP;
@@ -58,6 +58,8 @@ void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow)
     z.n[2] = 2 * (int64_t)f.total_tiles;
     z.p[3] = keep_overflow ? nullptr : w.overflow;
     z.n[3] = 1;
+    z.p[4] = w.scanE;
+    z.n[4] = pair_scan_words(f.E);
     launch_zero_u32(z, s);
 }
 
@@ -74,8 +76,7 @@ const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hi
     pf.end(VCGS_STAGE_DEPTH_SORT, s);
     const uint32_t* ord = which ? w.valtE : w.order;
     pf.begin(VCGS_STAGE_PAIR_SCAN, s);
-    launch_gather_counts(f.E, ord, f.count, w.nvis, w.cnt, s);
-    exclusive_scan_u32(w.cnt, w.offs, f.E, w.total, w.scanE, s);
+    pair_offsets(ord, f.count, Count{f.E, w.nvis}, w.cnt, w.offs, w.total, w.scanE, s);
     pf.end(VCGS_STAGE_PAIR_SCAN, s);
     return ord;
 }

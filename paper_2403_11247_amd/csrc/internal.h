@@ -131,6 +131,14 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, 
 // the sum is written there.  Sums saturate at 2^31 instead of wrapping.
 void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
                         hipStream_t s);
+// Words of pair_offsets' look-back state for n entries (zero before each call).
+int64_t pair_scan_words(int64_t n);
+// Tile counts of the depth-ordered entries and their exclusive prefix sums in
+// one launch: cnt[k] = count[order[k]] for k below the device count n.dev
+// (0 up to n.cap), offs[k] = sum of cnt[j] for j < k, *total = the sum (all
+// saturating at 2^31).  state: pair_scan_words(n.cap) words, zero on entry.
+void pair_offsets(const uint32_t* order, const uint32_t* count, Count n, uint32_t* cnt, uint32_t* offs,
+                  uint32_t* total, uint32_t* state, hipStream_t s);
 
 // binning.hip
 struct EmitTab {
@@ -140,8 +148,6 @@ struct EmitTab {
     uint32_t tile_base[kMaxViews];
 };
 // out[k] = count[order[k]] for k < min(n, *nvis), 0 above (order is only read below *nvis).
-void launch_gather_counts(int64_t n, const uint32_t* order, const uint32_t* count, const uint32_t* nvis,
-                          uint32_t* out, hipStream_t s);
 // Entries k < min(n_entries, *nvis) of the depth order (offsets offs and
 // counts cnt in that order) emit their pairs; writes pairs p < cap only; if the
 // total exceeds cap raises *overflow to the total (when non-null; the flag
@@ -155,9 +161,10 @@ int64_t emit_chunk_words(int64_t cap);
 void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 // Zeroes up to four buffers (null or empty ones are skipped) in one launch.
+constexpr int kZeroSegs = 5;
 struct ZeroSegs {
-    uint32_t* p[4];
-    int64_t n[4];
+    uint32_t* p[kZeroSegs];
+    int64_t n[kZeroSegs];
 };
 void launch_zero_u32(const ZeroSegs& z, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);

@@ -187,6 +187,124 @@ void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
 }
 
 // ---------------------------------------------------------------------------
+// Pair offsets: gathered tile counts and their exclusive scan in one pass
+// ---------------------------------------------------------------------------
+
+// Look-back words, one per 4096-entry partition: the partition's own sum
+// (flag kPsAgg) or the sum of it and every lower partition (kPsInc) in the
+// low 32 bits.  Word 0 is the partition counter.
+constexpr unsigned long long kPsAgg = 1ull << 62, kPsInc = 2ull << 62, kPsFlags = 3ull << 62;
+
+int64_t pair_scan_words(int64_t n) { return 2 * ((std::max<int64_t>(n, 0) + kBlockItems - 1) / kBlockItems + 1); }
+
+__device__ __forceinline__ unsigned long long load_agent64(const unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent64(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Saturating sum over the 64 lanes, result in every lane.
+__device__ __forceinline__ uint32_t wave_sum_sat(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = sat_add(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+// cnt[k] = count[order[k]] for k below the device count (0 up to n_all),
+// offs = the exclusive prefix sums of cnt, *total = their sum.  Each block
+// takes the next partition from the counter, publishes its own sum, and wave 0
+// looks back over 64 lower partitions at a time until it meets an inclusive
+// sum; a partition only waits on partitions taken earlier, by running blocks.
+__global__ void __launch_bounds__(kThreads) k_pair_offsets(int64_t n_all, const uint32_t* __restrict__ ndev,
+                                                           const uint32_t* __restrict__ order,
+                                                           const uint32_t* __restrict__ count,
+                                                           uint32_t* __restrict__ cnt, uint32_t* __restrict__ offs,
+                                                           uint32_t* __restrict__ total,
+                                                           unsigned long long* __restrict__ state)
+{
+    __shared__ uint32_t tile[kBlockItems + kBlockItems / 16];
+    __shared__ uint32_t s_part, s_excl;
+    unsigned long long* const look = state + 1;
+    if (threadIdx.x == 0) s_part = (uint32_t)atomicAdd(state, 1ull);
+    __syncthreads();
+    const int64_t part = s_part;
+    const int64_t n = dev_count(n_all, ndev);
+    const int64_t base = part * kBlockItems;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const int k = i * kThreads + threadIdx.x;
+        const int64_t idx = base + k;
+        const uint32_t c = idx < n ? count[order[idx]] : 0u;
+        tile[scan_pad(k)] = c;
+        if (idx < n_all) cnt[idx] = c;
+    }
+    __syncthreads();
+    uint32_t v[kItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        v[i] = tile[scan_pad(threadIdx.x * kItems + i)];
+        sum = sat_add(sum, v[i]);
+    }
+    uint32_t tot;
+    const uint32_t local = block_excl_scan(sum, &tot);
+    if (threadIdx.x < 64) {
+        const int lane = (int)threadIdx.x;
+        if (lane == 0) store_agent64(look + part, (part == 0 ? kPsInc : kPsAgg) | tot);
+        uint32_t excl = 0u;
+        if (part > 0) {
+            int64_t q = part - 1;
+            for (;;) {  // partition 0 is inclusive, so this ends there at the latest
+                const unsigned long long w = q - lane >= 0 ? load_agent64(look + (q - lane)) : kPsInc;
+                const unsigned long long f = w & kPsFlags;
+                const uint64_t incm = __ballot(f == kPsInc);
+                const uint64_t unpub = __ballot(f == 0ull);
+                const int fi = incm ? __builtin_ctzll(incm) : 64;
+                const int fu = unpub ? __builtin_ctzll(unpub) : 64;
+                // lanes [0, take) are published; with fu > fi they end at an inclusive sum
+                const int take = fu > fi ? fi + 1 : fu;
+                excl = sat_add(excl, wave_sum_sat(lane < take ? (uint32_t)w : 0u));
+                if (fu > fi) break;
+                q -= take;
+                if (take == 0) __builtin_amdgcn_s_sleep(1);  // partition q is running and has not published yet
+            }
+            if (lane == 0) store_agent64(look + part, kPsInc | sat_add(excl, tot));
+        }
+        if (lane == 0) s_excl = excl;
+    }
+    __syncthreads();
+    uint32_t run = sat_add(s_excl, local);
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        tile[scan_pad(threadIdx.x * kItems + i)] = run;
+        run = sat_add(run, v[i]);
+    }
+    if (threadIdx.x == kThreads - 1 && base + kBlockItems >= n_all) *total = run;  // the last partition
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const int k = i * kThreads + threadIdx.x;
+        if (base + k < n_all) offs[base + k] = tile[scan_pad(k)];
+    }
+}
+
+void pair_offsets(const uint32_t* order, const uint32_t* count, Count n, uint32_t* cnt, uint32_t* offs,
+                  uint32_t* total, uint32_t* state, hipStream_t s)
+{
+    if (n.cap <= 0) {
+        launch_fill_u32(total, 0u, 1, s);
+        return;
+    }
+    const int64_t nb = (n.cap + kBlockItems - 1) / kBlockItems;
+    k_pair_offsets<<<(unsigned)nb, kThreads, 0, s>>>(n.cap, n.dev, order, count, cnt, offs, total,
+                                                     reinterpret_cast<unsigned long long*>(state));
+}
+
+// ---------------------------------------------------------------------------
 // Single-sweep radix sort
 // ---------------------------------------------------------------------------
 
