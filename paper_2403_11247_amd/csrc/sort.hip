@@ -333,7 +333,11 @@ __device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v)
 
 // Digit counts of every pass over all n items (per-wave LDS histograms).  With
 // drop, items whose key is kDropKey are left out and the number of the others
-// is added to *kept.
+// is added to *kept.  Blocks count 1024-item chunks (4 per thread): the kernel
+// is latency bound, and more, shorter blocks finish sooner than 4096-item ones
+// (room depth sort 76 -> 71 us).
+constexpr int kHistItems = 4;
+constexpr int kHistBlockItems = kThreads * kHistItems;
 __global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restrict__ keys, int64_t cap,
                                                         const uint32_t* __restrict__ ndev, int passes,
                                                         uint32_t* __restrict__ ghist, int drop,
@@ -356,17 +360,17 @@ __global__ void __launch_bounds__(kThreads) k_sort_hist(const uint32_t* __restri
         for (int p = 0; p < passes; ++p)
             for (int64_t i = gt; i < words; i += gs) state[(int64_t)p * state_stride + i] = 0u;
     }
-    // each thread counts kItems keys per 4096-item chunk, all loaded before any
-    // is counted so that their latencies overlap; chunks are strided by the grid
-    for (int64_t i0 = (int64_t)blockIdx.x * kBlockItems; i0 < n; i0 += (int64_t)gridDim.x * kBlockItems) {
-    uint32_t key[kItems];
+    // each thread counts kHistItems keys per chunk, all loaded before any is
+    // counted so that their latencies overlap; chunks are strided by the grid
+    for (int64_t i0 = (int64_t)blockIdx.x * kHistBlockItems; i0 < n; i0 += (int64_t)gridDim.x * kHistBlockItems) {
+    uint32_t key[kHistItems];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kHistItems; ++r) {
         const int64_t i = i0 + (int64_t)r * kThreads + threadIdx.x;
         key[r] = i < n ? keys[i] : kDropKey;
     }
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kHistItems; ++r) {
         const int64_t i = i0 + (int64_t)r * kThreads + threadIdx.x;
         const uint32_t k = key[r];
         const bool valid = i < n && !(drop && k == kDropKey);
@@ -537,7 +541,7 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, 
     uint32_t* kept_dev = counters + kMaxPasses;
     uint32_t* state = t.state;  // the look-back words: zeroed by k_sort_hist
     const int drop = kept != nullptr;
-    const int hb = std::min(nb, 1024);
+    const int hb = (int)std::min<int64_t>(std::max<int64_t>(nb, (n.cap + kHistBlockItems - 1) / kHistBlockItems), 2048);
     const int pb = std::min(nb, 2048);
     const uint32_t* first = keys_src ? keys_src : keys;
     k_sort_hist<<<hb, kThreads, 0, s>>>(first, n.cap, n.dev, passes, ghist, drop, kept_dev, state,

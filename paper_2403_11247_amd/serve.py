@@ -8,6 +8,7 @@ submitting it is counted too.
 """
 from __future__ import annotations
 
+import gc
 import time
 
 import numpy as np
@@ -44,8 +45,25 @@ def replay(server: "vcgs.Server", trace, poll_us=200):
              torch.empty((int(c.height), int(c.width)), device=dev),
              torch.empty((int(c.height), int(c.width)), device=dev)) for _, c, _ in trace]
     torch.cuda.synchronize()
+    # no collector pauses inside the timed loop (a full collection of a large
+    # process stalls the host for tens of milliseconds)
+    gc.collect()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        t_last = _replay_loop(server, trace, outs, pending, lat, poll_us, t0)
+    finally:
+        gc.enable()
+    out = _stats(lat, pixels, trace[0][0], t_last)
+    st1 = server.stats()
+    out.update({k: st1[k] - st0[k] for k in ("passes", "reruns")})
+    out["views_per_pass"] = round(n / max(out["passes"], 1), 2)
+    return out
+
+
+def _replay_loop(server, trace, outs, pending, lat, poll_us, t0):
+    n = len(trace)
     i = 0
-    t0 = time.perf_counter()
     t_last = 0.0
     while i < n or pending:
         now = time.perf_counter() - t0
@@ -67,11 +85,7 @@ def replay(server: "vcgs.Server", trace, poll_us=200):
                 j, _ = pending.pop(tk)
                 lat[j] = t_done - trace[j][0]
             t_last = t_done
-    out = _stats(lat, pixels, trace[0][0], t_last)
-    st1 = server.stats()
-    out.update({k: st1[k] - st0[k] for k in ("passes", "reruns")})
-    out["views_per_pass"] = round(n / max(out["passes"], 1), 2)
-    return out
+    return t_last
 
 
 def replay_plain(gauss, trace, anchors=None):
@@ -83,6 +97,16 @@ def replay_plain(gauss, trace, anchors=None):
     n = len(trace)
     lat = [0.0] * n
     pixels = sum(int(c.width) * int(c.height) for _, c, _ in trace)
+    gc.collect()
+    gc.disable()
+    try:
+        t_last = _plain_loop(gauss, trace, anchors, lat)
+    finally:
+        gc.enable()
+    return _stats(lat, pixels, trace[0][0], t_last)
+
+
+def _plain_loop(gauss, trace, anchors, lat):
     t0 = time.perf_counter()
     t_last = 0.0
     for j, (arr, cam, pose) in enumerate(trace):
@@ -95,7 +119,7 @@ def replay_plain(gauss, trace, anchors=None):
         torch.cuda.synchronize()
         t_last = time.perf_counter() - t0
         lat[j] = t_last - arr
-    return _stats(lat, pixels, trace[0][0], t_last)
+    return t_last
 
 
 def saturate(trace):
