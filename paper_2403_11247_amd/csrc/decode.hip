@@ -16,11 +16,12 @@
 //
 // Backward recomputes the forward MLP, forms dL/dy in LDS, and runs the three
 // transposed products (dh = W2^T dy, df = W1^T dpre, and the weight gradients
-// dW2 = dy h^T, dW1 = dpre f^T summed over anchors) on MFMA as well.  Weight
-// gradients are summed per wave in registers, per block in a fixed wave order,
-// and across blocks in a fixed order (deterministic).  The backward reads the
-// weights from a block-shared LDS copy instead of registers, which leaves room
-// for two waves per SIMD.
+// dW2 = dy h^T, dW1 = dpre f^T summed over anchors) on MFMA as well.  A block
+// of four waves takes one 16-anchor group at a time and splits its steps over
+// the waves (output tiles, feature tiles), so a group's chain of dependent
+// steps is about a quarter as long as one wave's; every weight-gradient value
+// has one owning lane, and the per-block partial rows are summed across blocks
+// in a fixed order (deterministic).
 #include "internal.h"
 
 namespace vcgs {
@@ -47,6 +48,16 @@ __device__ __forceinline__ void wsync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// Block barrier that orders LDS only: the waves' global stores (per-anchor
+// outputs) stay in flight across it, since no wave reads another's global
+// writes.  (__syncthreads would wait for every outstanding store first.)
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Codebook row of Gaussian g at stage s; indices outside [0, size) are clamped.
 __device__ __forceinline__ int code_index(const DecodeArgs& a, int s, int64_t n, int64_t g)
 {
@@ -60,7 +71,8 @@ struct Decoded {
     bool keep;
 };
 
-__device__ __forceinline__ Decoded decode_one(const DecodeArgs& a, const float* y, int64_t g)
+// mask_logit: the Gaussian's mask logit (read only when a.mask_logit is set).
+__device__ __forceinline__ Decoded decode_one(const DecodeArgs& a, const float* y, int64_t g, float mask_logit)
 {
     Decoded d;
     d.o_raw = sigm(y[0]);
@@ -83,7 +95,7 @@ __device__ __forceinline__ Decoded decode_one(const DecodeArgs& a, const float* 
     for (int i = 0; i < 3; ++i) d.s_raw[i] = __expf(d.v[i]);
 #pragma unroll
     for (int i = 0; i < 4; ++i) d.q[i] = d.v[3 + i];
-    d.keep = a.mask_logit ? (a.mask_logit[g] > a.mask_thr) : true;
+    d.keep = a.mask_logit ? (mask_logit > a.mask_thr) : true;
     return d;
 }
 
@@ -221,7 +233,7 @@ __global__ void __launch_bounds__(256) k_decode_fwd(DecodeArgs a, float* __restr
             const int64_t anc = a0 + al;
             if (anc >= a.na) continue;
             const int64_t g = anc * a.k + off;
-            const Decoded d = decode_one(a, &ys[wave][al][off * 11], g);
+            const Decoded d = decode_one(a, &ys[wave][al][off * 11], g, a.mask_logit ? a.mask_logit[g] : 0.0f);
             opac[g] = d.keep ? d.o_raw : 0.0f;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -264,9 +276,6 @@ void launch_decode_fwd(const DecodeArgs& a, const vcgs_gaussian_buffers& out, hi
 // Backward
 // ---------------------------------------------------------------------------
 constexpr int kBwdWaves = 4;
-// Grid cap: two blocks per CU where registers and LDS allow two waves per SIMD
-// (up to 8 output tiles), else one.
-constexpr int kBwdMaxBlocks = 512;
 
 // Partial row of one block: dW2 [O][32], db2 [O], dW1 [32][in_dim], db1 [32], dL/dcam [views][3].
 __host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim, int views)
@@ -274,126 +283,172 @@ __host__ __device__ int64_t decode_bwd_partial_floats(int k, int in_dim, int vie
     return (int64_t)k * 11 * kF + k * 11 + (int64_t)kF * in_dim + kF + 3 * views;
 }
 
-// Block reduction buffer, padded so that every lane owns a slot for each of
-// its accumulators (no bounds tests, hence no per-slot branches): dW2 [OT*16][32],
-// db2 [192], dW1 [32][48], db1 [64], dL/dcam [64].  The per-wave y buffers of
-// a block double as it.
-constexpr int kRedB2 = 192, kRedW1Cols = 48;
-constexpr int red_b2(int OT) { return OT * 16 * kF; }
-constexpr int red_w1(int OT) { return red_b2(OT) + kRedB2; }
-constexpr int red_b1(int OT) { return red_w1(OT) + kF * kRedW1Cols; }
-constexpr int red_cam(int OT) { return red_b1(OT) + 64; }
-constexpr int bwd_red_floats(int OT) { return red_cam(OT) + 64; }
-constexpr int bwd_smem_floats(int OT)
+// Output tiles (16 rows of the k * 11 MLP outputs) of wave w: t = w, w + 4, w + 8.
+constexpr int wave_tiles(int OT) { return (OT + kBwdWaves - 1) / kBwdWaves; }
+
+// LDS of one block of the backward, in floats: the weights, y / dL/dy of the
+// group [16][lds_o], the per-entry staging [256][6], h, dL/dpre and view inputs
+// [16][33], the four waves' partial dL/dh [4][8][64], the camera-centre sums.
+constexpr int bwd_lds_floats(int OT)
 {
-    return kBwdWaves * 16 * lds_o(OT) > bwd_red_floats(OT) ? kBwdWaves * 16 * lds_o(OT) : bwd_red_floats(OT);
+    return OT * 16 * kW2S + kF * kW1S + OT * 16 + kF + 16 * lds_o(OT) + 256 * 6 + 2 * 16 * (kF + 1) + 16 * 4 +
+           kBwdWaves * 8 * 64 + kDecodeMaxViews * 3;
+}
+// Blocks per CU that the LDS admits (160 KB per CU).
+constexpr int bwd_blocks_per_cu(int OT)
+{
+    return (160 * 1024) / (bwd_lds_floats(OT) * 4) < 1 ? 1 : (160 * 1024) / (bwd_lds_floats(OT) * 4);
 }
 
 int decode_bwd_blocks(int64_t na, int k)
 {
     const int64_t groups = (na + 15) / 16;
-    const int cap = out_tiles(k) <= 8 ? kBwdMaxBlocks : kBwdMaxBlocks / 2;
-    return (int)std::max<int64_t>(1, std::min<int64_t>((groups + kBwdWaves - 1) / kBwdWaves, cap));
+    int per_cu = 1;
+    switch (out_tiles(k)) {
+        case 1: per_cu = bwd_blocks_per_cu(1); break;
+        case 2: per_cu = bwd_blocks_per_cu(2); break;
+        case 3: per_cu = bwd_blocks_per_cu(3); break;
+        case 4: per_cu = bwd_blocks_per_cu(4); break;
+        case 5: per_cu = bwd_blocks_per_cu(5); break;
+        case 6: per_cu = bwd_blocks_per_cu(6); break;
+        case 7: per_cu = bwd_blocks_per_cu(7); break;
+        case 8: per_cu = bwd_blocks_per_cu(8); break;
+        case 9: per_cu = bwd_blocks_per_cu(9); break;
+        case 10: per_cu = bwd_blocks_per_cu(10); break;
+        default: per_cu = bwd_blocks_per_cu(11); break;
+    }
+    return (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)256 * per_cu));
 }
 
+// One 16-anchor group at a time per block, its work spread over the four
+// waves with block barriers between the steps:
+//   1. every thread loads one (anchor, offset) entry's inputs and attribute
+//      gradients (16 k <= 256 entries) and stages the mean gradient and its
+//      offset product; wave 2 then sums them per anchor (anchor position and
+//      scaling gradients);
+//   2. every wave recomputes the first layer (16 MFMA steps; it needs h and
+//      the pre-activations in its own registers) and the second layer for its
+//      output tiles t = w, w + 4, ... into the group's y buffer;
+//   3. every thread turns its entry's y into dL/dy in place (sigmoid and exp
+//      adjoints, mask and codebook gradients);
+//   4. each wave accumulates dW2 = dy h^T and db2 for its tiles and the part
+//      of dh = W2^T dy that its tiles contribute;
+//   5. every wave adds the four partial dh in wave order and applies the ReLU
+//      mask; waves 0 and 1 form df = W1^T dpre for features 0-15 and 16-31 (the
+//      anchor-feature gradients), wave 2 the view rows (camera-centre
+//      gradient);
+//   6. waves 0-2 accumulate dW1 = dpre f^T for their feature tile, wave 3 db1.
+// Every weight-gradient element has one owning lane in the block, so the
+// block's partial row is written without a block reduction, and the partial
+// rows are summed over blocks in a fixed order by k_decode_bwd_reduce
+// (deterministic).  With several camera centres the block takes its group
+// through every view in turn: per-anchor outputs are stored by the first view
+// and added by the later ones, always by the same lane.
 template <int OT>
-__global__ void __launch_bounds__(64 * kBwdWaves, 2) k_decode_bwd(DecodeArgs a, vcgs_gaussian_buffers dG,
-                                                               vcgs_anchor_grads out, float* __restrict__ partial,
-                                                               float* __restrict__ dvbuf)
+__global__ void __launch_bounds__(64 * kBwdWaves, 3) k_decode_bwd(DecodeArgs a, vcgs_gaussian_buffers dG,
+                                                              vcgs_anchor_grads out, float* __restrict__ partial,
+                                                              float* __restrict__ dvbuf)
 {
-    // Each wave's [16 anchors][k * 11] outputs y are overwritten in place by
-    // dL/dy (every slot is read before it is written, by the same lane); the
-    // buffer also holds the block reduction at the end.
     constexpr int LO = lds_o(OT);
-    __shared__ float smem[bwd_smem_floats(OT)];
-    float (*ys)[16][LO] = reinterpret_cast<float (*)[16][LO]>(smem);
-    float (*dys)[16][LO] = ys;
-    __shared__ float hs[kBwdWaves][16][kF + 1];
-    __shared__ float ps[kBwdWaves][16][kF + 1];
-    __shared__ float vs[kBwdWaves][16][4];  // view inputs of the wave's 16 anchors
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int O = a.k * 11;
-    const int64_t n = a.na * a.k;
-    const bool view = a.in_dim > kF;  // uniform
+    constexpr int WT = wave_tiles(OT);
     __shared__ __align__(16) float w2s[OT * 16 * kW2S];
     __shared__ float w1s[kF * kW1S];
     __shared__ float b2s[OT * 16];
     __shared__ float b1s[kF];
+    __shared__ float ys[16][LO];          // y, then dL/dy in place
+    __shared__ float stg[256 * 6];        // per entry: dL/dmean, dL/dmean * offset
+    __shared__ float hs[16][kF + 1];      // h [anchor][hidden]
+    __shared__ float ps[16][kF + 1];      // dL/dpre [anchor][hidden]
+    __shared__ float vs[16][4];           // view inputs [anchor][distance, direction]
+    __shared__ float dhp[kBwdWaves][8][64];  // partial dL/dh per wave, accumulator layout
+    __shared__ float camw[kDecodeMaxViews * 3];  // dL/d camera centre per view (wave 2)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int O = a.k * 11;
+    const int64_t n = a.na * a.k;
+    const bool view = a.in_dim > kF;  // uniform
     fill_weights<OT>(a, w2s, w1s, b2s, b1s);
-    v4f accW2[OT][2], accW1[2][3];
+    if (threadIdx.x < kDecodeMaxViews * 3) camw[threadIdx.x] = 0.0f;
+    v4f accW2[WT][2], accW1[2];
 #pragma unroll
-    for (int t = 0; t < OT; ++t) accW2[t][0] = accW2[t][1] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int ft = 0; ft < 3; ++ft) accW1[nt][ft] = v4f{0.f, 0.f, 0.f, 0.f};
-    float accB2[(kMaxO + 63) / 64] = {0.f, 0.f, 0.f};
-    float accB1 = 0.0f;
-    __shared__ float camw[kBwdWaves][kDecodeMaxViews * 3];  // dL/d camera centre per wave and view
-    if (lane < kDecodeMaxViews * 3) camw[wave][lane] = 0.0f;
+    for (int j = 0; j < WT; ++j) accW2[j][0] = accW2[j][1] = v4f{0.f, 0.f, 0.f, 0.f};
+    accW1[0] = accW1[1] = v4f{0.f, 0.f, 0.f, 0.f};
+    float accB2 = 0.0f, accB1 = 0.0f;
+    const int e = threadIdx.x;  // this thread's (anchor, offset) entry of the group
+    const int eal = e / a.k, eoff = e - eal * a.k;
+    const int ft = wave;        // df / dW1 feature tile of waves 0-2
 
-    // each wave takes a 16-anchor group through every view in turn, so the
-    // per-anchor outputs add up over the views without races
     const int64_t groups = (a.na + 15) / 16;
-    for (int64_t grp = (int64_t)blockIdx.x * kBwdWaves + wave; grp < groups; grp += (int64_t)gridDim.x * kBwdWaves) {
+    for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        const int64_t a0 = grp * 16;
+        const int64_t an = a0 + (lane & 15);  // the anchor of this lane's MFMA column
+        const bool avalid = an < a.na;
+        const int64_t eanc = a0 + eal;
+        const bool eok = e < 16 * a.k && eanc < a.na;
+        const int64_t g = eanc * a.k + eoff;
+        // anchor features: the first layer's B operand (8 per lane) and, for
+        // waves 0-1, the dW1 B operand of their feature tile (4 per lane)
+        float fb[8], fw[4];
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) fb[ks] = avalid ? a.feat[an * kF + ks * 4 + (lane >> 4)] : 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int64_t anc = a0 + ks * 4 + (lane >> 4);
+            fw[ks] = (ft < 2 && anc < a.na) ? a.feat[anc * kF + ft * 16 + (lane & 15)] : 0.0f;
+        }
+        const float sc0 = (eok && out.offset) ? a.scaling[eanc] : 0.0f;
+        const float sc1 = (eok && out.offset) ? a.scaling[a.na + eanc] : 0.0f;
+        const float sc2 = (eok && out.offset) ? a.scaling[2 * a.na + eanc] : 0.0f;
+        const float of0 = eok ? a.offset[g * 3] : 0.0f;
+        const float of1 = eok ? a.offset[g * 3 + 1] : 0.0f;
+        const float of2 = eok ? a.offset[g * 3 + 2] : 0.0f;
+        const float mlog = (eok && a.mask_logit) ? a.mask_logit[g] : 0.0f;
         for (int v = 0; v < a.views; ++v) {
             const bool first = v == 0;
             const vcgs_gaussian_buffers dGv = view_block(dG, v, n);
-            const int64_t a0 = grp * 16;
-            const int64_t an = a0 + (lane & 15);
-            const bool avalid = an < a.na;
-            {
-                // per-anchor sums over offsets (anchor position, scaling) and the offsets'
-                // gradients: the (anchor, offset) pairs spread over the 64 lanes, their
-                // contributions staged in the wave's y buffer (free until layer 2), then
-                // added per anchor in offset order by 16 lanes
-                float* stg = &ys[wave][0][0];  // 16 * LO >= 16 * k * 6 floats
-                for (int e = lane; e < 16 * a.k; e += 64) {
-                    const int al = e / a.k, off = e - al * a.k;
-                    const int64_t anc = a0 + al;
-                    float dm[3] = {0.0f, 0.0f, 0.0f}, dl[3] = {0.0f, 0.0f, 0.0f};
-                    if (anc < a.na) {
-                        const int64_t g = anc * a.k + off;
+            lds_barrier();  // the previous group's or view's LDS is no longer read
+            // ---- 1. this entry's gradients; per-anchor sums
+            float dm[3], pg[11];
+            dm[0] = (eok && dGv.mean) ? dGv.mean[g] : 0.0f;
+            dm[1] = (eok && dGv.mean) ? dGv.mean[n + g] : 0.0f;
+            dm[2] = (eok && dGv.mean) ? dGv.mean[2 * n + g] : 0.0f;
 #pragma unroll
-                        for (int i = 0; i < 3; ++i) {
-                            dm[i] = dGv.mean ? dGv.mean[i * n + g] : 0.0f;
-                            dl[i] = dm[i] * a.offset[g * 3 + i];
-                        }
-                        if (out.offset) {
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) put(out.offset + g * 3 + i, first, dm[i] * a.scaling[i * a.na + anc]);
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        stg[e * 6 + i] = dm[i];
-                        stg[e * 6 + 3 + i] = dl[i];
-                    }
-                }
-                wsync();
-                if (lane < 16 && a0 + lane < a.na) {
-                    const int64_t anc = a0 + lane;
-                    float dx[3] = {0.0f, 0.0f, 0.0f}, dls[3] = {0.0f, 0.0f, 0.0f};
-                    for (int off = 0; off < a.k; ++off) {
-                        const float* q = stg + (lane * a.k + off) * 6;
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) {
-                            dx[i] += q[i];
-                            dls[i] += q[3 + i];
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        if (out.scaling) put(out.scaling + i * a.na + anc, first, dls[i]);
-                        if (out.xa) put(out.xa + i * a.na + anc, first, dx[i]);
-                    }
-                }
-                wsync();
+            for (int i = 0; i < 3; ++i) {
+                pg[i] = (eok && dGv.scale) ? dGv.scale[i * n + g] : 0.0f;
+                pg[3 + i] = (eok && dGv.color) ? dGv.color[i * n + g] : 0.0f;
             }
-            v4f d1[2];
-            float vin;
-            layer1_lds(w1s, a, a.cam[v], an, avalid, lane, d1, vin);
-            if (view) vs[wave][lane & 15][lane >> 4] = vin;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pg[6 + i] = (eok && dGv.quat) ? dGv.quat[i * n + g] : 0.0f;
+            pg[10] = (eok && dGv.opacity) ? dGv.opacity[g] : 0.0f;
+            if (e < 16 * a.k) {
+                stg[e * 6 + 0] = dm[0];
+                stg[e * 6 + 1] = dm[1];
+                stg[e * 6 + 2] = dm[2];
+                stg[e * 6 + 3] = dm[0] * of0;
+                stg[e * 6 + 4] = dm[1] * of1;
+                stg[e * 6 + 5] = dm[2] * of2;
+            }
+            if (eok && out.offset) {
+                put(out.offset + g * 3, first, dm[0] * sc0);
+                put(out.offset + g * 3 + 1, first, dm[1] * sc1);
+                put(out.offset + g * 3 + 2, first, dm[2] * sc2);
+            }
+            // ---- 2. first layer (every wave), second layer for this wave's tiles
+            v4f d1[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+            {
+                const float* r0 = w1s + (lane & 15) * kW1S + (lane >> 4);
+                const float* r1 = r0 + 16 * kW1S;
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) {
+                    d1[0] = mfma4(r0[ks * 4], fb[ks], d1[0]);
+                    d1[1] = mfma4(r1[ks * 4], fb[ks], d1[1]);
+                }
+                if (view) {
+                    const float vin = avalid ? view_input(a, a.cam[v], an, lane >> 4) : 0.0f;
+                    d1[0] = mfma4(r0[32], vin, d1[0]);
+                    d1[1] = mfma4(r1[32], vin, d1[1]);
+                    if (wave == 2) vs[lane & 15][lane >> 4] = vin;
+                }
+            }
             float pre[2][4], h[2][4];
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt)
@@ -402,252 +457,237 @@ __global__ void __launch_bounds__(64 * kBwdWaves, 2) k_decode_bwd(DecodeArgs a, 
                     pre[mt][i] = d1[mt][i] + b1s[mt * 16 + 4 * (lane >> 4) + i];
                     h[mt][i] = avalid ? fmaxf(pre[mt][i], 0.0f) : 0.0f;
                 }
-            wsync();
+            if (wave == 0) {
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
+                for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) hs[wave][lane & 15][mt * 16 + 4 * (lane >> 4) + i] = h[mt][i];
-            layer2_lds<OT, LO>(w2s, b2s, h, O, lane, ys[wave]);
-            wsync();
-            // dL/dy per (anchor, offset); codebook and mask gradients
-            for (int e = lane; e < 16 * a.k; e += 64) {
-                const int al = e / a.k, off = e - al * a.k;
-                const int64_t anc = a0 + al;
-                float* dy = &dys[wave][al][off * 11];
-                if (anc >= a.na) {
+                    for (int i = 0; i < 4; ++i) hs[lane & 15][mt * 16 + 4 * (lane >> 4) + i] = h[mt][i];
+            }
 #pragma unroll
-                    for (int i = 0; i < 11; ++i) dy[i] = 0.0f;
-                    continue;
-                }
-                const int64_t g = anc * a.k + off;
-                const Decoded d = decode_one(a, &ys[wave][al][off * 11], g);
-                float ds[3], dq[4], dc[3], dop;
+            for (int j = 0; j < WT; ++j) {
+                const int t = wave + kBwdWaves * j;
+                if (t < OT) {
+                    v4f d2 = {0.f, 0.f, 0.f, 0.f};
+                    const float* wr = w2s + (t * 16 + (lane & 15)) * kW2S + 4 * (lane >> 4);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    ds[i] = dGv.scale ? dGv.scale[i * n + g] : 0.0f;
-                    dc[i] = dGv.color ? dGv.color[i * n + g] : 0.0f;
-                }
+                    for (int st = 0; st < 8; ++st) d2 = mfma4(wr[(st >> 2) * 16 + (st & 3)], h[st >> 2][st & 3], d2);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) dq[i] = dGv.quat ? dGv.quat[i * n + g] : 0.0f;
-                dop = dGv.opacity ? dGv.opacity[g] : 0.0f;
-                if (a.mask_logit) {
-                    const float m = a.mask_logit[g];
-                    float gm = 0.0f;
-                    if (d.keep) {
-                        const float sg = sigm(m);
-                        gm = sg * (1.0f - sg) * (ds[0] * d.s_raw[0] + ds[1] * d.s_raw[1] + ds[2] * d.s_raw[2] + dop * d.o_raw);
-                    } else {
-                        ds[0] = ds[1] = ds[2] = 0.0f;
-                        dop = 0.0f;
+                    for (int i = 0; i < 4; ++i) {
+                        const int m = t * 16 + 4 * (lane >> 4) + i;
+                        if (m < O) ys[lane & 15][m] = d2[i] + b2s[m];
                     }
-                    if (out.mask_logit) put(out.mask_logit + g, first, gm);
-                }
-                dy[0] = dop * d.o_raw * (1.0f - d.o_raw);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) dy[1 + i] = dc[i] * d.c[i] * (1.0f - d.c[i]);
-                float dv[7];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) dv[i] = ds[i] * d.s_raw[i];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) dv[3 + i] = dq[i];
-                if (a.books) {
-#pragma unroll
-                    for (int i = 0; i < 7; ++i) dy[4 + i] = 0.0f;
-                    if (out.books && dvbuf) {  // per-Gaussian rows, summed per code by k_books_partial
-#pragma unroll
-                        for (int i = 0; i < 7; ++i) put(dvbuf + g * 8 + i, first, dv[i]);
-                    } else if (out.books) {
-                        for (int s = 0; s < a.stages; ++s) {
-                            float* row = out.books + ((int64_t)s * a.cb_size + code_index(a, s, n, g)) * 7;
-#pragma unroll
-                            for (int i = 0; i < 7; ++i) atomicAdd(row + i, dv[i]);
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 7; ++i) dy[4 + i] = dv[i];
                 }
             }
-            wsync();
-            // db2 and dW2 += dy h^T  (K = the 16 anchors)
-#pragma unroll
-            for (int j = 0; j < (kMaxO + 63) / 64; ++j) {
-                const int m = lane + 64 * j;
-                if (m < O) {
-                    float sacc = 0.0f;
-#pragma unroll
-                    for (int al = 0; al < 16; ++al) sacc += dys[wave][al][m];
-                    accB2[j] += sacc;
-                }
-            }
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int al = ks * 4 + (lane >> 4);
-                const float hb0 = hs[wave][al][lane & 15];
-                const float hb1 = hs[wave][al][16 + (lane & 15)];
-#pragma unroll
-                for (int t = 0; t < OT; ++t) {
-                    const int m = t * 16 + (lane & 15);
-                    const float av = m < O ? dys[wave][al][m] : 0.0f;
-                    accW2[t][0] = mfma4(av, hb0, accW2[t][0]);
-                    accW2[t][1] = mfma4(av, hb1, accW2[t][1]);
-                }
-            }
-            // dh = W2^T dy  (K = m)
-            v4f dh[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-            for (int ks = 0; ks < OT * 4; ++ks) {
-                const int m = ks * 4 + (lane >> 4);
-                const float bv = m < O ? dys[wave][lane & 15][m] : 0.0f;
-                const float* wr = w2s + (ks * 4 + (lane >> 4)) * kW2S + (lane & 15);
-                dh[0] = mfma4(wr[0], bv, dh[0]);
-                dh[1] = mfma4(wr[16], bv, dh[1]);
-            }
-            float dpre[2][4];
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) dpre[mt][i] = (avalid && pre[mt][i] > 0.0f) ? dh[mt][i] : 0.0f;
-            // df = W1^T dpre (tile 2: the view inputs)
-            v4f df[3] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-            for (int st = 0; st < 8; ++st) {
-                const float* wr = w1s + ((st >> 2) * 16 + 4 * (lane >> 4) + (st & 3)) * kW1S + (lane & 15);
-                df[0] = mfma4(wr[0], dpre[st >> 2][st & 3], df[0]);
-                df[1] = mfma4(wr[16], dpre[st >> 2][st & 3], df[1]);
-                if (view) df[2] = mfma4(wr[32], dpre[st >> 2][st & 3], df[2]);
-            }
-            if (view) {  // uniform
-                float dc[3] = {0.0f, 0.0f, 0.0f};  // this anchor's share of dL/d camera centre
-                if (lane < 16 && avalid) {
-                    // lanes 0-15 hold rows 32..35 (dL/d distance, dL/d direction) of anchor `lane`:
-                    // dL/dv = dL/ddelta d + (dL/dd - (dL/dd . d) d) / delta,  v = x_a - x_c
-                    const float dist = vs[wave][lane][0];
-                    const float d0 = vs[wave][lane][1], d1v = vs[wave][lane][2], d2 = vs[wave][lane][3];
-                    const float gd = df[2][1] * d0 + df[2][2] * d1v + df[2][3] * d2;
-                    const float dv[3] = {df[2][0] * d0 + (df[2][1] - gd * d0) / dist,
-                                         df[2][0] * d1v + (df[2][2] - gd * d1v) / dist,
-                                         df[2][0] * d2 + (df[2][3] - gd * d2) / dist};
+            lds_barrier();
+            if (wave == 2 && lane < 16 && a0 + lane < a.na) {
+                // anchor position and scaling gradients: sums over the offsets in order
+                const int64_t anc = a0 + lane;
+                float dx[3] = {0.0f, 0.0f, 0.0f}, dls[3] = {0.0f, 0.0f, 0.0f};
+                for (int off = 0; off < a.k; ++off) {
+                    const float* q = stg + (lane * a.k + off) * 6;
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        if (out.xa) out.xa[i * a.na + an] += dv[i];
-                        dc[i] = -dv[i];
+                        dx[i] += q[i];
+                        dls[i] += q[3 + i];
                     }
                 }
-                // the 16 anchors' sum (lanes 0-15), added to this wave's view-v total
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int o = 8; o > 0; o >>= 1) dc[i] += __shfl_xor(dc[i], o, 16);
-                if (lane == 0) {
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) camw[wave][v * 3 + i] += dc[i];
+                for (int i = 0; i < 3; ++i) {
+                    if (out.scaling) put(out.scaling + i * a.na + anc, first, dls[i]);
+                    if (out.xa) put(out.xa + i * a.na + anc, first, dx[i]);
                 }
             }
-            if (out.feat && avalid) {
+            // ---- 3. dL/dy of this entry, in place
+            if (e < 16 * a.k) {
+                float* dy = &ys[eal][eoff * 11];
+                if (!eok) {
 #pragma unroll
-                for (int ft = 0; ft < 2; ++ft)
+                    for (int i = 0; i < 11; ++i) dy[i] = 0.0f;
+                } else {
+                    const Decoded d = decode_one(a, dy, g, mlog);
+                    float ds[3] = {pg[0], pg[1], pg[2]};
+                    float dop = pg[10];
+                    if (a.mask_logit) {
+                        float gm = 0.0f;
+                        if (d.keep) {
+                            const float sg = sigm(mlog);
+                            gm = sg * (1.0f - sg) * (ds[0] * d.s_raw[0] + ds[1] * d.s_raw[1] + ds[2] * d.s_raw[2] + dop * d.o_raw);
+                        } else {
+                            ds[0] = ds[1] = ds[2] = 0.0f;
+                            dop = 0.0f;
+                        }
+                        if (out.mask_logit) put(out.mask_logit + g, first, gm);
+                    }
+                    dy[0] = dop * d.o_raw * (1.0f - d.o_raw);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) put(out.feat + an * kF + ft * 16 + 4 * (lane >> 4) + i, first, df[ft][i]);
+                    for (int i = 0; i < 3; ++i) dy[1 + i] = pg[3 + i] * d.c[i] * (1.0f - d.c[i]);
+                    float dv[7];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) dv[i] = ds[i] * d.s_raw[i];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) dv[3 + i] = pg[6 + i];
+                    if (a.books) {
+#pragma unroll
+                        for (int i = 0; i < 7; ++i) dy[4 + i] = 0.0f;
+                        if (out.books && dvbuf) {  // per-Gaussian rows, summed per code by k_books_partial
+#pragma unroll
+                            for (int i = 0; i < 7; ++i) put(dvbuf + g * 8 + i, first, dv[i]);
+                        } else if (out.books) {
+                            for (int s = 0; s < a.stages; ++s) {
+                                float* row = out.books + ((int64_t)s * a.cb_size + code_index(a, s, n, g)) * 7;
+#pragma unroll
+                                for (int i = 0; i < 7; ++i) atomicAdd(row + i, dv[i]);
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 7; ++i) dy[4 + i] = dv[i];
+                    }
+                }
             }
-            // dW1 += dpre f^T, db1 += sum dpre (K = the 16 anchors)
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) ps[wave][lane & 15][mt * 16 + 4 * (lane >> 4) + i] = dpre[mt][i];
-            wsync();
-            if (lane < kF) {
+            // entries of anchors beyond the group's 16 * k slots are never read
+            lds_barrier();
+            // ---- 4. db2, dW2 = dy h^T and this wave's share of dh = W2^T dy
+            if (e < O) {
                 float sacc = 0.0f;
 #pragma unroll
-                for (int al = 0; al < 16; ++al) sacc += ps[wave][al][lane];
-                accB1 += sacc;
+                for (int al = 0; al < 16; ++al) sacc += ys[al][e];
+                accB2 += sacc;
             }
+            v4f dh[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int al = ks * 4 + (lane >> 4);
-                const int64_t anc = a0 + al;
-                const float f0 = anc < a.na ? a.feat[anc * kF + (lane & 15)] : 0.0f;
-                const float f1 = anc < a.na ? a.feat[anc * kF + 16 + (lane & 15)] : 0.0f;
-                const float f2 = (view && (lane & 15) < 4) ? vs[wave][al][lane & 15] : 0.0f;
+            for (int j = 0; j < WT; ++j) {
+                const int t = wave + kBwdWaves * j;
+                if (t < OT) {
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    const float av = ps[wave][al][nt * 16 + (lane & 15)];
-                    accW1[nt][0] = mfma4(av, f0, accW1[nt][0]);
-                    accW1[nt][1] = mfma4(av, f1, accW1[nt][1]);
-                    if (view) accW1[nt][2] = mfma4(av, f2, accW1[nt][2]);
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int al = ks * 4 + (lane >> 4);
+                        const int m = t * 16 + (lane & 15);
+                        const float av = m < O ? ys[al][m] : 0.0f;
+                        accW2[j][0] = mfma4(av, hs[al][lane & 15], accW2[j][0]);
+                        accW2[j][1] = mfma4(av, hs[al][16 + (lane & 15)], accW2[j][1]);
+                    }
+#pragma unroll
+                    for (int kq = 0; kq < 4; ++kq) {
+                        const int ks = t * 4 + kq;
+                        const int m = ks * 4 + (lane >> 4);
+                        const float bv = m < O ? ys[lane & 15][m] : 0.0f;
+                        const float* wr = w2s + m * kW2S + (lane & 15);
+                        dh[0] = mfma4(wr[0], bv, dh[0]);
+                        dh[1] = mfma4(wr[16], bv, dh[1]);
+                    }
                 }
             }
-            wsync();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                dhp[wave][i][lane] = dh[0][i];
+                dhp[wave][4 + i][lane] = dh[1][i];
+            }
+            lds_barrier();
+            // ---- 5. dpre (the four partial dh in wave order), df
+            float dpre[2][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float s0 = ((dhp[0][i][lane] + dhp[1][i][lane]) + dhp[2][i][lane]) + dhp[3][i][lane];
+                const float s1 = ((dhp[0][4 + i][lane] + dhp[1][4 + i][lane]) + dhp[2][4 + i][lane]) + dhp[3][4 + i][lane];
+                dpre[0][i] = (avalid && pre[0][i] > 0.0f) ? s0 : 0.0f;
+                dpre[1][i] = (avalid && pre[1][i] > 0.0f) ? s1 : 0.0f;
+            }
+            if (wave == 3) {
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) ps[lane & 15][mt * 16 + 4 * (lane >> 4) + i] = dpre[mt][i];
+            }
+            if (ft < 2 || (ft == 2 && view)) {
+                v4f df = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int st = 0; st < 8; ++st) {
+                    const float* wr = w1s + ((st >> 2) * 16 + 4 * (lane >> 4) + (st & 3)) * kW1S + ft * 16 + (lane & 15);
+                    df = mfma4(wr[0], dpre[st >> 2][st & 3], df);
+                }
+                if (ft < 2) {
+                    if (out.feat && avalid) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) put(out.feat + an * kF + ft * 16 + 4 * (lane >> 4) + i, first, df[i]);
+                    }
+                } else {
+                    float dc[3] = {0.0f, 0.0f, 0.0f};  // this anchor's share of dL/d camera centre
+                    if (lane < 16 && avalid) {
+                        // lanes 0-15 hold rows 32..35 (dL/d distance, dL/d direction) of anchor `lane`:
+                        // dL/dv = dL/ddelta d + (dL/dd - (dL/dd . d) d) / delta,  v = x_a - x_c
+                        const float dist = vs[lane][0];
+                        const float d0 = vs[lane][1], d1v = vs[lane][2], d2 = vs[lane][3];
+                        const float gd = df[1] * d0 + df[2] * d1v + df[3] * d2;
+                        const float dv[3] = {df[0] * d0 + (df[1] - gd * d0) / dist,
+                                             df[0] * d1v + (df[2] - gd * d1v) / dist,
+                                             df[0] * d2 + (df[3] - gd * d2) / dist};
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            if (out.xa) out.xa[i * a.na + an] += dv[i];
+                            dc[i] = -dv[i];
+                        }
+                    }
+                    // the 16 anchors' sum (lanes 0-15), added to view v's total
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int o = 8; o > 0; o >>= 1) dc[i] += __shfl_xor(dc[i], o, 16);
+                    if (lane == 0) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) camw[v * 3 + i] += dc[i];
+                    }
+                }
+            }
+            lds_barrier();
+            // ---- 6. dW1 += dpre f^T (waves 0-2, their feature tile), db1 (wave 3)
+            if (ft < 2 || (ft == 2 && view)) {
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int al = ks * 4 + (lane >> 4);
+                    const float f = ft < 2 ? fw[ks] : ((lane & 15) < 4 ? vs[al][lane & 15] : 0.0f);
+                    accW1[0] = mfma4(ps[al][lane & 15], f, accW1[0]);
+                    accW1[1] = mfma4(ps[al][16 + (lane & 15)], f, accW1[1]);
+                }
+            } else if (wave == 3 && lane < kF) {
+                float sacc = 0.0f;
+#pragma unroll
+                for (int al = 0; al < 16; ++al) sacc += ps[al][lane];
+                accB1 += sacc;
+            }
         }
     }
-    // block reduction in wave order, then one partial row per block
-    __syncthreads();
-    float* red = smem;  // bwd_smem_floats(OT) >= bwd_red_floats(OT)
-    // Wave w adds the sum of waves 0..w-1 into its accumulators, then stores
-    // them: all its loads are issued before any store.
-    for (int w = 0; w < kBwdWaves; ++w) {
-        if (wave == w) {
-            if (w > 0) {
+    lds_barrier();
+    // partial row: dW2 [O][32] | db2 [O] | dW1 [32][in_dim] | db1 [32] | dcam [views][3]
+    const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim, a.views);
+    const int oB2 = O * kF, oW1 = oB2 + O, oB1 = oW1 + kF * a.in_dim, oCam = oB1 + kF;
+    float* row = partial + (int64_t)blockIdx.x * PF;
 #pragma unroll
-                for (int t = 0; t < OT; ++t)
-#pragma unroll
-                    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            accW2[t][nt][i] += red[(t * 16 + 4 * (lane >> 4) + i) * kF + nt * 16 + (lane & 15)];
-#pragma unroll
-                for (int j = 0; j < (kMaxO + 63) / 64; ++j) accB2[j] += red[red_b2(OT) + lane + 64 * j];
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                    for (int ft = 0; ft < 3; ++ft)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            accW1[nt][ft][i] +=
-                                red[red_w1(OT) + (nt * 16 + 4 * (lane >> 4) + i) * kRedW1Cols + ft * 16 + (lane & 15)];
-                accB1 += red[red_b1(OT) + lane];
-            }
-#pragma unroll
-            for (int t = 0; t < OT; ++t)
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        red[(t * 16 + 4 * (lane >> 4) + i) * kF + nt * 16 + (lane & 15)] = accW2[t][nt][i];
-#pragma unroll
-            for (int j = 0; j < (kMaxO + 63) / 64; ++j) red[red_b2(OT) + lane + 64 * j] = accB2[j];
+    for (int j = 0; j < WT; ++j) {
+        const int t = wave + kBwdWaves * j;
+        if (t < OT) {
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-                for (int ft = 0; ft < 3; ++ft)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        red[red_w1(OT) + (nt * 16 + 4 * (lane >> 4) + i) * kRedW1Cols + ft * 16 + (lane & 15)] =
-                            accW1[nt][ft][i];
-            red[red_b1(OT) + lane] = accB1;
+                for (int i = 0; i < 4; ++i) {
+                    const int m = t * 16 + 4 * (lane >> 4) + i;
+                    if (m < O) row[m * kF + nt * 16 + (lane & 15)] = accW2[j][nt][i];
+                }
         }
-        __syncthreads();
     }
-    if (threadIdx.x < 3 * a.views) {  // camera-centre sums in wave order
-        float c = camw[0][threadIdx.x];
-        for (int w = 1; w < kBwdWaves; ++w) c += camw[w][threadIdx.x];
-        red[red_cam(OT) + threadIdx.x] = c;
+    if (e < O) row[oB2 + e] = accB2;
+    if (ft < 2 || (ft == 2 && view)) {
+        const int col = ft * 16 + (lane & 15);
+        if (col < a.in_dim) {
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) row[oW1 + (nt * 16 + 4 * (lane >> 4) + i) * a.in_dim + col] = accW1[nt][i];
+        }
+    } else if (wave == 3 && lane < kF) {
+        row[oB1 + lane] = accB1;
     }
-    __syncthreads();
-    // compact partial row: dW2 [O][32] | db2 [O] | dW1 [32][in_dim] | db1 [32] | dcam [views][3]
-    const int64_t PF = decode_bwd_partial_floats(a.k, a.in_dim, a.views);
-    const int oB2 = O * kF, oW1 = oB2 + O, oB1 = oW1 + kF * a.in_dim, oCam = oB1 + kF;
-    for (int i = threadIdx.x; i < PF; i += blockDim.x) {
-        int src;
-        if (i < oB2) src = i;
-        else if (i < oW1) src = red_b2(OT) + (i - oB2);
-        else if (i < oB1) {
-            const int j = i - oW1, nn = j / a.in_dim;
-            src = red_w1(OT) + nn * kRedW1Cols + (j - nn * a.in_dim);
-        } else if (i < oCam) src = red_b1(OT) + (i - oB1);
-        else src = red_cam(OT) + (i - oCam);
-        partial[blockIdx.x * PF + i] = red[src];
-    }
+    if (threadIdx.x < 3 * a.views) row[oCam + threadIdx.x] = camw[threadIdx.x];
 }
 
 // Sum of the per-block partial rows: each block owns 64 consecutive outputs;
