@@ -27,25 +27,13 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
 
 __global__ void __launch_bounds__(256) k_zero_u32(ZeroSegs z, int64_t total)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t k = i;
-        int seg = 0;
-        while (seg < kZeroSegs - 1 && k >= z.n[seg]) {
-            k -= z.n[seg];
-            ++seg;
-        }
-        z.p[seg][k] = 0u;
-    }
+    zero_segs(z, total, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 void launch_zero_u32(const ZeroSegs& zin, hipStream_t s)
 {
     ZeroSegs z = zin;
-    int64_t total = 0;
-    for (int i = 0; i < kZeroSegs; ++i) {
-        if (!z.p[i] || z.n[i] < 0) z.n[i] = 0;
-        total += z.n[i];
-    }
+    const int64_t total = zero_segs_normalise(z);
     if (total <= 0) return;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
     k_zero_u32<<<(unsigned)blocks, 256, 0, s>>>(z, total);

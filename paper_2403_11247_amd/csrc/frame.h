@@ -42,8 +42,9 @@ void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* po
 // pair scan's look-back words, the tile ranges and (unless keep_overflow) the
 // overflow flag.
 void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow = false);
-// zero_pass, projection, depth order of all entries, pair offsets; the pair
-// count ends up in w.total on the device.  Returns the depth order.
+// zero_pass's clearing (done by the projection launch), projection, depth
+// order of all entries, pair offsets; the pair count ends up in w.total on the
+// device.  Returns the depth order.
 const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s,
                         bool keep_overflow = false);
 // Pairs (at most f.cap, overflow flagged in w.overflow), stable tile sort,

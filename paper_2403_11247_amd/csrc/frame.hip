@@ -45,9 +45,9 @@ void build_tables(int V, int64_t n, const vcgs_camera* cams, const vcgs_pose* po
     for (int i = 0; i < 3; ++i) f.vt.bg[i] = bg[i];
 }
 
-// Projection, depth order of all entries, pair offsets; the pair count ends
-// up in w.total on the device.  Returns the depth order.
-void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow)
+// What a pass needs at zero: both sorts' counters, the tile ranges, the pair
+// scan's look-back words and (unless keep_overflow) the overflow flag.
+static ZeroSegs pass_zero_segs(Frame& f, Work& w, bool keep_overflow)
 {
     ZeroSegs z{};
     z.p[0] = w.headE;
@@ -60,14 +60,22 @@ void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow)
     z.n[3] = 1;
     z.p[4] = w.scanE;
     z.n[4] = pair_scan_words(f.E);
-    launch_zero_u32(z, s);
+    return z;
 }
 
+void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow)
+{
+    launch_zero_u32(pass_zero_segs(f, w, keep_overflow), s);
+}
+
+// Projection, depth order of all entries, pair offsets; the pair count ends
+// up in w.total on the device.  Returns the depth order.
 const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s, bool keep_overflow)
 {
-    zero_pass(f, w, s, keep_overflow);
+    // the projection's threads also clear what zero_pass would (one launch fewer)
+    const ZeroSegs z = pass_zero_segs(f, w, keep_overflow);
     pf.begin(VCGS_STAGE_PREPROCESS, s);
-    launch_preprocess(f.pt, f.pt_dev, g, f.rec, f.depth_key, f.rect, f.count, f.g2, s);
+    launch_preprocess(f.pt, f.pt_dev, g, f.rec, f.depth_key, f.rect, f.count, f.g2, s, &z);
     pf.end(VCGS_STAGE_PREPROCESS, s);
     pf.begin(VCGS_STAGE_DEPTH_SORT, s);
     // culled entries carry the drop key and leave the depth order in its first pass

@@ -92,8 +92,11 @@ struct Count {
 // The kernels read the table from device memory (t_dev, a copy of t) so that a
 // captured graph can be replayed with new poses.
 // g2_zero (optional): kG2 floats per entry, zeroed for every visible entry.
+struct ZeroSegs;
+// zero: words the pass needs at zero (the projection's threads clear them too), or null.
 void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
-                       uint32_t* depth_key, uint2* rect, uint32_t* count, float* g2_zero, hipStream_t s);
+                       uint32_t* depth_key, uint2* rect, uint32_t* count, float* g2_zero, hipStream_t s,
+                       const ZeroSegs* zero = nullptr);
 int preprocess_bwd_blocks(int64_t n);
 // g2, count and rec have n_views * n entries; pose_partial holds n_views * blocks * 6 floats.
 void launch_preprocess_bwd(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, const uint32_t* count,
@@ -166,6 +169,30 @@ struct ZeroSegs {
     uint32_t* p[kZeroSegs];
     int64_t n[kZeroSegs];
 };
+// Drops null or empty segments and returns the total word count.
+inline int64_t zero_segs_normalise(ZeroSegs& z)
+{
+    int64_t total = 0;
+    for (int i = 0; i < kZeroSegs; ++i) {
+        if (!z.p[i] || z.n[i] < 0) z.n[i] = 0;
+        total += z.n[i];
+    }
+    return total;
+}
+// Zeroes words [0, total) of the segments, thread tid of nthreads taking every
+// nthreads-th word (a normalised z).
+__device__ __forceinline__ void zero_segs(const ZeroSegs& z, int64_t total, int64_t tid, int64_t nthreads)
+{
+    for (int64_t i = tid; i < total; i += nthreads) {
+        int64_t k = i;
+        int seg = 0;
+        while (seg < kZeroSegs - 1 && k >= z.n[seg]) {
+            k -= z.n[seg];
+            ++seg;
+        }
+        z.p[seg][k] = 0u;
+    }
+}
 void launch_zero_u32(const ZeroSegs& z, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 void launch_copy_u32(uint32_t* dst, const uint32_t* src, Count n, hipStream_t s);

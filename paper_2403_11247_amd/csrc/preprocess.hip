@@ -142,11 +142,13 @@ __global__ void __launch_bounds__(256) k_preprocess(const ProjTab* __restrict__ 
                                                     const float* __restrict__ opac, const float* __restrict__ color,
                                                     Splat* __restrict__ rec, uint32_t* __restrict__ depth_key,
                                                     uint2* __restrict__ rect, uint32_t* __restrict__ count,
-                                                    float* __restrict__ g2_zero)
+                                                    float* __restrict__ g2_zero, ZeroSegs z, int64_t ztotal)
 {
     const ProjTab& tab = *tabp;
     const int64_t n = tab.n;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the pass's counters, ranges and look-back words (read only by later launches)
+    if (ztotal > 0) zero_segs(z, ztotal, e, (int64_t)gridDim.x * blockDim.x);
     if (e >= n * tab.n_views) return;
     const int v = (int)(e / n);
     const int64_t g = e - (int64_t)v * n;
@@ -195,12 +197,22 @@ __global__ void __launch_bounds__(256) k_preprocess(const ProjTab* __restrict__ 
 }
 
 void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
-                       uint32_t* depth_key, uint2* rect, uint32_t* count, float* g2_zero, hipStream_t s)
+                       uint32_t* depth_key, uint2* rect, uint32_t* count, float* g2_zero, hipStream_t s,
+                       const ZeroSegs* zero)
 {
+    ZeroSegs z{};
+    int64_t ztotal = 0;
+    if (zero) {
+        z = *zero;
+        ztotal = zero_segs_normalise(z);
+    }
     const int64_t total = t.n * t.n_views;
-    if (total <= 0) return;
+    if (total <= 0) {
+        if (zero) launch_zero_u32(*zero, s);
+        return;
+    }
     k_preprocess<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(t_dev, g.mean, g.scale, g.quat, g.opacity, g.color, rec,
-                                                                 depth_key, rect, count, g2_zero);
+                                                                 depth_key, rect, count, g2_zero, z, ztotal);
 }
 
 // ---------------------------------------------------------------------------
