@@ -224,13 +224,21 @@ void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussi
 // ---------------------------------------------------------------------------
 constexpr int kBwdThreads = 256;
 
+// Block barrier ordering LDS only (global stores may stay in flight).
+__device__ __forceinline__ void pp_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
     const ProjTab* __restrict__ tabp, const float* __restrict__ mean, const float* __restrict__ scale,
     const float* __restrict__ quat, const uint32_t* __restrict__ count, const Splat* __restrict__ rec,
     const float* __restrict__ g2, float* __restrict__ d_mean, float* __restrict__ d_scale, float* __restrict__ d_quat,
     float* __restrict__ d_opac, float* __restrict__ d_color, float* __restrict__ pose_partial)
 {
-    __shared__ float red[6][kBwdThreads];
+    __shared__ float red[kBwdThreads / 64][6];  // per wave: its pose 6-vector total
     const ProjTab& tab = *tabp;
     const int64_t n = tab.n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -429,19 +437,21 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
             }
         }
     }
-    // block reduction of this view's pose 6-vector, fixed order
+    // block sum of this view's pose 6-vector in a fixed order: a butterfly over
+    // each wave's lanes, then the four wave totals in wave order.  The
+    // barriers order LDS only, so the gradient stores above stay in flight.
 #pragma unroll
-    for (int i = 0; i < 6; ++i) red[i][threadIdx.x] = pose6[i];
-    __syncthreads();
-    for (int w = kBwdThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
+    for (int i = 0; i < 6; ++i) {
+        float v = pose6[i];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
-        }
-        __syncthreads();
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][i] = v;
     }
-    if (threadIdx.x < 6) pose_partial[((int64_t)vw * gridDim.x + blockIdx.x) * 6 + threadIdx.x] = red[threadIdx.x][0];
-    __syncthreads();
+    pp_barrier();
+    if (threadIdx.x < 6)
+        pose_partial[((int64_t)vw * gridDim.x + blockIdx.x) * 6 + threadIdx.x] =
+            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    pp_barrier();
     // a view's own set takes its gradients here; a shared set after all views
     if (tab.per_view || vw == tab.n_views - 1) {
         if (g < n) {
