@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
     const float* __restrict__ g2, float* __restrict__ d_mean, float* __restrict__ d_scale, float* __restrict__ d_quat,
     float* __restrict__ d_opac, float* __restrict__ d_color, float* __restrict__ pose_partial)
 {
-    __shared__ float red[kBwdThreads / 64][6];  // per wave: its pose 6-vector total
+    __shared__ float red[kBwdThreads / 64][kMaxViews][6];  // per wave and view: its pose 6-vector total
     const ProjTab& tab = *tabp;
     const int64_t n = tab.n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -437,21 +437,16 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
             }
         }
     }
-    // block sum of this view's pose 6-vector in a fixed order: a butterfly over
-    // each wave's lanes, then the four wave totals in wave order.  The
-    // barriers order LDS only, so the gradient stores above stay in flight.
+    // this view's pose 6-vector summed over the wave's lanes (a butterfly) and
+    // parked per wave; the waves' totals are added after the view loop, so
+    // the views need no block barrier
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         float v = pose6[i];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][i] = v;
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][vw][i] = v;
     }
-    pp_barrier();
-    if (threadIdx.x < 6)
-        pose_partial[((int64_t)vw * gridDim.x + blockIdx.x) * 6 + threadIdx.x] =
-            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
-    pp_barrier();
     // a view's own set takes its gradients here; a shared set after all views
     if (tab.per_view || vw == tab.n_views - 1) {
         if (g < n) {
@@ -479,6 +474,13 @@ __global__ void __launch_bounds__(kBwdThreads) k_preprocess_bwd(
 #pragma unroll
         for (int i = 0; i < 4; ++i) dqt[i] = 0.0f;
     }
+    }
+    // per view, the four wave totals in wave order (deterministic)
+    pp_barrier();
+    for (int i = threadIdx.x; i < 6 * tab.n_views; i += kBwdThreads) {
+        const int vw = i / 6, c = i - 6 * vw;
+        pose_partial[((int64_t)vw * gridDim.x + blockIdx.x) * 6 + c] =
+            ((red[0][vw][c] + red[1][vw][c]) + red[2][vw][c]) + red[3][vw][c];
     }
 }
 
