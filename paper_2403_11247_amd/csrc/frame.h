@@ -21,6 +21,7 @@ struct Frame {
     uint32_t* ranges = nullptr;
     uint32_t* gids = nullptr;
     int64_t cap = 0;  // pair capacity (exact pair count in the synchronising path)
+    int64_t pair_hint = 0;  // expected pair count when cap is a generous bound (0: cap)
     // per-entry gradient sums of the backward: the projection zeroes the
     // slots of the visible entries when this is set (no separate fill)
     float* g2 = nullptr;
@@ -30,6 +31,7 @@ struct Work {
     uint32_t *dk, *order, *kaltE, *valtE, *headE, *stateE, *scanE, *cnt, *offs, *total, *overflow;
     uint32_t *headP;  // the pair sort's counters (entry-sized work, so that one launch can zero it early)
     uint32_t *tile_ids, *kaltP, *valtP, *stateP, *scanP;  // scanP: emission chunk starts
+    int64_t stateP_words = 0;  // words at stateP
     const uint32_t* nvis;  // device count of entries in the depth order (culled ones are dropped)
 };
 
@@ -85,6 +87,7 @@ inline void alloc_work_p(Work& w, int64_t cap, Get get)
     w.kaltP = get(cap);
     w.valtP = get(cap);
     w.stateP = get(sort_state_words(cap));
+    w.stateP_words = sort_state_words(cap);
     w.scanP = get(emit_chunk_words(cap));
 }
 

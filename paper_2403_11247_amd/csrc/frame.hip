@@ -99,8 +99,9 @@ void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s)
                           w.total, w.overflow, s);
         pf.end(VCGS_STAGE_EMIT, s);
         pf.begin(VCGS_STAGE_TILE_SORT, s);
-        const SortTemp tp{w.kaltP, w.valtP, w.headP, w.stateP};
-        const int ws = radix_sort_u32(w.tile_ids, f.gids, false, P, bits_for(f.total_tiles - 1), tp, s);
+        const SortTemp tp{w.kaltP, w.valtP, w.headP, w.stateP, w.stateP_words};
+        const int ws = radix_sort_u32(w.tile_ids, f.gids, false, P, bits_for(f.total_tiles - 1), tp, s, nullptr, nullptr,
+                                      f.pair_hint);
         const uint32_t* tsorted = ws ? w.kaltP : w.tile_ids;
         if (ws) launch_copy_u32(f.gids, w.valtP, P, s);
         pf.end(VCGS_STAGE_TILE_SORT, s);

@@ -60,6 +60,11 @@ struct ViewTab {
     const float* dl_da[kMaxViews];
     float bg[3];
     uint32_t* hits;  // optional: per-Gaussian count of blended pixels, accumulated (Gaussian = entry % n)
+    // optional: host-visible pinned words that receive flags_src[0..1] (the
+    // pass's pair count and overflow word) from the forward's first thread,
+    // so that a poller needs no copy after the pass
+    uint32_t* flags_out;
+    const uint32_t* flags_src;
 };
 
 // Projected splat record, 64 bytes: (u, v, u_lo, v_lo) (s1 ex, s1 ey, s2 ex, s2 ey)
@@ -111,6 +116,7 @@ struct SortTemp {
     uint32_t* vals_alt;
     uint32_t* head;     // sort_head_words(): digit counts and partition counters, zero on entry
     uint32_t* state;    // sort_state_words(cap): look-back state (the sort zeroes what it uses)
+    int64_t state_words = 0;  // words at state if more than sort_state_words(cap) (0: exactly that)
 };
 constexpr int64_t kMaxSortItems = (1ll << 30) - 1;
 int radix_blocks(int64_t n);
@@ -128,8 +134,11 @@ int64_t scan_temp_words(int64_t n);
 // With keys_src, the first pass reads its keys from there (not modified) and
 // `keys` is only used as a buffer.
 constexpr uint32_t kDropKey = 0xFFFFFFFFu;
+// size_hint (> 0): the expected item count when the capacity n.cap is a
+// generous bound; the partition size follows it if t.state holds enough words.
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
-                   hipStream_t s, const uint32_t** kept = nullptr, const uint32_t* keys_src = nullptr);
+                   hipStream_t s, const uint32_t** kept = nullptr, const uint32_t* keys_src = nullptr,
+                   int64_t size_hint = 0);
 // Exclusive scan of n uint32 values (out may equal in); if total != nullptr
 // the sum is written there.  Sums saturate at 2^31 instead of wrapping.
 void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,

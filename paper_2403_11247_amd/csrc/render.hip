@@ -135,6 +135,10 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     __shared__ float slab_z[4][64];
     __shared__ uint32_t slab_gid[4][64];  // entries of the slab (kept only for hit counts)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (tab.flags_out && blockIdx.x == 0 && threadIdx.x == 0) {
+        tab.flags_out[0] = tab.flags_src[0];
+        tab.flags_out[1] = tab.flags_src[1];
+    }
     const int gw = (sched ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + wave;
     const uint32_t gt = (uint32_t)(gw / WPT);
     const int sub = gw % WPT;

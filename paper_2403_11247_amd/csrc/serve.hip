@@ -204,6 +204,7 @@ struct vcgs_server {
         // grids of the pair stages are sized from the capacity: use the pass's own
         // estimate (with a margin) rather than the whole slot
         f.cap = std::min<int64_t>(sl.cap, est + est / 4 + 4096);
+        f.pair_hint = std::min<int64_t>(f.cap, est);  // the tile sort sizes its partitions for this
         // order the pass after whatever each request's submitting stream had
         // enqueued; an event that has already completed needs no wait
         for (const Req& r : sl.reqs)
@@ -214,9 +215,12 @@ struct vcgs_server {
         if (f.E > 0) {
             if (decode) launch_decode_fwd(dec, sl.set, sl.s);
             const uint32_t* ord = phase_a(quiet_prof(), g, f, sl.w, sl.s);
+            // the compositing launch writes the pair total and overflow flag
+            // (adjacent words) into the slot's pinned words: no copy after it
+            f.vt.flags_out = sl.flags_host;
+            f.vt.flags_src = sl.w.total;
             phase_b(quiet_prof(), f, sl.w, ord, sl.s);
-            // pair total and overflow flag are adjacent words
-            HIP_TRY(hipMemcpyAsync(sl.flags_host, sl.w.total, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, sl.s));
+            f.vt.flags_out = nullptr;
         } else {
             f.cap = 0;
             zero_pass(f, sl.w, sl.s);

@@ -47,11 +47,12 @@ __device__ __forceinline__ uint64_t match8(uint32_t d, uint64_t active)
 // large ones (the tile sort over the pairs) 4096.
 constexpr int64_t kSmallSort = 1 << 20;
 int sort_items(int64_t cap) { return cap <= kSmallSort ? 8 : 16; }
-int radix_blocks(int64_t cap)
+static int radix_blocks_items(int64_t cap, int items)
 {
-    const int64_t part = (int64_t)kThreads * sort_items(cap);
+    const int64_t part = (int64_t)kThreads * items;
     return (int)std::max<int64_t>(1, (cap + part - 1) / part);
 }
+int radix_blocks(int64_t cap) { return radix_blocks_items(cap, sort_items(cap)); }
 
 __device__ __forceinline__ int64_t dev_count(int64_t cap, const uint32_t* dev)
 {
@@ -528,13 +529,19 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
 }
 
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
-                   hipStream_t s, const uint32_t** kept, const uint32_t* keys_src)
+                   hipStream_t s, const uint32_t** kept, const uint32_t* keys_src, int64_t size_hint)
 {
     if (kept) *kept = nullptr;
     if (n.cap <= 0) return 0;
     if (n.cap > (int64_t)kCountMask) return -1;  // counts share a word with the look-back flags
-    const int nb = radix_blocks(n.cap);
-    const int items = sort_items(n.cap);
+    int items = sort_items(n.cap);
+    if (size_hint > 0 && size_hint < n.cap && sort_items(size_hint) != items) {
+        // smaller partitions for an expected count below the capacity, when
+        // the look-back state has room for their number
+        const int hi = sort_items(size_hint);
+        if (t.state_words >= (int64_t)kMaxPasses * radix_blocks_items(n.cap, hi) * kBins) items = hi;
+    }
+    const int nb = radix_blocks_items(n.cap, items);
     const int passes = std::min(kMaxPasses, (end_bit + 7) / 8);
     uint32_t* ghist = t.head;  // histograms and counters: zero on entry
     uint32_t* counters = t.head + kHistWords;
