@@ -294,29 +294,12 @@ constexpr int bwd_lds_floats(int OT)
     return OT * 16 * kW2S + kF * kW1S + OT * 16 + kF + 16 * lds_o(OT) + 256 * 6 + 2 * 16 * (kF + 1) + 16 * 4 +
            kBwdWaves * 8 * 64 + kDecodeMaxViews * 3;
 }
-// Blocks per CU that the LDS admits (160 KB per CU).
-constexpr int bwd_blocks_per_cu(int OT)
-{
-    return (160 * 1024) / (bwd_lds_floats(OT) * 4) < 1 ? 1 : (160 * 1024) / (bwd_lds_floats(OT) * 4);
-}
 
 int decode_bwd_blocks(int64_t na, int k)
 {
     const int64_t groups = (na + 15) / 16;
-    int per_cu = 1;
-    switch (out_tiles(k)) {
-        case 1: per_cu = bwd_blocks_per_cu(1); break;
-        case 2: per_cu = bwd_blocks_per_cu(2); break;
-        case 3: per_cu = bwd_blocks_per_cu(3); break;
-        case 4: per_cu = bwd_blocks_per_cu(4); break;
-        case 5: per_cu = bwd_blocks_per_cu(5); break;
-        case 6: per_cu = bwd_blocks_per_cu(6); break;
-        case 7: per_cu = bwd_blocks_per_cu(7); break;
-        case 8: per_cu = bwd_blocks_per_cu(8); break;
-        case 9: per_cu = bwd_blocks_per_cu(9); break;
-        case 10: per_cu = bwd_blocks_per_cu(10); break;
-        default: per_cu = bwd_blocks_per_cu(11); break;
-    }
+    const int ot = std::min(std::max(out_tiles(k), 1), 11);
+    const int per_cu = std::max(1, (160 * 1024) / (bwd_lds_floats(ot) * 4));  // blocks per CU that the LDS admits
     return (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)256 * per_cu));
 }
 
