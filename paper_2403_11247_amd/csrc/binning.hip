@@ -159,27 +159,53 @@ void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis
 int64_t emit_chunk_words(int64_t cap) { return (cap + kChunk - 1) / kChunk + 1; }
 
 // [start, end) of every tile's run in the tile-sorted pair list (ranges must
-// be zero-filled beforehand so that empty tiles read [0, 0)).
+// be zero-filled beforehand so that empty tiles read [0, 0)).  A thread takes
+// four consecutive pairs (one 16-byte load when the list is 16-byte aligned);
+// the neighbours across thread boundaries come from the adjacent lanes, and
+// only the wave's two edge lanes load one more id.
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 __global__ void __launch_bounds__(256) k_tile_ranges(int64_t cap, const uint32_t* __restrict__ ndev,
                                                      const uint32_t* __restrict__ t, uint32_t n_tiles,
-                                                     uint32_t* __restrict__ ranges)
+                                                     uint32_t* __restrict__ ranges, int vec)
 {
     const int64_t P = ndev ? min((int64_t)*ndev, cap) : cap;
-    // grid-stride: the grid is sized for at most 4M pairs per sweep, so a
-    // generous capacity does not launch blocks that only exit
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t cur = t[p];
-        if (cur >= n_tiles) continue;
-        if (p == 0 || t[p - 1] != cur) ranges[2 * cur] = (uint32_t)p;
-        if (p == P - 1 || t[p + 1] != cur) ranges[2 * cur + 1] = (uint32_t)(p + 1);
+    const int lane = threadIdx.x & 63;
+    // grid-stride over 1024-pair block chunks (uniform per block): a generous
+    // capacity does not launch blocks that only exit
+    for (int64_t base = (int64_t)blockIdx.x * 1024; base < P; base += (int64_t)gridDim.x * 1024) {
+        const int64_t p0 = base + 4 * threadIdx.x;
+        uint32_t v[4];
+        if (vec && p0 + 3 < P) {
+            const uint4 q = *reinterpret_cast<const uint4*>(t + p0);
+            v[0] = q.x;
+            v[1] = q.y;
+            v[2] = q.z;
+            v[3] = q.w;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = p0 + i < P ? t[p0 + i] : kNoTile;
+        }
+        uint32_t prev = __shfl_up(v[3], 1, 64), next = __shfl_down(v[0], 1, 64);
+        if (lane == 0) prev = (p0 > 0 && p0 - 1 < P) ? t[p0 - 1] : kNoTile;
+        if (lane == 63) next = p0 + 4 < P ? t[p0 + 4] : kNoTile;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t p = p0 + i;
+            const uint32_t cur = v[i];
+            if (p >= P || cur >= n_tiles) continue;
+            const uint32_t left = i > 0 ? v[i - 1] : prev, right = i < 3 ? v[i + 1] : next;
+            if (p == 0 || left != cur) ranges[2 * cur] = (uint32_t)p;
+            if (p == P - 1 || right != cur) ranges[2 * cur + 1] = (uint32_t)(p + 1);
+        }
     }
 }
 
 void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s)
 {
     if (P.cap <= 0) return;
-    const int64_t blocks = std::min<int64_t>((P.cap + 255) / 256, 16384);
-    k_tile_ranges<<<(unsigned)blocks, 256, 0, s>>>(P.cap, P.dev, tile_sorted, n_tiles, ranges);
+    const int64_t blocks = std::min<int64_t>((P.cap + 1023) / 1024, 4096);
+    const int vec = (reinterpret_cast<uintptr_t>(tile_sorted) & 15u) == 0u;
+    k_tile_ranges<<<(unsigned)blocks, 256, 0, s>>>(P.cap, P.dev, tile_sorted, n_tiles, ranges, vec);
 }
 
 }  // namespace vcgs

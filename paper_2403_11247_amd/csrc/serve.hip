@@ -11,6 +11,7 @@
 // (8)-(9)): a pass first decodes its requests' camera centres in one launch
 // into the slot's stacked per-view sets, then renders each request from its
 // own set (the per-view form of the same pass).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <deque>
@@ -66,19 +67,30 @@ struct vcgs_server {
     std::deque<int64_t> ready;
     int64_t next_ticket = 0, passes = 0, reruns = 0;
     double ppp = 1.0;           // pairs-per-pixel estimate used for admission
+    double typ = 1.0;           // typical pairs per pixel: sizes the tile sort's partitions
     double recent[32] = {};     // observed pairs per pixel of the last 32 passes
     int n_recent = 0;
     bool oom = false;
 
-    // The estimate follows 1.25 x the largest observed pairs-per-pixel of the
-    // last 32 passes (an underestimate only costs a rerun).
+    // The admission estimate follows 1.25 x the largest observed pairs per
+    // pixel of the last 32 passes (an underestimate only costs a rerun); the
+    // typical value is their median (pairs per pixel varies several-fold with
+    // the pose, so the bound would put most small views on the large sort
+    // partitions).
     void observe(double obs)
     {
         recent[n_recent % 32] = obs;
         ++n_recent;
+        const int m = std::min(n_recent, 32);
+        double v[32];
         double mx = 0.0;
-        for (int i = 0; i < std::min(n_recent, 32); ++i) mx = std::max(mx, recent[i]);
+        for (int i = 0; i < m; ++i) {
+            v[i] = recent[i];
+            mx = std::max(mx, recent[i]);
+        }
+        std::nth_element(v, v + m / 2, v + m);
         ppp = std::max(1.25 * mx, 1e-3);
+        typ = std::max(v[m / 2], 1e-3);
     }
     std::vector<hipEvent_t> spare_events;
 
@@ -173,7 +185,9 @@ struct vcgs_server {
         }
         vcgs_camera cams[kMaxViews];
         vcgs_pose poses[kMaxViews];
+        int64_t pix = 0;
         for (int v = 0; v < V; ++v) {
+            pix += sl.reqs[v].pixels;
             cams[v] = sl.reqs[v].cam;
             poses[v] = sl.reqs[v].pose;
         }
@@ -204,7 +218,8 @@ struct vcgs_server {
         // grids of the pair stages are sized from the capacity: use the pass's own
         // estimate (with a margin) rather than the whole slot
         f.cap = std::min<int64_t>(sl.cap, est + est / 4 + 4096);
-        f.pair_hint = std::min<int64_t>(f.cap, est);  // the tile sort sizes its partitions for this
+        // the tile sort sizes its partitions for the typical count
+        f.pair_hint = std::min<int64_t>(f.cap, (int64_t)std::ceil((double)pix * typ));
         // order the pass after whatever each request's submitting stream had
         // enqueued; an event that has already completed needs no wait
         for (const Req& r : sl.reqs)
@@ -310,6 +325,7 @@ int create_server(vcgs_ctx* ctx, const vcgs_gaussians* map, const DecodeArgs* de
     }
     srv->cfg = *cfg;
     srv->ppp = cfg->pairs_per_pixel;
+    srv->typ = cfg->pairs_per_pixel;
     srv->slots.resize(cfg->slots);
     const int64_t Emax = (int64_t)cfg->max_views * map->n;
     for (Slot& sl : srv->slots) {

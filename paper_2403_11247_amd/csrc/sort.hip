@@ -424,7 +424,12 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
     __shared__ uint32_t s_part;
     const int64_t n = dev_count(cap, ndev);
     // blocks take partitions in counter order until none is left, so the grid
-    // need not match the (device-side) item count
+    // need not match the (device-side) item count.  Blocks beyond the
+    // partition count leave before touching the counter (with a generous
+    // capacity most of the grid would otherwise queue on that one word just to
+    // exit), so the first `parts` blocks take one partition each.
+    const int64_t parts = (n + BI - 1) / BI;
+    if ((int64_t)blockIdx.x >= parts) return;
     for (;;) {
     __syncthreads();  // the previous partition's LDS is no longer read
     if (threadIdx.x == 0) s_part = atomicAdd(counter, 1u);
@@ -525,6 +530,7 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
         keys_out[pos] = k;
         vals_out[pos] = s_val[i];
     }
+    if ((int64_t)gridDim.x >= parts) return;  // one partition per block: none left
     }
 }
 
