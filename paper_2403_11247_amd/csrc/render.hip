@@ -426,12 +426,14 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
     constexpr int SW = PPL == 1 ? 8 : 16;
     constexpr int LR = 64 / SW;
     constexpr int SH = LR * PPL;
-    // splat records staged component-major (conflict-free stores, broadcast reads); only z of the 4th row is used
-    __shared__ float4 slab[4][3][64];
-    __shared__ float slab_z[4][64];
-    __shared__ uint32_t slab_gid[4][64];
-    // per-Gaussian totals (10 values) waiting to be added to g2
-    __shared__ float pend[4][kPend][10];
+    // splat records staged component-major (conflict-free stores, broadcast
+    // reads), rows grouped by use so that every read is at a fixed offset from
+    // entry k's first row: 0 = (u, v, u_lo, v_lo), 1 = scaled eigen rows, both
+    // read for every entry; 2 = (r, g, b, depth), read only for a blending
+    // entry; 3 = (opacity, Gaussian id as bits, -, -)
+    __shared__ float4 slab[4][4][64];
+    // per-Gaussian totals (10 values) waiting to be added to g2, slot-major
+    __shared__ float pend[4][kPend * 10];
     __shared__ uint32_t pend_gid[4][kPend];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gw = (sched ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + wave;
@@ -448,8 +450,9 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
     const float* __restrict__ dl_da = tab.dl_da[vw];
     const float bg0 = tab.bg[0], bg1 = tab.bg[1], bg2 = tab.bg[2];
     uint32_t n_eval = 0, n_blend = 0, n_flush = 0;
-    int npend = 0;  // uniform
+    int npend = 0, poff = 0;  // uniform; poff = 10 npend, kept by addition (no multiply in the address)
     const int wrv = wr_value(lane);
+    float* const pend_lane = &pend[wave][wrv < 0 ? 0 : wrv];  // this lane's total, slot 0
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int qx = PPL == 1 ? (sub & 1) : 0, qy = PPL == 1 ? (sub >> 1) : sub;
     const int px = tx * kTile + qx * SW + lane % SW;
@@ -491,11 +494,17 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
         wave_lds_sync();
         if (lane < 10 * count) {
             const int sl = lane / 10, v = lane - 10 * sl;
-            atomicAdd(g2 + (size_t)kG2 * pend_gid[wave][sl] + v, pend[wave][sl][v]);
+            atomicAdd(g2 + (size_t)kG2 * pend_gid[wave][sl] + v, pend[wave][lane]);
         }
         wave_lds_sync();
     };
-    for (int bs = (int)((wl - 1u) & ~63u); bs >= 0; bs -= 64) {
+    // rem[j] = last[j] - bs: entry k of the slab at bs lies in front of pixel
+    // j's last contributor iff k < rem[j]
+    int rem[PPL];
+    const int bs0 = (int)((wl - 1u) & ~63u);
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) rem[j] = (int)last[j] - bs0;
+    for (int bs = bs0; bs >= 0; bs -= 64) {
         wave_lds_sync();
         const uint32_t li = (uint32_t)bs + lane;
         bool keep = false;
@@ -505,16 +514,14 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
             keep = !cull || reaches_rect(sp, rx0, rx1, ry0, ry1);
             slab[wave][0][lane] = sp.a;
             slab[wave][1][lane] = sp.b;
-            slab[wave][2][lane] = sp.c;
-            slab_z[wave][lane] = sp.d.x;
-            slab_gid[wave][lane] = g;
+            slab[wave][2][lane] = make_float4(sp.c.y, sp.c.z, sp.c.w, sp.d.x);
+            slab[wave][3][lane] = make_float4(sp.c.x, __uint_as_float(g), 0.0f, 0.0f);
         }
         uint64_t hits = __ballot(keep);
         wave_lds_sync();
         while (hits) {
             const int k = 63 - __builtin_clzll(hits);
             hits &= ~(1ull << k);
-            const uint32_t local = (uint32_t)(bs + k);
             const float4 ra = slab[wave][0][k], rb = slab[wave][1][k];
             const float dx = (pxf - ra.x) - ra.z;
             // footprints first: a wave-entry that blends into none of the wave's
@@ -524,15 +531,14 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
             bool any = false;
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
-                fj[j] = footprint(dx, (pyf[j] - ra.y) - ra.w, rb.x, rb.y, rb.z, rb.w, slab[wave][2][k].x);
-                const bool in = local < last[j];
+                fj[j] = footprint(dx, (pyf[j] - ra.y) - ra.w, rb.x, rb.y, rb.z, rb.w, slab[wave][3][k].x);
+                const bool in = k < rem[j];
                 cj[j] = in && fj[j].alpha >= kAlphaMin;
                 if (COUNT) { n_eval += in ? 1u : 0u; n_blend += cj[j] ? 1u : 0u; }
                 any = any || cj[j];
             }
             if (__ballot(any) == 0ull) continue;
-            const float4 rc = slab[wave][2][k];
-            const float rz = slab_z[wave][k];
+            const float4 rc = slab[wave][2][k];  // (r, g, b, depth)
             // Per-lane sums: p0 = sum dP q1, p1 = sum dP q2, p2 = sum dP q1^2,
             // p3 = sum dP q1 q2, p4 = sum dP q2^2 (dP = dL/dpower, (q1, q2) the
             // scaled pixel offset in the footprint's eigen frame; the projection
@@ -548,7 +554,7 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
                 const bool c = cj[j];
                 const float a = f.alpha;
                 const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
-                const float X = fmaf(up[j][0], rc.y, fmaf(up[j][1], rc.z, fmaf(up[j][2], rc.w, fmaf(up[j][3], rz, up[j][4]))));
+                const float X = fmaf(up[j][0], rc.x, fmaf(up[j][1], rc.y, fmaf(up[j][2], rc.z, fmaf(up[j][3], rc.w, up[j][4]))));
                 const float d = X - U[j];
                 U[j] = fmaf(c ? a : 0.0f, d, U[j]);
                 const float w = c ? a * Ti : 0.0f;
@@ -568,15 +574,19 @@ __global__ void __launch_bounds__(256) k_composite_bwd(ViewTab tab, uint32_t tot
                 T[j] = c ? Ti : T[j];
             }
             const float tot = wave_reduce10(p, lane);
-            if (wrv >= 0) pend[wave][npend][wrv] = tot;
-            if (lane == 0) pend_gid[wave][npend] = slab_gid[wave][k];
+            if (wrv >= 0) pend_lane[poff] = tot;
+            if (lane == 0) pend_gid[wave][npend] = __float_as_uint(slab[wave][3][k].y);
             ++npend;
+            poff += 10;
             if (COUNT && lane == 0) ++n_flush;
             if (npend == kPend) {
                 flush(kPend);
                 npend = 0;
+                poff = 0;
             }
         }
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) rem[j] += 64;
     }
     if (npend > 0) flush(npend);
     if (COUNT) {
