@@ -130,10 +130,11 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     constexpr int SW = PPL == 1 ? 8 : 16;  // width of a wave's pixel block (8x8 quadrants at 1 pixel per lane)
     constexpr int LR = 64 / SW;            // rows of lanes
     constexpr int SH = LR * PPL;           // height of a wave's pixel block
-    // splat records staged component-major (conflict-free stores, broadcast reads); only z of the 4th row is used
-    __shared__ float4 slab[4][3][64];
-    __shared__ float slab_z[4][64];
-    __shared__ uint32_t slab_gid[4][64];  // entries of the slab (kept only for hit counts)
+    // splat records staged component-major (conflict-free stores, broadcast
+    // reads): rows (u, v, u_lo, v_lo), scaled eigen rows, (opacity, r, g, b),
+    // (depth, Gaussian id as bits, -, -), so that every read of entry k is at a
+    // fixed offset from its first row
+    __shared__ float4 slab[4][4][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (tab.flags_out && blockIdx.x == 0 && threadIdx.x == 0) {
         tab.flags_out[0] = tab.flags_src[0];
@@ -177,7 +178,9 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
         last[j] = 0u;
     }
     const float pxf = (float)px + 0.5f;
-    const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
+    // the tile's list (wave-uniform: list positions and indices stay scalar)
+    const uint32_t start = __builtin_amdgcn_readfirstlane(ranges[2 * gt]);
+    const uint32_t end = __builtin_amdgcn_readfirstlane(ranges[2 * gt + 1]);
     // One footprint blended front to back into pixel j.  A Gaussian below
     // 1/255 takes alpha 0, which leaves T (>= 1e-4 while running) unchanged;
     // one that would take T below 1e-4 stops the pixel with weight 0; a stopped
@@ -196,7 +199,7 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
     };
     // pixels of the wave that blended Gaussian slot k, added to its hit count
     auto add_hits = [&](int k, uint32_t nh) {
-        if (lane == 0 && nh) atomicAdd(hits + slab_gid[wave][k] % (uint32_t)tab.n, nh);
+        if (lane == 0 && nh) atomicAdd(hits + __float_as_uint(slab[wave][3][k].y) % (uint32_t)tab.n, nh);
     };
     auto wave_done = [&]() {
         bool mine = true;
@@ -216,8 +219,7 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
             slab[wave][0][lane] = sp.a;
             slab[wave][1][lane] = sp.b;
             slab[wave][2][lane] = sp.c;
-            slab_z[wave][lane] = sp.d.x;
-            if (hits) slab_gid[wave][lane] = e;
+            slab[wave][3][lane] = make_float4(sp.d.x, __uint_as_float(e), 0.0f, 0.0f);
         }
         uint64_t todo = __ballot(keep);
         wave_lds_sync();
@@ -230,9 +232,9 @@ __global__ void __launch_bounds__(256) k_composite_fwd(ViewTab tab, uint32_t tot
             const int k2 = two ? __builtin_ctzll(todo) : k1;
             todo &= todo - 1ull;
             const float4 a1 = slab[wave][0][k1], b1 = slab[wave][1][k1], r1 = slab[wave][2][k1];
-            const float z1 = slab_z[wave][k1];
+            const float z1 = slab[wave][3][k1].x;
             const float4 a2 = slab[wave][0][k2], b2 = slab[wave][1][k2], r2 = slab[wave][2][k2];
-            const float z2 = slab_z[wave][k2];
+            const float z2 = slab[wave][3][k2].x;
             const float dx1 = (pxf - a1.x) - a1.z, dx2 = (pxf - a2.x) - a2.z;
             uint32_t h1 = 0u, h2 = 0u;
 #pragma unroll
