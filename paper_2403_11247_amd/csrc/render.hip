@@ -776,23 +776,42 @@ void launch_composite_bwd(const ViewTab& v, uint32_t total_tiles, const Splat* r
 // pixel; the scalar is reduced per block and then over blocks in block order.
 constexpr int kLossThreads = 256;
 
+// Sign of e scaled by g (0 at e = 0): the L1 gradient of one value.
+__device__ __forceinline__ float l1_grad(float e, float g) { return e > 0.0f ? g : (e < 0.0f ? -g : 0.0f); }
+
+// PX consecutive pixels per thread: 4 with 16-byte loads and stores (every
+// plane 16-byte aligned and npix a multiple of 4), else 1.
+template <int PX>
 __global__ void __launch_bounds__(kLossThreads) k_l1_loss(int64_t npix, const float* __restrict__ c,
                                                           const float* __restrict__ d, const float* __restrict__ tc,
                                                           const float* __restrict__ td, float w_depth, float inv_n,
                                                           float* __restrict__ dl_dc, float* __restrict__ dl_dd,
                                                           float* __restrict__ partial)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * PX;
+    const float gd = w_depth * inv_n;
     float l = 0.0f;
-    if (p < npix) {
+    if (PX == 4 && p < npix) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const float* a = ch < 3 ? c + ch * npix : d;
+            const float* b = ch < 3 ? tc + ch * npix : td;
+            float* o = ch < 3 ? dl_dc + ch * npix : dl_dd;
+            const float g = ch < 3 ? inv_n : gd, w = ch < 3 ? 1.0f : w_depth;
+            const float4 x = *reinterpret_cast<const float4*>(a + p), y = *reinterpret_cast<const float4*>(b + p);
+            const float e0 = x.x - y.x, e1 = x.y - y.y, e2 = x.z - y.z, e3 = x.w - y.w;
+            *reinterpret_cast<float4*>(o + p) = make_float4(l1_grad(e0, g), l1_grad(e1, g), l1_grad(e2, g), l1_grad(e3, g));
+            l += w * ((fabsf(e0) + fabsf(e1)) + (fabsf(e2) + fabsf(e3)));
+        }
+    } else if (PX == 1 && p < npix) {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             const float e = c[ch * npix + p] - tc[ch * npix + p];
-            dl_dc[ch * npix + p] = e > 0.0f ? inv_n : (e < 0.0f ? -inv_n : 0.0f);
+            dl_dc[ch * npix + p] = l1_grad(e, inv_n);
             l += fabsf(e);
         }
         const float e = d[p] - td[p];
-        dl_dd[p] = e > 0.0f ? w_depth * inv_n : (e < 0.0f ? -w_depth * inv_n : 0.0f);
+        dl_dd[p] = l1_grad(e, gd);
         l += w_depth * fabsf(e);
     }
     if (partial) {
@@ -882,9 +901,18 @@ void launch_l1_loss(int64_t npix, const float* c, const float* d, const float* t
         if (loss) launch_fill_f32(loss, 0.0f, 1, s);
         return;
     }
-    const int nb = l1_loss_blocks(npix);
     const float inv_n = 1.0f / (float)npix;
-    k_l1_loss<<<nb, kLossThreads, 0, s>>>(npix, c, d, tc, td, w_depth, inv_n, dl_dc, dl_dd, loss ? partial : nullptr);
+    bool vec = npix % 4 == 0;
+    for (const void* q : {(const void*)c, (const void*)d, (const void*)tc, (const void*)td, (const void*)dl_dc,
+                          (const void*)dl_dd})
+        vec = vec && (reinterpret_cast<uintptr_t>(q) & 15u) == 0u;
+    // at most l1_loss_blocks(npix) partials either way
+    const int nb = vec ? (int)((npix / 4 + kLossThreads - 1) / kLossThreads) : l1_loss_blocks(npix);
+    float* part = loss ? partial : nullptr;
+    if (vec)
+        k_l1_loss<4><<<nb, kLossThreads, 0, s>>>(npix, c, d, tc, td, w_depth, inv_n, dl_dc, dl_dd, part);
+    else
+        k_l1_loss<1><<<nb, kLossThreads, 0, s>>>(npix, c, d, tc, td, w_depth, inv_n, dl_dc, dl_dd, part);
     if (loss) k_sum_partials<<<1, 256, 0, s>>>(partial, nb, inv_n, loss);
 }
 

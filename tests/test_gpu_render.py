@@ -171,15 +171,18 @@ def test_posed_backward_with_background(V):
     check_backward(V, g, cam, pose, up, bg=(0.3, 0.6, 0.9), name="posed-bg")
 
 
-def test_l1_loss_kernel(V):
+@pytest.mark.parametrize("H,W", [(20, 30), (19, 31), (68, 120), (67, 121)])
+def test_l1_loss_kernel(V, H, W):
+    # pixel counts divisible by 4 take the 4-pixel vector path, the others one pixel per thread;
+    # equal values (zero error, zero gradient) in every other row
     rng = np.random.default_rng(0)
-    C = rng.uniform(0, 1, (3, 20, 30)).astype(np.float32)
-    D = rng.uniform(1, 5, (20, 30)).astype(np.float32)
+    C = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
+    D = rng.uniform(1, 5, (H, W)).astype(np.float32)
     Ct, Dt = C.copy(), D.copy()
     Ct[:, ::2] += 0.1
     Dt[1::3] -= 0.2
     loss, dlc, dld = V.l1_loss(dev(C), dev(D), dev(Ct), dev(Dt), 0.5)
-    n = 600
+    n = H * W
     exp_loss = (np.abs(C.astype(np.float64) - Ct).sum() + 0.5 * np.abs(D.astype(np.float64) - Dt).sum()) / n
     assert abs(float(loss.cpu()) - exp_loss) < 1e-5 * exp_loss
     np.testing.assert_array_equal(dlc.cpu().numpy(), (np.sign(C - Ct) / np.float32(n)).astype(np.float32))
