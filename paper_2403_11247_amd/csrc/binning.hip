@@ -71,6 +71,7 @@ void launch_copy_u32(uint32_t* dst, const uint32_t* src, Count n, hipStream_t s)
 constexpr int kEmitG = 256;
 constexpr int kChunk = 2048;  // pairs per block
 constexpr int kSpan = 1024;   // entries staged at a time
+constexpr int kRun = 8;       // consecutive pairs per thread
 
 __global__ void __launch_bounds__(256) k_chunk_starts(int64_t n_all, const uint32_t* __restrict__ nvis,
                                                       const uint32_t* __restrict__ offs,
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
                                                        const uint32_t* __restrict__ chunk_start,
                                                        uint32_t* __restrict__ tile_ids, uint32_t* __restrict__ gids,
                                                        int64_t cap, const uint32_t* __restrict__ total,
-                                                       uint32_t* __restrict__ overflow)
+                                                       uint32_t* __restrict__ overflow, int vec)
 {
     __shared__ uint32_t s_off[kSpan + 1];
     __shared__ uint32_t s_gid[kSpan];
@@ -120,22 +121,67 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
         }
         __syncthreads();
         const int64_t pend = min(p1, (int64_t)s_off[S]);
-        for (int64_t p = pcur + threadIdx.x; p < pend; p += kEmitG) {
-            // largest j in [0, S) with s_off[j] <= p
+        // kRun consecutive pairs per thread: one binary search for the first,
+        // then the owner and its tile advance by increments (an owner's pairs
+        // are its rectangle's tiles in row-major order)
+        for (int64_t q0 = pcur + (int64_t)threadIdx.x * kRun; q0 < pend; q0 += (int64_t)kEmitG * kRun) {
+            // largest j in [0, S) with s_off[j] <= q0
             int a = 0, b = S - 1;
             while (a < b) {
                 const int mid = (a + b + 1) >> 1;
-                if ((int64_t)s_off[mid] <= p) a = mid; else b = mid - 1;
+                if ((int64_t)s_off[mid] <= q0) a = mid; else b = mid - 1;
             }
-            const uint32_t e = s_gid[a];
-            const int v = (int)(e / (uint32_t)tab.n);
-            const uint2 r = s_rect[a];
-            const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu;
-            const uint32_t w = tx1 - tx0 + 1u;
-            const uint32_t local = (uint32_t)p - s_off[a];
-            const uint32_t ty = ty0 + local / w, tx = tx0 + local % w;
-            tile_ids[p] = tab.tile_base[v] + ty * (uint32_t)tab.tiles_x[v] + tx;
-            gids[p] = e;
+            uint32_t e = s_gid[a], row = 0, tx0 = 0, tx1 = 0, tx = 0, ty = 0, tbase = 0;
+            // the owner's tile of pair p (local index p - s_off[a])
+            auto owner = [&](int64_t p) {
+                e = s_gid[a];
+                const int v = (int)(e / (uint32_t)tab.n);
+                const uint2 r = s_rect[a];
+                tx0 = r.x & 0xFFFFu;
+                tx1 = r.y & 0xFFFFu;
+                const uint32_t w = tx1 - tx0 + 1u, local = (uint32_t)(p - (int64_t)s_off[a]);
+                ty = (r.x >> 16) + local / w;
+                tx = tx0 + local % w;
+                row = (uint32_t)tab.tiles_x[v];
+                tbase = tab.tile_base[v];
+            };
+            owner(q0);
+            uint32_t next = s_off[a + 1];  // a + 1 <= S: s_off[S] > q0
+            uint32_t tt[kRun], gg[kRun];
+#pragma unroll
+            for (int i = 0; i < kRun; ++i) {
+                const int64_t p = q0 + i;
+                if (p < pend) {
+                    if ((int64_t)next <= p) {
+                        // the next owner with pairs starts exactly at p (owners without pairs share its offset)
+                        do {
+                            ++a;
+                            next = s_off[a + 1];
+                        } while ((int64_t)next <= p);
+                        owner(p);
+                    }
+                    tt[i] = tbase + ty * row + tx;
+                    gg[i] = e;
+                    if (++tx > tx1) {
+                        tx = tx0;
+                        ++ty;
+                    }
+                }
+            }
+            if (vec && (q0 & (kRun - 1)) == 0 && q0 + kRun <= pend) {
+#pragma unroll
+                for (int i = 0; i < kRun; i += 4) {
+                    *reinterpret_cast<uint4*>(tile_ids + q0 + i) = make_uint4(tt[i], tt[i + 1], tt[i + 2], tt[i + 3]);
+                    *reinterpret_cast<uint4*>(gids + q0 + i) = make_uint4(gg[i], gg[i + 1], gg[i + 2], gg[i + 3]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < kRun; ++i)
+                    if (q0 + i < pend) {
+                        tile_ids[q0 + i] = tt[i];
+                        gids[q0 + i] = gg[i];
+                    }
+            }
         }
         __syncthreads();
         pcur = pend;
@@ -152,8 +198,10 @@ void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis
     if (n_entries <= 0 || cap <= 0) return;
     k_chunk_starts<<<(unsigned)((n_entries + 255) / 256), 256, 0, s>>>(n_entries, nvis, offs, cnt, cap, chunk_start);
     const int64_t blocks = std::min<int64_t>((cap + kChunk - 1) / kChunk, 4096);
+    // 16-byte stores of whole runs need 16-byte aligned outputs
+    const int vec = ((reinterpret_cast<uintptr_t>(tile_ids) | reinterpret_cast<uintptr_t>(gids)) & 15u) == 0u;
     k_emit_pairs<<<(unsigned)blocks, kEmitG, 0, s>>>(
-        t, n_entries, nvis, order, offs, cnt, rect, chunk_start, tile_ids, gids, cap, total, overflow);
+        t, n_entries, nvis, order, offs, cnt, rect, chunk_start, tile_ids, gids, cap, total, overflow, vec);
 }
 
 int64_t emit_chunk_words(int64_t cap) { return (cap + kChunk - 1) / kChunk + 1; }
