@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
                                                        const uint32_t* __restrict__ chunk_start,
                                                        uint32_t* __restrict__ tile_ids, uint32_t* __restrict__ gids,
                                                        int64_t cap, const uint32_t* __restrict__ total,
-                                                       uint32_t* __restrict__ overflow, int vec)
+                                                       uint32_t* __restrict__ overflow, int vec, SortPrep sp)
 {
     __shared__ uint32_t s_off[kSpan + 1];
     __shared__ uint32_t s_gid[kSpan];
@@ -102,6 +102,17 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
     const int64_t P = min((int64_t)*total, cap);
     // sticky: the largest pair count of any pass that outgrew the buffers since the flag was cleared
     if (blockIdx.x == 0 && threadIdx.x == 0 && overflow && (int64_t)*total > cap) *overflow = max(*overflow, *total);
+    // the tile sort's digit histograms of this block's pairs, and its look-back
+    // words cleared, so that the sort needs no histogram launch of its own
+    __shared__ uint32_t s_hist[kSortPassStride];
+    const int hp = sp.ghist ? sp.passes : 0;  // uniform
+    if (hp) {
+        for (int i = threadIdx.x; i < hp * 256; i += kEmitG) s_hist[i] = 0u;
+        const int64_t words = ((P + sp.part_items - 1) / sp.part_items) * 256;
+        const int64_t gt = (int64_t)blockIdx.x * kEmitG + threadIdx.x, gs = (int64_t)gridDim.x * kEmitG;
+        for (int q = 0; q < hp; ++q)
+            for (int64_t i = gt; i < words; i += gs) sp.state[q * sp.state_stride + i] = 0u;
+    }
     // chunks strided by the grid, so a generous capacity does not launch blocks that only exit
     for (int64_t c = blockIdx.x; c * kChunk < P; c += gridDim.x) {  // uniform
     const int64_t p0 = c * kChunk;
@@ -162,6 +173,7 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
                     }
                     tt[i] = tbase + ty * row + tx;
                     gg[i] = e;
+                    for (int q = 0; q < hp; ++q) atomicAdd(&s_hist[q * 256 + ((tt[i] >> (8 * q)) & 0xFFu)], 1u);
                     if (++tx > tx1) {
                         tx = tx0;
                         ++ty;
@@ -188,20 +200,29 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
         kbase += S;
     }
     }
+    if (hp) {
+        __syncthreads();
+        uint32_t* gh = sp.ghist + (int64_t)(blockIdx.x % kSortHistCopies) * kSortPassStride;
+        for (int i = threadIdx.x; i < hp * 256; i += kEmitG) {
+            const uint32_t c = s_hist[i];
+            if (c) atomicAdd(gh + i, c);
+        }
+    }
 }
 
-void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis, const uint32_t* order,
+bool launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis, const uint32_t* order,
                        const uint32_t* offs, const uint32_t* cnt, const uint2* rect, uint32_t* chunk_start,
                        uint32_t* tile_ids, uint32_t* gids, int64_t cap, const uint32_t* total, uint32_t* overflow,
-                       hipStream_t s)
+                       const SortPrep& sp, hipStream_t s)
 {
-    if (n_entries <= 0 || cap <= 0) return;
+    if (n_entries <= 0 || cap <= 0) return false;
     k_chunk_starts<<<(unsigned)((n_entries + 255) / 256), 256, 0, s>>>(n_entries, nvis, offs, cnt, cap, chunk_start);
     const int64_t blocks = std::min<int64_t>((cap + kChunk - 1) / kChunk, 4096);
     // 16-byte stores of whole runs need 16-byte aligned outputs
     const int vec = ((reinterpret_cast<uintptr_t>(tile_ids) | reinterpret_cast<uintptr_t>(gids)) & 15u) == 0u;
     k_emit_pairs<<<(unsigned)blocks, kEmitG, 0, s>>>(
-        t, n_entries, nvis, order, offs, cnt, rect, chunk_start, tile_ids, gids, cap, total, overflow, vec);
+        t, n_entries, nvis, order, offs, cnt, rect, chunk_start, tile_ids, gids, cap, total, overflow, vec, sp);
+    return true;
 }
 
 int64_t emit_chunk_words(int64_t cap) { return (cap + kChunk - 1) / kChunk + 1; }

@@ -94,14 +94,18 @@ void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s)
 {
     if (f.cap > 0) {
         const Count P{f.cap, w.total};
+        const int end_bit = bits_for(f.total_tiles - 1);
+        const SortTemp tp{w.kaltP, w.valtP, w.headP, w.stateP, w.stateP_words};
+        // the emission builds the tile sort's histograms (the projection launch cleared them)
+        const SortPrep sp = radix_sort_prep(P, end_bit, tp, f.pair_hint);
         pf.begin(VCGS_STAGE_EMIT, s);
-        launch_emit_pairs(f.et, f.E, w.nvis, ord, w.offs, w.cnt, f.rect, w.scanP, w.tile_ids, f.gids, f.cap,
-                          w.total, w.overflow, s);
+        const bool hist = launch_emit_pairs(f.et, f.E, w.nvis, ord, w.offs, w.cnt, f.rect, w.scanP, w.tile_ids,
+                                            f.gids, f.cap, w.total, w.overflow, sp, s) &&
+                          sp.ghist != nullptr;
         pf.end(VCGS_STAGE_EMIT, s);
         pf.begin(VCGS_STAGE_TILE_SORT, s);
-        const SortTemp tp{w.kaltP, w.valtP, w.headP, w.stateP, w.stateP_words};
-        const int ws = radix_sort_u32(w.tile_ids, f.gids, false, P, bits_for(f.total_tiles - 1), tp, s, nullptr, nullptr,
-                                      f.pair_hint);
+        const int ws = radix_sort_u32(w.tile_ids, f.gids, false, P, end_bit, tp, s, nullptr, nullptr, f.pair_hint,
+                                      hist);
         const uint32_t* tsorted = ws ? w.kaltP : w.tile_ids;
         if (ws) launch_copy_u32(f.gids, w.valtP, P, s);
         pf.end(VCGS_STAGE_TILE_SORT, s);

@@ -138,7 +138,23 @@ constexpr uint32_t kDropKey = 0xFFFFFFFFu;
 // generous bound; the partition size follows it if t.state holds enough words.
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
                    hipStream_t s, const uint32_t** kept = nullptr, const uint32_t* keys_src = nullptr,
-                   int64_t size_hint = 0);
+                   int64_t size_hint = 0, bool hist_done = false);
+// What a kernel that writes the keys must do so that radix_sort_u32 can skip
+// its histogram launch (hist_done, no dropping; same n, end_bit, t and
+// size_hint): add each key's digit of pass p, (key >> 8p) & 255 for p <
+// passes, to ghist[(b % kSortHistCopies) * kSortPassStride + p * 256 + digit]
+// (any copy b; t.head is zero on entry), and zero, for every pass p, the
+// ceil(items / part_items) * 256 words at state + p * state_stride, items
+// being the device count.  ghist == nullptr: nothing to do (n.cap <= 0).
+constexpr int kSortHistCopies = 8;
+constexpr int kSortPassStride = 4 * 256;
+struct SortPrep {
+    uint32_t* ghist = nullptr;
+    uint32_t* state = nullptr;
+    int64_t state_stride = 0, part_items = 0;
+    int passes = 0;
+};
+SortPrep radix_sort_prep(Count n, int end_bit, const SortTemp& t, int64_t size_hint = 0);
 // Exclusive scan of n uint32 values (out may equal in); if total != nullptr
 // the sum is written there.  Sums saturate at 2^31 instead of wrapping.
 void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
@@ -165,10 +181,13 @@ struct EmitTab {
 // total exceeds cap raises *overflow to the total (when non-null; the flag
 // keeps the largest such total until the host clears it).  chunk_start: scratch
 // of emit_chunk_words(cap) words.
-void launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis, const uint32_t* order,
+// With sp.ghist set, it also does what sp asks of the tile ids for the tile
+// sort (see radix_sort_prep); returns false if it launched nothing (then the
+// sort must build its own histogram).
+bool launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis, const uint32_t* order,
                        const uint32_t* offs, const uint32_t* cnt, const uint2* rect, uint32_t* chunk_start,
                        uint32_t* tile_ids, uint32_t* gids, int64_t cap, const uint32_t* total, uint32_t* overflow,
-                       hipStream_t s);
+                       const SortPrep& sp, hipStream_t s);
 int64_t emit_chunk_words(int64_t cap);
 void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);

@@ -313,7 +313,8 @@ constexpr uint32_t kFlagAgg = 1u << 30;       // partition's own digit count pub
 constexpr uint32_t kFlagInc = 2u << 30;       // count including all lower partitions
 constexpr uint32_t kCountMask = kFlagAgg - 1u;
 constexpr int kMaxPasses = 4;
-constexpr int kHistRep = 8;  // histogram copies (block b adds to copy b % 8): 8x less atomic contention
+constexpr int kHistRep = kSortHistCopies;  // histogram copies (block b adds to copy b % 8): 8x less atomic contention
+static_assert(kSortPassStride == kMaxPasses * kBins, "histogram copy stride");
 constexpr int64_t kHistWords = (int64_t)kHistRep * kMaxPasses * kBins;
 constexpr int64_t kStateBase = kHistWords + 64;  // words: histograms, counters, kept count
 
@@ -534,19 +535,38 @@ __global__ void __launch_bounds__(kThreads) k_sort_pass(const uint32_t* __restri
     }
 }
 
+// Items per thread: from the capacity, or smaller partitions for an expected
+// count below it when the look-back state has room for their number.
+static int plan_items(int64_t cap, const SortTemp& t, int64_t size_hint)
+{
+    int items = sort_items(cap);
+    if (size_hint > 0 && size_hint < cap && sort_items(size_hint) != items) {
+        const int hi = sort_items(size_hint);
+        if (t.state_words >= (int64_t)kMaxPasses * radix_blocks_items(cap, hi) * kBins) items = hi;
+    }
+    return items;
+}
+
+SortPrep radix_sort_prep(Count n, int end_bit, const SortTemp& t, int64_t size_hint)
+{
+    SortPrep p;
+    if (n.cap <= 0 || n.cap > (int64_t)kCountMask) return p;
+    const int items = plan_items(n.cap, t, size_hint);
+    p.ghist = t.head;
+    p.state = t.state;
+    p.state_stride = (int64_t)radix_blocks_items(n.cap, items) * kBins;
+    p.part_items = (int64_t)kThreads * items;
+    p.passes = std::min(kMaxPasses, (end_bit + 7) / 8);
+    return p;
+}
+
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
-                   hipStream_t s, const uint32_t** kept, const uint32_t* keys_src, int64_t size_hint)
+                   hipStream_t s, const uint32_t** kept, const uint32_t* keys_src, int64_t size_hint, bool hist_done)
 {
     if (kept) *kept = nullptr;
     if (n.cap <= 0) return 0;
     if (n.cap > (int64_t)kCountMask) return -1;  // counts share a word with the look-back flags
-    int items = sort_items(n.cap);
-    if (size_hint > 0 && size_hint < n.cap && sort_items(size_hint) != items) {
-        // smaller partitions for an expected count below the capacity, when
-        // the look-back state has room for their number
-        const int hi = sort_items(size_hint);
-        if (t.state_words >= (int64_t)kMaxPasses * radix_blocks_items(n.cap, hi) * kBins) items = hi;
-    }
+    const int items = plan_items(n.cap, t, size_hint);
     const int nb = radix_blocks_items(n.cap, items);
     const int passes = std::min(kMaxPasses, (end_bit + 7) / 8);
     uint32_t* ghist = t.head;  // histograms and counters: zero on entry
@@ -557,8 +577,9 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, 
     const int hb = (int)std::min<int64_t>(std::max<int64_t>(nb, (n.cap + kHistBlockItems - 1) / kHistBlockItems), 2048);
     const int pb = std::min(nb, 2048);
     const uint32_t* first = keys_src ? keys_src : keys;
-    k_sort_hist<<<hb, kThreads, 0, s>>>(first, n.cap, n.dev, passes, ghist, drop, kept_dev, state,
-                                        (int64_t)nb * kBins, (int64_t)kThreads * items);
+    if (!hist_done || drop)
+        k_sort_hist<<<hb, kThreads, 0, s>>>(first, n.cap, n.dev, passes, ghist, drop, kept_dev, state,
+                                            (int64_t)nb * kBins, (int64_t)kThreads * items);
     uint32_t* kb[2] = {keys, t.keys_alt};
     uint32_t* vb[2] = {vals, t.vals_alt};
     int cur = 0;
