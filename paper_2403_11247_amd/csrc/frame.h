@@ -48,7 +48,7 @@ void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow = false);
 // order of all entries, pair offsets; the pair count ends up in w.total on the
 // device.  Returns the depth order.
 const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s,
-                        bool keep_overflow = false);
+                        bool keep_overflow = false, uint32_t* host_total = nullptr);
 // Pairs (at most f.cap, overflow flagged in w.overflow), stable tile sort,
 // tile ranges, forward compositing (after phase_a, or zero_pass when there
 // are no entries).

@@ -70,7 +70,8 @@ void zero_pass(Frame& f, Work& w, hipStream_t s, bool keep_overflow)
 
 // Projection, depth order of all entries, pair offsets; the pair count ends
 // up in w.total on the device.  Returns the depth order.
-const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s, bool keep_overflow)
+const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hipStream_t s, bool keep_overflow,
+                        uint32_t* host_total)
 {
     // the projection's threads also clear what zero_pass would (one launch fewer)
     const ZeroSegs z = pass_zero_segs(f, w, keep_overflow);
@@ -84,7 +85,7 @@ const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hi
     pf.end(VCGS_STAGE_DEPTH_SORT, s);
     const uint32_t* ord = which ? w.valtE : w.order;
     pf.begin(VCGS_STAGE_PAIR_SCAN, s);
-    pair_offsets(ord, f.count, Count{f.E, w.nvis}, w.cnt, w.offs, w.total, w.scanE, s);
+    pair_offsets(ord, f.count, Count{f.E, w.nvis}, w.cnt, w.offs, w.total, w.scanE, s, host_total);
     pf.end(VCGS_STAGE_PAIR_SCAN, s);
     return ord;
 }
@@ -423,11 +424,11 @@ static int render_forward_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
         if (hipMemcpyAsync(f.pt_dev, ctx->host_tab, sizeof(ProjTab), hipMemcpyHostToDevice, s) != hipSuccess)
             return drop(VCGS_E_HIP, "table upload failed");
         const uint32_t* ord = nullptr;
-        if (f.E > 0) ord = phase_a(ctx->prof, *g, f, w, s);
+        // the pair scan also writes the pair count into the pinned word: no copy before the synchronisation
+        if (f.E > 0) ord = phase_a(ctx->prof, *g, f, w, s, false, ctx->host_u32);
         else zero_pass(f, w, s);
         if (f.E > 0) {
-            if (hipMemcpyAsync(ctx->host_u32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
+            if (hipStreamSynchronize(s) != hipSuccess)
                 return drop(VCGS_E_HIP, std::string("pair count readback failed: ") +
                                             hipGetErrorString(hipGetLastError()));
             st->P = ctx->host_u32[0];

@@ -165,8 +165,10 @@ int64_t pair_scan_words(int64_t n);
 // one launch: cnt[k] = count[order[k]] for k below the device count n.dev
 // (0 up to n.cap), offs[k] = sum of cnt[j] for j < k, *total = the sum (all
 // saturating at 2^31).  state: pair_scan_words(n.cap) words, zero on entry.
+// host_total (optional): pinned host word that also receives the sum, so that
+// a caller that synchronises needs no copy.
 void pair_offsets(const uint32_t* order, const uint32_t* count, Count n, uint32_t* cnt, uint32_t* offs,
-                  uint32_t* total, uint32_t* state, hipStream_t s);
+                  uint32_t* total, uint32_t* state, hipStream_t s, uint32_t* host_total = nullptr);
 
 // binning.hip
 struct EmitTab {
@@ -220,6 +222,27 @@ __device__ __forceinline__ void zero_segs(const ZeroSegs& z, int64_t total, int6
         }
         z.p[seg][k] = 0u;
     }
+}
+
+// Sums of N per-thread values over a 256-thread block in a fixed order
+// (butterfly within each wave, then the four waves in order): the results are
+// in thread 0.  lds: 4 * N doubles of shared memory.  Every thread of the
+// block must call it.
+template <int N>
+__device__ __forceinline__ void block_sum_f64(double (&v)[N], double* lds)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) lds[w * N + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = (lds[i] + lds[N + i]) + (lds[2 * N + i] + lds[3 * N + i]);
 }
 void launch_zero_u32(const ZeroSegs& z, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);

@@ -110,11 +110,11 @@ int vcgs_render_forward_noalloc(vcgs_ctx* ctx, const vcgs_gaussians* g, const vc
     std::memcpy(ctx->host_tab, &f.pt, sizeof(ProjTab));
     HIP_TRY(hipMemcpyAsync(f.pt_dev, ctx->host_tab, sizeof(ProjTab), hipMemcpyHostToDevice, s));
     const uint32_t* ord = nullptr;
-    if (f.E > 0) ord = phase_a(ctx->prof, *g, f, w, s);
+    // the pair scan also writes the pair count into the pinned word: no copy before the synchronisation
+    if (f.E > 0) ord = phase_a(ctx->prof, *g, f, w, s, false, ctx->host_u32);
     else zero_pass(f, w, s);
     int64_t P = 0;
     if (f.E > 0) {
-        HIP_TRY(hipMemcpyAsync(ctx->host_u32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         P = ctx->host_u32[0];
         if (P > kMaxSortItems) return fail(VCGS_E_UNSUPPORTED, "more than 2^30-1 (tile, Gaussian) pairs");

@@ -499,22 +499,16 @@ void launch_preprocess_bwd(const ProjTab& t, const ProjTab* t_dev, const vcgs_ga
 __global__ void __launch_bounds__(256) k_pose_reduce(const float* __restrict__ partial, int nblocks,
                                                      float* __restrict__ out)
 {
-    __shared__ double acc[6][256];
+    __shared__ double acc[4 * 6];
     const float* part = partial + (int64_t)blockIdx.x * nblocks * 6;
     double a[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblocks; b += 256)
 #pragma unroll
         for (int i = 0; i < 6; ++i) a[i] += (double)part[6 * b + i];
+    block_sum_f64<6>(a, acc);
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int i = 0; i < 6; ++i) acc[i][threadIdx.x] = a[i];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-#pragma unroll
-            for (int i = 0; i < 6; ++i) acc[i][threadIdx.x] += acc[i][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 6) out[6 * blockIdx.x + threadIdx.x] = (float)acc[threadIdx.x][0];
+        for (int i = 0; i < 6; ++i) out[6 * blockIdx.x + i] = (float)a[i];
 }
 
 void launch_pose_reduce(const float* partial, int n_views, int nblocks, float* dl_dpose, hipStream_t s)

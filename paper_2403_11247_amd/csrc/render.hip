@@ -826,16 +826,11 @@ __global__ void __launch_bounds__(kLossThreads) k_l1_loss(int64_t npix, const fl
 __device__ __forceinline__ void k_sum_partials_body(const float* __restrict__ partial, int n, float scale,
                                                     float* __restrict__ out)
 {
-    __shared__ double acc[256];
-    double a = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) a += (double)partial[i];
-    acc[threadIdx.x] = a;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) acc[threadIdx.x] += acc[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = (float)(acc[0] * (double)scale);
+    __shared__ double acc[4];
+    double a[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += 256) a[0] += (double)partial[i];
+    block_sum_f64<1>(a, acc);
+    if (threadIdx.x == 0) *out = (float)(a[0] * (double)scale);
 }
 
 __global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ partial, int n, float scale,

@@ -225,7 +225,8 @@ __global__ void __launch_bounds__(kThreads) k_pair_offsets(int64_t n_all, const 
                                                            const uint32_t* __restrict__ count,
                                                            uint32_t* __restrict__ cnt, uint32_t* __restrict__ offs,
                                                            uint32_t* __restrict__ total,
-                                                           unsigned long long* __restrict__ state)
+                                                           unsigned long long* __restrict__ state,
+                                                           uint32_t* __restrict__ host_total)
 {
     __shared__ uint32_t tile[kBlockItems + kBlockItems / 16];
     __shared__ uint32_t s_part, s_excl;
@@ -284,7 +285,10 @@ __global__ void __launch_bounds__(kThreads) k_pair_offsets(int64_t n_all, const 
         tile[scan_pad(threadIdx.x * kItems + i)] = run;
         run = sat_add(run, v[i]);
     }
-    if (threadIdx.x == kThreads - 1 && base + kBlockItems >= n_all) *total = run;  // the last partition
+    if (threadIdx.x == kThreads - 1 && base + kBlockItems >= n_all) {  // the last partition
+        *total = run;
+        if (host_total) *host_total = run;
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
@@ -294,15 +298,16 @@ __global__ void __launch_bounds__(kThreads) k_pair_offsets(int64_t n_all, const 
 }
 
 void pair_offsets(const uint32_t* order, const uint32_t* count, Count n, uint32_t* cnt, uint32_t* offs,
-                  uint32_t* total, uint32_t* state, hipStream_t s)
+                  uint32_t* total, uint32_t* state, hipStream_t s, uint32_t* host_total)
 {
     if (n.cap <= 0) {
         launch_fill_u32(total, 0u, 1, s);
+        if (host_total) launch_fill_u32(host_total, 0u, 1, s);
         return;
     }
     const int64_t nb = (n.cap + kBlockItems - 1) / kBlockItems;
     k_pair_offsets<<<(unsigned)nb, kThreads, 0, s>>>(n.cap, n.dev, order, count, cnt, offs, total,
-                                                     reinterpret_cast<unsigned long long*>(state));
+                                                     reinterpret_cast<unsigned long long*>(state), host_total);
 }
 
 // ---------------------------------------------------------------------------
