@@ -22,6 +22,9 @@ struct Frame {
     uint32_t* gids = nullptr;
     int64_t cap = 0;  // pair capacity (exact pair count in the synchronising path)
     int64_t pair_hint = 0;  // expected pair count when cap is a generous bound (0: cap)
+    // the projection takes pt as a kernel argument and writes it to pt_dev
+    // (false: the caller uploads pt_dev, e.g. for a captured graph)
+    bool tab_by_value = false;
     // per-entry gradient sums of the backward: the projection zeroes the
     // slots of the visible entries when this is set (no separate fill)
     float* g2 = nullptr;

@@ -76,7 +76,7 @@ const uint32_t* phase_a(Prof& pf, const vcgs_gaussians& g, Frame& f, Work& w, hi
     // the projection's threads also clear what zero_pass would (one launch fewer)
     const ZeroSegs z = pass_zero_segs(f, w, keep_overflow);
     pf.begin(VCGS_STAGE_PREPROCESS, s);
-    launch_preprocess(f.pt, f.pt_dev, g, f.rec, f.depth_key, f.rect, f.count, f.g2, s, &z);
+    launch_preprocess(f.pt, f.pt_dev, g, f.rec, f.depth_key, f.rect, f.count, f.g2, s, &z, f.tab_by_value);
     pf.end(VCGS_STAGE_PREPROCESS, s);
     pf.begin(VCGS_STAGE_DEPTH_SORT, s);
     // culled entries carry the drop key and leave the depth order in its first pass
@@ -418,11 +418,16 @@ static int render_forward_impl(vcgs_ctx* ctx, const vcgs_gaussians* g, const vcg
         Work w{};
         alloc_work_e(w, f.E, [&](int64_t c) { return sc.get<uint32_t>(c); });
         if (sc.oom) return drop(VCGS_E_NOMEM, "device allocation failed (depth sort)");
-        // the table is read by the kernels from device memory; the stream is
-        // synchronised below, so the pinned staging copy is free again on return
-        std::memcpy(ctx->host_tab, &f.pt, sizeof(ProjTab));
-        if (hipMemcpyAsync(f.pt_dev, ctx->host_tab, sizeof(ProjTab), hipMemcpyHostToDevice, s) != hipSuccess)
-            return drop(VCGS_E_HIP, "table upload failed");
+        // the projection takes the table as a kernel argument and leaves the
+        // device copy the backward reads; with nothing to project it is
+        // uploaded (the stream is synchronised below, so the pinned staging
+        // copy is free again on return)
+        f.tab_by_value = f.E > 0;
+        if (!f.tab_by_value) {
+            std::memcpy(ctx->host_tab, &f.pt, sizeof(ProjTab));
+            if (hipMemcpyAsync(f.pt_dev, ctx->host_tab, sizeof(ProjTab), hipMemcpyHostToDevice, s) != hipSuccess)
+                return drop(VCGS_E_HIP, "table upload failed");
+        }
         const uint32_t* ord = nullptr;
         // the pair scan also writes the pair count into the pinned word: no copy before the synchronisation
         if (f.E > 0) ord = phase_a(ctx->prof, *g, f, w, s, false, ctx->host_u32);

@@ -94,14 +94,16 @@ struct Count {
 
 // ---- launchers (all asynchronous on `s`) --------------------------------
 // preprocess.hip
-// The kernels read the table from device memory (t_dev, a copy of t) so that a
-// captured graph can be replayed with new poses.
+// The backward reads the table from device memory (t_dev) so that a captured
+// graph can be replayed with new poses.  The projection reads it from t_dev
+// too, unless by_value: then it takes t as a kernel argument (no upload) and
+// writes the copy at t_dev (when non-null) for the backward.
 // g2_zero (optional): kG2 floats per entry, zeroed for every visible entry.
 struct ZeroSegs;
 // zero: words the pass needs at zero (the projection's threads clear them too), or null.
-void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
+void launch_preprocess(const ProjTab& t, ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
                        uint32_t* depth_key, uint2* rect, uint32_t* count, float* g2_zero, hipStream_t s,
-                       const ZeroSegs* zero = nullptr);
+                       const ZeroSegs* zero = nullptr, bool by_value = false);
 int preprocess_bwd_blocks(int64_t n);
 // g2, count and rec have n_views * n entries; pose_partial holds n_views * blocks * 6 floats.
 void launch_preprocess_bwd(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, const uint32_t* count,

@@ -106,9 +106,8 @@ int vcgs_render_forward_noalloc(vcgs_ctx* ctx, const vcgs_gaussians* g, const vc
         return fail(VCGS_E_CAPACITY, "the Gaussians and pixels need " + std::to_string(cv.used) +
                                          " bytes of scratch before the pairs; the array holds " +
                                          std::to_string(kNoAllocBytes));
-    // the pinned staging copy is free again after the synchronisation below
-    std::memcpy(ctx->host_tab, &f.pt, sizeof(ProjTab));
-    HIP_TRY(hipMemcpyAsync(f.pt_dev, ctx->host_tab, sizeof(ProjTab), hipMemcpyHostToDevice, s));
+    // the projection takes the table as a kernel argument (forward only: no device copy is read)
+    f.tab_by_value = true;
     const uint32_t* ord = nullptr;
     // the pair scan also writes the pair count into the pinned word: no copy before the synchronisation
     if (f.E > 0) ord = phase_a(ctx->prof, *g, f, w, s, false, ctx->host_u32);

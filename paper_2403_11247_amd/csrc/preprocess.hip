@@ -137,18 +137,29 @@ __device__ __forceinline__ KeyOut key_path(float x, float y, float z, float s0, 
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_preprocess(const ProjTab* __restrict__ tabp, const float* __restrict__ mean,
+// DEV: the table is read from device memory (tabp; a captured graph replays
+// with the poses uploaded there), else from the kernel argument tab_val, which
+// block 0 also copies to save (when set) for the launches of the backward.
+template <bool DEV>
+__global__ void __launch_bounds__(256) k_preprocess(ProjTab tab_val, const ProjTab* __restrict__ tabp,
+                                                    ProjTab* __restrict__ save, const float* __restrict__ mean,
                                                     const float* __restrict__ scale, const float* __restrict__ quat,
                                                     const float* __restrict__ opac, const float* __restrict__ color,
                                                     Splat* __restrict__ rec, uint32_t* __restrict__ depth_key,
                                                     uint2* __restrict__ rect, uint32_t* __restrict__ count,
                                                     float* __restrict__ g2_zero, ZeroSegs z, int64_t ztotal)
 {
-    const ProjTab& tab = *tabp;
+    const ProjTab& tab = DEV ? *tabp : tab_val;
     const int64_t n = tab.n;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // the pass's counters, ranges and look-back words (read only by later launches)
     if (ztotal > 0) zero_segs(z, ztotal, e, (int64_t)gridDim.x * blockDim.x);
+    if (!DEV && save && blockIdx.x == 0) {
+        static_assert(sizeof(ProjTab) % 4 == 0, "table copied in words");
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&tab_val);
+        for (int i = threadIdx.x; i < (int)(sizeof(ProjTab) / 4); i += blockDim.x)
+            reinterpret_cast<uint32_t*>(save)[i] = src[i];
+    }
     if (e >= n * tab.n_views) return;
     const int v = (int)(e / n);
     const int64_t g = e - (int64_t)v * n;
@@ -196,9 +207,9 @@ __global__ void __launch_bounds__(256) k_preprocess(const ProjTab* __restrict__ 
     }
 }
 
-void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
+void launch_preprocess(const ProjTab& t, ProjTab* t_dev, const vcgs_gaussians& g, Splat* rec,
                        uint32_t* depth_key, uint2* rect, uint32_t* count, float* g2_zero, hipStream_t s,
-                       const ZeroSegs* zero)
+                       const ZeroSegs* zero, bool by_value)
 {
     ZeroSegs z{};
     int64_t ztotal = 0;
@@ -211,8 +222,13 @@ void launch_preprocess(const ProjTab& t, const ProjTab* t_dev, const vcgs_gaussi
         if (zero) launch_zero_u32(*zero, s);
         return;
     }
-    k_preprocess<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(t_dev, g.mean, g.scale, g.quat, g.opacity, g.color, rec,
-                                                                 depth_key, rect, count, g2_zero, z, ztotal);
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    if (by_value)
+        k_preprocess<false><<<blocks, 256, 0, s>>>(t, nullptr, t_dev, g.mean, g.scale, g.quat, g.opacity, g.color, rec,
+                                                   depth_key, rect, count, g2_zero, z, ztotal);
+    else
+        k_preprocess<true><<<blocks, 256, 0, s>>>(t, t_dev, nullptr, g.mean, g.scale, g.quat, g.opacity, g.color, rec,
+                                                  depth_key, rect, count, g2_zero, z, ztotal);
 }
 
 // ---------------------------------------------------------------------------

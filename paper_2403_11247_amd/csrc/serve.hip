@@ -37,7 +37,6 @@ struct Slot {
     hipEvent_t done = nullptr;
     Frame f;
     Work w{};
-    ProjTab* pt_host = nullptr;      // pinned
     uint32_t* flags_host = nullptr;  // pinned: pair count, overflow
     int64_t cap = 0;                 // pair capacity
     int64_t tiles_cap = 0;           // capacity of f.ranges in tiles
@@ -224,9 +223,8 @@ struct vcgs_server {
         // enqueued; an event that has already completed needs no wait
         for (const Req& r : sl.reqs)
             if (hipEventQuery(r.submitted) != hipSuccess) HIP_TRY(hipStreamWaitEvent(sl.s, r.submitted, 0));
-        // the slot is idle, so its previous table upload has completed
-        std::memcpy(sl.pt_host, &f.pt, sizeof(ProjTab));
-        HIP_TRY(hipMemcpyAsync(f.pt_dev, sl.pt_host, sizeof(ProjTab), hipMemcpyHostToDevice, sl.s));
+        // the projection takes the table as a kernel argument (no upload)
+        f.tab_by_value = true;
         if (f.E > 0) {
             if (decode) launch_decode_fwd(dec, sl.set, sl.s);
             const uint32_t* ord = phase_a(quiet_prof(), g, f, sl.w, sl.s);
@@ -289,7 +287,6 @@ struct vcgs_server {
             dfree(sl.blocks_e);
             dfree(sl.blocks_p);
             dfree(sl.blocks_r);
-            if (sl.pt_host) (void)hipHostFree(sl.pt_host);
             if (sl.flags_host) (void)hipHostFree(sl.flags_host);
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.s) (void)hipStreamDestroy(sl.s);
@@ -331,7 +328,6 @@ int create_server(vcgs_ctx* ctx, const vcgs_gaussians* map, const DecodeArgs* de
     for (Slot& sl : srv->slots) {
         bool ok = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
-                  hipHostMalloc((void**)&sl.pt_host, sizeof(ProjTab), hipHostMallocDefault) == hipSuccess &&
                   hipHostMalloc((void**)&sl.flags_host, 16, hipHostMallocDefault) == hipSuccess;
         if (!ok) {
             srv->release();
