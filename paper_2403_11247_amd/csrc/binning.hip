@@ -213,11 +213,13 @@ __global__ void __launch_bounds__(kEmitG) k_emit_pairs(EmitTab tab, int64_t n_al
 bool launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis, const uint32_t* order,
                        const uint32_t* offs, const uint32_t* cnt, const uint2* rect, uint32_t* chunk_start,
                        uint32_t* tile_ids, uint32_t* gids, int64_t cap, const uint32_t* total, uint32_t* overflow,
-                       const SortPrep& sp, hipStream_t s)
+                       const SortPrep& sp, hipStream_t s, int64_t grid_items)
 {
     if (n_entries <= 0 || cap <= 0) return false;
     k_chunk_starts<<<(unsigned)((n_entries + 255) / 256), 256, 0, s>>>(n_entries, nvis, offs, cnt, cap, chunk_start);
-    const int64_t blocks = std::min<int64_t>((cap + kChunk - 1) / kChunk, 4096);
+    // blocks stride over the chunks, so the grid follows the expected count when given
+    const int64_t gi = grid_items > 0 ? std::min(cap, grid_items) : cap;
+    const int64_t blocks = std::min<int64_t>((gi + kChunk - 1) / kChunk, 4096);
     // 16-byte stores of whole runs need 16-byte aligned outputs
     const int vec = ((reinterpret_cast<uintptr_t>(tile_ids) | reinterpret_cast<uintptr_t>(gids)) & 15u) == 0u;
     k_emit_pairs<<<(unsigned)blocks, kEmitG, 0, s>>>(
@@ -269,10 +271,12 @@ __global__ void __launch_bounds__(256) k_tile_ranges(int64_t cap, const uint32_t
     }
 }
 
-void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s)
+void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s,
+                        int64_t grid_items)
 {
     if (P.cap <= 0) return;
-    const int64_t blocks = std::min<int64_t>((P.cap + 1023) / 1024, 4096);
+    const int64_t gi = grid_items > 0 ? std::min(P.cap, grid_items) : P.cap;  // grid-stride loop
+    const int64_t blocks = std::min<int64_t>((gi + 1023) / 1024, 4096);
     const int vec = (reinterpret_cast<uintptr_t>(tile_sorted) & 15u) == 0u;
     k_tile_ranges<<<(unsigned)blocks, 256, 0, s>>>(P.cap, P.dev, tile_sorted, n_tiles, ranges, vec);
 }

@@ -100,8 +100,11 @@ void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s)
         // the emission builds the tile sort's histograms (the projection launch cleared them)
         const SortPrep sp = radix_sort_prep(P, end_bit, tp, f.pair_hint);
         pf.begin(VCGS_STAGE_EMIT, s);
+        // grids follow the expected count (with a margin) when the capacity is only a bound
+        const int64_t grid_items =
+            f.pair_hint > 0 ? std::min<int64_t>(f.cap, f.pair_hint + f.pair_hint / 2 + 4096) : f.cap;
         const bool hist = launch_emit_pairs(f.et, f.E, w.nvis, ord, w.offs, w.cnt, f.rect, w.scanP, w.tile_ids,
-                                            f.gids, f.cap, w.total, w.overflow, sp, s) &&
+                                            f.gids, f.cap, w.total, w.overflow, sp, s, grid_items) &&
                           sp.ghist != nullptr;
         pf.end(VCGS_STAGE_EMIT, s);
         pf.begin(VCGS_STAGE_TILE_SORT, s);
@@ -111,7 +114,7 @@ void phase_b(Prof& pf, Frame& f, Work& w, const uint32_t* ord, hipStream_t s)
         if (ws) launch_copy_u32(f.gids, w.valtP, P, s);
         pf.end(VCGS_STAGE_TILE_SORT, s);
         pf.begin(VCGS_STAGE_TILE_RANGES, s);
-        launch_tile_ranges(P, tsorted, f.total_tiles, f.ranges, s);
+        launch_tile_ranges(P, tsorted, f.total_tiles, f.ranges, s, grid_items);
         pf.end(VCGS_STAGE_TILE_RANGES, s);
     }
     unsigned long long* cnts = nullptr;

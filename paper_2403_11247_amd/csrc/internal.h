@@ -137,7 +137,9 @@ int64_t scan_temp_words(int64_t n);
 // `keys` is only used as a buffer.
 constexpr uint32_t kDropKey = 0xFFFFFFFFu;
 // size_hint (> 0): the expected item count when the capacity n.cap is a
-// generous bound; the partition size follows it if t.state holds enough words.
+// generous bound; the partition size follows it if t.state holds enough words,
+// and the passes' grids are sized for it (with a margin; any count up to the
+// capacity is still sorted).
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, int end_bit, const SortTemp& t,
                    hipStream_t s, const uint32_t** kept = nullptr, const uint32_t* keys_src = nullptr,
                    int64_t size_hint = 0, bool hist_done = false);
@@ -188,12 +190,15 @@ struct EmitTab {
 // With sp.ghist set, it also does what sp asks of the tile ids for the tile
 // sort (see radix_sort_prep); returns false if it launched nothing (then the
 // sort must build its own histogram).
+// grid_items (> 0): the expected pair count when cap is a generous bound; the
+// grid is sized for it (any count up to cap is still emitted).
 bool launch_emit_pairs(const EmitTab& t, int64_t n_entries, const uint32_t* nvis, const uint32_t* order,
                        const uint32_t* offs, const uint32_t* cnt, const uint2* rect, uint32_t* chunk_start,
                        uint32_t* tile_ids, uint32_t* gids, int64_t cap, const uint32_t* total, uint32_t* overflow,
-                       const SortPrep& sp, hipStream_t s);
+                       const SortPrep& sp, hipStream_t s, int64_t grid_items = 0);
 int64_t emit_chunk_words(int64_t cap);
-void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s);
+void launch_tile_ranges(Count P, const uint32_t* tile_sorted, uint32_t n_tiles, uint32_t* ranges, hipStream_t s,
+                        int64_t grid_items = 0);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 // Zeroes up to four buffers (null or empty ones are skipped) in one launch.
 constexpr int kZeroSegs = 5;

@@ -580,7 +580,11 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, bool identity_vals, Count n, 
     uint32_t* state = t.state;  // the look-back words: zeroed by k_sort_hist
     const int drop = kept != nullptr;
     const int hb = (int)std::min<int64_t>(std::max<int64_t>(nb, (n.cap + kHistBlockItems - 1) / kHistBlockItems), 2048);
-    const int pb = std::min(nb, 2048);
+    // pass grid: blocks take partitions until none is left, so with an
+    // expected count (capacity a generous bound) the grid follows it (with a
+    // margin) rather than the capacity
+    const int64_t grid_items = size_hint > 0 ? std::min<int64_t>(n.cap, size_hint + size_hint / 2 + 4096) : n.cap;
+    const int pb = std::min(radix_blocks_items(grid_items, items), 2048);
     const uint32_t* first = keys_src ? keys_src : keys;
     if (!hist_done || drop)
         k_sort_hist<<<hb, kThreads, 0, s>>>(first, n.cap, n.dev, passes, ghist, drop, kept_dev, state,
