@@ -29,21 +29,29 @@ def _stats(lat, pixels, t_first, t_last):
             "span_s": round(span, 3)}
 
 
-def replay(server: "vcgs.Server", trace, poll_us=200):
+def replay(server: "vcgs.Server", trace, poll_us=200, ring=64):
     """Submits each request at its arrival time and polls the server until all
     complete.  Returns latency percentiles, throughput and server counters.
-    The output images of every request are allocated before the replay starts
-    (a serving loop reuses its image buffers), so an arrival costs only the
-    submission and the launch."""
+    Output images come from a ring of `ring` buffer sets per image size,
+    allocated before the replay starts, as a serving loop reuses its image
+    buffers (more sets than the server can have in running passes, so no two
+    running requests share one); an arrival costs only the submission and the
+    launch."""
     n = len(trace)
     lat = [0.0] * n
     pending = {}
     st0 = server.stats()
     pixels = sum(int(c.width) * int(c.height) for _, c, _ in trace)
     dev = server.dev
-    outs = [(torch.empty((3, int(c.height), int(c.width)), device=dev),
-             torch.empty((int(c.height), int(c.width)), device=dev),
-             torch.empty((int(c.height), int(c.width)), device=dev)) for _, c, _ in trace]
+    pools, seen, outs = {}, {}, []
+    for _, c, _ in trace:
+        key = (int(c.height), int(c.width))
+        k = seen.get(key, 0)
+        seen[key] = k + 1
+        pool = pools.setdefault(key, [])
+        if k < ring:
+            pool.append((torch.empty((3,) + key, device=dev), torch.empty(key, device=dev), torch.empty(key, device=dev)))
+        outs.append(pool[k % ring])
     torch.cuda.synchronize()
     # no collector pauses inside the timed loop (a full collection of a large
     # process stalls the host for tens of milliseconds)
